@@ -1,0 +1,292 @@
+"""FP64 CPU oracle of the ImLoc pose-estimation hot path (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the GPU library (``paper_2601_04185_amd``) and never imports it.
+
+The C source (``imloc_oracle.c``) holds the definitions; this module only
+marshals numpy arrays.  Which passage of the paper each function follows is
+stated in ``imloc_oracle.h``:
+  lift              -- Sec. 3.3 "Query Time Matching and 2D-3D Lifting"
+  sample / p3p      -- Sec. 3.3 "Pose Estimation" (minimal sets, P3P solver)
+  score             -- Sec. 3.3 (truncated, confidence-weighted reprojection error)
+  lo                -- Sec. 3.3 (non-linear refinement of the truncated cost)
+  required_samples  -- Sec. 3.3 (stop when P(missing the best model) is small)
+  refine            -- Sec. 3.3 (final robust Cauchy refinement on all inliers)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C11 + OpenMP)."""
+    if force or not os.path.exists(_SO):
+        src = os.path.join(_HERE, "imloc_oracle.c")
+        tmp = _SO + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-std=gnu11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+               "-Wno-unused-parameter", src, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class Camera(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class Corr(C.Structure):
+    _fields_ = [("u", C.c_void_p), ("v", C.c_void_p), ("X", C.c_void_p), ("Y", C.c_void_p),
+                ("Z", C.c_void_p), ("w", C.c_void_p), ("n", C.c_int64)]
+
+
+class Params(C.Structure):
+    _fields_ = [("threshold_px", C.c_double), ("fixed_samples", C.c_int64), ("batch", C.c_int64),
+                ("min_iters", C.c_int64), ("max_iters", C.c_int64), ("confidence", C.c_double),
+                ("lo_top_k", C.c_int32), ("lo_iters", C.c_int32), ("max_score_points", C.c_int64),
+                ("final_iters", C.c_int32), ("cauchy_scale_px", C.c_double), ("exhaustive", C.c_int32),
+                ("seed", C.c_uint64), ("query_id", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("samples", C.c_int64), ("candidates", C.c_int64), ("residuals", C.c_int64),
+                ("best_count", C.c_int64), ("full_count", C.c_int64), ("batches", C.c_int64),
+                ("lo_runs", C.c_int32), ("status", C.c_int32), ("best_msac", C.c_double),
+                ("final_cost", C.c_double), ("best_h", C.c_int64), ("best_j", C.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = C.CDLL(_SO)
+        vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        L.orc_philox4x64_10.argtypes = [vp, vp, vp]
+        L.orc_sample_triple.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, i64, vp]
+        L.orc_sample_triple.restype = C.c_int
+        L.orc_unrank_triple.argtypes = [C.c_uint64, i64, vp]
+        L.orc_unrank_triple.restype = C.c_int
+        L.orc_p3p.argtypes = [vp, vp, vp, vp, vp]
+        L.orc_p3p.restype = C.c_int
+        L.orc_score.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
+        L.orc_score_band.argtypes = [vp, i64, vp, vp, dbl, dbl, i32, vp, vp, vp]
+        L.orc_lo.argtypes = [vp, vp, vp, dbl, i32, vp, vp, vp]
+        L.orc_lo.restype = C.c_int
+        L.orc_refine.argtypes = [vp, vp, vp, dbl, dbl, i32, vp, vp, vp]
+        L.orc_refine.restype = C.c_int
+        L.orc_required_samples.argtypes = [dbl, dbl, i64]
+        L.orc_required_samples.restype = i64
+        L.orc_lo_ransac_pnp.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.orc_lo_ransac_pnp.restype = C.c_int
+        L.orc_lift.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp, i32, i32, i32, vp, vp, C.c_float,
+                               vp, vp, vp, vp, vp, vp, vp]
+        L.orc_lift.restype = i64
+        L.orc_normal_equations.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
+        L.orc_normal_equations.restype = dbl
+        L.orc_pose_update.argtypes = [vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _cam(K) -> Camera:
+    fx, fy, cx, cy = [float(x) for x in K]
+    return Camera(fx, fy, cx, cy)
+
+
+def pose_array(R, t) -> np.ndarray:
+    """(R, t) -> the 12-double layout of orc_pose (R row-major, then t)."""
+    return np.concatenate([np.asarray(R, np.float64).reshape(9), np.asarray(t, np.float64).reshape(3)])
+
+
+def split_pose(a):
+    a = np.asarray(a, np.float64)
+    return a[:9].reshape(3, 3).copy(), a[9:12].copy()
+
+
+class _CorrHold:
+    """Keeps float32 SoA copies alive while the C side reads them."""
+
+    def __init__(self, corr):
+        self.arrs = {}
+        for k in ("u", "v", "X", "Y", "Z"):
+            self.arrs[k] = np.ascontiguousarray(corr[k], dtype=np.float32)
+        w = corr.get("w")
+        self.arrs["w"] = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
+        n = self.arrs["u"].shape[0]
+        self.c = Corr(*[self.arrs[k].ctypes.data for k in ("u", "v", "X", "Y", "Z")],
+                      None if self.arrs["w"] is None else self.arrs["w"].ctypes.data, n)
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, np.uint64)
+    k = np.asarray(key, np.uint64)
+    o = np.zeros(4, np.uint64)
+    lib().orc_philox4x64_10(_p(c), _p(k), _p(o))
+    return o
+
+
+def sample_triple(seed: int, query_id: int, h: int, n: int):
+    idx = np.zeros(3, np.int32)
+    ok = lib().orc_sample_triple(seed, query_id, h, n, _p(idx))
+    return bool(ok), idx
+
+
+def unrank_triple(h: int, n: int):
+    idx = np.zeros(3, np.int32)
+    ok = lib().orc_unrank_triple(h, n, _p(idx))
+    return bool(ok), idx
+
+
+def p3p(uv, Xw, K):
+    """uv: (3,2) pixels, Xw: (3,3) world points -> (list of (R, t), ill flag)."""
+    uv = np.ascontiguousarray(uv, np.float64).reshape(6)
+    Xw = np.ascontiguousarray(Xw, np.float64).reshape(9)
+    out = np.zeros((4, 12), np.float64)
+    ill = np.zeros(1, np.int32)
+    cam = _cam(K)
+    ns = lib().orc_p3p(_p(uv), _p(Xw), C.byref(cam), _p(out), _p(ill))
+    return [split_pose(out[k]) for k in range(ns)], bool(ill[0])
+
+
+def _poses(poses) -> np.ndarray:
+    if isinstance(poses, np.ndarray) and poses.ndim == 2 and poses.shape[1] == 12:
+        return np.ascontiguousarray(poses, np.float64)
+    return np.ascontiguousarray(np.stack([pose_array(R, t) for R, t in poses]), np.float64)
+
+
+def score(poses, corr, K, tau):
+    P = _poses(poses)
+    h = _CorrHold(corr)
+    cnt = np.zeros(P.shape[0], np.int32)
+    ms = np.zeros(P.shape[0], np.float64)
+    cam = _cam(K)
+    lib().orc_score(_p(P), P.shape[0], C.byref(h.c), C.byref(cam), float(tau), _p(cnt), _p(ms))
+    return cnt, ms
+
+
+def score_band(poses, corr, K, tau, band_abs=1e-5, with_f32=True):
+    P = _poses(poses)
+    h = _CorrHold(corr)
+    lo = np.zeros(P.shape[0], np.int32)
+    hi = np.zeros(P.shape[0], np.int32)
+    eb = np.zeros(P.shape[0], np.float64)
+    cam = _cam(K)
+    lib().orc_score_band(_p(P), P.shape[0], C.byref(h.c), C.byref(cam), float(tau), float(band_abs),
+                         1 if with_f32 else 0, _p(lo), _p(hi), _p(eb))
+    return lo, hi, eb
+
+
+def lo(start, corr, K, tau, iters=10):
+    s = pose_array(*start) if isinstance(start, tuple) else np.asarray(start, np.float64)
+    out = np.zeros(12, np.float64)
+    cost = np.zeros(1, np.float64)
+    cnt = np.zeros(1, np.int64)
+    h = _CorrHold(corr)
+    cam = _cam(K)
+    acc = lib().orc_lo(_p(s), C.byref(h.c), C.byref(cam), float(tau), int(iters), _p(out), _p(cost), _p(cnt))
+    R, t = split_pose(out)
+    return R, t, float(cost[0]), int(cnt[0]), int(acc)
+
+
+def normal_equations(pose, corr, K, tau):
+    """-> (cost, H (6,6), g (6,), inlier count) at the pose."""
+    s = pose_array(*pose) if isinstance(pose, tuple) else np.asarray(pose, np.float64)
+    H = np.zeros(36, np.float64)
+    g = np.zeros(6, np.float64)
+    cnt = np.zeros(1, np.int64)
+    h = _CorrHold(corr)
+    cam = _cam(K)
+    cost = lib().orc_normal_equations(_p(s), C.byref(h.c), C.byref(cam), float(tau), _p(H), _p(g), _p(cnt))
+    return float(cost), H.reshape(6, 6), g, int(cnt[0])
+
+
+def pose_update(pose, d):
+    s = pose_array(*pose) if isinstance(pose, tuple) else np.asarray(pose, np.float64)
+    dd = np.ascontiguousarray(d, np.float64)
+    out = np.zeros(12, np.float64)
+    lib().orc_pose_update(_p(s), _p(dd), _p(out))
+    return split_pose(out)
+
+
+def refine(start, corr, K, tau, s, iters=10):
+    st = pose_array(*start) if isinstance(start, tuple) else np.asarray(start, np.float64)
+    out = np.zeros(12, np.float64)
+    cost = np.zeros(1, np.float64)
+    ninl = np.zeros(1, np.int64)
+    h = _CorrHold(corr)
+    cam = _cam(K)
+    acc = lib().orc_refine(_p(st), C.byref(h.c), C.byref(cam), float(tau), float(s), int(iters), _p(out),
+                           _p(cost), _p(ninl))
+    R, t = split_pose(out)
+    return R, t, float(cost[0]), int(ninl[0]), int(acc)
+
+
+def required_samples(eps: float, confidence: float, max_iters: int = 100000) -> int:
+    return int(lib().orc_required_samples(float(eps), float(confidence), int(max_iters)))
+
+
+DEFAULT_PARAMS = dict(threshold_px=4.0, fixed_samples=0, batch=1024, min_iters=1024, max_iters=100000,
+                      confidence=0.9999, lo_top_k=8, lo_iters=10, max_score_points=0, final_iters=10,
+                      cauchy_scale_px=None, exhaustive=0, seed=0, query_id=0)
+
+
+def make_params(**kw) -> Params:
+    d = dict(DEFAULT_PARAMS)
+    d.update(kw)
+    if d["cauchy_scale_px"] is None:
+        d["cauchy_scale_px"] = 0.5 * d["threshold_px"]
+    return Params(float(d["threshold_px"]), int(d["fixed_samples"]), int(d["batch"]), int(d["min_iters"]),
+                  int(d["max_iters"]), float(d["confidence"]), int(d["lo_top_k"]), int(d["lo_iters"]),
+                  int(d["max_score_points"]), int(d["final_iters"]), float(d["cauchy_scale_px"]),
+                  int(d["exhaustive"]), int(d["seed"]), int(d["query_id"]))
+
+
+def lo_ransac_pnp(corr, K, **params):
+    """Whole LO-RANSAC PnP for one query -> dict(R, t, mask, stats...)."""
+    h = _CorrHold(corr)
+    n = h.c.n
+    cam = _cam(K)
+    prm = make_params(**params)
+    pose = np.zeros(12, np.float64)
+    mask = np.zeros(max(n, 1), np.uint8)
+    st = Stats()
+    status = lib().orc_lo_ransac_pnp(C.byref(h.c), C.byref(cam), C.byref(prm), _p(pose), _p(mask), C.byref(st))
+    R, t = split_pose(pose)
+    out = dict(R=R, t=t, mask=mask[:n].copy(), status=int(status))
+    for f, _ in Stats._fields_:
+        out[f] = getattr(st, f)
+    return out
+
+
+def lift(matches, depth, cams, poses, min_conf=0.05, subpixel=True):
+    """matches: dict q_u, q_v, db_u, db_v, conf (float32), view (int32).
+    depth: (K, H, W) float32.  cams: (K, 4).  poses: (K, 12) cam_from_world."""
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    qu, qv, du, dv, cf = (f32(matches[k]) for k in ("q_u", "q_v", "db_u", "db_v", "conf"))
+    vw = np.ascontiguousarray(matches["view"], np.int32)
+    D = f32(depth)
+    nv, H, W = D.shape
+    cams_a = np.ascontiguousarray(np.asarray(cams, np.float64).reshape(nv, 4))
+    poses_a = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(nv, 12))
+    n = qu.shape[0]
+    outs = [np.zeros(max(n, 1), np.float64) for _ in range(6)]
+    src = np.zeros(max(n, 1), np.int64)
+    cnt = lib().orc_lift(_p(qu), _p(qv), _p(du), _p(dv), _p(cf), _p(vw), n, 1 if subpixel else 0, _p(D), nv, H, W,
+                         _p(cams_a), _p(poses_a), C.c_float(np.float32(min_conf)), *[_p(o) for o in outs], _p(src))
+    names = ("u", "v", "X", "Y", "Z", "w")
+    res = {k: o[:cnt].copy() for k, o in zip(names, outs)}
+    res["src"] = src[:cnt].copy()
+    return res

@@ -1,0 +1,150 @@
+/*
+ * imloc_oracle.h -- FP64 CPU oracle for the ImLoc pose-estimation hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously-correct
+ * definition that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no source with the GPU library and includes none of its headers.
+ *
+ * What it follows (ImLoc, Jiang et al., arXiv 2601.04185):
+ *   - Sec. 3.3 "Query Time Matching and 2D-3D Lifting": lift 2D-2D matches to
+ *     2D-3D through the stored depth maps (bilinear at sub-pixel database
+ *     coordinates, plain lookup otherwise), keep matches with valid depth and
+ *     confidence above 0.05.
+ *   - Sec. 3.3 "Pose Estimation": LO-RANSAC over P3P minimal sets, scoring by a
+ *     confidence-weighted truncated squared reprojection error, non-linear
+ *     refinement of that truncated cost on each new best, stop at an
+ *     iteration cap or when the probability of missing the best model falls
+ *     below a bound, final robust Cauchy refinement on all inliers.
+ *   - Sec. 1 cites the Haralick et al. (1994) review for PnP; the P3P here is
+ *     Grunert's law-of-cosines elimination described in that review.
+ * The paper prints no formulas; the readings taken where it is silent are the
+ * ones listed with each function below.
+ *
+ * Everything is FP64.  Float32 inputs are promoted to double on entry.
+ */
+#ifndef IMLOC_ORACLE_H
+#define IMLOC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double fx, fy, cx, cy; } orc_camera;      /* pinhole, no distortion */
+typedef struct { double R[9]; double t[3]; } orc_pose;      /* cam_from_world, R row-major */
+
+/* Correspondence set in structure-of-arrays form, float32 as the GPU sees it. */
+typedef struct {
+  const float *u, *v;          /* observed query pixel (continuous coords) */
+  const float *X, *Y, *Z;      /* world point */
+  const float *w;              /* confidence weight; NULL means all 1 */
+  int64_t n;
+} orc_corr;
+
+typedef struct {
+  double threshold_px;         /* tau: inlier iff squared error < tau^2 */
+  int64_t fixed_samples;       /* > 0: draw exactly this many samples, no adaptive stop */
+  int64_t batch;               /* samples per batch */
+  int64_t min_iters, max_iters;
+  double confidence;           /* stop when P(miss best) < 1 - confidence */
+  int32_t lo_top_k;            /* candidates refined per batch */
+  int32_t lo_iters;            /* Gauss-Newton iterations of the local optimisation */
+  int64_t max_score_points;    /* 0: score all; else stride-subsample to this many */
+  int32_t final_iters;         /* Cauchy IRLS iterations of the final refinement */
+  double cauchy_scale_px;      /* s of the Cauchy loss */
+  int32_t exhaustive;          /* 1: sample h is the h-th 3-combination (tiny n only) */
+  uint64_t seed, query_id;
+} orc_params;
+
+typedef struct {
+  int64_t samples, candidates, residuals;
+  int64_t best_count;          /* inliers of the best model on the scoring set */
+  int64_t full_count;          /* inliers on the full set at the final pose */
+  int64_t batches;
+  int32_t lo_runs, status;     /* status 0 = pose, 1 = no pose */
+  double best_msac;            /* truncated cost of the best model on the scoring set */
+  double final_cost;           /* Cauchy cost at the final pose */
+  int64_t best_h; int32_t best_j;  /* sample / solution the best model grew from */
+} orc_stats;
+
+/* Philox4x64-10 block function (Salmon et al., SC'11). */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Minimal sample h of a query: three distinct indices in [0, n).
+ * Counter (h, query_id, attempt, 0), key (seed, 0); index k = floor(word_k * n / 2^64);
+ * up to 16 attempts, else the sample is empty.  Returns 1 if valid. */
+int orc_sample_triple(uint64_t seed, uint64_t query_id, uint64_t h, int64_t n, int32_t idx[3]);
+
+/* h-th 3-combination of [0, n) in colexicographic order (exhaustive mode). */
+int orc_unrank_triple(uint64_t h, int64_t n, int32_t idx[3]);
+
+/* P3P (Grunert via Haralick et al. 1994).  Inputs: pixel coords uv[2*k+{0,1}],
+ * world points Xw[3*k+{0,1,2}] for k = 0..2.  Writes up to 4 poses, ordered by
+ * camera depth of point 0, then point 1.  *ill is set to 1 when a root is
+ * near-double, a depth is near zero or the triple is near-degenerate, i.e.
+ * where another correct formulation may return a different solution count. */
+int orc_p3p(const double uv[6], const double Xw[9], const orc_camera *K,
+            orc_pose out[4], int32_t *ill);
+
+/* Truncated (MSAC) scoring of np poses against all points: count of inliers
+ * (z > 0 and r^2 < tau^2) and sum_i w_i * min(r_i^2, tau^2), points behind the
+ * camera contributing tau^2. */
+void orc_score(const orc_pose *poses, int64_t np, const orc_corr *c,
+               const orc_camera *K, double tau, int32_t *count, double *msac);
+
+/* Same test with an ambiguity band per residual: count_lo counts residuals
+ * inside tau - b_i, count_hi those inside tau + b_i, where
+ * b_i = max(band_abs, f32_bound_i) and f32_bound_i (used when with_f32 != 0)
+ * bounds the error of evaluating the residual in float32 from a float32-rounded
+ * projection matrix. */
+void orc_score_band(const orc_pose *poses, int64_t np, const orc_corr *c,
+                    const orc_camera *K, double tau, double band_abs, int32_t with_f32,
+                    int32_t *count_lo, int32_t *count_hi, double *msac_err_bound);
+
+/* Truncated cost at a pose and the Gauss-Newton normal equations over its
+ * inliers: H = sum_i w_i J_i^T J_i, g = sum_i w_i J_i^T r_i, with J_i the
+ * Jacobian of the pixel residual w.r.t. the left update (dw, dt). */
+double orc_normal_equations(const orc_pose *P, const orc_corr *c, const orc_camera *K, double tau, double H[36],
+                            double g[6], int64_t *count);
+
+/* Left update on SO(3) x R^3: R' = Exp(dw) R, t' = Exp(dw) t + dt. */
+void orc_pose_update(const orc_pose *P, const double d[6], orc_pose *o);
+
+/* Local optimisation: Gauss-Newton on sum_i w_i min(r_i^2, tau^2) over the
+ * given point set, inlier set re-evaluated at every iterate, left update on
+ * SO(3), a step that raises the cost is rejected and ends the run.
+ * Returns the number of accepted steps; *cost / *count at the output pose. */
+int orc_lo(const orc_pose *start, const orc_corr *c, const orc_camera *K, double tau,
+           int32_t iters, orc_pose *out, double *cost, int64_t *count);
+
+/* Final refinement: IRLS Gauss-Newton on sum_{i in I} w_i s^2 ln(1 + r_i^2/s^2)
+ * over the fixed set I = inliers of the full set at the start pose (tau).
+ * Returns accepted steps; *cost at the output pose; *n_inl = |I|. */
+int orc_refine(const orc_pose *start, const orc_corr *c, const orc_camera *K, double tau,
+               double s, int32_t iters, orc_pose *out, double *cost, int64_t *n_inl);
+
+/* Samples required by the stopping rule for inlier ratio eps, minimal size 3. */
+int64_t orc_required_samples(double eps, double confidence, int64_t max_iters);
+
+/* Whole LO-RANSAC PnP for one query.  mask (n bytes, may be NULL) receives the
+ * inlier mask over all points at the final pose.  Returns status (0 pose, 1 none). */
+int orc_lo_ransac_pnp(const orc_corr *c, const orc_camera *K, const orc_params *p,
+                      orc_pose *pose, uint8_t *mask, orc_stats *stats);
+
+/* Lifting of 2D-2D matches to 2D-3D.  Views: depth[k*H*W + row*W + col].
+ * cams[k], poses[k] per view (cam_from_world).  subpixel != 0: bilinear depth at
+ * (db_u - 0.5, db_v - 0.5); else lookup at (floor(db_v), floor(db_u)).
+ * Keeps a match iff conf > min_conf (compared in float32), view in range and
+ * depth valid.  Outputs in input order; returns the count. */
+int64_t orc_lift(const float *q_u, const float *q_v, const float *db_u, const float *db_v,
+                 const float *conf, const int32_t *view, int64_t n_matches, int32_t subpixel,
+                 const float *depth, int32_t n_views, int32_t H, int32_t W,
+                 const orc_camera *cams, const orc_pose *poses, float min_conf,
+                 double *out_u, double *out_v, double *out_X, double *out_Y, double *out_Z,
+                 double *out_w, int64_t *out_src);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

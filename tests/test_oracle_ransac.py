@@ -1,0 +1,118 @@
+"""Pins of the oracle's whole LO-RANSAC PnP (Sec. 3.3 "Pose Estimation").
+
+Pins: exhaustive mode on tiny inputs selects the same candidate as a separate
+brute-force enumeration of all triples; noise-free scenes give the
+least-squares pose of the true inliers (scipy) and the ground truth; the
+stopping rule and the sample accounting; degenerate inputs; invariants."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import least_squares
+from scipy.spatial.transform import Rotation
+
+from conftest import rot_angle
+from paper_2601_04185_amd import synth
+
+
+def _colex_rank(i, j, k):
+    return math.comb(k, 3) + math.comb(j, 2) + i
+
+
+@pytest.mark.parametrize("n,batch", [(12, 10 ** 6), (20, 10 ** 6), (24, 10 ** 6), (20, 100)])
+def test_exhaustive_matches_bruteforce(orc, n, batch):
+    q = synth.make_query(21 + n, n, 0.5, 1.0)
+    corr = q.corr()
+    cands = []
+    for (i, j, k) in itertools.combinations(range(n), 3):
+        idx = [i, j, k]
+        uv = np.stack([q.u[idx], q.v[idx]], 1).astype(np.float64)
+        Xw = np.stack([q.X[idx], q.Y[idx], q.Z[idx]], 1).astype(np.float64)
+        sols, _ = orc.p3p(uv, Xw, q.K)
+        for jj, (R, t) in enumerate(sols):
+            cands.append((_colex_rank(i, j, k), jj, R, t))
+    cnt, ms = orc.score([(c[2], c[3]) for c in cands], corr, q.K, 4.0)
+    key = min(range(len(cands)), key=lambda a: (ms[a], -cnt[a], cands[a][0], cands[a][1]))
+    total = math.comb(n, 3)
+    res = orc.lo_ransac_pnp(corr, q.K, threshold_px=4.0, fixed_samples=total, batch=batch, exhaustive=1,
+                            lo_top_k=1, lo_iters=0, final_iters=0)
+    assert res["status"] == 0
+    assert (res["best_h"], res["best_j"]) == (cands[key][0], cands[key][1])
+    assert res["candidates"] == len(cands)
+    assert abs(res["best_msac"] - ms[key]) <= 1e-12 * ms[key]
+    assert rot_angle(res["R"], cands[key][2]) < 1e-12
+
+
+def test_noise_free_recovers_lsq_pose_and_ground_truth(orc):
+    q = synth.make_query(31, 2000, 0.4, 0.0)
+    res = orc.lo_ransac_pnp(q.corr(), q.K, threshold_px=4.0, fixed_samples=1024, lo_top_k=1)
+    assert res["status"] == 0
+    # inputs are float32, so the "noise-free" points carry rounding noise of ~1e-7 relative
+    assert rot_angle(res["R"], q.R) < 1e-6 and np.linalg.norm(res["t"] - q.t) < 1e-5
+    inl = q.is_inlier
+    sub = {k: np.asarray(v)[inl].astype(np.float64) for k, v in q.corr().items() if v is not None}
+
+    def f(p):
+        R = Rotation.from_rotvec(p[:3]).as_matrix()
+        xc = np.stack([sub["X"], sub["Y"], sub["Z"]], 1) @ R.T + p[3:]
+        return np.concatenate([500 * xc[:, 0] / xc[:, 2] + 320 - sub["u"], 500 * xc[:, 1] / xc[:, 2] + 240 - sub["v"]])
+
+    p0 = np.concatenate([Rotation.from_matrix(q.R).as_rotvec(), q.t])
+    ls = least_squares(f, p0, xtol=1e-15, ftol=1e-15, gtol=1e-15, method="lm")
+    assert rot_angle(res["R"], Rotation.from_rotvec(ls.x[:3]).as_matrix()) < 1e-9
+    assert np.linalg.norm(res["t"] - ls.x[3:]) < 1e-8
+    assert res["full_count"] >= inl.sum()
+
+
+def test_config1_shape_and_invariants(orc):
+    q = synth.config1_single_small()
+    res = orc.lo_ransac_pnp(q.corr(), q.K, threshold_px=4.0, fixed_samples=1024, batch=1024, lo_top_k=1)
+    R = res["R"]
+    assert np.abs(R.T @ R - np.eye(3)).max() < 1e-12 and abs(np.linalg.det(R) - 1) < 1e-12
+    assert res["samples"] == 1024 and res["batches"] == 1
+    assert res["residuals"] == res["candidates"] * q.n
+    assert np.degrees(rot_angle(R, q.R)) < 0.1 and np.linalg.norm(res["t"] - q.t) < 0.05
+    assert res["mask"].sum() == res["full_count"]
+    # the mask is the inlier test at the final pose
+    cnt, _ = orc.score([(res["R"], res["t"])], q.corr(), q.K, 4.0)
+    assert cnt[0] == res["full_count"]
+    # most true inliers are found, few outliers
+    assert (res["mask"].astype(bool) & q.is_inlier).sum() > 0.95 * q.is_inlier.sum()
+
+
+def test_adaptive_stopping(orc):
+    q = synth.make_query(41, 3000, 0.6, 1.0)
+    res = orc.lo_ransac_pnp(q.corr(), q.K, threshold_px=4.0, confidence=0.999, batch=1024, min_iters=1024,
+                            max_iters=100000)
+    assert res["samples"] == 1024 and res["batches"] == 1
+    q = synth.make_query(42, 3000, 0.08, 1.0)
+    res = orc.lo_ransac_pnp(q.corr(), q.K, threshold_px=4.0, confidence=0.999, batch=1024, min_iters=1024,
+                            max_iters=5000)
+    eps = res["best_count"] / q.n
+    req = orc.required_samples(eps, 0.999, 5000)
+    assert res["samples"] == min(5000, max(1024, 1024 * math.ceil(req / 1024)))
+    assert res["batches"] == math.ceil(res["samples"] / 1024)
+
+
+def test_scoring_subsample(orc):
+    q = synth.make_query(43, 5000, 0.4, 1.0)
+    res = orc.lo_ransac_pnp(q.corr(), q.K, threshold_px=4.0, fixed_samples=512, max_score_points=1000)
+    assert res["status"] == 0
+    assert res["residuals"] == res["candidates"] * 1000
+    assert res["best_count"] <= 1000
+    assert np.degrees(rot_angle(res["R"], q.R)) < 0.2
+
+
+def test_weighted_query(orc):
+    q = synth.make_query(44, 3000, 0.4, 1.0, weights="conf")
+    res = orc.lo_ransac_pnp(q.corr(), q.K, threshold_px=4.0, fixed_samples=1024)
+    assert res["status"] == 0 and np.degrees(rot_angle(res["R"], q.R)) < 0.1
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_too_few_points(orc, n):
+    corr = {k: np.zeros(n, np.float32) for k in ("u", "v", "X", "Y", "Z")}
+    corr["w"] = None
+    res = orc.lo_ransac_pnp(corr, (500, 500, 320, 240), fixed_samples=16)
+    assert res["status"] == 1 and np.array_equal(res["R"], np.eye(3)) and not res["t"].any()
