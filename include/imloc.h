@@ -1,0 +1,231 @@
+/*
+ * imloc.h -- C ABI of the MI355X pose-estimation library (libimloc.so).
+ *
+ * The library implements the query-time hot path of ImLoc (Jiang et al.,
+ * arXiv 2601.04185, Sec. 3.3): dense query-to-database matches are lifted to
+ * 2D-3D correspondences through the stored depth maps, intrinsics and poses
+ * ("Query Time Matching and 2D-3D Lifting"), then the query pose is estimated
+ * by LO-RANSAC over P3P minimal sets with confidence-weighted truncated
+ * reprojection scoring, non-linear refinement of each new best, an adaptive
+ * stopping rule and a final robust Cauchy refinement on all inliers ("Pose
+ * Estimation").  Every step runs in HIP kernels on the GPU.
+ *
+ * Conventions (the paper fixes none of them):
+ *   - pinhole cameras without distortion; pixel (row i, col j) has its centre
+ *     at (j + 0.5, i + 0.5);
+ *   - poses are cam_from_world, x_cam = R X + t, R row-major;
+ *   - depth maps store z-depth (distance along the optical axis).
+ *
+ * Memory: every array argument marked "device" is a caller-owned device
+ * pointer on the context's device; "host" arguments are ordinary host
+ * memory.  The library never frees or keeps a caller pointer beyond the call.
+ * Scratch memory comes from a caller-provided workspace
+ * (imloc_set_workspace); the library itself allocates no device memory after
+ * imloc_create.  Work is enqueued on the context's stream; calls that return
+ * host results synchronise that stream before returning.
+ *
+ * Errors: functions return IMLOC_OK (0), IMLOC_NO_POSE (1, the call ran but
+ * no pose candidate exists), or a negative code; imloc_last_error() gives a
+ * message.  A context is used by one host thread at a time.
+ */
+#ifndef IMLOC_H
+#define IMLOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IMLOC_OK 0
+#define IMLOC_NO_POSE 1
+#define IMLOC_EINVAL (-1)   /* bad argument (null pointer, size, threshold, intrinsics) */
+#define IMLOC_ENOMEM (-2)   /* workspace too small: see imloc_workspace_bytes */
+#define IMLOC_EHIP (-3)     /* HIP runtime error */
+
+#define IMLOC_FP32_SCORE 0  /* scoring in float32; P3P, local optimisation, refinement in float64 */
+#define IMLOC_FP64_ALL 1    /* every step in float64 */
+
+typedef struct imloc_ctx imloc_ctx;
+
+typedef struct { double fx, fy, cx, cy; } imloc_camera;
+typedef struct { double R[9]; double t[3]; } imloc_pose;   /* 12 doubles, R row-major */
+
+/* 2D-3D correspondences, structure of arrays, float32, device pointers of
+ * length n: observed query pixel (u, v), world point (X, Y, Z), weight w (the
+ * matching confidence; NULL means every weight is 1). */
+typedef struct {
+  const float *u, *v, *X, *Y, *Z, *w;
+} imloc_corr;
+
+/* Output arrays of imloc_lift (device, capacity entries each; w and src may
+ * be NULL if not wanted). */
+typedef struct {
+  float *u, *v, *X, *Y, *Z, *w;
+  int32_t *src;    /* index of the match each correspondence came from */
+} imloc_corr_out;
+
+/* 2D-2D matches, device arrays of length n: query pixel, database pixel,
+ * matching confidence, database view index. */
+typedef struct {
+  const float *q_u, *q_v, *db_u, *db_v, *conf;
+  const int32_t *view;
+} imloc_matches;
+
+typedef struct {
+  double threshold_px;       /* tau: a residual is an inlier iff r^2 < tau^2 (and depth > 0) */
+  int64_t fixed_samples;     /* > 0: draw exactly this many minimal samples, no adaptive stop */
+  int64_t batch;             /* samples per batch (the paper uses 1,000) */
+  int64_t min_iters;         /* adaptive mode: never stop before this many samples */
+  int64_t max_iters;         /* adaptive mode: cap (the paper: 100,000) */
+  double confidence;         /* adaptive mode: stop when P(missing the best model) < 1 - confidence */
+  int32_t lo_top_k;          /* candidates of a batch refined when they beat the running best (clamped to [1, 32]) */
+  int32_t lo_iters;          /* Gauss-Newton iterations of the local optimisation */
+  int64_t max_score_points;  /* 0: score every correspondence; else stride-subsample to this many */
+  int32_t final_iters;       /* Cauchy refinement iterations (0: skip) */
+  double cauchy_scale_px;    /* s of rho(r^2) = s^2 ln(1 + r^2 / s^2) */
+  int32_t exhaustive;        /* 1: sample h is the h-th 3-combination instead of a Philox draw */
+  int32_t precision;         /* IMLOC_FP32_SCORE or IMLOC_FP64_ALL */
+  uint64_t seed, query_id;   /* Philox key word 0 and counter word 1 */
+} imloc_ransac_params;
+
+typedef struct {
+  int64_t samples;           /* minimal samples drawn */
+  int64_t candidates;        /* pose candidates scored (0-4 per sample) */
+  int64_t residuals;         /* candidate x scored-point pairs evaluated */
+  int64_t inlier_residuals;  /* of those, the ones inside the threshold */
+  int64_t best_count;        /* inliers of the best model on the scoring set */
+  int64_t full_count;        /* inliers of the final pose on the full set */
+  int64_t batches;
+  int32_t lo_runs;           /* local optimisations run */
+  int32_t status;            /* IMLOC_OK or IMLOC_NO_POSE */
+  double best_msac;          /* truncated cost of the best model on the scoring set */
+  double final_cost;         /* Cauchy cost at the final pose */
+  int64_t best_h;            /* sample the best model grew from */
+  int32_t best_j;            /* its P3P solution index */
+  int32_t score_launches;    /* scoring kernel launches (for per-launch timing) */
+  float ms_sample, ms_score, ms_select, ms_lo, ms_refine, ms_total;  /* device time, if timing is on */
+} imloc_stats;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  Returns IMLOC_OK or IMLOC_EHIP / IMLOC_EINVAL. */
+int imloc_create(imloc_ctx **out, int device, void *hip_stream);
+void imloc_destroy(imloc_ctx *ctx);
+int imloc_set_stream(imloc_ctx *ctx, void *hip_stream);
+const char *imloc_last_error(const imloc_ctx *ctx);
+
+/* Hand the context a device scratch buffer of `bytes` bytes (caller-owned,
+ * must stay valid while calls that use it are in flight). */
+int imloc_set_workspace(imloc_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* Workspace bytes imloc_lo_ransac_pnp needs for up to n correspondences. */
+size_t imloc_workspace_bytes(int64_t n, const imloc_ransac_params *p);
+
+/* Workspace bytes imloc_lo_ransac_pnp_batch needs for nq queries of the given
+ * sizes (host array). */
+size_t imloc_batch_workspace_bytes(int32_t nq, const int64_t *n, const imloc_ransac_params *p);
+
+/* Workspace bytes of the stage entry points: imloc_score for n
+ * correspondences and np poses, imloc_lift for n_matches matches over
+ * n_views views.  imloc_sample_p3p needs 64 * 4 * count + 256 bytes and
+ * imloc_refine n + 256 bytes. */
+size_t imloc_score_workspace_bytes(int64_t n, int64_t np, int32_t precision);
+size_t imloc_lift_workspace_bytes(int64_t n_matches, int32_t n_views);
+
+/* 1: record per-stage device time with HIP events into imloc_stats. */
+int imloc_set_timing(imloc_ctx *ctx, int enable);
+
+/* ---- the hot path -------------------------------------------------------- */
+
+/* Lift 2D-2D matches to 2D-3D correspondences (Sec. 3.3 "Query Time Matching
+ * and 2D-3D Lifting").  A match is kept iff conf > min_conf (float32
+ * comparison; the paper uses 0.05), its view index is in [0, n_views), its
+ * coordinates are finite, and its depth is valid: subpixel != 0 interpolates
+ * bilinearly at (db_u - 0.5, db_v - 0.5) and needs all four taps inside the
+ * image, finite and > 0; subpixel == 0 reads texel (floor(db_v), floor(db_u))
+ * and needs it inside the image, finite and > 0.  The world point is
+ * R_k^T (d K_k^-1 [db_u, db_v, 1]^T - t_k).  Kept matches are written in input
+ * order (a stable compaction).
+ *   m: device arrays of n_matches entries.  depth: device float32
+ *   [n_views][H][W].  cams, poses: host arrays of n_views entries.
+ *   out: device arrays of `capacity` entries.  n_out: device int32, receives
+ *   the number kept (no host synchronisation).  Matches beyond `capacity`
+ *   kept ones are dropped (n_out still counts them). */
+int imloc_lift(imloc_ctx *ctx, const imloc_matches *m, int64_t n_matches, const float *depth, int32_t n_views,
+               int32_t H, int32_t W, const imloc_camera *cams, const imloc_pose *poses, int32_t subpixel,
+               float min_conf, const imloc_corr_out *out, int64_t capacity, int32_t *n_out);
+
+/* LO-RANSAC PnP for one query (Sec. 3.3 "Pose Estimation").  Minimal sample
+ * h draws three distinct indices of the scoring set from Philox4x64-10 with
+ * key (seed, 0) and counter (h, query_id, attempt, 0), index = floor(word *
+ * size / 2^64), redrawn while not distinct (at most 16 attempts).  P3P gives
+ * up to four candidates per sample; each is scored against every scored
+ * correspondence by sum_i w_i min(r_i^2, tau^2) (points behind the camera
+ * count tau^2).  Per batch the lo_top_k lowest-scoring candidates that beat
+ * the running best are refined by lo_iters Gauss-Newton iterations on that
+ * truncated cost, and the lowest refined cost becomes the best model.  The
+ * adaptive rule stops once samples >= min(max_iters, max(min_iters,
+ * ceil(ln(1 - confidence) / ln(1 - eps^3)))), eps = best inlier ratio.  The
+ * best pose is then refined by final_iters Cauchy IRLS iterations over the
+ * inliers of the full set.
+ *   pts: device arrays of n entries.  pose_out, stats: host (stats may be
+ *   NULL).  inlier_mask: device uint8 [n] (may be NULL): 1 where the point
+ *   is an inlier of the final pose.  Returns IMLOC_OK, IMLOC_NO_POSE (n < 3 or
+ *   no candidate; pose = identity, mask = 0) or an error. */
+int imloc_lo_ransac_pnp(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K_query,
+                        const imloc_ransac_params *p, imloc_pose *pose_out, uint8_t *inlier_mask,
+                        imloc_stats *stats);
+
+/* The same for nq independent queries in one batched pipeline: the samples,
+ * P3P solves, scoring, selection and local optimisation of all queries run in
+ * shared launches.  Each query's result equals what imloc_lo_ransac_pnp gives
+ * for it alone (same Philox counters, same reduction order).
+ *   pts, n, K, params: host arrays of nq entries (params may have 1 entry,
+ *   shared).  poses, stats, status: host arrays of nq entries (stats may be
+ *   NULL).  masks: host array of nq device pointers (array or entries may be
+ *   NULL). */
+int imloc_lo_ransac_pnp_batch(imloc_ctx *ctx, const imloc_corr *pts, const int64_t *n, const imloc_camera *K,
+                              int32_t nq, const imloc_ransac_params *params, int32_t n_params, imloc_pose *poses,
+                              uint8_t *const *masks, imloc_stats *stats, int32_t *status);
+
+/* ---- stages of the path, for inspection and parity checks ---------------- */
+
+/* Draw samples [h0, h0 + count) and solve P3P on each (float64).  Writes the
+ * candidates, compacted in an unspecified order: poses (device double
+ * [4*count][12]), sample index h_out (device int64 [4*count]), solution index
+ * j_out (device int32 [4*count], rank in the canonical order: camera depth of
+ * the first sample point ascending, then of the second), n_cand (device
+ * int32, the count).  triples (device int32 [count][3], may be NULL) receives
+ * each sample's indices, -1 for an empty sample. */
+int imloc_sample_p3p(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K, uint64_t seed,
+                     uint64_t query_id, int32_t exhaustive, int64_t h0, int64_t count, double *poses,
+                     int64_t *h_out, int32_t *j_out, int32_t *n_cand, int32_t *triples);
+
+/* Score np poses (device double [np][12]) against n correspondences: inlier
+ * count (device int32 [np]) and truncated cost (device double [np]).
+ * precision as in imloc_ransac_params. */
+int imloc_score(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K, const double *poses,
+                int64_t np, double threshold_px, int32_t precision, int32_t *count, double *msac);
+
+/* Local optimisation of np start poses (device double [np][12]) on n
+ * correspondences; out_poses (device double [np][12]), cost (device double
+ * [np]), count (device int64 [np]). */
+int imloc_local_optimize(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K,
+                         const double *start, int32_t np, double threshold_px, int32_t iters, double *out_poses,
+                         double *cost, int64_t *count);
+
+/* Final Cauchy refinement of one start pose (device double [12]) over the
+ * inliers of the n correspondences at that pose; out_pose (device double
+ * [12]), cost (device double), mask (device uint8 [n], may be NULL) at the
+ * refined pose. */
+int imloc_refine(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K, const double *start,
+                 double threshold_px, double cauchy_scale_px, int32_t iters, double *out_pose, double *cost,
+                 uint8_t *mask);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -762,9 +762,9 @@ int orc_lo_ransac_pnp(const orc_corr *c, const orc_camera *K, const orc_params *
 
     /* top-k of the batch whose score beats the running best */
     const double gate = best_cost;
-    int32_t chosen[64];
+    int32_t chosen[32];
     int nch = 0;
-    int kmax = p->lo_top_k < 64 ? p->lo_top_k : 64;
+    int kmax = p->lo_top_k < 1 ? 1 : (p->lo_top_k < 32 ? p->lo_top_k : 32);
     for (int sel = 0; sel < kmax; ++sel) {
       int64_t arg = -1;
       for (int64_t k = 0; k < nc; ++k) {

@@ -48,7 +48,7 @@ typedef struct {
   int64_t batch;               /* samples per batch */
   int64_t min_iters, max_iters;
   double confidence;           /* stop when P(miss best) < 1 - confidence */
-  int32_t lo_top_k;            /* candidates refined per batch */
+  int32_t lo_top_k;            /* candidates refined per batch (clamped to [1, 32]) */
   int32_t lo_iters;            /* Gauss-Newton iterations of the local optimisation */
   int64_t max_score_points;    /* 0: score all; else stride-subsample to this many */
   int32_t final_iters;         /* Cauchy IRLS iterations of the final refinement */

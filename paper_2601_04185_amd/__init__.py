@@ -1,0 +1,324 @@
+"""MI355X pose-estimation hot path of ImLoc (arXiv 2601.04185, Sec. 3.3).
+
+Thin ctypes binding of ``libimloc.so`` (C ABI in ``include/imloc.h``).  The
+functions below carry the C names and only marshal arguments: every step of
+lifting and LO-RANSAC PnP runs in the library's HIP kernels.  PyTorch supplies
+device memory (tensors on ``cuda``) and the stream.
+
+The library must be built first (``python -m paper_2601_04185_amd.build`` or
+``__graft_entry__.build()``); importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libimloc.so")
+
+IMLOC_OK = 0
+IMLOC_NO_POSE = 1
+IMLOC_EINVAL = -1
+IMLOC_ENOMEM = -2
+IMLOC_EHIP = -3
+IMLOC_FP32_SCORE = 0
+IMLOC_FP64_ALL = 1
+
+EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_error", "imloc_set_workspace",
+            "imloc_workspace_bytes", "imloc_batch_workspace_bytes", "imloc_score_workspace_bytes",
+            "imloc_lift_workspace_bytes", "imloc_set_timing", "imloc_lift",
+            "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score",
+            "imloc_local_optimize", "imloc_refine"]
+
+
+class ImlocError(RuntimeError):
+    pass
+
+
+class Camera(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class Pose(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class Corr(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("u", "v", "X", "Y", "Z", "w")]
+
+
+class CorrOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("u", "v", "X", "Y", "Z", "w", "src")]
+
+
+class Matches(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("q_u", "q_v", "db_u", "db_v", "conf", "view")]
+
+
+class RansacParams(C.Structure):
+    _fields_ = [("threshold_px", C.c_double), ("fixed_samples", C.c_int64), ("batch", C.c_int64),
+                ("min_iters", C.c_int64), ("max_iters", C.c_int64), ("confidence", C.c_double),
+                ("lo_top_k", C.c_int32), ("lo_iters", C.c_int32), ("max_score_points", C.c_int64),
+                ("final_iters", C.c_int32), ("cauchy_scale_px", C.c_double), ("exhaustive", C.c_int32),
+                ("precision", C.c_int32), ("seed", C.c_uint64), ("query_id", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("samples", C.c_int64), ("candidates", C.c_int64), ("residuals", C.c_int64),
+                ("inlier_residuals", C.c_int64), ("best_count", C.c_int64), ("full_count", C.c_int64),
+                ("batches", C.c_int64), ("lo_runs", C.c_int32), ("status", C.c_int32), ("best_msac", C.c_double),
+                ("final_cost", C.c_double), ("best_h", C.c_int64), ("best_j", C.c_int32),
+                ("score_launches", C.c_int32), ("ms_sample", C.c_float), ("ms_score", C.c_float),
+                ("ms_select", C.c_float), ("ms_lo", C.c_float), ("ms_refine", C.c_float), ("ms_total", C.c_float)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libimloc.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_04185_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64
+        sig = {
+            "imloc_create": ([C.POINTER(vp), C.c_int, vp], C.c_int),
+            "imloc_destroy": ([vp], None),
+            "imloc_set_stream": ([vp, vp], C.c_int),
+            "imloc_last_error": ([vp], C.c_char_p),
+            "imloc_set_workspace": ([vp, vp, C.c_size_t], C.c_int),
+            "imloc_workspace_bytes": ([i64, vp], C.c_size_t),
+            "imloc_batch_workspace_bytes": ([i32, vp, vp], C.c_size_t),
+            "imloc_score_workspace_bytes": ([i64, i64, i32], C.c_size_t),
+            "imloc_lift_workspace_bytes": ([i64, i32], C.c_size_t),
+            "imloc_set_timing": ([vp, C.c_int], C.c_int),
+            "imloc_lift": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
+            "imloc_lo_ransac_pnp": ([vp, vp, i64, vp, vp, vp, vp, vp], C.c_int),
+            "imloc_lo_ransac_pnp_batch": ([vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp], C.c_int),
+            "imloc_sample_p3p": ([vp, vp, i64, vp, u64, u64, i32, i64, i64, vp, vp, vp, vp, vp], C.c_int),
+            "imloc_score": ([vp, vp, i64, vp, vp, i64, dbl, i32, vp, vp], C.c_int),
+            "imloc_local_optimize": ([vp, vp, i64, vp, vp, i32, dbl, i32, vp, vp, vp], C.c_int),
+            "imloc_refine": ([vp, vp, i64, vp, vp, dbl, dbl, i32, vp, vp, vp], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _cam(K) -> Camera:
+    return Camera(*[float(x) for x in K])
+
+
+def make_params(threshold_px=4.0, fixed_samples=0, batch=1024, min_iters=1024, max_iters=100000, confidence=0.9999,
+                lo_top_k=8, lo_iters=10, max_score_points=0, final_iters=10, cauchy_scale_px=None, exhaustive=0,
+                precision=IMLOC_FP32_SCORE, seed=0, query_id=0) -> RansacParams:
+    if cauchy_scale_px is None:
+        cauchy_scale_px = 0.5 * threshold_px
+    return RansacParams(float(threshold_px), int(fixed_samples), int(batch), int(min_iters), int(max_iters),
+                        float(confidence), int(lo_top_k), int(lo_iters), int(max_score_points), int(final_iters),
+                        float(cauchy_scale_px), int(exhaustive), int(precision), int(seed), int(query_id))
+
+
+class Context:
+    """An imloc_ctx bound to a device and a torch stream, with a workspace
+    tensor that grows on demand."""
+
+    def __init__(self, device: int = 0, stream=None, timing: bool = False):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        rc = lib().imloc_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if rc != IMLOC_OK:
+            raise ImlocError(f"imloc_create failed ({rc})")
+        self.h = h
+        self.ws = None
+        lib().imloc_set_timing(self.h, 1 if timing else 0)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().imloc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return lib().imloc_last_error(self.h).decode()
+
+    def check(self, rc: int) -> int:
+        if rc < 0:
+            raise ImlocError(f"imloc error {rc}: {self.error()}")
+        return rc
+
+    def ensure_workspace(self, nbytes: int):
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=f"cuda:{self.device}")
+            self.check(lib().imloc_set_workspace(self.h, C.c_void_p(self.ws.data_ptr()), self.ws.numel()))
+
+
+def corr_struct(u, v, X, Y, Z, w=None) -> Corr:
+    for t in (u, v, X, Y, Z) + ((w,) if w is not None else ()):
+        assert t.is_cuda and t.dtype.is_floating_point and t.element_size() == 4 and t.is_contiguous()
+    return Corr(*[t.data_ptr() for t in (u, v, X, Y, Z)], None if w is None else w.data_ptr())
+
+
+def imloc_lo_ransac_pnp(ctx: Context, corr: dict, K, params: RansacParams, mask=None):
+    """corr: dict of float32 cuda tensors u, v, X, Y, Z (and optional w).
+    Returns (status, R (3x3), t (3,), stats dict)."""
+    n = int(corr["u"].numel())
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    ctx.ensure_workspace(lib().imloc_workspace_bytes(n, C.byref(params)))
+    pose = Pose()
+    st = Stats()
+    cam = _cam(K)
+    rc = ctx.check(lib().imloc_lo_ransac_pnp(ctx.h, C.byref(cs), n, C.byref(cam), C.byref(params), C.byref(pose),
+                                             _ptr(mask), C.byref(st)))
+    R = np.array(pose.R[:], dtype=np.float64).reshape(3, 3)
+    t = np.array(pose.t[:], dtype=np.float64)
+    return rc, R, t, st.as_dict()
+
+
+def imloc_lo_ransac_pnp_batch(ctx: Context, corrs: list, Ks: list, params, masks=None):
+    """corrs: list of dicts of float32 cuda tensors; params: one RansacParams or a
+    list.  Returns (status list, list of (R, t), list of stats dicts)."""
+    nq = len(corrs)
+    ns = (C.c_int64 * nq)(*[int(c["u"].numel()) for c in corrs])
+    cs = (Corr * nq)(*[corr_struct(c["u"], c["v"], c["X"], c["Y"], c["Z"], c.get("w")) for c in corrs])
+    cams = (Camera * nq)(*[_cam(K) for K in Ks])
+    plist = params if isinstance(params, (list, tuple)) else [params]
+    pa = (RansacParams * len(plist))(*plist)
+    ctx.ensure_workspace(lib().imloc_batch_workspace_bytes(nq, ns, pa))
+    poses = (Pose * nq)()
+    stats = (Stats * nq)()
+    status = (C.c_int32 * nq)()
+    mk = None
+    if masks is not None:
+        mk = (C.c_void_p * nq)(*[None if m is None else m.data_ptr() for m in masks])
+    ctx.check(lib().imloc_lo_ransac_pnp_batch(ctx.h, cs, ns, cams, nq, pa, len(plist), poses, mk, stats, status))
+    out = [(np.array(p.R[:]).reshape(3, 3), np.array(p.t[:])) for p in poses]
+    return list(status), out, [s.as_dict() for s in stats]
+
+
+def imloc_lift(ctx: Context, matches: dict, depth, cams, poses, subpixel=True, min_conf=0.05, capacity=None):
+    """matches: dict of cuda tensors q_u, q_v, db_u, db_v, conf (float32), view (int32).
+    depth: cuda float32 (K, H, W).  cams: (K, 4) host; poses: (K, 12) host.
+    Returns dict of cuda tensors u, v, X, Y, Z, w (float32), src (int32) and n (int)."""
+    torch = ctx.torch
+    n = int(matches["q_u"].numel())
+    cap = n if capacity is None else int(capacity)
+    nv, H, W = depth.shape
+    dev = depth.device
+    out = {k: torch.empty(max(cap, 1), dtype=torch.float32, device=dev) for k in ("u", "v", "X", "Y", "Z", "w")}
+    out["src"] = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int32, device=dev)
+    m = Matches(*[matches[k].data_ptr() for k in ("q_u", "q_v", "db_u", "db_v", "conf", "view")])
+    co = CorrOut(*[out[k].data_ptr() for k in ("u", "v", "X", "Y", "Z", "w", "src")])
+    cams_a = (Camera * nv)(*[_cam(c) for c in np.asarray(cams).reshape(nv, 4)])
+    P = np.asarray(poses, np.float64).reshape(nv, 12)
+    poses_a = (Pose * nv)(*[Pose((C.c_double * 9)(*P[k, :9]), (C.c_double * 3)(*P[k, 9:])) for k in range(nv)])
+    ctx.ensure_workspace(lib().imloc_lift_workspace_bytes(n, nv))
+    ctx.check(lib().imloc_lift(ctx.h, C.byref(m), n, C.c_void_p(depth.data_ptr()), nv, H, W, cams_a, poses_a,
+                               1 if subpixel else 0, C.c_float(min_conf), C.byref(co), cap, C.c_void_p(n_out.data_ptr())))
+    k = int(n_out.item())
+    res = {key: v[:min(k, cap)] for key, v in out.items()}
+    res["n"] = k
+    return res
+
+
+def imloc_sample_p3p(ctx: Context, corr: dict, K, seed: int, query_id: int, h0: int, count: int, exhaustive=0,
+                     want_triples=False):
+    """-> dict of cuda tensors poses (nc, 12) float64, h (nc,), j (nc,), and triples (count, 3)."""
+    torch = ctx.torch
+    dev = corr["u"].device
+    n = int(corr["u"].numel())
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    cap = 4 * max(count, 1)
+    poses = torch.empty((cap, 12), dtype=torch.float64, device=dev)
+    h = torch.empty(cap, dtype=torch.int64, device=dev)
+    j = torch.empty(cap, dtype=torch.int32, device=dev)
+    nc = torch.zeros(1, dtype=torch.int32, device=dev)
+    tri = torch.empty((max(count, 1), 3), dtype=torch.int32, device=dev) if want_triples else None
+    ctx.ensure_workspace(64 * cap + 256)
+    cam = _cam(K)
+    ctx.check(lib().imloc_sample_p3p(ctx.h, C.byref(cs), n, C.byref(cam), seed, query_id, exhaustive, h0, count,
+                                     _ptr(poses), _ptr(h), _ptr(j), _ptr(nc), _ptr(tri)))
+    k = int(nc.item())
+    out = dict(poses=poses[:k], h=h[:k], j=j[:k])
+    if want_triples:
+        out["triples"] = tri[:count]
+    return out
+
+
+def imloc_score(ctx: Context, corr: dict, K, poses, threshold_px: float, precision=IMLOC_FP32_SCORE):
+    """poses: cuda float64 (np, 12).  -> (count int32 (np,), msac float64 (np,)) cuda tensors."""
+    torch = ctx.torch
+    n = int(corr["u"].numel())
+    npz = int(poses.shape[0])
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    cnt = torch.empty(max(npz, 1), dtype=torch.int32, device=poses.device)
+    ms = torch.empty(max(npz, 1), dtype=torch.float64, device=poses.device)
+    ctx.ensure_workspace(lib().imloc_score_workspace_bytes(n, npz, int(precision)))
+    cam = _cam(K)
+    ctx.check(lib().imloc_score(ctx.h, C.byref(cs), n, C.byref(cam), _ptr(poses.contiguous()), npz, float(threshold_px),
+                                int(precision), _ptr(cnt), _ptr(ms)))
+    return cnt[:npz], ms[:npz]
+
+
+def imloc_local_optimize(ctx: Context, corr: dict, K, start, threshold_px: float, iters: int = 10):
+    """start: cuda float64 (np, 12) -> (poses (np, 12), cost (np,), count (np,))."""
+    torch = ctx.torch
+    n = int(corr["u"].numel())
+    npz = int(start.shape[0])
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    out = torch.empty((max(npz, 1), 12), dtype=torch.float64, device=start.device)
+    cost = torch.empty(max(npz, 1), dtype=torch.float64, device=start.device)
+    cnt = torch.empty(max(npz, 1), dtype=torch.int64, device=start.device)
+    cam = _cam(K)
+    ctx.check(lib().imloc_local_optimize(ctx.h, C.byref(cs), n, C.byref(cam), _ptr(start.contiguous()), npz,
+                                         float(threshold_px), int(iters), _ptr(out), _ptr(cost), _ptr(cnt)))
+    return out[:npz], cost[:npz], cnt[:npz]
+
+
+def imloc_refine(ctx: Context, corr: dict, K, start, threshold_px: float, scale_px: float, iters: int = 10,
+                 mask=None):
+    """start: cuda float64 (12,) -> (pose (12,), cost (1,))."""
+    torch = ctx.torch
+    n = int(corr["u"].numel())
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    out = torch.empty(12, dtype=torch.float64, device=start.device)
+    cost = torch.empty(1, dtype=torch.float64, device=start.device)
+    ctx.ensure_workspace(n + 256)
+    cam = _cam(K)
+    ctx.check(lib().imloc_refine(ctx.h, C.byref(cs), n, C.byref(cam), _ptr(start.contiguous()), float(threshold_px),
+                                 float(scale_px), int(iters), _ptr(out), _ptr(cost), _ptr(mask)))
+    return out, cost
+
+
+def to_device(query_or_corr, device="cuda:0") -> dict:
+    """Synthetic numpy correspondences (a synth.Query or dict) -> dict of cuda tensors."""
+    import torch
+    d = query_or_corr.corr() if hasattr(query_or_corr, "corr") else query_or_corr
+    out = {}
+    for k in ("u", "v", "X", "Y", "Z", "w"):
+        a = d.get(k)
+        out[k] = None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+    return out

@@ -1,0 +1,473 @@
+// imloc_device.h -- device-side building blocks of the pose-estimation path
+// (gfx950).  Included by the kernel translation units only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace imloc {
+
+constexpr int kWave = 64;
+
+struct Cam { double fx, fy, cx, cy; };
+struct Pose { double R[9]; double t[3]; };
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC 2011): per round two 64x64->128 products;
+// the high halves are xor-ed with the other two words and the round key; the
+// key advances by the Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ inline void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1,
+                                     uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += W0; k1 += W1;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// Minimal sample h: three distinct indices of [0, n) from the stream keyed by
+// (seed, 0) at counter (h, query, attempt, 0); index = high word of word * n.
+__device__ inline bool sample_triple(uint64_t seed, uint64_t query, uint64_t h, uint64_t n, int idx[3]) {
+  if (n < 3) return false;
+  for (uint64_t attempt = 0; attempt < 16; ++attempt) {
+    uint64_t w[4];
+    philox4x64_10(h, query, attempt, 0, seed, 0, w);
+    const int a = (int)__umul64hi(w[0], n), b = (int)__umul64hi(w[1], n), c = (int)__umul64hi(w[2], n);
+    if (a != b && a != c && b != c) {
+      idx[0] = a; idx[1] = b; idx[2] = c;
+      return true;
+    }
+  }
+  return false;
+}
+
+__device__ inline uint64_t binom(uint64_t n, uint64_t k) {
+  if (k > n) return 0;
+  uint64_t r = 1;
+  for (uint64_t i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// h-th 3-combination of [0, n), colexicographic (combinatorial number system).
+__device__ inline bool unrank_triple(uint64_t h, uint64_t n, int idx[3]) {
+  if (n < 3 || h >= binom(n, 3)) return false;
+  uint64_t k = 2;
+  while (binom(k + 1, 3) <= h) ++k;
+  h -= binom(k, 3);
+  uint64_t j = 1;
+  while (binom(j + 1, 2) <= h) ++j;
+  h -= binom(j, 2);
+  idx[0] = (int)h; idx[1] = (int)j; idx[2] = (int)k;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Small dense algebra (float64).
+// ---------------------------------------------------------------------------
+__device__ inline double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ inline void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ inline double det3(const double M[9]) {
+  return M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) + M[2] * (M[3] * M[7] - M[4] * M[6]);
+}
+// adjugate (transpose of the cofactor matrix)
+__device__ inline void adj3(const double M[9], double A[9]) {
+  A[0] = M[4] * M[8] - M[5] * M[7];
+  A[1] = M[2] * M[7] - M[1] * M[8];
+  A[2] = M[1] * M[5] - M[2] * M[4];
+  A[3] = M[5] * M[6] - M[3] * M[8];
+  A[4] = M[0] * M[8] - M[2] * M[6];
+  A[5] = M[2] * M[3] - M[0] * M[5];
+  A[6] = M[3] * M[7] - M[4] * M[6];
+  A[7] = M[1] * M[6] - M[0] * M[7];
+  A[8] = M[0] * M[4] - M[1] * M[3];
+}
+__device__ inline double trace_prod(const double A[9], const double B[9]) {
+  double s = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) s += A[3 * r + c] * B[3 * c + r];
+  return s;
+}
+
+// Exp on SO(3) (Rodrigues), series for small angles.
+__device__ inline void so3_exp(const double w[3], double E[9]) {
+  const double th2 = dot3(w, w), th = sqrt(th2);
+  double A, B;
+  if (th < 1e-4) {
+    A = 1.0 - th2 * (1.0 / 6.0) + th2 * th2 * (1.0 / 120.0);
+    B = 0.5 - th2 * (1.0 / 24.0) + th2 * th2 * (1.0 / 720.0);
+  } else {
+    double s, c;
+    sincos(th, &s, &c);
+    A = s / th;
+    B = (1.0 - c) / th2;
+  }
+  const double x = w[0], y = w[1], z = w[2];
+  // I + A [w]x + B [w]x^2, with [w]x^2 = w w^T - th2 I
+  E[0] = 1.0 + B * (x * x - th2);
+  E[1] = -A * z + B * x * y;
+  E[2] = A * y + B * x * z;
+  E[3] = A * z + B * x * y;
+  E[4] = 1.0 + B * (y * y - th2);
+  E[5] = -A * x + B * y * z;
+  E[6] = -A * y + B * x * z;
+  E[7] = A * x + B * y * z;
+  E[8] = 1.0 + B * (z * z - th2);
+}
+
+// x' = Exp(dw) x + dt : R' = Exp(dw) R, t' = Exp(dw) t + dt.
+__device__ inline void pose_left_update(const Pose& P, const double d[6], Pose& o) {
+  double E[9];
+  so3_exp(d, E);
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) o.R[3 * r + c] = E[3 * r] * P.R[c] + E[3 * r + 1] * P.R[3 + c] + E[3 * r + 2] * P.R[6 + c];
+    o.t[r] = E[3 * r] * P.t[0] + E[3 * r + 1] * P.t[1] + E[3 * r + 2] * P.t[2] + d[3 + r];
+  }
+}
+
+// Solve H x = b, H symmetric positive definite 6x6 given by its upper triangle
+// packed row-wise (21 entries).  false if a pivot is not positive.
+__device__ inline bool chol6_solve_packed(const double Hp[21], const double b[6], double x[6]) {
+  double L[6][6];
+  int k = 0;
+  double H[6][6];
+  for (int r = 0; r < 6; ++r)
+    for (int c = r; c < 6; ++c) { H[r][c] = Hp[k]; H[c][r] = Hp[k]; ++k; }
+  for (int i = 0; i < 6; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      double s = H[i][j];
+      for (int m = 0; m < j; ++m) s -= L[i][m] * L[j][m];
+      if (i == j) {
+        if (!(s > 0.0)) return false;
+        L[i][i] = sqrt(s);
+      } else {
+        L[i][j] = s / L[j][j];
+      }
+    }
+  }
+  double y[6];
+  for (int i = 0; i < 6; ++i) {
+    double s = b[i];
+    for (int m = 0; m < i; ++m) s -= L[i][m] * y[m];
+    y[i] = s / L[i][i];
+  }
+  for (int i = 5; i >= 0; --i) {
+    double s = y[i];
+    for (int m = i + 1; m < 6; ++m) s -= L[m][i] * x[m];
+    x[i] = s / L[i][i];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// P3P in float64, as an intersection of a pencil of conics.
+//
+// Unknowns: depths l = (l1, l2, l3) > 0 along unit bearings y_i.  With
+// b_ij = -y_i.y_j and a_ij = |x_i - x_j|^2 each pair gives the quadric
+// l^T M_ij l = a_ij (M_ij has ones on the (i,i), (j,j) diagonal entries and
+// b_ij off the diagonal).  Eliminating the right-hand sides gives two
+// homogeneous conics D1 = M12 - (a12/a23) M23 and D2 = M13 - (a13/a23) M23
+// through all solutions.  A degenerate member D0 = D1 + g D2 of their pencil
+// (det = 0, a cubic in g) is a pair of lines through the solutions; each line
+// meets D1 or D2 in at most two points, scaled by l^T M23 l = a23.  The pose
+// follows from the three camera-frame points l_i y_i.
+// ---------------------------------------------------------------------------
+
+// Real roots of c3 x^3 + c2 x^2 + c1 x + c0 on [lo, hi]: split at the
+// critical points and bisect every sign change.
+__device__ inline int cubic_roots_in(double c0, double c1, double c2, double c3, double lo, double hi, double r[3]) {
+  double pts[4];
+  int np = 0;
+  pts[np++] = lo;
+  // critical points: 3 c3 x^2 + 2 c2 x + c1 = 0
+  const double qa = 3.0 * c3, qb = 2.0 * c2, qc = c1;
+  double cr[2];
+  int nc = 0;
+  const double scale = fabs(qa) + fabs(qb) + fabs(qc);
+  if (fabs(qa) > 1e-300 + 1e-15 * scale) {
+    const double disc = qb * qb - 4.0 * qa * qc;
+    if (disc > 0.0) {
+      const double q = -0.5 * (qb + copysign(sqrt(disc), qb));
+      double x1 = q / qa, x2 = (q != 0.0) ? qc / q : x1;
+      if (x1 > x2) { double tt = x1; x1 = x2; x2 = tt; }
+      cr[nc++] = x1;
+      cr[nc++] = x2;
+    }
+  } else if (fabs(qb) > 0.0) {
+    cr[nc++] = -qc / qb;
+  }
+  for (int i = 0; i < nc; ++i)
+    if (cr[i] > lo && cr[i] < hi) pts[np++] = cr[i];
+  pts[np++] = hi;
+  int nr = 0;
+  for (int i = 0; i + 1 < np; ++i) {
+    double a = pts[i], b = pts[i + 1];
+    double fa = ((c3 * a + c2) * a + c1) * a + c0;
+    double fb = ((c3 * b + c2) * b + c1) * b + c0;
+    if (fa == 0.0) { r[nr++] = a; continue; }
+    if (fb == 0.0 && i + 2 == np) { r[nr++] = b; continue; }
+    if ((fa < 0.0) == (fb < 0.0)) continue;
+    for (int it = 0; it < 200; ++it) {
+      const double m = 0.5 * (a + b);
+      if (m <= a || m >= b) break;
+      const double fm = ((c3 * m + c2) * m + c1) * m + c0;
+      if (fm == 0.0) { a = b = m; break; }
+      if ((fm < 0.0) == (fa < 0.0)) { a = m; fa = fm; } else { b = m; }
+    }
+    r[nr++] = 0.5 * (a + b);
+  }
+  return nr;
+}
+
+// Eigenvector of symmetric M for eigenvalue s: the longest cross product of
+// two rows of (M - s I).
+__device__ inline void sym_eigvec(const double M[9], double s, double v[3]) {
+  double r0[3] = {M[0] - s, M[1], M[2]}, r1[3] = {M[3], M[4] - s, M[5]}, r2[3] = {M[6], M[7], M[8] - s};
+  double a[3], b[3], c[3];
+  cross3(r0, r1, a);
+  cross3(r0, r2, b);
+  cross3(r1, r2, c);
+  const double na = dot3(a, a), nb = dot3(b, b), nc = dot3(c, c);
+  const double* best = a;
+  double nbest = na;
+  if (nb > nbest) { best = b; nbest = nb; }
+  if (nc > nbest) { best = c; nbest = nc; }
+  const double inv = nbest > 0.0 ? 1.0 / sqrt(nbest) : 0.0;
+  v[0] = best[0] * inv; v[1] = best[1] * inv; v[2] = best[2] * inv;
+}
+
+// Newton polishing of the depths on the three quadrics; a step is kept while
+// it lowers the squared residual.
+__device__ inline void polish_depths(double l[3], double a12, double a13, double a23, double b12, double b13,
+                                     double b23) {
+  for (int it = 0; it < 6; ++it) {
+    const double F0 = l[0] * l[0] + l[1] * l[1] + 2.0 * b12 * l[0] * l[1] - a12;
+    const double F1 = l[0] * l[0] + l[2] * l[2] + 2.0 * b13 * l[0] * l[2] - a13;
+    const double F2 = l[1] * l[1] + l[2] * l[2] + 2.0 * b23 * l[1] * l[2] - a23;
+    const double J[9] = {2.0 * (l[0] + b12 * l[1]), 2.0 * (l[1] + b12 * l[0]), 0.0,
+                         2.0 * (l[0] + b13 * l[2]), 0.0, 2.0 * (l[2] + b13 * l[0]),
+                         0.0, 2.0 * (l[1] + b23 * l[2]), 2.0 * (l[2] + b23 * l[1])};
+    const double det = det3(J);
+    if (!(fabs(det) > 0.0)) return;
+    double A[9];
+    adj3(J, A);
+    const double F[3] = {F0, F1, F2};
+    double n[3];
+    for (int r = 0; r < 3; ++r) n[r] = l[r] - (A[3 * r] * F[0] + A[3 * r + 1] * F[1] + A[3 * r + 2] * F[2]) / det;
+    const double G0 = n[0] * n[0] + n[1] * n[1] + 2.0 * b12 * n[0] * n[1] - a12;
+    const double G1 = n[0] * n[0] + n[2] * n[2] + 2.0 * b13 * n[0] * n[2] - a13;
+    const double G2 = n[1] * n[1] + n[2] * n[2] + 2.0 * b23 * n[1] * n[2] - a23;
+    if (!(G0 * G0 + G1 * G1 + G2 * G2 < F0 * F0 + F1 * F1 + F2 * F2)) return;
+    l[0] = n[0]; l[1] = n[1]; l[2] = n[2];
+  }
+}
+
+// y: unit bearings (row per point), x: world points.  Returns the number of
+// solutions (<= 4) written to out, in canonical order (camera depth of point
+// 0 ascending, then of point 1).
+__device__ inline int p3p_pencil(const double y[3][3], const double x[3][3], Pose out[4]) {
+  double d12[3], d13[3], d23[3];
+  for (int k = 0; k < 3; ++k) { d12[k] = x[0][k] - x[1][k]; d13[k] = x[0][k] - x[2][k]; d23[k] = x[1][k] - x[2][k]; }
+  const double a12 = dot3(d12, d12), a13 = dot3(d13, d13), a23 = dot3(d23, d23);
+  double crs[3];
+  cross3(d12, d13, crs);
+  if (!(a12 > 0.0 && a13 > 0.0 && a23 > 0.0)) return 0;
+  if (!(sqrt(dot3(crs, crs)) > 1e-9 * (a12 + a13 + a23))) return 0;
+  const double b12 = -dot3(y[0], y[1]), b13 = -dot3(y[0], y[2]), b23 = -dot3(y[1], y[2]);
+  const double r12 = a12 / a23, r13 = a13 / a23;
+  const double D1[9] = {1.0, b12, 0.0, b12, 1.0 - r12, -r12 * b23, 0.0, -r12 * b23, -r12};
+  const double D2[9] = {1.0, 0.0, b13, 0.0, -r13, -r13 * b23, b13, -r13 * b23, 1.0 - r13};
+  double A1[9], A2[9];
+  adj3(D1, A1);
+  adj3(D2, A2);
+  const double c0 = det3(D1), c1 = trace_prod(A1, D2), c2 = trace_prod(D1, A2), c3 = det3(D2);
+
+  // degenerate pencil members: D1 + g D2 for |g| <= 1, e D1 + D2 for |e| < 1
+  double roots[6];
+  int from_f[6];
+  int nr = 0;
+  double rr[3];
+  int k = cubic_roots_in(c0, c1, c2, c3, -1.0, 1.0, rr);
+  for (int i = 0; i < k; ++i) { roots[nr] = rr[i]; from_f[nr++] = 1; }
+  k = cubic_roots_in(c3, c2, c1, c0, -1.0, 1.0, rr);
+  for (int i = 0; i < k; ++i)
+    if (fabs(rr[i]) < 1.0) { roots[nr] = rr[i]; from_f[nr++] = 0; }
+
+  double D0[9];
+  double best_q = 0.0, bestT = 0.0, bestS = 0.0;
+  int best = -1;
+  for (int i = 0; i < nr; ++i) {
+    double M[9], mx = 0.0;
+    for (int e = 0; e < 9; ++e) {
+      M[e] = from_f[i] ? D1[e] + roots[i] * D2[e] : roots[i] * D1[e] + D2[e];
+      mx = fmax(mx, fabs(M[e]));
+    }
+    if (!(mx > 0.0)) continue;
+    for (int e = 0; e < 9; ++e) M[e] /= mx;
+    const double T = M[0] + M[4] + M[8];
+    const double S = (M[0] * M[4] - M[1] * M[3]) + (M[0] * M[8] - M[2] * M[6]) + (M[4] * M[8] - M[5] * M[7]);
+    const double den = T * T - 2.0 * S;
+    if (!(den > 0.0)) continue;
+    const double q = -S / den;
+    if (q > best_q) {
+      best_q = q; best = i; bestT = T; bestS = S;
+      for (int e = 0; e < 9; ++e) D0[e] = M[e];
+    }
+  }
+  if (best < 0) return 0;
+  // conic restricted to the lines: the pencil member farthest from D0
+  const double* Q = from_f[best] ? D2 : D1;
+  const double half = 0.5 * bestT, disc = sqrt(half * half - bestS);
+  const double s1 = half + disc, s2 = half - disc;  // s1 > 0 > s2
+  double e1[3], e2[3], e3[3];
+  sym_eigvec(D0, s1, e1);
+  sym_eigvec(D0, s2, e2);
+  cross3(e1, e2, e3);
+  const double w1 = sqrt(s1), w2 = sqrt(-s2);
+
+  double lam[4][3];
+  int nl = 0;
+  for (int sgn = -1; sgn <= 1; sgn += 2) {
+    double nrm[3], m[3];
+    for (int c = 0; c < 3; ++c) nrm[c] = w1 * e1[c] + sgn * w2 * e2[c];
+    cross3(nrm, e3, m);
+    const double mn = sqrt(dot3(m, m));
+    if (!(mn > 0.0)) continue;
+    for (int c = 0; c < 3; ++c) m[c] /= mn;
+    double Qe[3], Qm[3];
+    for (int r = 0; r < 3; ++r) {
+      Qe[r] = Q[3 * r] * e3[0] + Q[3 * r + 1] * e3[1] + Q[3 * r + 2] * e3[2];
+      Qm[r] = Q[3 * r] * m[0] + Q[3 * r + 1] * m[1] + Q[3 * r + 2] * m[2];
+    }
+    const double A = dot3(e3, Qe), B = dot3(e3, Qm), C = dot3(m, Qm);
+    const double dq = B * B - A * C;
+    if (dq < 0.0) continue;
+    const double sq = sqrt(dq);
+    double dirs[2][3];
+    if (fabs(A) >= fabs(C) && A != 0.0) {
+      const double ra = (-B + sq) / A, rb = (-B - sq) / A;  // alpha / beta
+      for (int c = 0; c < 3; ++c) { dirs[0][c] = ra * e3[c] + m[c]; dirs[1][c] = rb * e3[c] + m[c]; }
+    } else if (C != 0.0) {
+      const double ra = (-B + sq) / C, rb = (-B - sq) / C;  // beta / alpha
+      for (int c = 0; c < 3; ++c) { dirs[0][c] = e3[c] + ra * m[c]; dirs[1][c] = e3[c] + rb * m[c]; }
+    } else {
+      for (int c = 0; c < 3; ++c) { dirs[0][c] = e3[c]; dirs[1][c] = m[c]; }
+    }
+    for (int d = 0; d < 2; ++d) {
+      const double* v = dirs[d];
+      const double s23 = v[1] * v[1] + v[2] * v[2] + 2.0 * b23 * v[1] * v[2];
+      if (!(s23 > 0.0)) continue;
+      const double sc = sqrt(a23 / s23) * ((v[0] + v[1] + v[2]) < 0.0 ? -1.0 : 1.0);
+      double l[3] = {sc * v[0], sc * v[1], sc * v[2]};
+      if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) continue;
+      polish_depths(l, a12, a13, a23, b12, b13, b23);
+      if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) continue;
+      const double F0 = l[0] * l[0] + l[1] * l[1] + 2.0 * b12 * l[0] * l[1] - a12;
+      const double F1 = l[0] * l[0] + l[2] * l[2] + 2.0 * b13 * l[0] * l[2] - a13;
+      const double F2 = l[1] * l[1] + l[2] * l[2] + 2.0 * b23 * l[1] * l[2] - a23;
+      if (!(fabs(F0) + fabs(F1) + fabs(F2) < 1e-6 * (a12 + a13 + a23))) continue;
+      bool dup = false;
+      for (int e = 0; e < nl; ++e) {
+        const double dl = fabs(lam[e][0] - l[0]) + fabs(lam[e][1] - l[1]) + fabs(lam[e][2] - l[2]);
+        if (dl <= 1e-9 * (l[0] + l[1] + l[2])) dup = true;
+      }
+      if (dup || nl >= 4) continue;
+      lam[nl][0] = l[0]; lam[nl][1] = l[1]; lam[nl][2] = l[2];
+      ++nl;
+    }
+  }
+
+  // poses: R maps the world triangle frame [d12, d13, d12 x d13] onto the camera one
+  double X[9];
+  for (int r = 0; r < 3; ++r) { X[3 * r] = d12[r]; X[3 * r + 1] = d13[r]; X[3 * r + 2] = crs[r]; }
+  double Xa[9];
+  adj3(X, Xa);
+  const double Xdet = det3(X);
+  int ns = 0;
+  for (int s = 0; s < nl; ++s) {
+    double z[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c < 3; ++c) z[i][c] = lam[s][i] * y[i][c];
+    double e12[3], e13[3], ec[3];
+    for (int c = 0; c < 3; ++c) { e12[c] = z[0][c] - z[1][c]; e13[c] = z[0][c] - z[2][c]; }
+    cross3(e12, e13, ec);
+    double Y[9];
+    for (int r = 0; r < 3; ++r) { Y[3 * r] = e12[r]; Y[3 * r + 1] = e13[r]; Y[3 * r + 2] = ec[r]; }
+    Pose P;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        P.R[3 * r + c] = (Y[3 * r] * Xa[c] + Y[3 * r + 1] * Xa[3 + c] + Y[3 * r + 2] * Xa[6 + c]) / Xdet;
+    // one Newton-Schulz step towards the nearest rotation: R <- R (3 I - R^T R) / 2
+    double RtR[9], Rn[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        RtR[3 * r + c] = P.R[r] * P.R[c] + P.R[3 + r] * P.R[3 + c] + P.R[6 + r] * P.R[6 + c];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double s2 = 0.0;
+        for (int m = 0; m < 3; ++m) s2 += P.R[3 * r + m] * ((m == c ? 3.0 : 0.0) - RtR[3 * m + c]);
+        Rn[3 * r + c] = 0.5 * s2;
+      }
+    for (int e = 0; e < 9; ++e) P.R[e] = Rn[e];
+    for (int r = 0; r < 3; ++r)
+      P.t[r] = z[0][r] - (P.R[3 * r] * x[0][0] + P.R[3 * r + 1] * x[0][1] + P.R[3 * r + 2] * x[0][2]);
+    out[ns++] = P;
+  }
+  // canonical order by (depth of point 0, depth of point 1) = (l1 y1_z, l2 y2_z)
+  double key0[4], key1[4];
+  for (int s = 0; s < ns; ++s) { key0[s] = lam[s][0] * y[0][2]; key1[s] = lam[s][1] * y[1][2]; }
+  for (int a = 1; a < ns; ++a) {
+    Pose kp = out[a];
+    const double ka = key0[a], kb = key1[a];
+    int b = a - 1;
+    while (b >= 0 && (key0[b] > ka || (key0[b] == ka && key1[b] > kb))) {
+      out[b + 1] = out[b]; key0[b + 1] = key0[b]; key1[b + 1] = key1[b];
+      --b;
+    }
+    out[b + 1] = kp; key0[b + 1] = ka; key1[b + 1] = kb;
+  }
+  return ns;
+}
+
+// Folded projection P = K [R | t] rows (a, b, w) = P [X, 1].
+__device__ inline void projection_rows(const Pose& P, const Cam& K, double M[12]) {
+  for (int c = 0; c < 3; ++c) {
+    M[c] = K.fx * P.R[c] + K.cx * P.R[6 + c];
+    M[4 + c] = K.fy * P.R[3 + c] + K.cy * P.R[6 + c];
+    M[8 + c] = P.R[6 + c];
+  }
+  M[3] = K.fx * P.t[0] + K.cx * P.t[2];
+  M[7] = K.fy * P.t[1] + K.cy * P.t[2];
+  M[11] = P.t[2];
+}
+
+// ---------------------------------------------------------------------------
+// Wave / block reductions.
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+__device__ inline long long wave_sum(long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+}  // namespace imloc
