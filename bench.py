@@ -79,6 +79,54 @@ def _rot_deg(Ra, Rb):
     return float(np.degrees(np.arctan2(np.linalg.norm(s), 0.5 * (np.trace(M) - 1.0))))
 
 
+def batch_leg(pk, ctx_plain, steps, n_queries=256):
+    """The 256-query batch: the fused batched form (one call, shared launches)
+    against the plain form (one call per query), same seeds and parameters."""
+    import numpy as np
+    import torch
+    from paper_2601_04185_amd import synth
+    qs = synth.config3_batch(n_queries)
+    ds = [pk.to_device(q) for q in qs]
+    Ks = [q.K for q in qs]
+    prms = [pk.make_params(threshold_px=4.0, fixed_samples=4096, batch=4096, lo_top_k=8, query_id=i)
+            for i in range(len(qs))]
+    ctx = pk.Context(0)
+    pk.imloc_lo_ransac_pnp_batch(ctx, ds, Ks, prms)  # warm-up (and workspace)
+    torch.cuda.synchronize()
+    t_f = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        status, poses, stats = pk.imloc_lo_ransac_pnp_batch(ctx, ds, Ks, prms)
+        t_f.append(time.perf_counter() - t0)
+    res = sum(s["residuals"] for s in stats)
+    inl = sum(s["inlier_residuals"] for s in stats)
+    tctx = pk.Context(0, timing=True)
+    _, _, st_t = pk.imloc_lo_ransac_pnp_batch(tctx, ds, Ks, prms)
+    score_ms = st_t[0]["ms_score"]
+    # plain form: one query per call
+    for i in range(min(4, len(qs))):
+        pk.imloc_lo_ransac_pnp(ctx_plain, ds[i], Ks[i], prms[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [pk.imloc_lo_ransac_pnp(ctx_plain, ds[i], Ks[i], prms[i]) for i in range(len(qs))]
+    t_plain = time.perf_counter() - t0
+    same = all(np.array_equal(plain[i][1], poses[i][0]) and np.array_equal(plain[i][2], poses[i][1])
+               for i in range(len(qs)))
+    tf = statistics.median(t_f)
+    flops = FLOP_PER_RESIDUAL * res + FLOP_PER_INLIER * inl
+    return dict(workload=f"{len(qs)} queries, correspondences uniform in [5,000, 80,000] "
+                         f"(total {sum(q.n for q in qs):,}), inlier ratios uniform in [10%, 60%], sigma 1 px, "
+                         f"4,096 samples each, tau 4 px, LO top-8",
+                fused_ms=round(tf * 1e3, 3), fused_queries_per_s=round(len(qs) / tf, 2),
+                fused_residuals_per_s=round(res / tf, 1),
+                plain_ms=round(t_plain * 1e3, 3), plain_queries_per_s=round(len(qs) / t_plain, 2),
+                speedup_fused_vs_plain=round(t_plain / tf, 3), residuals=res,
+                score_ms=round(score_ms, 3), score_tflops=round(flops / (score_ms * 1e-3) / 1e12, 3),
+                score_frac_of_peak=round(flops / (score_ms * 1e-3) / 1e12 / PEAK_F32_NONPACKED_TFLOPS, 4),
+                poses_identical_fused_vs_plain=bool(same),
+                failed=int(sum(1 for x in status if x != 0)))
+
+
 def cpu_baseline(q, params, reps):
     """The oracle as it stands, on the host cores, on the same query."""
     import oracle
@@ -103,6 +151,8 @@ def main():
     ap.add_argument("--workload", default="single_large", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-query fused-vs-plain leg")
+    ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported (queries are independent, "
@@ -173,6 +223,8 @@ def main():
                    within_tolerance=bool(_rot_deg(R, ref["R"]) <= 1e-3 and
                                          np.linalg.norm(t - ref["t"]) <= 1e-4 * max(1.0, np.linalg.norm(ref["t"]))))
     out["accuracy"] = acc
+    if not args.no_batch:
+        out["batch256"] = batch_leg(pk, ctx, args.batch_steps)
     print(json.dumps(out))
 
 

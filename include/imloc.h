@@ -40,6 +40,7 @@ extern "C" {
 
 #define IMLOC_OK 0
 #define IMLOC_NO_POSE 1
+#define IMLOC_PENDING 2     /* imloc_server_poll: the query has not finished yet */
 #define IMLOC_EINVAL (-1)   /* bad argument (null pointer, size, threshold, intrinsics) */
 #define IMLOC_ENOMEM (-2)   /* workspace too small: see imloc_workspace_bytes */
 #define IMLOC_EHIP (-3)     /* HIP runtime error */
@@ -125,18 +126,35 @@ int imloc_set_workspace(imloc_ctx *ctx, void *device_ptr, size_t bytes);
 size_t imloc_workspace_bytes(int64_t n, const imloc_ransac_params *p);
 
 /* Workspace bytes imloc_lo_ransac_pnp_batch needs for nq queries of the given
- * sizes (host array). */
-size_t imloc_batch_workspace_bytes(int32_t nq, const int64_t *n, const imloc_ransac_params *p);
+ * sizes (host array) and parameters (host array of n_params = 1 or nq). */
+size_t imloc_batch_workspace_bytes(int32_t nq, const int64_t *n, const imloc_ransac_params *p, int32_t n_params);
 
 /* Workspace bytes of the stage entry points: imloc_score for n
- * correspondences and np poses, imloc_lift for n_matches matches over
- * n_views views.  imloc_sample_p3p needs 64 * 4 * count + 256 bytes and
- * imloc_refine n + 256 bytes. */
+ * correspondences and np poses, imloc_local_optimize for n correspondences
+ * and np start poses, imloc_refine for n correspondences, imloc_sample_p3p
+ * for count samples of n correspondences, imloc_lift for n_matches matches over n_views views. */
 size_t imloc_score_workspace_bytes(int64_t n, int64_t np, int32_t precision);
+size_t imloc_sample_workspace_bytes(int64_t n, int64_t count);
+size_t imloc_lo_workspace_bytes(int64_t n, int32_t np);
+size_t imloc_refine_workspace_bytes(int64_t n);
 size_t imloc_lift_workspace_bytes(int64_t n_matches, int32_t n_views);
 
 /* 1: record per-stage device time with HIP events into imloc_stats. */
 int imloc_set_timing(imloc_ctx *ctx, int enable);
+
+/* 1: run batches with a fixed sample count as one captured hipGraph, replayed
+ * while the batch shape (query count and sizes, parameters, workspace) stays
+ * the same; 0 (default): enqueue every launch.  Results are identical.
+ * imloc_graph_counters reports captures and replays so far. */
+int imloc_set_graphs(imloc_ctx *ctx, int enable);
+int imloc_graph_counters(const imloc_ctx *ctx, int64_t *captures, int64_t *launches);
+
+/* Launch shape of the scoring kernel: candidates per work item (32, 64 or
+ * 128) and persistent workgroups.  Neither changes any result (per-candidate
+ * sums are integer-accumulated), only the speed; the autotuner in the Python
+ * package picks them by timing. */
+int imloc_set_score_tuning(imloc_ctx *ctx, int32_t candidates_per_item, int32_t workgroups);
+int imloc_get_score_tuning(const imloc_ctx *ctx, int32_t *candidates_per_item, int32_t *workgroups);
 
 /* ---- the hot path -------------------------------------------------------- */
 
@@ -224,6 +242,53 @@ int imloc_local_optimize(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const
 int imloc_refine(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K, const double *start,
                  double threshold_px, double cauchy_scale_px, int32_t iters, double *out_pose, double *cost,
                  uint8_t *mask);
+
+/* ---- serving: continuous batching ---------------------------------------- */
+
+/* A server keeps up to max_slots queries resident on the device.  Queries are
+ * admitted first come first served when a slot is free and their buffers fit
+ * the two pools: 4 * batch candidate slots from the candidate pool, and n
+ * bytes (plus 24 bytes per point of a subsampled scoring set) from the byte
+ * pool.  Every step runs one round (one batch of minimal samples, scoring,
+ * selection, local optimisation, stopping rule) for every resident query at
+ * once; queries whose stopping rule fires get their final refinement and mask
+ * in the same step and leave.  A query's result is the one
+ * imloc_lo_ransac_pnp gives for it alone. */
+typedef struct imloc_server imloc_server;
+
+typedef struct {
+  int32_t max_slots;        /* resident queries at most (<= 4096) */
+  int32_t max_top_k;        /* largest lo_top_k accepted (<= 32) */
+  int64_t max_n;            /* largest query accepted (correspondences) */
+  int64_t candidate_pool;   /* candidate slots shared by the resident queries */
+  int64_t byte_pool;        /* bytes shared by the resident queries */
+} imloc_server_config;
+
+/* Workspace bytes a server needs; the server uses the context's workspace
+ * (imloc_set_workspace) from creation until it is destroyed, and the context
+ * serves no other call meanwhile. */
+size_t imloc_server_workspace_bytes(const imloc_server_config *cfg);
+int imloc_server_create(imloc_ctx *ctx, const imloc_server_config *cfg, imloc_server **out);
+void imloc_server_destroy(imloc_server *srv);
+
+/* Queue a query (arguments as for imloc_lo_ransac_pnp; the arrays must stay
+ * valid until the query has finished).  *ticket identifies it. */
+int imloc_server_submit(imloc_server *srv, const imloc_corr *pts, int64_t n, const imloc_camera *K,
+                        const imloc_ransac_params *p, uint8_t *inlier_mask, int64_t *ticket);
+
+/* Admit what fits, run one round, finish the queries whose stopping rule
+ * fired.  done_tickets (host, capacity entries, may be NULL) receives the
+ * tickets finished in this step; *n_done their number, *n_resident the
+ * queries still on the device, *n_queued those waiting. */
+int imloc_server_step(imloc_server *srv, int64_t *done_tickets, int32_t capacity, int32_t *n_done,
+                      int32_t *n_resident, int32_t *n_queued);
+
+/* Result of a finished query (once per ticket): IMLOC_OK or IMLOC_NO_POSE with
+ * pose and stats (host) filled, or IMLOC_PENDING. */
+int imloc_server_poll(imloc_server *srv, int64_t ticket, imloc_pose *pose, imloc_stats *stats);
+
+/* Pool occupancy: candidate slots and bytes held by resident queries. */
+int imloc_server_usage(const imloc_server *srv, int64_t *candidate_slots_used, int64_t *bytes_used);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libimloc.so")
 
 IMLOC_OK = 0
 IMLOC_NO_POSE = 1
+IMLOC_PENDING = 2
 IMLOC_EINVAL = -1
 IMLOC_ENOMEM = -2
 IMLOC_EHIP = -3
@@ -28,7 +29,12 @@ IMLOC_FP64_ALL = 1
 
 EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_error", "imloc_set_workspace",
             "imloc_workspace_bytes", "imloc_batch_workspace_bytes", "imloc_score_workspace_bytes",
-            "imloc_lift_workspace_bytes", "imloc_set_timing", "imloc_lift",
+            "imloc_lift_workspace_bytes", "imloc_lo_workspace_bytes", "imloc_refine_workspace_bytes",
+            "imloc_sample_workspace_bytes", "imloc_set_timing", "imloc_set_score_tuning", "imloc_get_score_tuning",
+            "imloc_set_graphs", "imloc_graph_counters", "imloc_server_workspace_bytes", "imloc_server_create",
+            "imloc_server_destroy", "imloc_server_submit", "imloc_server_step", "imloc_server_poll",
+            "imloc_server_usage",
+            "imloc_lift",
             "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score",
             "imloc_local_optimize", "imloc_refine"]
 
@@ -77,6 +83,11 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("max_top_k", C.c_int32), ("max_n", C.c_int64),
+                ("candidate_pool", C.c_int64), ("byte_pool", C.c_int64)]
+
+
 _lib = None
 
 
@@ -95,9 +106,23 @@ def lib():
             "imloc_last_error": ([vp], C.c_char_p),
             "imloc_set_workspace": ([vp, vp, C.c_size_t], C.c_int),
             "imloc_workspace_bytes": ([i64, vp], C.c_size_t),
-            "imloc_batch_workspace_bytes": ([i32, vp, vp], C.c_size_t),
+            "imloc_batch_workspace_bytes": ([i32, vp, vp, i32], C.c_size_t),
+            "imloc_sample_workspace_bytes": ([i64, i64], C.c_size_t),
+            "imloc_set_score_tuning": ([vp, i32, i32], C.c_int),
+            "imloc_set_graphs": ([vp, C.c_int], C.c_int),
+            "imloc_graph_counters": ([vp, vp, vp], C.c_int),
+            "imloc_server_workspace_bytes": ([vp], C.c_size_t),
+            "imloc_server_create": ([vp, vp, C.POINTER(vp)], C.c_int),
+            "imloc_server_destroy": ([vp], None),
+            "imloc_server_submit": ([vp, vp, i64, vp, vp, vp, vp], C.c_int),
+            "imloc_server_step": ([vp, vp, i32, vp, vp, vp], C.c_int),
+            "imloc_server_poll": ([vp, i64, vp, vp], C.c_int),
+            "imloc_server_usage": ([vp, vp, vp], C.c_int),
+            "imloc_get_score_tuning": ([vp, vp, vp], C.c_int),
             "imloc_score_workspace_bytes": ([i64, i64, i32], C.c_size_t),
             "imloc_lift_workspace_bytes": ([i64, i32], C.c_size_t),
+            "imloc_lo_workspace_bytes": ([i64, i32], C.c_size_t),
+            "imloc_refine_workspace_bytes": ([i64], C.c_size_t),
             "imloc_set_timing": ([vp, C.c_int], C.c_int),
             "imloc_lift": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_lo_ransac_pnp": ([vp, vp, i64, vp, vp, vp, vp, vp], C.c_int),
@@ -137,7 +162,7 @@ class Context:
     """An imloc_ctx bound to a device and a torch stream, with a workspace
     tensor that grows on demand."""
 
-    def __init__(self, device: int = 0, stream=None, timing: bool = False):
+    def __init__(self, device: int = 0, stream=None, timing: bool = False, graphs: bool = False):
         import torch
         self.torch = torch
         self.device = device
@@ -149,6 +174,12 @@ class Context:
         self.h = h
         self.ws = None
         lib().imloc_set_timing(self.h, 1 if timing else 0)
+        lib().imloc_set_graphs(self.h, 1 if graphs else 0)
+
+    def graph_counters(self):
+        a, b = C.c_int64(), C.c_int64()
+        self.check(lib().imloc_graph_counters(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def close(self):
         if getattr(self, "h", None):
@@ -168,6 +199,14 @@ class Context:
         if rc < 0:
             raise ImlocError(f"imloc error {rc}: {self.error()}")
         return rc
+
+    def set_score_tuning(self, candidates_per_item: int, workgroups: int):
+        self.check(lib().imloc_set_score_tuning(self.h, int(candidates_per_item), int(workgroups)))
+
+    def score_tuning(self):
+        a, b = C.c_int32(), C.c_int32()
+        self.check(lib().imloc_get_score_tuning(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def ensure_workspace(self, nbytes: int):
         if self.ws is None or self.ws.numel() < nbytes:
@@ -206,7 +245,7 @@ def imloc_lo_ransac_pnp_batch(ctx: Context, corrs: list, Ks: list, params, masks
     cams = (Camera * nq)(*[_cam(K) for K in Ks])
     plist = params if isinstance(params, (list, tuple)) else [params]
     pa = (RansacParams * len(plist))(*plist)
-    ctx.ensure_workspace(lib().imloc_batch_workspace_bytes(nq, ns, pa))
+    ctx.ensure_workspace(lib().imloc_batch_workspace_bytes(nq, ns, pa, len(plist)))
     poses = (Pose * nq)()
     stats = (Stats * nq)()
     status = (C.c_int32 * nq)()
@@ -257,7 +296,7 @@ def imloc_sample_p3p(ctx: Context, corr: dict, K, seed: int, query_id: int, h0: 
     j = torch.empty(cap, dtype=torch.int32, device=dev)
     nc = torch.zeros(1, dtype=torch.int32, device=dev)
     tri = torch.empty((max(count, 1), 3), dtype=torch.int32, device=dev) if want_triples else None
-    ctx.ensure_workspace(64 * cap + 256)
+    ctx.ensure_workspace(lib().imloc_sample_workspace_bytes(n, count))
     cam = _cam(K)
     ctx.check(lib().imloc_sample_p3p(ctx.h, C.byref(cs), n, C.byref(cam), seed, query_id, exhaustive, h0, count,
                                      _ptr(poses), _ptr(h), _ptr(j), _ptr(nc), _ptr(tri)))
@@ -292,6 +331,7 @@ def imloc_local_optimize(ctx: Context, corr: dict, K, start, threshold_px: float
     out = torch.empty((max(npz, 1), 12), dtype=torch.float64, device=start.device)
     cost = torch.empty(max(npz, 1), dtype=torch.float64, device=start.device)
     cnt = torch.empty(max(npz, 1), dtype=torch.int64, device=start.device)
+    ctx.ensure_workspace(lib().imloc_lo_workspace_bytes(n, npz))
     cam = _cam(K)
     ctx.check(lib().imloc_local_optimize(ctx.h, C.byref(cs), n, C.byref(cam), _ptr(start.contiguous()), npz,
                                          float(threshold_px), int(iters), _ptr(out), _ptr(cost), _ptr(cnt)))
@@ -306,7 +346,7 @@ def imloc_refine(ctx: Context, corr: dict, K, start, threshold_px: float, scale_
     cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
     out = torch.empty(12, dtype=torch.float64, device=start.device)
     cost = torch.empty(1, dtype=torch.float64, device=start.device)
-    ctx.ensure_workspace(n + 256)
+    ctx.ensure_workspace(lib().imloc_refine_workspace_bytes(n))
     cam = _cam(K)
     ctx.check(lib().imloc_refine(ctx.h, C.byref(cs), n, C.byref(cam), _ptr(start.contiguous()), float(threshold_px),
                                  float(scale_px), int(iters), _ptr(out), _ptr(cost), _ptr(mask)))
@@ -322,3 +362,74 @@ def to_device(query_or_corr, device="cuda:0") -> dict:
         a = d.get(k)
         out[k] = None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
     return out
+
+
+class Server:
+    """Continuous-batching front end of imloc_server_* on a context of its own.
+
+    submit() queues a query (its tensors are kept alive until it finishes),
+    step() admits what fits and runs one round for every resident query,
+    poll() returns a finished query's result once."""
+
+    def __init__(self, device: int = 0, max_slots: int = 64, max_top_k: int = 8, max_n: int = 200000,
+                 candidate_pool: int | None = None, byte_pool: int | None = None, stream=None):
+        self.ctx = Context(device, stream=stream)
+        if candidate_pool is None:
+            candidate_pool = max_slots * 4 * 1024
+        if byte_pool is None:
+            byte_pool = max_slots * (max_n + 256)
+        self.cfg = ServerConfig(int(max_slots), int(max_top_k), int(max_n), int(candidate_pool), int(byte_pool))
+        nbytes = lib().imloc_server_workspace_bytes(C.byref(self.cfg))
+        if nbytes == 0:
+            raise ImlocError("bad server configuration")
+        self.ctx.ensure_workspace(nbytes)
+        h = C.c_void_p()
+        self.ctx.check(lib().imloc_server_create(self.ctx.h, C.byref(self.cfg), C.byref(h)))
+        self.h = h
+        self._keep = {}
+        self._buf = (C.c_int64 * 4096)()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().imloc_server_destroy(self.h)
+            self.h = None
+        self.ctx.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, corr: dict, K, params: RansacParams, mask=None) -> int:
+        n = int(corr["u"].numel())
+        cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+        cam = _cam(K)
+        t = C.c_int64()
+        self.ctx.check(lib().imloc_server_submit(self.h, C.byref(cs), n, C.byref(cam), C.byref(params), _ptr(mask),
+                                                 C.byref(t)))
+        self._keep[t.value] = (corr, mask)
+        return t.value
+
+    def step(self):
+        """-> (finished tickets, resident, queued)."""
+        nd, nr, nqd = C.c_int32(), C.c_int32(), C.c_int32()
+        self.ctx.check(lib().imloc_server_step(self.h, self._buf, len(self._buf), C.byref(nd), C.byref(nr),
+                                               C.byref(nqd)))
+        done = [self._buf[i] for i in range(min(nd.value, len(self._buf)))]
+        return done, nr.value, nqd.value
+
+    def poll(self, ticket: int):
+        """-> None while pending, else (status, R, t, stats)."""
+        pose = Pose()
+        st = Stats()
+        rc = self.ctx.check(lib().imloc_server_poll(self.h, int(ticket), C.byref(pose), C.byref(st)))
+        if rc == IMLOC_PENDING:
+            return None
+        self._keep.pop(ticket, None)
+        return rc, np.array(pose.R[:]).reshape(3, 3), np.array(pose.t[:]), st.as_dict()
+
+    def usage(self):
+        a, b = C.c_int64(), C.c_int64()
+        self.ctx.check(lib().imloc_server_usage(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value

@@ -10,6 +10,13 @@ namespace imloc {
 constexpr int kWave = 64;
 
 struct Cam { double fx, fy, cx, cy; };
+
+// Pointers read from a device-side table carry no address space; viewing them
+// as global lets the compiler emit global (not flat) loads.
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
 struct Pose { double R[9]; double t[3]; };
 
 // ---------------------------------------------------------------------------

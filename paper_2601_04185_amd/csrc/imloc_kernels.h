@@ -1,5 +1,10 @@
-// imloc_kernels.h -- host-side launchers of the HIP kernels (internal to
-// libimloc.so; the public interface is include/imloc.h).
+// imloc_kernels.h -- device data structures and host-side launchers of the
+// HIP kernels (internal to libimloc.so; the public interface is
+// include/imloc.h).
+//
+// Every kernel of the LO-RANSAC path works on a batch of queries described by
+// a device-resident table of QueryDesc; a single query is a batch of one, so
+// a query's arithmetic is the same alone and in a mix.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,6 +18,11 @@ struct CorrF32 {
 };
 
 struct CamH { double fx, fy, cx, cy; };
+
+constexpr int kMaxTopK = 32;       // local optimisations per query and batch, at most
+constexpr int kScorePPL32 = 4;     // correspondences per lane, float32 scoring (fixes the summation order)
+constexpr int kScorePPL64 = 2;     // correspondences per lane, float64 scoring
+constexpr double kGainScale = 4294967296.0;  // fixed-point scale of the accumulated truncated-cost gain
 
 // Per-query running state of one LO-RANSAC, resident on the device.
 struct BestState {
@@ -28,18 +38,48 @@ struct BestState {
   double weight_sum;         // sum of weights over the scoring set
   double final_cost;
   int64_t full_count;
+  int64_t drawn;             // samples drawn so far
+  int64_t batches;
+  int32_t active;            // still sampling
+  int32_t finished;          // 0 sampling, 1 sampling ended (final refinement pending), 2 retired
 };
 
-// Candidate arrays of one batch (device).
+// Device descriptor of one query of a batch.
+struct QueryDesc {
+  CorrF32 full;          // all correspondences
+  CorrF32 S;             // scoring set (the full set, or its stride subsample)
+  int64_t n, m;          // sizes of the two
+  double fx, fy, cx, cy;
+  double tau;            // inlier threshold (px)
+  double cauchy_s;       // scale of the final Cauchy loss
+  double confidence;
+  uint64_t seed, qid;
+  int64_t total;         // sample budget: fixed count, or the adaptive cap
+  int64_t batch;         // samples per round
+  int64_t min_iters;
+  int32_t fixed;         // 1: exactly `total` samples
+  int32_t exhaustive;
+  int32_t precision;     // 0: float32 scoring, 1: float64 scoring
+  int32_t k;             // local optimisations per round
+  int32_t lo_iters, final_iters;
+  int64_t cand_off;      // first candidate slot of this query
+  int64_t cap;           // candidate slots (4 per sample of a round)
+  int64_t in_set_off;    // offset of this query's bytes in the in-set array
+  int64_t B;             // samples of the current round (0: inactive)
+  uint8_t* mask;         // inlier mask output (device) or null
+  int32_t fresh;         // 1: admitted with this table upload (initialise, gather its subset)
+  int32_t pad_;
+};
+
+// Candidate arrays of all queries of a batch (device), indexed by slot.
 struct CandBuf {
-  double* pose;     // [cap][12]
-  float* proj;      // [cap][16] float32 rows of K [R | t], rows a and b divided by tau (12 used)
-  int64_t* h;       // [cap]
-  int32_t* j;       // [cap]
-  int32_t* n;       // device count
-  int32_t* count;   // [cap] inliers after reduction
-  double* msac;     // [cap]
-  int64_t cap;
+  double* pose;      // [slots][12]
+  float* proj;       // [slots][16] float32 rows of K [R | t], rows a and b divided by tau (12 used)
+  int64_t* h;        // [slots] sample index
+  int32_t* j;        // [slots] solution index
+  uint32_t* cnt;     // [slots] inlier count (accumulated by scoring)
+  uint64_t* gain;    // [slots] sum of w (1 - r^2 / tau^2) over inliers, fixed point 2^-32 (accumulated)
+  int32_t* n;        // [queries] candidates of the current round
 };
 
 // --- lift ------------------------------------------------------------------
@@ -62,48 +102,67 @@ struct LiftArgs {
 int lift_blocks(int64_t n);
 hipError_t launch_lift(const LiftArgs& a, hipStream_t s);
 
-// --- sampling + P3P ----------------------------------------------------------
-hipError_t launch_sample_p3p(const CorrF32& c, int64_t m, CamH K, uint64_t seed, uint64_t query, int exhaustive,
-                             int64_t h0, int64_t count, double tau, const CandBuf& cb, int32_t* triples,
-                             hipStream_t s);
+// --- small utilities ---------------------------------------------------------
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
+hipError_t launch_gather_subset(const CorrF32& c, int64_t n, int64_t m, float* dst /*[6][m]*/, hipStream_t s);
+// stride subsets of every query whose scoring set is not its full set (the
+// table says from where to where); max_m bounds the subset sizes
+hipError_t launch_gather_subsets(const QueryDesc* qd, int nq, int64_t max_m, hipStream_t s);
 
-// Float32 projection rows (rows a, b divided by tau) from float64 poses.
-hipError_t launch_make_proj(const double* poses, int64_t np, CamH K, double tau, float* proj, hipStream_t s);
+// --- round bookkeeping ---------------------------------------------------------
+// init: state and the weight sum of the scoring set of every fresh query.
+hipError_t launch_init_queries(const QueryDesc* qd, BestState* st, int nq, hipStream_t s);
+// finished queries (final refinement and mask done) leave the round loop
+hipError_t launch_retire(BestState* st, int nq, hipStream_t s);
+// begin: samples of this round per query, zero candidate counts.
+hipError_t launch_begin_round(QueryDesc* qd, const BestState* st, CandBuf cb, int nq, hipStream_t s);
+// end: advance the sample count, apply the stopping rule; *active_count
+// receives the number of queries that keep sampling.
+hipError_t launch_end_round(const QueryDesc* qd, BestState* st, int nq, int32_t* active_count, hipStream_t s);
+
+// --- sampling + P3P ----------------------------------------------------------
+// Samples [drawn, drawn + B) of every query; max_b bounds B.
+hipError_t launch_sample_p3p(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int64_t max_b,
+                             int32_t* triples, hipStream_t s);
+// Candidates from given float64 poses (query 0): projection rows, zeroed accumulators.
+hipError_t launch_set_candidates(const QueryDesc* qd, const double* poses, int64_t np, CandBuf cb, hipStream_t s);
 
 // --- scoring -----------------------------------------------------------------
-struct ScorePlan {
-  int ppl;        // points per lane
-  int ct;         // candidates per tile
-  int chunks;     // point chunks (blocks along x)
-  int tiles;      // candidate tiles (blocks along y)
-  int64_t cap;    // candidate capacity (row stride of the partial arrays)
+struct ScoreTune {
+  int ct;       // candidates per work item (32, 64 or 128)
+  int blocks;   // persistent workgroups
 };
-ScorePlan plan_score(int64_t m, int64_t cand_cap, int precision);
-size_t score_partial_bytes(const ScorePlan& p);
-hipError_t launch_score(const CorrF32& c, int64_t m, CamH K, double tau, int precision, const ScorePlan& plan,
-                        const CandBuf& cb, uint32_t* part_cnt, float* part_gain, double* part_gain64,
-                        hipStream_t s);
-// sums the partials of each candidate in chunk order; msac = tau^2 (C - sum gain)
-hipError_t launch_reduce_scores(const ScorePlan& plan, const CandBuf& cb, double tau, const uint32_t* part_cnt,
-                                const float* part_gain, const double* part_gain64, int precision, BestState* st,
-                                hipStream_t s);
-hipError_t launch_weight_sum(const CorrF32& c, int64_t m, BestState* st, hipStream_t s);
-hipError_t launch_gather_subset(const CorrF32& c, int64_t n, int64_t m, float* dst /*[6][m]*/, hipStream_t s);
+hipError_t launch_worklist(const QueryDesc* qd, CandBuf cb, int nq, int ct, int64_t* item_off, hipStream_t s);
+hipError_t launch_score(const QueryDesc* qd, CandBuf cb, BestState* st, int nq, const int64_t* item_off,
+                        ScoreTune tune, int precision, hipStream_t s);
+// truncated cost of the candidates of query 0: count and msac outputs
+hipError_t launch_candidate_costs(const QueryDesc* qd, const BestState* st, CandBuf cb, int64_t np, int32_t* count,
+                                  double* msac, hipStream_t s);
 
 // --- selection / local optimisation / refinement ------------------------------
-hipError_t launch_select(const CandBuf& cb, int32_t k, const BestState* st, int32_t* sel, int32_t* n_sel,
+hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int kmax, int32_t* sel,
+                         int32_t* n_sel, hipStream_t s);
+
+// Gauss-Newton problems.  LO: problem p = q * kmax + slot starts from the
+// candidate sel[q * kMaxTopK + slot] (or from start_direct[p] when given, all
+// on query 0) and runs on the scoring set of its query.  Refine: problem q
+// starts from the best pose of query q (or start_direct[q]) and runs on its
+// full set, if the query has just finished sampling.
+int gn_chunks(int64_t n);
+size_t gn_scratch_bytes(int nprob, int chunks_max);
+hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
+                     const double* start_direct, int nprob, int kmax, int chunks_max, int iters_max, void* scratch,
+                     double* out_pose, double* out_cost, int64_t* out_count, hipStream_t s);
+hipError_t launch_update_best(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
+                              const double* lo_pose, const double* lo_cost, const int64_t* lo_count, int nq,
+                              int kmax, BestState* st, hipStream_t s);
+hipError_t launch_refine(const QueryDesc* qd, BestState* st, const double* start_direct, int nq, int chunks_max,
+                         int iters_max, uint8_t* in_set, void* scratch, double* out_pose, double* out_cost,
                          hipStream_t s);
-hipError_t launch_lo(const CorrF32& c, int64_t m, CamH K, double tau, int32_t iters, const double* cand_pose,
-                     const int32_t* sel, const int32_t* n_sel, int32_t k, double* out_pose, double* out_cost,
-                     int64_t* out_count, hipStream_t s);
-hipError_t launch_update_best(const CandBuf& cb, const int32_t* sel, const int32_t* n_sel, const double* lo_pose,
-                              const double* lo_cost, const int64_t* lo_count, BestState* st, hipStream_t s);
-hipError_t launch_refine(const CorrF32& c, int64_t n, CamH K, double tau, double scale, int32_t iters,
-                         const double* start, uint8_t* in_set, double* out_pose, double* out_cost, hipStream_t s);
-hipError_t launch_mask(const CorrF32& c, int64_t n, CamH K, double tau, const double* pose, uint8_t* mask,
-                       int64_t* count, hipStream_t s);
-hipError_t launch_init_state(BestState* st, hipStream_t s);
+// mask and inlier count of the final pose of every query that just finished
+// (all != 0: of every query, each with a pose)
+hipError_t launch_mask(const QueryDesc* qd, BestState* st, const double* fin_pose, int nq, int64_t max_n, int all,
+                       hipStream_t s);
 
 }  // namespace imloc

@@ -1,27 +1,28 @@
-// refine.hip -- float64 Gauss-Newton passes of LO-RANSAC (ImLoc Sec. 3.3):
+// refine.hip -- float64 Gauss-Newton of LO-RANSAC (ImLoc Sec. 3.3):
 //   local optimisation: non-linear refinement of the truncated squared
 //     reprojection error of a new best hypothesis on the scoring set, the
 //     inlier set re-evaluated at every iterate;
 //   final refinement: robust Cauchy loss, weighted by the confidences, over
 //     all inliers of the full set at the best pose (held fixed).
-// One workgroup per problem; every pass accumulates the 6x6 normal equations
-// (upper triangle), the gradient, the cost and the inlier count in float64
-// with a fixed thread-to-point map and a fixed reduction tree, so the result
-// is deterministic.  Residual r = pi(R X + t) - x; left update on SO(3).
+// Each Gauss-Newton iteration is one launch over (point chunk x problem)
+// workgroups for every problem of a batch of queries.  A workgroup
+// accumulates the 6x6 normal equations (upper triangle), the gradient, the
+// cost and the inlier count in float64 with a fixed thread-to-point map and
+// reduction tree; partial sums are combined in chunk order, so the result is
+// deterministic.  Residual r = pi(R X + t) - x; left update on SO(3).
 #include "imloc_device.h"
 #include "imloc_kernels.h"
 
 namespace imloc {
 
-constexpr int kGNBlock = 1024;
-constexpr int kGNWaves = kGNBlock / kWave;
 constexpr int kAcc = 29;  // 21 (H upper) + 6 (g) + cost + count
+constexpr int kGNThreads = 256;
+constexpr int kGNWaves = kGNThreads / kWave;
+constexpr int kGNPPT = 8;                       // points per thread per chunk
+constexpr int kGNChunk = kGNThreads * kGNPPT;   // points per workgroup
 
-struct Acc {
-  double v[kAcc];
-};
-
-__device__ inline void acc_point(Acc& a, const Cam& K, double x, double y, double z, double du, double dv, double wt) {
+__device__ inline void acc_point(double* a, const Cam& K, double x, double y, double z, double du, double dv,
+                                 double wt) {
   const double iz = 1.0 / z;
   const double a00 = K.fx * iz, a02 = -K.fx * x * iz * iz;
   const double a11 = K.fy * iz, a12 = -K.fy * y * iz * iz;
@@ -32,50 +33,218 @@ __device__ inline void acc_point(Acc& a, const Cam& K, double x, double y, doubl
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
 #pragma unroll
-    for (int c = r; c < 6; ++c) { a.v[k] = fma(wt, J0[r] * J0[c] + J1[r] * J1[c], a.v[k]); ++k; }
+    for (int c = r; c < 6; ++c) { a[k] = fma(wt, J0[r] * J0[c] + J1[r] * J1[c], a[k]); ++k; }
   }
 #pragma unroll
-  for (int r = 0; r < 6; ++r) a.v[21 + r] = fma(wt, J0[r] * du + J1[r] * dv, a.v[21 + r]);
+  for (int r = 0; r < 6; ++r) a[21 + r] = fma(wt, J0[r] * du + J1[r] * dv, a[21 + r]);
 }
 
-// MODE 0: truncated cost over all m points.  MODE 1: Cauchy over the set
-// marked in in_set (built at the first pass when build is true).
+// Per-problem Gauss-Newton state, double-buffered across launches.
+struct GNState {
+  double cur[12];      // accepted pose
+  double eval[12];     // pose evaluated by the launch that wrote this state
+  double cur_cost;
+  double cur_count;
+  int32_t done;
+  int32_t accepted;
+};
+
+__host__ __device__ inline int chunks_for(int64_t n) {
+  const int64_t c = (n + kGNChunk - 1) / kGNChunk;
+  return c > 0 ? (int)c : 1;
+}
+
+int gn_chunks(int64_t n) { return chunks_for(n); }
+
+size_t gn_scratch_bytes(int nprob, int chunks_max) {
+  if (nprob < 1) nprob = 1;
+  if (chunks_max < 1) chunks_max = 1;
+  return (((size_t)2 * nprob * sizeof(GNState) + 255) & ~size_t(255)) +
+         (size_t)2 * nprob * chunks_max * kAcc * sizeof(double) + 256;
+}
+
+// Solve from the reduced sums in LDS; thread 0 only.  Returns false if the
+// normal matrix is not positive definite.
+__device__ bool gn_solve_step(const double* tot, const double* cur, double* next) {
+  double b[6], d[6];
+  for (int r = 0; r < 6; ++r) b[r] = -tot[21 + r];
+  if (!chol6_solve_packed(tot, b, d)) return false;
+  Pose P, O;
+  for (int e = 0; e < 9; ++e) P.R[e] = cur[e];
+  for (int e = 0; e < 3; ++e) P.t[e] = cur[9 + e];
+  pose_left_update(P, d, O);
+  for (int e = 0; e < 9; ++e) next[e] = O.R[e];
+  for (int e = 0; e < 3; ++e) next[9 + e] = O.t[e];
+  return true;
+}
+
+// One launch of a batched multi-workgroup Gauss-Newton run.  Launch k of a
+// problem:
+//   k = 0: evaluate the start pose;
+//   k >= 1: reduce the partial sums of launch k-1 (every workgroup of the
+//     problem, in chunk order, so all take the same decision), accept the
+//     evaluated pose if its cost did not rise (at k = 1 it is the start),
+//     solve the normal equations of the accepted pose for the next pose
+//     (unless the iteration budget is spent), and evaluate that.
+// MODE 0 (local optimisation): truncated cost over the scoring set.
+// MODE 1 (final refinement): Cauchy cost over the in-set, which launch 0
+// marks as the inliers (tau) of the start pose.
 template <int MODE>
-__device__ void gn_pass(const CorrF32& c, int64_t m, const Cam& K, const Pose& P, double tau2, double s2,
-                        uint8_t* in_set, bool build, double* s_tot) {
-  Acc a;
+__global__ __launch_bounds__(kGNThreads) void gn_kernel(
+    const QueryDesc* __restrict__ qd, CandBuf cb, const int32_t* __restrict__ sel, const int32_t* __restrict__ n_sel,
+    const double* __restrict__ start_direct, BestState* __restrict__ bst, int kmax, int k, GNState* __restrict__ gst,
+    double* __restrict__ part, int chunks_max, int nprob, uint8_t* __restrict__ in_set_all,
+    double* __restrict__ out_pose, double* __restrict__ out_cost, int64_t* __restrict__ out_count) {
+  const int p = blockIdx.y;
+  const int chunk = blockIdx.x;
+  int q;
+  const double* start;
+  if (MODE == 0) {
+    q = start_direct ? 0 : p / kmax;
+    const int slot = p - q * kmax;
+    if (!start_direct && slot >= n_sel[q]) return;
+    start = start_direct ? start_direct + 12 * (int64_t)p
+                         : cb.pose + 12 * (qd[q].cand_off + sel[q * kMaxTopK + slot]);
+  } else {
+    q = p;
+    if (!start_direct && !(bst[q].finished == 1 && bst[q].have)) return;
+    start = start_direct ? start_direct + 12 * (int64_t)q : bst[q].pose;
+  }
+  const QueryDesc& d = qd[q];
+  const CorrF32 c = MODE == 0 ? d.S : d.full;
+  const int64_t n = MODE == 0 ? d.m : d.n;
+  const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
+  const double tau2 = d.tau * d.tau, s2 = d.cauchy_s * d.cauchy_s;
+  const Cam K{d.fx, d.fy, d.cx, d.cy};
+  const int chunks = chunks_for(n);
+  if (chunk >= chunks) return;
+  uint8_t* in_set = MODE == 1 ? in_set_all + d.in_set_off : nullptr;
+
+  GNState* prev = gst + (int64_t)((k + 1) & 1) * nprob + p;
+  GNState* next = gst + (int64_t)(k & 1) * nprob + p;
+  const double* part_prev = part + ((int64_t)((k + 1) & 1) * nprob + p) * chunks_max * kAcc;
+  double* part_next = part + ((int64_t)(k & 1) * nprob + p) * chunks_max * kAcc;
+
+  __shared__ double s_grp[8][kAcc];
+  __shared__ double s_tot[kAcc];
+  __shared__ double s_cur[12], s_eval[12];
+  __shared__ double s_cost, s_count;
+  __shared__ int s_done, s_accepted;
+  if (k == 0) {
+    if (threadIdx.x < 12) {
+      s_cur[threadIdx.x] = start[threadIdx.x];
+      s_eval[threadIdx.x] = start[threadIdx.x];
+    }
+    if (threadIdx.x == 0) {
+      s_cost = __builtin_inf();
+      s_count = 0.0;
+      s_done = 0;
+      s_accepted = 0;
+    }
+    __syncthreads();
+  } else {
+    // partial sums of launch k-1 in chunk order: thread (v, g) sums chunks g, g+8, ...
+    const int v = threadIdx.x % kAcc, g = threadIdx.x / kAcc;
+    const bool prev_done = prev->done != 0;
+    if (!prev_done && g < 8) {
+      double sum = 0.0;
+      for (int ch = g; ch < chunks; ch += 8) sum += part_prev[(int64_t)ch * kAcc + v];
+      s_grp[g][v] = sum;
+    }
+    if (threadIdx.x < 12) {
+      s_cur[threadIdx.x] = prev->cur[threadIdx.x];
+      s_eval[threadIdx.x] = prev->eval[threadIdx.x];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kAcc && !prev_done) {
+      double t = 0.0;
+      for (int gg = 0; gg < 8; ++gg) t += s_grp[gg][threadIdx.x];
+      s_tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_cost = prev->cur_cost;
+      s_count = prev->cur_count;
+      s_done = prev->done;
+      s_accepted = prev->accepted;
+      if (!s_done) {
+        // the evaluated pose becomes the accepted one if its cost did not rise
+        if (k == 1 || s_tot[27] <= s_cost) {
+          for (int e = 0; e < 12; ++e) s_cur[e] = s_eval[e];
+          s_cost = s_tot[27];
+          s_count = s_tot[28];
+          if (k > 1) s_accepted += 1;
+          if (k - 1 >= iters || !gn_solve_step(s_tot, s_cur, s_eval)) s_done = 1;
+        } else {
+          s_done = 1;  // the step raised the cost: keep the accepted pose
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // workgroup (0, p) records the state for the next launch and the outputs
+  if (chunk == 0) {
+    if (threadIdx.x < 12) {
+      next->cur[threadIdx.x] = s_cur[threadIdx.x];
+      next->eval[threadIdx.x] = s_eval[threadIdx.x];
+      if (s_done && out_pose) out_pose[12 * (int64_t)p + threadIdx.x] = s_cur[threadIdx.x];
+    }
+    if (threadIdx.x == 0) {
+      next->cur_cost = s_cost;
+      next->cur_count = s_count;
+      next->done = s_done;
+      next->accepted = s_accepted;
+      if (s_done) {
+        if (out_cost) out_cost[p] = s_cost;
+        if (out_count) out_count[p] = (int64_t)s_count;
+      }
+    }
+  }
+  if (s_done) return;
+
+  // accumulate this chunk at the evaluated pose
+  double P[12];
+  for (int e = 0; e < 12; ++e) P[e] = s_eval[e];
+  double a[kAcc];
 #pragma unroll
-  for (int e = 0; e < kAcc; ++e) a.v[e] = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += kGNBlock) {
-    const double X = c.X[i], Y = c.Y[i], Z = c.Z[i];
-    const double w = c.w ? (double)c.w[i] : 1.0;
-    const double x = P.R[0] * X + P.R[1] * Y + P.R[2] * Z + P.t[0];
-    const double y = P.R[3] * X + P.R[4] * Y + P.R[5] * Z + P.t[1];
-    const double z = P.R[6] * X + P.R[7] * Y + P.R[8] * Z + P.t[2];
+  for (int e = 0; e < kAcc; ++e) a[e] = 0.0;
+  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
+  for (int t = 0; t < kGNPPT; ++t) {
+    const int64_t i = base + (int64_t)t * kGNThreads;
+    if (i >= n) break;
+    if (MODE == 1 && k > 0 && !in_set[i]) continue;
+    const double X = gmem(c.X)[i], Y = gmem(c.Y)[i], Z = gmem(c.Z)[i];
+    const double w = c.w ? (double)gmem(c.w)[i] : 1.0;
+    const double x = P[0] * X + P[1] * Y + P[2] * Z + P[9];
+    const double y = P[3] * X + P[4] * Y + P[5] * Z + P[10];
+    const double z = P[6] * X + P[7] * Y + P[8] * Z + P[11];
     double du = 0.0, dv = 0.0, r2 = 0.0;
     const bool front = z > 0.0;
     if (front) {
-      du = K.fx * x / z + K.cx - (double)c.u[i];
-      dv = K.fy * y / z + K.cy - (double)c.v[i];
+      du = K.fx * x / z + K.cx - (double)gmem(c.u)[i];
+      dv = K.fy * y / z + K.cy - (double)gmem(c.v)[i];
       r2 = du * du + dv * dv;
     }
     if (MODE == 0) {
       if (front && r2 < tau2) {
-        a.v[27] += w * r2;
-        a.v[28] += 1.0;
+        a[27] += w * r2;
+        a[28] += 1.0;
         acc_point(a, K, x, y, z, du, dv, w);
       } else {
-        a.v[27] += w * tau2;
+        a[27] += w * tau2;
       }
     } else {
-      if (build) in_set[i] = (front && r2 < tau2) ? 1 : 0;
-      if (!in_set[i]) continue;
-      a.v[28] += 1.0;
+      if (k == 0) {
+        const bool in = front && r2 < tau2;
+        in_set[i] = in ? 1 : 0;
+        if (!in) continue;
+      }
+      a[28] += 1.0;
       if (!front) {
-        a.v[27] += w * s2 * log1p(tau2 / s2);
+        a[27] += w * s2 * log1p(tau2 / s2);
         continue;
       }
-      a.v[27] += w * s2 * log1p(r2 / s2);
+      a[27] += w * s2 * log1p(r2 / s2);
       acc_point(a, K, x, y, z, du, dv, w / (1.0 + r2 / s2));
     }
   }
@@ -83,186 +252,119 @@ __device__ void gn_pass(const CorrF32& c, int64_t m, const Cam& K, const Pose& P
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
   for (int e = 0; e < kAcc; ++e) {
-    const double v = wave_sum(a.v[e]);
+    const double v = wave_sum(a[e]);
     if (lane == 0) s_part[wave][e] = v;
   }
   __syncthreads();
   if ((int)threadIdx.x < kAcc) {
     double t = 0.0;
+#pragma unroll
     for (int w = 0; w < kGNWaves; ++w) t += s_part[w][threadIdx.x];
-    s_tot[threadIdx.x] = t;
+    part_next[(int64_t)chunk * kAcc + threadIdx.x] = t;
   }
-  __syncthreads();
 }
 
-template <int MODE>
-__device__ void gn_run(const CorrF32& c, int64_t m, const Cam& K, const double* start, double tau2, double s2,
-                       int iters, uint8_t* in_set, double* out_pose, double* out_cost, int64_t* out_count) {
-  __shared__ double s_tot[kAcc];
-  __shared__ double s_cur[12], s_cand[12];
-  __shared__ double s_H[21], s_g[6];
-  __shared__ int s_ok;
-  if ((int)threadIdx.x < 12) s_cur[threadIdx.x] = start[threadIdx.x];
-  __syncthreads();
-  Pose P;
-  for (int e = 0; e < 9; ++e) P.R[e] = s_cur[e];
-  for (int e = 0; e < 3; ++e) P.t[e] = s_cur[9 + e];
-  gn_pass<MODE>(c, m, K, P, tau2, s2, in_set, true, s_tot);
-  double cur_cost = s_tot[27];
-  double cur_cnt = s_tot[28];
-  if ((int)threadIdx.x < 21) s_H[threadIdx.x] = s_tot[threadIdx.x];
-  if ((int)threadIdx.x < 6) s_g[threadIdx.x] = s_tot[21 + threadIdx.x];
-  __syncthreads();
-  for (int it = 0; it < iters; ++it) {
-    if (threadIdx.x == 0) {
-      double b[6], d[6];
-      for (int r = 0; r < 6; ++r) b[r] = -s_g[r];
-      s_ok = chol6_solve_packed(s_H, b, d) ? 1 : 0;
-      if (s_ok) {
-        Pose Q;
-        for (int e = 0; e < 9; ++e) Q.R[e] = s_cur[e];
-        for (int e = 0; e < 3; ++e) Q.t[e] = s_cur[9 + e];
-        Pose O;
-        pose_left_update(Q, d, O);
-        for (int e = 0; e < 9; ++e) s_cand[e] = O.R[e];
-        for (int e = 0; e < 3; ++e) s_cand[9 + e] = O.t[e];
-      }
+static void split_scratch(void* scratch, int nprob, GNState** st, double** part) {
+  *st = reinterpret_cast<GNState*>(scratch);
+  *part = reinterpret_cast<double*>(reinterpret_cast<char*>(scratch) +
+                                    (((size_t)2 * nprob * sizeof(GNState) + 255) & ~size_t(255)));
+}
+
+hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
+                     const double* start_direct, int nprob, int kmax, int chunks_max, int iters_max, void* scratch,
+                     double* out_pose, double* out_cost, int64_t* out_count, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  GNState* st;
+  double* part;
+  split_scratch(scratch, nprob, &st, &part);
+  for (int k = 0; k <= iters_max + 1; ++k)
+    hipLaunchKernelGGL(gn_kernel<0>, dim3(chunks_max, nprob), dim3(kGNThreads), 0, s, qd, cb, sel, n_sel,
+                       start_direct, (BestState*)nullptr, kmax, k, st, part, chunks_max, nprob, (uint8_t*)nullptr,
+                       out_pose, out_cost, out_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine(const QueryDesc* qd, BestState* bst, const double* start_direct, int nq, int chunks_max,
+                         int iters_max, uint8_t* in_set, void* scratch, double* out_pose, double* out_cost,
+                         hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  GNState* st;
+  double* part;
+  split_scratch(scratch, nq, &st, &part);
+  CandBuf none{};
+  for (int k = 0; k <= iters_max + 1; ++k)
+    hipLaunchKernelGGL(gn_kernel<1>, dim3(chunks_max, nq), dim3(kGNThreads), 0, s, qd, none,
+                       (const int32_t*)nullptr, (const int32_t*)nullptr, start_direct, bst, 1, k, st, part, chunks_max,
+                       nq, in_set, out_pose, out_cost, (int64_t*)nullptr);
+  return hipGetLastError();
+}
+
+// Running best after a round's local optimisations: in selection order, a
+// strictly lower refined cost replaces the best.  One thread per query.
+__global__ void update_best_kernel(const QueryDesc* __restrict__ qd, CandBuf cb, const int32_t* __restrict__ sel,
+                                   const int32_t* __restrict__ n_sel, const double* __restrict__ lo_pose,
+                                   const double* __restrict__ lo_cost, const int64_t* __restrict__ lo_count, int nq,
+                                   int kmax, BestState* __restrict__ st) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq || qd[q].B <= 0) return;
+  BestState& b = st[q];
+  const int ns = n_sel[q];
+  for (int slot = 0; slot < ns; ++slot) {
+    const int p = q * kmax + slot;
+    if (lo_cost[p] < b.cost) {
+      b.cost = lo_cost[p];
+      b.count = lo_count[p];
+      for (int e = 0; e < 12; ++e) b.pose[e] = lo_pose[12 * (int64_t)p + e];
+      const int64_t o = qd[q].cand_off + sel[q * kMaxTopK + slot];
+      b.h = cb.h[o];
+      b.j = cb.j[o];
+      b.have = 1;
     }
-    __syncthreads();
-    if (!s_ok) break;
-    Pose Q;
-    for (int e = 0; e < 9; ++e) Q.R[e] = s_cand[e];
-    for (int e = 0; e < 3; ++e) Q.t[e] = s_cand[9 + e];
-    gn_pass<MODE>(c, m, K, Q, tau2, s2, in_set, false, s_tot);
-    const double new_cost = s_tot[27];
-    if (!(new_cost <= cur_cost)) break;
-    cur_cost = new_cost;
-    cur_cnt = s_tot[28];
-    if ((int)threadIdx.x < 12) s_cur[threadIdx.x] = s_cand[threadIdx.x];
-    if ((int)threadIdx.x < 21) s_H[threadIdx.x] = s_tot[threadIdx.x];
-    if ((int)threadIdx.x < 6) s_g[threadIdx.x] = s_tot[21 + threadIdx.x];
-    __syncthreads();
   }
-  if ((int)threadIdx.x < 12) out_pose[threadIdx.x] = s_cur[threadIdx.x];
-  if (threadIdx.x == 0) {
-    *out_cost = cur_cost;
-    if (out_count) *out_count = (int64_t)cur_cnt;
-  }
+  b.lo_runs += ns;
 }
 
-__global__ __launch_bounds__(kGNBlock) void lo_kernel(CorrF32 c, int64_t m, Cam K, double tau2, int iters,
-                                                      const double* __restrict__ cand_pose,
-                                                      const int32_t* __restrict__ sel,
-                                                      const int32_t* __restrict__ n_sel, double* __restrict__ out_pose,
-                                                      double* __restrict__ out_cost, int64_t* __restrict__ out_count) {
-  const int q = blockIdx.x;
-  if (n_sel && q >= *n_sel) return;
-  const int src = sel ? sel[q] : q;
-  gn_run<0>(c, m, K, cand_pose + 12 * (int64_t)src, tau2, 0.0, iters, nullptr, out_pose + 12 * q, out_cost + q,
-            out_count ? out_count + q : nullptr);
-}
-
-hipError_t launch_lo(const CorrF32& c, int64_t m, CamH Kh, double tau, int32_t iters, const double* cand_pose,
-                     const int32_t* sel, const int32_t* n_sel, int32_t k, double* out_pose, double* out_cost,
-                     int64_t* out_count, hipStream_t s) {
-  if (k <= 0) return hipSuccess;
-  Cam K{Kh.fx, Kh.fy, Kh.cx, Kh.cy};
-  hipLaunchKernelGGL(lo_kernel, dim3(k), dim3(kGNBlock), 0, s, c, m, K, tau * tau, iters, cand_pose, sel, n_sel,
-                     out_pose, out_cost, out_count);
+hipError_t launch_update_best(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
+                              const double* lo_pose, const double* lo_cost, const int64_t* lo_count, int nq,
+                              int kmax, BestState* st, hipStream_t s) {
+  hipLaunchKernelGGL(update_best_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, qd, cb, sel, n_sel, lo_pose,
+                     lo_cost, lo_count, nq, kmax, st);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kGNBlock) void refine_kernel(CorrF32 c, int64_t n, Cam K, double tau2, double s2,
-                                                          int iters, const double* __restrict__ start,
-                                                          uint8_t* __restrict__ in_set, double* __restrict__ out_pose,
-                                                          double* __restrict__ out_cost) {
-  gn_run<1>(c, n, K, start, tau2, s2, iters, in_set, out_pose, out_cost, nullptr);
-}
-
-hipError_t launch_refine(const CorrF32& c, int64_t n, CamH Kh, double tau, double scale, int32_t iters,
-                         const double* start, uint8_t* in_set, double* out_pose, double* out_cost, hipStream_t s) {
-  Cam K{Kh.fx, Kh.fy, Kh.cx, Kh.cy};
-  hipLaunchKernelGGL(refine_kernel, dim3(1), dim3(kGNBlock), 0, s, c, n, K, tau * tau, scale * scale, iters, start,
-                     in_set, out_pose, out_cost);
-  return hipGetLastError();
-}
-
-// Inlier mask over all points at a pose (float64), and its count.
-__global__ void mask_kernel(CorrF32 c, int64_t n, Cam K, double tau2, const double* __restrict__ pose,
-                            uint8_t* __restrict__ mask, int64_t* __restrict__ count) {
+// Inlier mask over all points of every query that just finished, at its final
+// pose (float64), and its count; a query without a pose gets a zero mask.
+__global__ void mask_kernel(const QueryDesc* __restrict__ qd, BestState* __restrict__ st,
+                            const double* __restrict__ fin_pose, int all) {
+  const int q = blockIdx.y;
+  if (!all && st[q].finished != 1) return;
+  const QueryDesc& d = qd[q];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int64_t)blockIdx.x * blockDim.x >= d.n) return;
+  const bool have = all || st[q].have != 0;
+  const double* pose = fin_pose + 12 * (int64_t)q;
   long long in = 0;
-  if (i < n) {
-    const double X = c.X[i], Y = c.Y[i], Z = c.Z[i];
+  if (i < d.n && have) {
+    const double X = gmem(d.full.X)[i], Y = gmem(d.full.Y)[i], Z = gmem(d.full.Z)[i];
     const double x = pose[0] * X + pose[1] * Y + pose[2] * Z + pose[9];
     const double y = pose[3] * X + pose[4] * Y + pose[5] * Z + pose[10];
     const double z = pose[6] * X + pose[7] * Y + pose[8] * Z + pose[11];
     if (z > 0.0) {
-      const double du = K.fx * x / z + K.cx - (double)c.u[i];
-      const double dv = K.fy * y / z + K.cy - (double)c.v[i];
-      in = (du * du + dv * dv < tau2) ? 1 : 0;
+      const double du = d.fx * x / z + d.cx - (double)gmem(d.full.u)[i];
+      const double dv = d.fy * y / z + d.cy - (double)gmem(d.full.v)[i];
+      in = (du * du + dv * dv < d.tau * d.tau) ? 1 : 0;
     }
-    if (mask) mask[i] = (uint8_t)in;
   }
+  if (i < d.n && d.mask) d.mask[i] = (uint8_t)in;
   const long long tot = wave_sum(in);
-  if ((threadIdx.x & (kWave - 1)) == 0 && tot && count) atomicAdd((unsigned long long*)count, (unsigned long long)tot);
+  if ((threadIdx.x & (kWave - 1)) == 0 && tot)
+    atomicAdd((unsigned long long*)&st[q].full_count, (unsigned long long)tot);
 }
 
-hipError_t launch_mask(const CorrF32& c, int64_t n, CamH Kh, double tau, const double* pose, uint8_t* mask,
-                       int64_t* count, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  Cam K{Kh.fx, Kh.fy, Kh.cx, Kh.cy};
-  hipLaunchKernelGGL(mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c, n, K, tau * tau, pose, mask,
-                     count);
-  return hipGetLastError();
-}
-
-// Running best after a batch's local optimisations: in selection order, a
-// strictly lower refined cost replaces the best.
-__global__ void update_best_kernel(const int64_t* __restrict__ ch, const int32_t* __restrict__ cj,
-                                   const int32_t* __restrict__ sel, const int32_t* __restrict__ n_sel,
-                                   const double* __restrict__ lo_pose, const double* __restrict__ lo_cost,
-                                   const int64_t* __restrict__ lo_count, BestState* st) {
-  if (threadIdx.x != 0) return;
-  const int ns = *n_sel;
-  for (int q = 0; q < ns; ++q) {
-    if (lo_cost[q] < st->cost) {
-      st->cost = lo_cost[q];
-      st->count = lo_count[q];
-      for (int e = 0; e < 12; ++e) st->pose[e] = lo_pose[12 * q + e];
-      st->h = ch[sel[q]];
-      st->j = cj[sel[q]];
-      st->have = 1;
-    }
-  }
-  st->lo_runs += ns;
-}
-
-hipError_t launch_update_best(const CandBuf& cb, const int32_t* sel, const int32_t* n_sel, const double* lo_pose,
-                              const double* lo_cost, const int64_t* lo_count, BestState* st, hipStream_t s) {
-  hipLaunchKernelGGL(update_best_kernel, dim3(1), dim3(64), 0, s, cb.h, cb.j, sel, n_sel, lo_pose, lo_cost, lo_count,
-                     st);
-  return hipGetLastError();
-}
-
-__global__ void init_state_kernel(BestState* st) {
-  if (threadIdx.x != 0) return;
-  for (int e = 0; e < 12; ++e) st->pose[e] = (e == 0 || e == 4 || e == 8) ? 1.0 : 0.0;
-  st->cost = __builtin_inf();
-  st->count = 0;
-  st->h = -1;
-  st->j = -1;
-  st->have = 0;
-  st->lo_runs = 0;
-  st->candidates = 0;
-  st->inlier_residuals = 0;
-  st->weight_sum = 0.0;
-  st->final_cost = 0.0;
-  st->full_count = 0;
-}
-
-hipError_t launch_init_state(BestState* st, hipStream_t s) {
-  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, st);
+hipError_t launch_mask(const QueryDesc* qd, BestState* st, const double* fin_pose, int nq, int64_t max_n, int all,
+                       hipStream_t s) {
+  if (nq <= 0 || max_n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mask_kernel, dim3((unsigned)((max_n + 255) / 256), nq), dim3(256), 0, s, qd, st, fin_pose, all);
   return hipGetLastError();
 }
 

@@ -1,13 +1,23 @@
 // runtime.cpp -- the C ABI of libimloc.so (include/imloc.h): context,
 // workspace carving, argument checks and the orchestration of the kernels of
 // the pose-estimation path (ImLoc Sec. 3.3).
+//
+// Queries run as batches: a device table of QueryDesc drives every kernel,
+// and a single query is a batch of one.  A round draws one batch of minimal
+// samples for every query still sampling, solves P3P, scores, selects, runs
+// the local optimisations and applies the stopping rule; after the last round
+// the final refinement and the inlier mask run for every query.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "imloc.h"
@@ -22,15 +32,22 @@ struct imloc_ctx {
   size_t ws_bytes = 0;
   bool timing = false;
   std::string err;
-  void* pinned = nullptr;  // host staging for small device->host reads
+  char* pinned = nullptr;  // host staging: query table in, states and poses out
   size_t pinned_bytes = 0;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
+  ScoreTune tune{64, 2048};
+  // hipGraph replay of the fixed-sample pipeline
+  bool graphs = false;
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::string gkey;
+  int64_t graph_launches = 0, graph_captures = 0;
 };
 
 namespace {
-
-constexpr int kMaxTopK = 32;
 
 int set_err(imloc_ctx* c, int code, const char* fmt, ...) {
   if (c) {
@@ -44,9 +61,9 @@ int set_err(imloc_ctx* c, int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(ctx, expr)                                                                     \
-  do {                                                                                         \
-    hipError_t e_ = (expr);                                                                    \
+#define HIP_TRY(ctx, expr)                                                                          \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
     if (e_ != hipSuccess) return set_err(ctx, IMLOC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
@@ -74,75 +91,7 @@ bool cam_ok(const imloc_camera* K) {
 bool corr_ok(const imloc_corr* p) { return p && p->u && p->v && p->X && p->Y && p->Z; }
 
 CorrF32 to_corr(const imloc_corr* p) { return CorrF32{p->u, p->v, p->X, p->Y, p->Z, p->w}; }
-CamH to_cam(const imloc_camera* K) { return CamH{K->fx, K->fy, K->cx, K->cy}; }
-
-// Sizes derived from the parameters of one query.
-struct QueryShape {
-  int64_t n, m;        // correspondences, scoring-set size
-  bool subset;
-  int64_t total;       // samples to draw at most
-  int64_t batch;       // samples per batch
-  int64_t cap;         // candidate capacity per batch
-  int32_t k;           // top-k refined per batch
-  ScorePlan plan;
-};
-
-QueryShape shape_of(int64_t n, const imloc_ransac_params* p) {
-  QueryShape s;
-  s.n = n;
-  s.subset = p->max_score_points > 0 && n > p->max_score_points;
-  s.m = s.subset ? p->max_score_points : n;
-  s.total = p->fixed_samples > 0 ? p->fixed_samples : p->max_iters;
-  s.batch = p->batch > 0 ? p->batch : 1024;
-  if (s.batch > s.total) s.batch = s.total;
-  if (s.batch < 1) s.batch = 1;
-  s.cap = 4 * s.batch;
-  s.k = p->lo_top_k < 1 ? 1 : (p->lo_top_k > kMaxTopK ? kMaxTopK : p->lo_top_k);
-  s.plan = plan_score(s.m, s.cap, p->precision);
-  return s;
-}
-
-// Device buffers of one single-query run, carved from the workspace.
-struct QueryBufs {
-  float* subset;
-  BestState* st;
-  CandBuf cb;
-  uint32_t* part_cnt;
-  double* part_gain;
-  int32_t* sel;
-  int32_t* n_sel;
-  double* lo_pose;
-  double* lo_cost;
-  int64_t* lo_count;
-  double* fin_pose;
-  double* fin_cost;
-  uint8_t* in_set;
-};
-
-QueryBufs carve(Arena& a, const QueryShape& s) {
-  QueryBufs b;
-  b.subset = s.subset ? a.take<float>(6 * (size_t)s.m) : nullptr;
-  b.st = a.take<BestState>(1);
-  b.cb.cap = s.cap;
-  b.cb.pose = a.take<double>(12 * (size_t)s.cap);
-  b.cb.proj = a.take<float>(16 * (size_t)s.cap);
-  b.cb.h = a.take<int64_t>((size_t)s.cap);
-  b.cb.j = a.take<int32_t>((size_t)s.cap);
-  b.cb.n = a.take<int32_t>(1);
-  b.cb.count = a.take<int32_t>((size_t)s.cap);
-  b.cb.msac = a.take<double>((size_t)s.cap);
-  b.part_cnt = a.take<uint32_t>((size_t)s.plan.chunks * (size_t)s.cap);
-  b.part_gain = a.take<double>((size_t)s.plan.chunks * (size_t)s.cap);
-  b.sel = a.take<int32_t>(kMaxTopK);
-  b.n_sel = a.take<int32_t>(1);
-  b.lo_pose = a.take<double>(12 * kMaxTopK);
-  b.lo_cost = a.take<double>(kMaxTopK);
-  b.lo_count = a.take<int64_t>(kMaxTopK);
-  b.fin_pose = a.take<double>(12);
-  b.fin_cost = a.take<double>(1);
-  b.in_set = a.take<uint8_t>((size_t)(s.n > 0 ? s.n : 1));
-  return b;
-}
+const CorrF32 kNoCorr{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 
 int check_params(imloc_ctx* ctx, const imloc_ransac_params* p) {
   if (!p) return set_err(ctx, IMLOC_EINVAL, "params is null");
@@ -152,23 +101,133 @@ int check_params(imloc_ctx* ctx, const imloc_ransac_params* p) {
     return set_err(ctx, IMLOC_EINVAL, "adaptive mode needs max_iters > 0 and 0 < confidence < 1");
   if (p->precision != IMLOC_FP32_SCORE && p->precision != IMLOC_FP64_ALL)
     return set_err(ctx, IMLOC_EINVAL, "unknown precision %d", p->precision);
-  if (p->final_iters > 0 && !(p->cauchy_scale_px > 0.0)) return set_err(ctx, IMLOC_EINVAL, "cauchy_scale_px must be > 0");
+  if (p->final_iters > 0 && !(p->cauchy_scale_px > 0.0))
+    return set_err(ctx, IMLOC_EINVAL, "cauchy_scale_px must be > 0");
   if (p->lo_iters < 0 || p->final_iters < 0) return set_err(ctx, IMLOC_EINVAL, "negative iteration count");
+  if (p->lo_iters > 1000 || p->final_iters > 1000) return set_err(ctx, IMLOC_EINVAL, "iteration count above 1000");
   if (p->max_score_points < 0) return set_err(ctx, IMLOC_EINVAL, "max_score_points < 0");
   if (p->max_score_points > 0 && p->max_score_points < 3) return set_err(ctx, IMLOC_EINVAL, "max_score_points < 3");
   return IMLOC_OK;
 }
 
-// Stopping rule: samples needed for inlier ratio eps (minimal size 3).
-int64_t required_samples(double eps, double conf, int64_t max_iters) {
-  if (!(eps > 0.0)) return max_iters;
-  if (eps >= 1.0) return 0;
-  const double denom = std::log1p(-eps * eps * eps);
-  if (!(denom < 0.0)) return max_iters;
-  const double k = std::ceil(std::log(1.0 - conf) / denom);
-  if (!(k < (double)max_iters)) return max_iters;
-  if (k < 0.0) return 0;
-  return (int64_t)k;
+// Host-side plan of one query.
+struct QPlan {
+  int64_t n, m;
+  bool subset;
+  int64_t total, batch, cap;
+  int k;
+};
+
+QPlan plan_query(int64_t n, const imloc_ransac_params* p) {
+  QPlan s;
+  s.n = n;
+  s.subset = p->max_score_points > 0 && n > p->max_score_points;
+  s.m = s.subset ? p->max_score_points : n;
+  s.total = p->fixed_samples > 0 ? p->fixed_samples : p->max_iters;
+  s.batch = p->batch > 0 ? p->batch : 1024;
+  if (s.batch > s.total) s.batch = s.total;
+  if (s.batch < 1) s.batch = 1;
+  s.cap = 4 * s.batch;
+  s.k = p->lo_top_k < 1 ? 1 : (p->lo_top_k > kMaxTopK ? kMaxTopK : p->lo_top_k);
+  return s;
+}
+
+// Device buffers of one batch, carved from the workspace.
+struct Engine {
+  int nq = 0, kmax = 1, chunks_lo = 1, chunks_fin = 1, lo_iters = 0, fin_iters = 0;
+  int64_t max_batch = 1, max_n = 0, slots = 0, max_rounds = 0;
+  bool all_fixed = true;
+  QueryDesc* qd;
+  BestState* st;
+  CandBuf cb;
+  int64_t* item_off;
+  int32_t* active_count;
+  int32_t* sel;
+  int32_t* n_sel;
+  double* lo_pose;
+  double* lo_cost;
+  int64_t* lo_count;
+  double* fin_pose;
+  double* fin_cost;
+  uint8_t* in_set;
+  void* gn_lo;
+  void* gn_fin;
+  float* subset;
+  std::vector<int64_t> cand_off, in_set_off, subset_off;
+};
+
+void plan_engine(Engine& e, int nq, const QPlan* pl, const imloc_ransac_params* const* pp) {
+  e.nq = nq;
+  e.cand_off.resize(nq);
+  e.in_set_off.resize(nq);
+  e.subset_off.resize(nq);
+  int64_t slots = 0, in_bytes = 0, sub = 0;
+  for (int q = 0; q < nq; ++q) {
+    e.cand_off[q] = slots;
+    slots += pl[q].cap;
+    e.in_set_off[q] = in_bytes;
+    in_bytes += (pl[q].n + 255) & ~int64_t(255);
+    e.subset_off[q] = sub;
+    if (pl[q].subset) sub += 6 * pl[q].m;
+    e.kmax = std::max(e.kmax, pl[q].k);
+    e.chunks_lo = std::max(e.chunks_lo, gn_chunks(pl[q].m));
+    e.chunks_fin = std::max(e.chunks_fin, gn_chunks(pl[q].n));
+    e.lo_iters = std::max(e.lo_iters, (int)pp[q]->lo_iters);
+    e.fin_iters = std::max(e.fin_iters, (int)pp[q]->final_iters);
+    e.max_batch = std::max(e.max_batch, pl[q].batch);
+    e.max_n = std::max(e.max_n, pl[q].n);
+    e.max_rounds = std::max(e.max_rounds, (pl[q].total + pl[q].batch - 1) / pl[q].batch);
+    if (pp[q]->fixed_samples <= 0) e.all_fixed = false;
+  }
+  e.slots = std::max<int64_t>(slots, 1);
+  e.in_set_off.push_back(in_bytes);
+  e.subset_off.push_back(sub);
+}
+
+void carve_engine(Arena& a, Engine& e) {
+  const int nq = e.nq;
+  const size_t S = (size_t)e.slots;
+  e.qd = a.take<QueryDesc>(nq);
+  e.st = a.take<BestState>(nq);
+  e.cb.pose = a.take<double>(12 * S);
+  e.cb.proj = a.take<float>(16 * S);
+  e.cb.h = a.take<int64_t>(S);
+  e.cb.j = a.take<int32_t>(S);
+  e.cb.cnt = a.take<uint32_t>(S);
+  e.cb.gain = a.take<uint64_t>(S);
+  e.cb.n = a.take<int32_t>(nq);
+  e.item_off = a.take<int64_t>(nq + 1);
+  e.active_count = a.take<int32_t>(1);
+  e.sel = a.take<int32_t>((size_t)nq * kMaxTopK);
+  e.n_sel = a.take<int32_t>(nq);
+  e.lo_pose = a.take<double>((size_t)nq * e.kmax * 12);
+  e.lo_cost = a.take<double>((size_t)nq * e.kmax);
+  e.lo_count = a.take<int64_t>((size_t)nq * e.kmax);
+  e.fin_pose = a.take<double>((size_t)nq * 12);
+  e.fin_cost = a.take<double>(nq);
+  e.in_set = a.take<uint8_t>((size_t)std::max<int64_t>(e.in_set_off.back(), 1));
+  e.gn_lo = a.take<char>(gn_scratch_bytes(nq * e.kmax, e.chunks_lo));
+  e.gn_fin = a.take<char>(gn_scratch_bytes(nq, e.chunks_fin));
+  e.subset = a.take<float>((size_t)std::max<int64_t>(e.subset_off.back(), 1));
+}
+
+bool ensure_pinned(imloc_ctx* c, size_t bytes) {
+  if (bytes <= c->pinned_bytes) return true;
+  if (c->gexec) {  // a captured graph copies from / to the old staging buffer
+    if (c->gstream) hipStreamSynchronize(c->gstream);
+    hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+    c->gkey.clear();
+  }
+  if (c->pinned) hipHostFree(c->pinned);
+  c->pinned = nullptr;
+  c->pinned_bytes = 0;
+  size_t sz = std::max<size_t>(bytes, 4096);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), sz, hipHostMallocDefault) != hipSuccess) return false;
+  c->pinned_bytes = sz;
+  return true;
 }
 
 hipEvent_t take_event(imloc_ctx* c) {
@@ -185,7 +244,6 @@ struct Timer {
   imloc_ctx* c;
   struct Span { int stage; hipEvent_t a, b; };
   std::vector<Span> spans;
-  hipEvent_t t0 = nullptr, t1 = nullptr;
   explicit Timer(imloc_ctx* cc) : c(cc) { c->next_event = 0; }
   hipEvent_t begin() {
     if (!c->timing) return nullptr;
@@ -218,6 +276,282 @@ void identity_pose(imloc_pose* p) {
   p->t[0] = p->t[1] = p->t[2] = 0.0;
 }
 
+QueryDesc make_desc(const imloc_corr* pts, int64_t n, const imloc_camera* K, const imloc_ransac_params* p,
+                    const QPlan& pl, const Engine& e, int q, uint8_t* mask) {
+  QueryDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.full = n > 0 ? to_corr(pts) : kNoCorr;
+  if (pl.subset) {
+    const float* b = e.subset + e.subset_off[q];
+    const int64_t m = pl.m;
+    d.S = CorrF32{b, b + m, b + 2 * m, b + 3 * m, b + 4 * m, b + 5 * m};
+  } else {
+    d.S = d.full;
+  }
+  d.n = n;
+  d.m = pl.m;
+  d.fx = K->fx; d.fy = K->fy; d.cx = K->cx; d.cy = K->cy;
+  d.tau = p->threshold_px;
+  d.cauchy_s = p->cauchy_scale_px > 0.0 ? p->cauchy_scale_px : 1.0;
+  d.confidence = p->confidence;
+  d.seed = p->seed;
+  d.qid = p->query_id;
+  d.total = pl.total;
+  d.batch = pl.batch;
+  d.min_iters = p->min_iters;
+  d.fixed = p->fixed_samples > 0 ? 1 : 0;
+  d.exhaustive = p->exhaustive ? 1 : 0;
+  d.precision = p->precision;
+  d.k = pl.k;
+  d.lo_iters = p->lo_iters;
+  d.final_iters = p->final_iters;
+  d.cand_off = e.cand_off[q];
+  d.cap = pl.cap;
+  d.in_set_off = e.in_set_off[q];
+  d.B = 0;
+  d.mask = mask;
+  d.fresh = 1;
+  return d;
+}
+
+// Validate, plan, carve and run a batch.  Outputs are host arrays of nq.
+int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, const imloc_camera* K,
+              const imloc_ransac_params* params, int n_params, imloc_pose* poses, uint8_t* const* masks,
+              imloc_stats* stats, int32_t* status) {
+  std::vector<const imloc_ransac_params*> pp(nq);
+  std::vector<QPlan> pl(nq);
+  for (int q = 0; q < nq; ++q) {
+    pp[q] = &params[n_params == 1 ? 0 : q];
+    int rc = check_params(ctx, pp[q]);
+    if (rc) return rc;
+    if (n[q] < 0 || n[q] > INT32_MAX) return set_err(ctx, IMLOC_EINVAL, "query %d: n out of range", q);
+    if (n[q] > 0 && !corr_ok(&pts[q])) return set_err(ctx, IMLOC_EINVAL, "query %d: null correspondence array", q);
+    if (!cam_ok(&K[q])) return set_err(ctx, IMLOC_EINVAL, "query %d: bad intrinsics", q);
+    pl[q] = plan_query(n[q], pp[q]);
+  }
+  hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  Engine e;
+  plan_engine(e, nq, pl.data(), pp.data());
+  Arena a{ctx->ws, ctx->ws_bytes};
+  carve_engine(a, e);
+  if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes, have %zu", a.off, ctx->ws_bytes);
+  const size_t tab = (size_t)nq * sizeof(QueryDesc);
+  const size_t outb = (size_t)nq * sizeof(BestState) + (size_t)nq * 13 * sizeof(double) + 64;
+  if (!ensure_pinned(ctx, tab + outb + 512)) return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
+  QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
+  for (int q = 0; q < nq; ++q) htab[q] = make_desc(&pts[q], n[q], &K[q], pp[q], pl[q], e, q, masks ? masks[q] : nullptr);
+
+  BestState* hst = reinterpret_cast<BestState*>(ctx->pinned + tab);
+  double* hfin = reinterpret_cast<double*>(ctx->pinned + tab + (size_t)nq * sizeof(BestState));
+  int32_t* hact = reinterpret_cast<int32_t*>(ctx->pinned + tab + outb);
+  int64_t max_m_sub = 0;
+  for (int q = 0; q < nq; ++q)
+    if (pl[q].subset) max_m_sub = std::max(max_m_sub, pl[q].m);
+
+  Timer tm(ctx);
+  int rounds = 0;
+  // The whole pipeline of a batch, enqueued on stream `st_`: table upload,
+  // rounds, final refinement, mask, readback into pinned memory.  `sync`
+  // lets adaptive batches read the active count after every round.
+  auto enqueue = [&](hipStream_t st_, bool sync) -> int {
+    hipEvent_t ev_total = tm.begin();
+    HIP_TRY(ctx, hipMemcpyAsync(e.qd, htab, tab, hipMemcpyHostToDevice, st_));
+    HIP_TRY(ctx, launch_gather_subsets(e.qd, nq, max_m_sub, st_));
+    HIP_TRY(ctx, launch_init_queries(e.qd, e.st, nq, st_));
+    rounds = 0;
+    for (int64_t r = 0; r < e.max_rounds; ++r) {
+      hipEvent_t e0 = tm.begin();
+      HIP_TRY(ctx, launch_begin_round(e.qd, e.st, e.cb, nq, st_));
+      HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
+      tm.end(kStSample, e0);
+      hipEvent_t e1 = tm.begin();
+      HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, ctx->tune.ct, e.item_off, st_));
+      HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, ctx->tune, 0, st_));
+      tm.end(kStScore, e1);
+      hipEvent_t e2 = tm.begin();
+      HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, e.kmax, e.sel, e.n_sel, st_));
+      tm.end(kStSelect, e2);
+      hipEvent_t e3 = tm.begin();
+      HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * e.kmax, e.kmax, e.chunks_lo, e.lo_iters,
+                             e.gn_lo, e.lo_pose, e.lo_cost, e.lo_count, st_));
+      HIP_TRY(ctx, launch_update_best(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, e.kmax, e.st,
+                                      st_));
+      HIP_TRY(ctx, launch_end_round(e.qd, e.st, nq, e.active_count, st_));
+      tm.end(kStLO, e3);
+      ++rounds;
+      if (sync) {
+        HIP_TRY(ctx, hipMemcpyAsync(hact, e.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+        HIP_TRY(ctx, hipStreamSynchronize(st_));
+        if (*hact == 0) break;
+      }
+    }
+    hipEvent_t e4 = tm.begin();
+    HIP_TRY(ctx, launch_refine(e.qd, e.st, nullptr, nq, e.chunks_fin, e.fin_iters, e.in_set, e.gn_fin, e.fin_pose,
+                               e.fin_cost, st_));
+    HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, e.max_n, 0, st_));
+    tm.end(kStRefine, e4);
+    tm.end(kStTotal, ev_total);
+    HIP_TRY(ctx, hipMemcpyAsync(hst, e.st, (size_t)nq * sizeof(BestState), hipMemcpyDeviceToHost, st_));
+    HIP_TRY(ctx, hipMemcpyAsync(hfin, e.fin_pose, (size_t)nq * 12 * sizeof(double), hipMemcpyDeviceToHost, st_));
+    HIP_TRY(ctx, hipMemcpyAsync(hfin + 12 * nq, e.fin_cost, (size_t)nq * sizeof(double), hipMemcpyDeviceToHost, st_));
+    return IMLOC_OK;
+  };
+
+  if (ctx->graphs && e.all_fixed && !ctx->timing) {
+    // key of everything a captured graph bakes in: shapes, workspace, staging
+    std::string key;
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%d|%p|%p|%d|%d|%d|%d|", nq, (void*)ctx->ws, (void*)ctx->pinned, ctx->tune.ct,
+             ctx->tune.blocks, e.lo_iters, e.fin_iters);
+    key += buf;
+    for (int q = 0; q < nq; ++q) {
+      snprintf(buf, sizeof(buf), "%lld,%lld,%d,%lld,%lld,%d;", (long long)pl[q].n, (long long)pl[q].m,
+               (int)pl[q].subset, (long long)pl[q].total, (long long)pl[q].batch, pl[q].k);
+      key += buf;
+    }
+    if (!ctx->gstream) {
+      HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+      HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+      HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+    }
+    if (key != ctx->gkey || !ctx->gexec) {
+      if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+      if (ctx->graph) hipGraphDestroy(ctx->graph);
+      ctx->gexec = nullptr;
+      ctx->graph = nullptr;
+      ctx->gkey.clear();
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeRelaxed));
+      int rc = enqueue(ctx->gstream, false);
+      hipGraph_t g = nullptr;
+      hipError_t ce = hipStreamEndCapture(ctx->gstream, &g);
+      if (rc) return rc;
+      if (ce != hipSuccess) return set_err(ctx, IMLOC_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
+      ctx->graph = g;
+      HIP_TRY(ctx, hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+      ctx->gkey = key;
+      ctx->graph_captures++;
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_in, s));
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
+    HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, ctx->gstream));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_out, ctx->gstream));
+    HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->ev_out, 0));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->gstream));
+    ctx->graph_launches++;
+    rounds = (int)e.max_rounds;
+  } else {
+    int rc = enqueue(s, !e.all_fixed);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+  }
+
+  imloc_stats shared_t;
+  std::memset(&shared_t, 0, sizeof(shared_t));
+  tm.fill(&shared_t);
+  for (int q = 0; q < nq; ++q) {
+    const BestState& b = hst[q];
+    const bool have = b.have != 0;
+    status[q] = have ? IMLOC_OK : IMLOC_NO_POSE;
+    identity_pose(&poses[q]);
+    if (have) {
+      for (int x = 0; x < 9; ++x) poses[q].R[x] = hfin[12 * q + x];
+      for (int x = 0; x < 3; ++x) poses[q].t[x] = hfin[12 * q + 9 + x];
+    }
+    if (stats) {
+      imloc_stats& o = stats[q];
+      o = shared_t;
+      o.samples = b.drawn;
+      o.candidates = b.candidates;
+      o.residuals = b.candidates * pl[q].m;
+      o.inlier_residuals = b.inlier_residuals;
+      o.best_count = have ? b.count : 0;
+      o.full_count = have ? b.full_count : 0;
+      o.batches = b.batches;
+      o.lo_runs = (int32_t)b.lo_runs;
+      o.status = status[q];
+      o.best_msac = have ? b.cost : 0.0;
+      o.final_cost = have ? hfin[12 * nq + q] : 0.0;
+      o.best_h = have ? b.h : -1;
+      o.best_j = have ? b.j : -1;
+      o.score_launches = rounds;
+    }
+  }
+  return IMLOC_OK;
+}
+
+size_t batch_bytes(int nq, const int64_t* n, const imloc_ransac_params* params, int n_params) {
+  std::vector<const imloc_ransac_params*> pp(nq);
+  std::vector<QPlan> pl(nq);
+  for (int q = 0; q < nq; ++q) {
+    pp[q] = &params[n_params == 1 ? 0 : q];
+    pl[q] = plan_query(n[q] < 0 ? 0 : n[q], pp[q]);
+  }
+  Engine e;
+  plan_engine(e, nq, pl.data(), pp.data());
+  Arena a{nullptr, (size_t)-1};
+  carve_engine(a, e);
+  return a.off + 256;
+}
+
+// A one-query engine for the stage entry points: the query's full set is its
+// scoring set, `cap` candidate slots.
+struct StageQuery {
+  Engine e;
+  QPlan pl;
+  imloc_ransac_params p;
+};
+
+void stage_setup(StageQuery& sq, int64_t n, int64_t cap, double tau, int precision, int lo_iters, int final_iters,
+                 double cauchy_s, int nprob_lo) {
+  std::memset(&sq.p, 0, sizeof(sq.p));
+  sq.p.threshold_px = tau;
+  sq.p.fixed_samples = 1;
+  sq.p.batch = 1;
+  sq.p.lo_top_k = 1;
+  sq.p.lo_iters = lo_iters;
+  sq.p.final_iters = final_iters;
+  sq.p.cauchy_scale_px = cauchy_s;
+  sq.p.precision = precision;
+  sq.pl = plan_query(n, &sq.p);
+  sq.pl.cap = std::max<int64_t>(cap, 1);
+  const imloc_ransac_params* pp = &sq.p;
+  plan_engine(sq.e, 1, &sq.pl, &pp);
+  sq.e.kmax = 1;
+  sq.e.chunks_lo = gn_chunks(n);
+  (void)nprob_lo;
+}
+
+size_t stage_bytes(StageQuery& sq, int nprob_lo) {
+  Arena a{nullptr, (size_t)-1};
+  carve_engine(a, sq.e);
+  a.take<char>(gn_scratch_bytes(nprob_lo, sq.e.chunks_lo));
+  return a.off + 256;
+}
+
+// Upload the one-query table (and optionally an initial state) and return the
+// device pointers.
+int stage_upload(imloc_ctx* ctx, StageQuery& sq, const imloc_corr* pts, int64_t n, const imloc_camera* K,
+                 int64_t B, int64_t drawn, uint8_t* mask) {
+  if (!ensure_pinned(ctx, sizeof(QueryDesc) + sizeof(BestState) + 512))
+    return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
+  QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
+  htab[0] = make_desc(pts, n, K, &sq.p, sq.pl, sq.e, 0, mask);
+  htab[0].B = B;
+  HIP_TRY(ctx, hipMemcpyAsync(sq.e.qd, htab, sizeof(QueryDesc), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, launch_init_queries(sq.e.qd, sq.e.st, 1, ctx->stream));
+  if (drawn) {
+    BestState* hb = reinterpret_cast<BestState*>(ctx->pinned + 256 * ((sizeof(QueryDesc) + 255) / 256));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(hb, sq.e.st, sizeof(BestState), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    hb->drawn = drawn;
+    HIP_TRY(ctx, hipMemcpyAsync(sq.e.st, hb, sizeof(BestState), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return IMLOC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -231,11 +565,13 @@ int imloc_create(imloc_ctx** out, int device, void* hip_stream) {
   imloc_ctx* c = new imloc_ctx();
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  c->pinned_bytes = 4096;
-  if (hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
+  if (!ensure_pinned(c, 64 * 1024)) {
     delete c;
     return IMLOC_EHIP;
   }
+  int cus = 256;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  c->tune.blocks = 8 * (cus > 0 ? cus : 256);
   *out = c;
   return IMLOC_OK;
 }
@@ -245,6 +581,14 @@ void imloc_destroy(imloc_ctx* c) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   for (auto e : c->events) hipEventDestroy(e);
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->ev_in) hipEventDestroy(c->ev_in);
+  if (c->ev_out) hipEventDestroy(c->ev_out);
+  if (c->gstream) {
+    hipStreamSynchronize(c->gstream);
+    hipStreamDestroy(c->gstream);
+  }
   if (c->pinned) hipHostFree(c->pinned);
   delete c;
 }
@@ -271,24 +615,72 @@ int imloc_set_timing(imloc_ctx* c, int enable) {
   return IMLOC_OK;
 }
 
+int imloc_set_graphs(imloc_ctx* c, int enable) {
+  if (!c) return IMLOC_EINVAL;
+  c->graphs = enable != 0;
+  return IMLOC_OK;
+}
+
+int imloc_graph_counters(const imloc_ctx* c, int64_t* captures, int64_t* launches) {
+  if (!c || !captures || !launches) return IMLOC_EINVAL;
+  *captures = c->graph_captures;
+  *launches = c->graph_launches;
+  return IMLOC_OK;
+}
+
+int imloc_set_score_tuning(imloc_ctx* c, int32_t candidates_per_item, int32_t workgroups) {
+  if (!c) return IMLOC_EINVAL;
+  if (candidates_per_item != 32 && candidates_per_item != 64 && candidates_per_item != 128)
+    return set_err(c, IMLOC_EINVAL, "candidates_per_item must be 32, 64 or 128");
+  if (workgroups < 1 || workgroups > (1 << 20)) return set_err(c, IMLOC_EINVAL, "workgroups out of range");
+  c->tune.ct = candidates_per_item;
+  c->tune.blocks = workgroups;
+  return IMLOC_OK;
+}
+
+int imloc_get_score_tuning(const imloc_ctx* c, int32_t* candidates_per_item, int32_t* workgroups) {
+  if (!c || !candidates_per_item || !workgroups) return IMLOC_EINVAL;
+  *candidates_per_item = c->tune.ct;
+  *workgroups = c->tune.blocks;
+  return IMLOC_OK;
+}
+
 size_t imloc_workspace_bytes(int64_t n, const imloc_ransac_params* p) {
   if (!p || n < 0) return 0;
-  QueryShape s = shape_of(n, p);
-  Arena a{nullptr, (size_t)-1};
-  carve(a, s);
-  return a.off + 256;
+  return batch_bytes(1, &n, p, 1);
+}
+
+size_t imloc_batch_workspace_bytes(int32_t nq, const int64_t* n, const imloc_ransac_params* p, int32_t n_params) {
+  if (nq <= 0 || !n || !p || (n_params != 1 && n_params != nq)) return 0;
+  return batch_bytes(nq, n, p, n_params);
 }
 
 size_t imloc_score_workspace_bytes(int64_t n, int64_t np, int32_t precision) {
   if (n < 0 || np < 0) return 0;
-  Arena a{nullptr, (size_t)-1};
-  ScorePlan pl = plan_score(n, np > 0 ? np : 1, precision);
-  a.take<BestState>(1);
-  a.take<float>(16 * (size_t)(np > 0 ? np : 1));
-  a.take<int32_t>(1);
-  a.take<uint32_t>((size_t)pl.chunks * (size_t)pl.cap);
-  a.take<double>((size_t)pl.chunks * (size_t)pl.cap);
-  return a.off + 256;
+  StageQuery sq;
+  stage_setup(sq, n, np, 1.0, precision, 0, 0, 1.0, 1);
+  return stage_bytes(sq, 1);
+}
+
+size_t imloc_lo_workspace_bytes(int64_t n, int32_t np) {
+  if (n < 0 || np < 0) return 0;
+  StageQuery sq;
+  stage_setup(sq, n, 1, 1.0, 0, 0, 0, 1.0, np);
+  return stage_bytes(sq, std::max(np, 1));
+}
+
+size_t imloc_refine_workspace_bytes(int64_t n) {
+  if (n < 0) return 0;
+  StageQuery sq;
+  stage_setup(sq, n, 1, 1.0, 0, 0, 0, 1.0, 1);
+  return stage_bytes(sq, 1);
+}
+
+size_t imloc_sample_workspace_bytes(int64_t n, int64_t count) {
+  if (n < 0 || count < 0) return 0;
+  StageQuery sq;
+  stage_setup(sq, n, 4 * std::max<int64_t>(count, 1), 1.0, 0, 0, 0, 1.0, 1);
+  return stage_bytes(sq, 1);
 }
 
 size_t imloc_lift_workspace_bytes(int64_t n_matches, int32_t n_views) {
@@ -312,6 +704,7 @@ int imloc_lift(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, const 
       return set_err(ctx, IMLOC_EINVAL, "null match array");
     if (!depth || n_views <= 0 || H < 2 || W < 2 || !cams || !poses)
       return set_err(ctx, IMLOC_EINVAL, "bad depth maps / views");
+    if ((int64_t)n_views * H * W > ((int64_t)1 << 40)) return set_err(ctx, IMLOC_EINVAL, "depth maps too large");
     if (capacity < 0 || (capacity > 0 && (!out->u || !out->v || !out->X || !out->Y || !out->Z)))
       return set_err(ctx, IMLOC_EINVAL, "bad output arrays");
     for (int k = 0; k < n_views; ++k)
@@ -325,16 +718,18 @@ int imloc_lift(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, const 
   int32_t* blk = a.take<int32_t>((size_t)(nb > 0 ? nb : 1));
   if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small for lift: need %zu bytes", a.off);
   if (n_matches > 0) {
-    std::vector<double> hc(4 * (size_t)n_views), hp(12 * (size_t)n_views);
+    const size_t hb = (size_t)n_views * 16 * sizeof(double);
+    if (!ensure_pinned(ctx, hb + 512)) return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the staging buffer may still feed an earlier copy
+    double* hc = reinterpret_cast<double*>(ctx->pinned);
+    double* hp = hc + 4 * (size_t)n_views;
     for (int k = 0; k < n_views; ++k) {
       hc[4 * k] = cams[k].fx; hc[4 * k + 1] = cams[k].fy; hc[4 * k + 2] = cams[k].cx; hc[4 * k + 3] = cams[k].cy;
       for (int e = 0; e < 9; ++e) hp[12 * k + e] = poses[k].R[e];
       for (int e = 0; e < 3; ++e) hp[12 * k + 9 + e] = poses[k].t[e];
     }
-    // synchronous copies: the host vectors die at return
-    HIP_TRY(ctx, hipMemcpyAsync(dcams, hc.data(), hc.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(dposes, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(dcams, hc, 4 * (size_t)n_views * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(dposes, hp, 12 * (size_t)n_views * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   }
   LiftArgs la;
   la.q_u = m ? m->q_u : nullptr; la.q_v = m ? m->q_v : nullptr; la.db_u = m ? m->db_u : nullptr;
@@ -350,136 +745,54 @@ int imloc_lift(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, const 
 int imloc_lo_ransac_pnp(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K,
                         const imloc_ransac_params* p, imloc_pose* pose_out, uint8_t* mask, imloc_stats* stats) {
   if (!ctx) return IMLOC_EINVAL;
-  int rc = check_params(ctx, p);
-  if (rc) return rc;
   if (!pose_out) return set_err(ctx, IMLOC_EINVAL, "pose_out is null");
-  if (n < 0 || n > INT32_MAX) return set_err(ctx, IMLOC_EINVAL, "n out of range");
-  if (n > 0 && !corr_ok(pts)) return set_err(ctx, IMLOC_EINVAL, "null correspondence array");
-  if (!cam_ok(K)) return set_err(ctx, IMLOC_EINVAL, "bad query intrinsics");
-  hipSetDevice(ctx->device);
-  hipStream_t s = ctx->stream;
-  const QueryShape sh = shape_of(n, p);
-  Arena a{ctx->ws, ctx->ws_bytes};
-  QueryBufs b = carve(a, sh);
-  if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes, have %zu", a.off, ctx->ws_bytes);
-  if (stats) std::memset(stats, 0, sizeof(*stats));
-  identity_pose(pose_out);
+  if (!p) return set_err(ctx, IMLOC_EINVAL, "params is null");
+  imloc_corr none{};
+  int32_t status = 0;
+  uint8_t* masks[1] = {mask};
+  int rc = run_batch(ctx, 1, pts ? pts : &none, &n, K, p, 1, pose_out, masks, stats, &status);
+  return rc < 0 ? rc : status;
+}
 
-  Timer tm(ctx);
-  hipEvent_t ev_total = tm.begin();
-  const CamH cam = to_cam(K);
-  const CorrF32 full = n > 0 ? to_corr(pts) : CorrF32{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  CorrF32 S = full;
-  if (sh.subset) {
-    HIP_TRY(ctx, launch_gather_subset(full, n, sh.m, b.subset, s));
-    const int64_t m = sh.m;
-    S = CorrF32{b.subset, b.subset + m, b.subset + 2 * m, b.subset + 3 * m, b.subset + 4 * m, b.subset + 5 * m};
-  }
-  HIP_TRY(ctx, launch_init_state(b.st, s));
-  HIP_TRY(ctx, launch_weight_sum(S, sh.m, b.st, s));
-
-  BestState* hst = reinterpret_cast<BestState*>(ctx->pinned);
-  int64_t drawn = 0, batches = 0;
-  int32_t score_launches = 0;
-  while (sh.m >= 3 && drawn < sh.total) {
-    const int64_t B = std::min(sh.batch, sh.total - drawn);
-    hipEvent_t e0 = tm.begin();
-    HIP_TRY(ctx, launch_fill_i32(b.cb.n, 1, 0, s));
-    HIP_TRY(ctx, launch_sample_p3p(S, sh.m, cam, p->seed, p->query_id, p->exhaustive, drawn, B, p->threshold_px,
-                                   b.cb, nullptr, s));
-    tm.end(kStSample, e0);
-    hipEvent_t e1 = tm.begin();
-    HIP_TRY(ctx, launch_score(S, sh.m, cam, p->threshold_px, p->precision, sh.plan, b.cb, b.part_cnt,
-                              reinterpret_cast<float*>(b.part_gain), b.part_gain, s));
-    ++score_launches;
-    tm.end(kStScore, e1);
-    hipEvent_t e2 = tm.begin();
-    HIP_TRY(ctx, launch_reduce_scores(sh.plan, b.cb, p->threshold_px, b.part_cnt, reinterpret_cast<float*>(b.part_gain),
-                                      b.part_gain, p->precision, b.st, s));
-    HIP_TRY(ctx, launch_select(b.cb, sh.k, b.st, b.sel, b.n_sel, s));
-    tm.end(kStSelect, e2);
-    hipEvent_t e3 = tm.begin();
-    if (sh.k > 0) {
-      HIP_TRY(ctx, launch_lo(S, sh.m, cam, p->threshold_px, p->lo_iters, b.cb.pose, b.sel, b.n_sel, sh.k, b.lo_pose,
-                             b.lo_cost, b.lo_count, s));
-      HIP_TRY(ctx, launch_update_best(b.cb, b.sel, b.n_sel, b.lo_pose, b.lo_cost, b.lo_count, b.st, s));
-    }
-    tm.end(kStLO, e3);
-    drawn += B;
-    ++batches;
-    if (p->fixed_samples <= 0) {
-      HIP_TRY(ctx, hipMemcpyAsync(hst, b.st, sizeof(BestState), hipMemcpyDeviceToHost, s));
-      HIP_TRY(ctx, hipStreamSynchronize(s));
-      const double eps = (double)hst->count / (double)sh.m;
-      int64_t need = required_samples(eps, p->confidence, p->max_iters);
-      if (need < p->min_iters) need = p->min_iters;
-      if (need > p->max_iters) need = p->max_iters;
-      if (drawn >= need) break;
-    }
-  }
-  HIP_TRY(ctx, hipMemcpyAsync(hst, b.st, sizeof(BestState), hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  const bool have = hst->have != 0;
-  int status = have ? IMLOC_OK : IMLOC_NO_POSE;
-  if (have) {
-    hipEvent_t e4 = tm.begin();
-    HIP_TRY(ctx, launch_refine(full, n, cam, p->threshold_px, p->cauchy_scale_px > 0 ? p->cauchy_scale_px : 1.0,
-                               p->final_iters, b.st->pose, b.in_set, b.fin_pose, b.fin_cost, s));
-    HIP_TRY(ctx, launch_mask(full, n, cam, p->threshold_px, b.fin_pose, mask, &b.st->full_count, s));
-    tm.end(kStRefine, e4);
-  } else if (mask && n > 0) {
-    HIP_TRY(ctx, launch_fill_u8(mask, n, 0, s));
-  }
-  tm.end(kStTotal, ev_total);
-  double* hpose = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->pinned) + 1024);
-  HIP_TRY(ctx, hipMemcpyAsync(hst, b.st, sizeof(BestState), hipMemcpyDeviceToHost, s));
-  if (have) {
-    HIP_TRY(ctx, hipMemcpyAsync(hpose, b.fin_pose, 12 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(hpose + 12, b.fin_cost, sizeof(double), hipMemcpyDeviceToHost, s));
-  }
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  if (have) {
-    for (int e = 0; e < 9; ++e) pose_out->R[e] = hpose[e];
-    for (int e = 0; e < 3; ++e) pose_out->t[e] = hpose[9 + e];
-  }
-  if (stats) {
-    stats->samples = drawn;
-    stats->candidates = hst->candidates;
-    stats->residuals = hst->candidates * sh.m;
-    stats->inlier_residuals = hst->inlier_residuals;
-    stats->best_count = have ? hst->count : 0;
-    stats->full_count = have ? hst->full_count : 0;
-    stats->batches = batches;
-    stats->lo_runs = (int32_t)hst->lo_runs;
-    stats->status = status;
-    stats->best_msac = have ? hst->cost : 0.0;
-    stats->final_cost = have ? hpose[12] : 0.0;
-    stats->best_h = have ? hst->h : -1;
-    stats->best_j = have ? hst->j : -1;
-    stats->score_launches = score_launches;
-    tm.fill(stats);
-  }
-  return status;
+int imloc_lo_ransac_pnp_batch(imloc_ctx* ctx, const imloc_corr* pts, const int64_t* n, const imloc_camera* K,
+                              int32_t nq, const imloc_ransac_params* params, int32_t n_params, imloc_pose* poses,
+                              uint8_t* const* masks, imloc_stats* stats, int32_t* status) {
+  if (!ctx) return IMLOC_EINVAL;
+  if (nq < 0 || (nq > 0 && (!pts || !n || !K || !params || !poses || !status)))
+    return set_err(ctx, IMLOC_EINVAL, "bad batch arguments");
+  if (nq > 65535) return set_err(ctx, IMLOC_EINVAL, "at most 65535 queries per batch");
+  if (n_params != 1 && n_params != nq) return set_err(ctx, IMLOC_EINVAL, "n_params must be 1 or nq");
+  if (nq == 0) return IMLOC_OK;
+  return run_batch(ctx, nq, pts, n, K, params, n_params, poses, masks, stats, status);
 }
 
 int imloc_sample_p3p(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K, uint64_t seed,
                      uint64_t query_id, int32_t exhaustive, int64_t h0, int64_t count, double* poses, int64_t* h_out,
                      int32_t* j_out, int32_t* n_cand, int32_t* triples) {
   if (!ctx) return IMLOC_EINVAL;
-  if (n < 0 || n > INT32_MAX || count < 0 || h0 < 0) return set_err(ctx, IMLOC_EINVAL, "bad sizes");
+  if (n < 0 || n > INT32_MAX || count < 0 || count > INT32_MAX || h0 < 0)
+    return set_err(ctx, IMLOC_EINVAL, "bad sizes");
   if (n > 0 && !corr_ok(pts)) return set_err(ctx, IMLOC_EINVAL, "null correspondence array");
   if (!cam_ok(K)) return set_err(ctx, IMLOC_EINVAL, "bad intrinsics");
   if (!poses || !h_out || !j_out || !n_cand) return set_err(ctx, IMLOC_EINVAL, "null output");
   hipSetDevice(ctx->device);
+  StageQuery sq;
+  stage_setup(sq, n, 4 * std::max<int64_t>(count, 1), 1.0, 0, 0, 0, 1.0, 1);
+  sq.p.seed = seed;
+  sq.p.query_id = query_id;
+  sq.p.exhaustive = exhaustive;
   Arena a{ctx->ws, ctx->ws_bytes};
-  float* proj = a.take<float>(16 * (size_t)(4 * count > 0 ? 4 * count : 1));
+  carve_engine(a, sq.e);
   if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes", a.off);
-  CandBuf cb;
-  cb.pose = poses; cb.proj = proj; cb.h = h_out; cb.j = j_out; cb.n = n_cand; cb.count = nullptr; cb.msac = nullptr;
-  cb.cap = 4 * count;
+  // the candidates go straight to the caller's arrays
+  sq.e.cb.pose = poses;
+  sq.e.cb.h = h_out;
+  sq.e.cb.j = j_out;
+  sq.e.cb.n = n_cand;
+  int rc = stage_upload(ctx, sq, pts, n, K, count, h0, nullptr);
+  if (rc) return rc;
   HIP_TRY(ctx, launch_fill_i32(n_cand, 1, 0, ctx->stream));
-  const CorrF32 c = n > 0 ? to_corr(pts) : CorrF32{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  HIP_TRY(ctx, launch_sample_p3p(c, n, to_cam(K), seed, query_id, exhaustive, h0, count, 1.0, cb, triples, ctx->stream));
+  HIP_TRY(ctx, launch_sample_p3p(sq.e.qd, sq.e.st, sq.e.cb, 1, count, triples, ctx->stream));
   return IMLOC_OK;
 }
 
@@ -494,82 +807,426 @@ int imloc_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_ca
   if (np == 0) return IMLOC_OK;
   if (!poses || !count || !msac) return set_err(ctx, IMLOC_EINVAL, "null pose / output array");
   hipSetDevice(ctx->device);
-  hipStream_t s = ctx->stream;
+  StageQuery sq;
+  stage_setup(sq, n, np, tau, precision, 0, 0, 1.0, 1);
   Arena a{ctx->ws, ctx->ws_bytes};
-  ScorePlan pl = plan_score(n, np, precision);
-  BestState* st = a.take<BestState>(1);
-  float* proj = a.take<float>(16 * (size_t)np);
-  int32_t* ncand = a.take<int32_t>(1);
-  uint32_t* pc = a.take<uint32_t>((size_t)pl.chunks * (size_t)pl.cap);
-  double* pg = a.take<double>((size_t)pl.chunks * (size_t)pl.cap);
+  carve_engine(a, sq.e);
   if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes", a.off);
-  const CorrF32 c = n > 0 ? to_corr(pts) : CorrF32{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  CandBuf cb;
-  cb.pose = const_cast<double*>(poses); cb.proj = proj; cb.h = nullptr; cb.j = nullptr; cb.n = ncand;
-  cb.count = count; cb.msac = msac; cb.cap = np;
-  HIP_TRY(ctx, launch_init_state(st, s));
-  HIP_TRY(ctx, launch_weight_sum(c, n, st, s));
-  HIP_TRY(ctx, launch_fill_i32(ncand, 1, (int32_t)np, s));
-  HIP_TRY(ctx, launch_make_proj(poses, np, to_cam(K), tau, proj, s));
-  HIP_TRY(ctx, launch_score(c, n, to_cam(K), tau, precision, pl, cb, pc, reinterpret_cast<float*>(pg), pg, s));
-  HIP_TRY(ctx, launch_reduce_scores(pl, cb, tau, pc, reinterpret_cast<float*>(pg), pg, precision, st, s));
+  int rc = stage_upload(ctx, sq, pts, n, K, 1, 0, nullptr);
+  if (rc) return rc;
+  hipStream_t s = ctx->stream;
+  HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
+  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, ctx->tune.ct, sq.e.item_off, s));
+  HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, ctx->tune, precision, s));
+  HIP_TRY(ctx, launch_candidate_costs(sq.e.qd, sq.e.st, sq.e.cb, np, count, msac, s));
   return IMLOC_OK;
 }
 
 int imloc_local_optimize(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K, const double* start,
                          int32_t np, double tau, int32_t iters, double* out_poses, double* cost, int64_t* count) {
   if (!ctx) return IMLOC_EINVAL;
-  if (n < 0 || n > INT32_MAX || np < 0 || iters < 0) return set_err(ctx, IMLOC_EINVAL, "bad sizes");
+  if (n < 0 || n > INT32_MAX || np < 0 || np > 65535 || iters < 0 || iters > 1000)
+    return set_err(ctx, IMLOC_EINVAL, "bad sizes");
   if (n > 0 && !corr_ok(pts)) return set_err(ctx, IMLOC_EINVAL, "null correspondence array");
   if (!cam_ok(K)) return set_err(ctx, IMLOC_EINVAL, "bad intrinsics");
   if (!(tau > 0.0)) return set_err(ctx, IMLOC_EINVAL, "threshold must be > 0");
   if (np == 0) return IMLOC_OK;
   if (!start || !out_poses || !cost) return set_err(ctx, IMLOC_EINVAL, "null pose / output array");
   hipSetDevice(ctx->device);
-  const CorrF32 c = n > 0 ? to_corr(pts) : CorrF32{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  HIP_TRY(ctx, launch_lo(c, n, to_cam(K), tau, iters, start, nullptr, nullptr, np, out_poses, cost, count, ctx->stream));
+  StageQuery sq;
+  stage_setup(sq, n, 1, tau, 0, iters, 0, 1.0, np);
+  Arena a{ctx->ws, ctx->ws_bytes};
+  carve_engine(a, sq.e);
+  void* scratch = a.take<char>(gn_scratch_bytes(np, sq.e.chunks_lo));
+  if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes", a.off);
+  int rc = stage_upload(ctx, sq, pts, n, K, 0, 0, nullptr);
+  if (rc) return rc;
+  HIP_TRY(ctx, launch_lo(sq.e.qd, sq.e.cb, nullptr, nullptr, start, np, 1, sq.e.chunks_lo, iters, scratch, out_poses,
+                         cost, count, ctx->stream));
   return IMLOC_OK;
 }
 
 int imloc_refine(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K, const double* start,
                  double tau, double scale, int32_t iters, double* out_pose, double* cost, uint8_t* mask) {
   if (!ctx) return IMLOC_EINVAL;
-  if (n < 0 || n > INT32_MAX || iters < 0) return set_err(ctx, IMLOC_EINVAL, "bad sizes");
+  if (n < 0 || n > INT32_MAX || iters < 0 || iters > 1000) return set_err(ctx, IMLOC_EINVAL, "bad sizes");
   if (n > 0 && !corr_ok(pts)) return set_err(ctx, IMLOC_EINVAL, "null correspondence array");
   if (!cam_ok(K)) return set_err(ctx, IMLOC_EINVAL, "bad intrinsics");
   if (!(tau > 0.0) || !(scale > 0.0)) return set_err(ctx, IMLOC_EINVAL, "threshold and scale must be > 0");
   if (!start || !out_pose || !cost) return set_err(ctx, IMLOC_EINVAL, "null pose / output array");
   hipSetDevice(ctx->device);
+  StageQuery sq;
+  stage_setup(sq, n, 1, tau, 0, 0, iters, scale, 1);
   Arena a{ctx->ws, ctx->ws_bytes};
-  uint8_t* in_set = a.take<uint8_t>((size_t)(n > 0 ? n : 1));
+  carve_engine(a, sq.e);
   if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes", a.off);
-  const CorrF32 c = n > 0 ? to_corr(pts) : CorrF32{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  HIP_TRY(ctx, launch_refine(c, n, to_cam(K), tau, scale, iters, start, in_set, out_pose, cost, ctx->stream));
-  if (mask) HIP_TRY(ctx, launch_mask(c, n, to_cam(K), tau, out_pose, mask, nullptr, ctx->stream));
+  int rc = stage_upload(ctx, sq, pts, n, K, 0, 0, mask);
+  if (rc) return rc;
+  HIP_TRY(ctx, launch_refine(sq.e.qd, sq.e.st, start, 1, sq.e.chunks_fin, iters, sq.e.in_set, sq.e.gn_fin, out_pose,
+                             cost, ctx->stream));
+  if (mask) HIP_TRY(ctx, launch_mask(sq.e.qd, sq.e.st, out_pose, 1, n, 1, ctx->stream));
   return IMLOC_OK;
 }
 
-size_t imloc_batch_workspace_bytes(int32_t nq, const int64_t* n, const imloc_ransac_params* p) {
-  if (nq <= 0 || !n || !p) return 0;
-  size_t mx = 0;
-  for (int32_t q = 0; q < nq; ++q) mx = std::max(mx, imloc_workspace_bytes(n[q], p));
-  return mx;
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching over a resident slot table.
+// ---------------------------------------------------------------------------
+namespace {
+
+// First-fit allocator over [0, cap) with coalescing of freed ranges.
+struct RangePool {
+  std::map<int64_t, int64_t> free_;  // offset -> length
+  int64_t cap = 0, used = 0;
+  void reset(int64_t c) {
+    free_.clear();
+    cap = c;
+    used = 0;
+    if (c > 0) free_[0] = c;
+  }
+  int64_t alloc(int64_t len) {
+    if (len <= 0) return 0;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < len) continue;
+      const int64_t off = it->first, rest = it->second - len;
+      free_.erase(it);
+      if (rest > 0) free_[off + len] = rest;
+      used += len;
+      return off;
+    }
+    return -1;
+  }
+  void release(int64_t off, int64_t len) {
+    if (len <= 0) return;
+    used -= len;
+    auto it = free_.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct ServerQuery {
+  int64_t ticket;
+  imloc_corr pts;
+  int64_t n;
+  imloc_camera K;
+  imloc_ransac_params p;
+  uint8_t* mask;
+};
+
+struct ServerSlot {
+  bool used = false;
+  bool fresh = false;
+  ServerQuery q;
+  QPlan pl;
+  int64_t cand_off = 0, cand_len = 0, byte_off = 0, byte_len = 0;
+};
+
+struct Finished {
+  int32_t status;
+  imloc_pose pose;
+  imloc_stats stats;
+};
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+int64_t query_bytes(const QPlan& pl) { return align256(pl.n) + (pl.subset ? align256(24 * pl.m) : 0); }
+
+}  // namespace
+
+struct imloc_server {
+  imloc_ctx* ctx;
+  imloc_server_config cfg;
+  Engine e;
+  char* byte_pool;
+  std::vector<ServerSlot> slots;
+  std::deque<ServerQuery> queue;
+  std::unordered_map<int64_t, Finished> done;
+  RangePool cand_pool, bytes_pool;
+  int64_t next_ticket = 0;
+  int64_t rounds = 0;
+};
+
+namespace {
+
+bool config_ok(const imloc_server_config* c) {
+  return c && c->max_slots >= 1 && c->max_slots <= 4096 && c->max_top_k >= 1 && c->max_top_k <= kMaxTopK &&
+         c->max_n >= 0 && c->max_n <= INT32_MAX && c->candidate_pool >= 4 && c->byte_pool >= 256;
 }
 
-int imloc_lo_ransac_pnp_batch(imloc_ctx* ctx, const imloc_corr* pts, const int64_t* n, const imloc_camera* K,
-                              int32_t nq, const imloc_ransac_params* params, int32_t n_params, imloc_pose* poses,
-                              uint8_t* const* masks, imloc_stats* stats, int32_t* status) {
-  if (!ctx) return IMLOC_EINVAL;
-  if (nq < 0 || (nq > 0 && (!pts || !n || !K || !params || !poses || !status)))
-    return set_err(ctx, IMLOC_EINVAL, "bad batch arguments");
-  if (n_params != 1 && n_params != nq) return set_err(ctx, IMLOC_EINVAL, "n_params must be 1 or nq");
-  for (int32_t q = 0; q < nq; ++q) {
-    const imloc_ransac_params* p = &params[n_params == 1 ? 0 : q];
-    int rc = imloc_lo_ransac_pnp(ctx, &pts[q], n[q], &K[q], p, &poses[q], masks ? masks[q] : nullptr,
-                                 stats ? &stats[q] : nullptr);
-    if (rc < 0) return rc;
-    status[q] = rc;
+// Slot-indexed engine of a server: candidate arrays sized by the candidate
+// pool, in-set and subset bytes in one byte pool.
+void server_engine(Engine& e, const imloc_server_config* c) {
+  e.nq = c->max_slots;
+  e.kmax = c->max_top_k;
+  e.chunks_lo = gn_chunks(c->max_n);
+  e.chunks_fin = gn_chunks(c->max_n);
+  e.slots = c->candidate_pool;
+  e.in_set_off.assign(1, 0);
+  e.subset_off.assign(1, 0);
+}
+
+size_t server_carve(Arena& a, Engine& e, const imloc_server_config* c, char** byte_pool) {
+  carve_engine(a, e);
+  *byte_pool = a.take<char>((size_t)c->byte_pool);
+  return a.off + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t imloc_server_workspace_bytes(const imloc_server_config* cfg) {
+  if (!config_ok(cfg)) return 0;
+  Engine e;
+  server_engine(e, cfg);
+  Arena a{nullptr, (size_t)-1};
+  char* bp;
+  return server_carve(a, e, cfg, &bp);
+}
+
+int imloc_server_create(imloc_ctx* ctx, const imloc_server_config* cfg, imloc_server** out) {
+  if (!ctx || !out) return IMLOC_EINVAL;
+  *out = nullptr;
+  if (!config_ok(cfg)) return set_err(ctx, IMLOC_EINVAL, "bad server configuration");
+  imloc_server* srv = new imloc_server();
+  srv->ctx = ctx;
+  srv->cfg = *cfg;
+  server_engine(srv->e, cfg);
+  Arena a{ctx->ws, ctx->ws_bytes};
+  server_carve(a, srv->e, cfg, &srv->byte_pool);
+  if (!a.ok) {
+    delete srv;
+    return set_err(ctx, IMLOC_ENOMEM, "workspace too small for the server: need %zu bytes", a.off);
   }
+  srv->slots.resize(cfg->max_slots);
+  srv->cand_pool.reset(cfg->candidate_pool);
+  srv->bytes_pool.reset(cfg->byte_pool);
+  // every slot starts retired
+  const size_t tab = (size_t)cfg->max_slots * sizeof(QueryDesc);
+  if (!ensure_pinned(ctx, tab + (size_t)cfg->max_slots * (sizeof(BestState) + 13 * sizeof(double)) + 512)) {
+    delete srv;
+    return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
+  }
+  hipSetDevice(ctx->device);
+  QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
+  std::memset(htab, 0, tab);
+  for (int q = 0; q < cfg->max_slots; ++q) htab[q].fresh = 1;
+  hipStream_t s = ctx->stream;
+  if (hipMemcpyAsync(srv->e.qd, htab, tab, hipMemcpyHostToDevice, s) != hipSuccess ||
+      launch_init_queries(srv->e.qd, srv->e.st, cfg->max_slots, s) != hipSuccess ||
+      launch_retire(srv->e.st, cfg->max_slots, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    delete srv;
+    return set_err(ctx, IMLOC_EHIP, "server initialisation failed");
+  }
+  *out = srv;
+  return IMLOC_OK;
+}
+
+void imloc_server_destroy(imloc_server* srv) {
+  if (!srv) return;
+  hipStreamSynchronize(srv->ctx->stream);
+  delete srv;
+}
+
+int imloc_server_submit(imloc_server* srv, const imloc_corr* pts, int64_t n, const imloc_camera* K,
+                        const imloc_ransac_params* p, uint8_t* mask, int64_t* ticket) {
+  if (!srv || !ticket) return IMLOC_EINVAL;
+  imloc_ctx* ctx = srv->ctx;
+  int rc = check_params(ctx, p);
+  if (rc) return rc;
+  if (n < 0 || n > srv->cfg.max_n) return set_err(ctx, IMLOC_EINVAL, "n out of range for this server");
+  if (n > 0 && !corr_ok(pts)) return set_err(ctx, IMLOC_EINVAL, "null correspondence array");
+  if (!cam_ok(K)) return set_err(ctx, IMLOC_EINVAL, "bad intrinsics");
+  if (p->lo_top_k > srv->cfg.max_top_k) return set_err(ctx, IMLOC_EINVAL, "lo_top_k above the server's maximum");
+  const QPlan pl = plan_query(n, p);
+  if (pl.cap > srv->cfg.candidate_pool || query_bytes(pl) > srv->cfg.byte_pool)
+    return set_err(ctx, IMLOC_ENOMEM, "query larger than the server's pools");
+  ServerQuery q;
+  q.ticket = srv->next_ticket++;
+  q.pts = n > 0 ? *pts : imloc_corr{};
+  q.n = n;
+  q.K = *K;
+  q.p = *p;
+  q.mask = mask;
+  srv->queue.push_back(q);
+  *ticket = q.ticket;
+  return IMLOC_OK;
+}
+
+int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity, int32_t* n_done,
+                      int32_t* n_resident, int32_t* n_queued) {
+  if (!srv) return IMLOC_EINVAL;
+  imloc_ctx* ctx = srv->ctx;
+  Engine& e = srv->e;
+  const int S = srv->cfg.max_slots;
+  // admission, first come first served: a slot and room in both pools
+  while (!srv->queue.empty()) {
+    const ServerQuery& q = srv->queue.front();
+    int slot = -1;
+    for (int i = 0; i < S; ++i)
+      if (!srv->slots[i].used) { slot = i; break; }
+    if (slot < 0) break;
+    const QPlan pl = plan_query(q.n, &q.p);
+    const int64_t co = srv->cand_pool.alloc(pl.cap);
+    if (co < 0) break;
+    const int64_t bl = query_bytes(pl);
+    const int64_t bo = srv->bytes_pool.alloc(bl);
+    if (bo < 0) {
+      srv->cand_pool.release(co, pl.cap);
+      break;
+    }
+    ServerSlot& sl = srv->slots[slot];
+    sl.used = true;
+    sl.fresh = true;
+    sl.q = q;
+    sl.pl = pl;
+    sl.cand_off = co;
+    sl.cand_len = pl.cap;
+    sl.byte_off = bo;
+    sl.byte_len = bl;
+    srv->queue.pop_front();
+  }
+  int nq = 0, kmax = 1, chunks_lo = 1, chunks_fin = 1, lo_iters = 0, fin_iters = 0, resident = 0;
+  int64_t max_batch = 1, max_n = 0, max_m_sub = 0;
+  for (int i = 0; i < S; ++i) {
+    const ServerSlot& sl = srv->slots[i];
+    if (!sl.used) continue;
+    ++resident;
+    nq = i + 1;
+    kmax = std::max(kmax, sl.pl.k);
+    chunks_lo = std::max(chunks_lo, gn_chunks(sl.pl.m));
+    chunks_fin = std::max(chunks_fin, gn_chunks(sl.pl.n));
+    lo_iters = std::max(lo_iters, (int)sl.q.p.lo_iters);
+    fin_iters = std::max(fin_iters, (int)sl.q.p.final_iters);
+    max_batch = std::max(max_batch, sl.pl.batch);
+    max_n = std::max(max_n, sl.pl.n);
+    if (sl.pl.subset && sl.fresh) max_m_sub = std::max(max_m_sub, sl.pl.m);
+  }
+  int32_t ndone = 0;
+  if (nq > 0) {
+    kmax = srv->cfg.max_top_k;  // problem index layout of the LO buffers
+    const size_t tab = (size_t)nq * sizeof(QueryDesc);
+    QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
+    for (int i = 0; i < nq; ++i) {
+      ServerSlot& sl = srv->slots[i];
+      if (!sl.used) {
+        std::memset(&htab[i], 0, sizeof(QueryDesc));
+        continue;
+      }
+      // per-slot view of the pools
+      e.cand_off.assign(1, sl.cand_off);
+      e.in_set_off.assign(1, 0);
+      e.subset_off.assign(1, 0);
+      QueryDesc d = make_desc(&sl.q.pts, sl.q.n, &sl.q.K, &sl.q.p, sl.pl, e, 0, sl.q.mask);
+      // the in-set bytes live in the byte pool, addressed relative to the in-set base
+      d.in_set_off = (int64_t)((srv->byte_pool + sl.byte_off) - reinterpret_cast<char*>(e.in_set));
+      if (sl.pl.subset) {
+        const float* b = reinterpret_cast<const float*>(srv->byte_pool + sl.byte_off + align256(sl.pl.n));
+        const int64_t m = sl.pl.m;
+        d.S = CorrF32{b, b + m, b + 2 * m, b + 3 * m, b + 4 * m, b + 5 * m};
+      }
+      d.fresh = sl.fresh ? 1 : 0;
+      htab[i] = d;
+    }
+    hipSetDevice(ctx->device);
+    hipStream_t s = ctx->stream;
+    Timer tm(ctx);
+    HIP_TRY(ctx, hipMemcpyAsync(e.qd, htab, tab, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, launch_gather_subsets(e.qd, nq, max_m_sub, s));
+    HIP_TRY(ctx, launch_init_queries(e.qd, e.st, nq, s));
+    HIP_TRY(ctx, launch_begin_round(e.qd, e.st, e.cb, nq, s));
+    HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, max_batch, nullptr, s));
+    HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, ctx->tune.ct, e.item_off, s));
+    HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, ctx->tune, 0, s));
+    HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, e.sel, e.n_sel, s));
+    HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * kmax, kmax, chunks_lo, lo_iters, e.gn_lo,
+                           e.lo_pose, e.lo_cost, e.lo_count, s));
+    HIP_TRY(ctx, launch_update_best(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, kmax, e.st, s));
+    HIP_TRY(ctx, launch_end_round(e.qd, e.st, nq, e.active_count, s));
+    HIP_TRY(ctx, launch_refine(e.qd, e.st, nullptr, nq, chunks_fin, fin_iters, e.in_set, e.gn_fin, e.fin_pose,
+                               e.fin_cost, s));
+    HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, max_n, 0, s));
+    HIP_TRY(ctx, launch_retire(e.st, nq, s));
+    BestState* hst = reinterpret_cast<BestState*>(ctx->pinned + tab);
+    double* hfin = reinterpret_cast<double*>(ctx->pinned + tab + (size_t)nq * sizeof(BestState));
+    HIP_TRY(ctx, hipMemcpyAsync(hst, e.st, (size_t)nq * sizeof(BestState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(hfin, e.fin_pose, (size_t)nq * 12 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(hfin + 12 * nq, e.fin_cost, (size_t)nq * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    srv->rounds++;
+    for (int i = 0; i < nq; ++i) {
+      ServerSlot& sl = srv->slots[i];
+      if (!sl.used) continue;
+      sl.fresh = false;
+      const BestState& b = hst[i];
+      if (b.finished != 2) continue;
+      Finished f;
+      const bool have = b.have != 0;
+      f.status = have ? IMLOC_OK : IMLOC_NO_POSE;
+      identity_pose(&f.pose);
+      if (have) {
+        for (int x = 0; x < 9; ++x) f.pose.R[x] = hfin[12 * i + x];
+        for (int x = 0; x < 3; ++x) f.pose.t[x] = hfin[12 * i + 9 + x];
+      }
+      std::memset(&f.stats, 0, sizeof(f.stats));
+      f.stats.samples = b.drawn;
+      f.stats.candidates = b.candidates;
+      f.stats.residuals = b.candidates * sl.pl.m;
+      f.stats.inlier_residuals = b.inlier_residuals;
+      f.stats.best_count = have ? b.count : 0;
+      f.stats.full_count = have ? b.full_count : 0;
+      f.stats.batches = b.batches;
+      f.stats.lo_runs = (int32_t)b.lo_runs;
+      f.stats.status = f.status;
+      f.stats.best_msac = have ? b.cost : 0.0;
+      f.stats.final_cost = have ? hfin[12 * nq + i] : 0.0;
+      f.stats.best_h = have ? b.h : -1;
+      f.stats.best_j = have ? b.j : -1;
+      f.stats.score_launches = (int32_t)b.batches;
+      srv->done[sl.q.ticket] = f;
+      if (done_tickets && ndone < capacity) done_tickets[ndone] = sl.q.ticket;
+      ++ndone;
+      srv->cand_pool.release(sl.cand_off, sl.cand_len);
+      srv->bytes_pool.release(sl.byte_off, sl.byte_len);
+      sl.used = false;
+      --resident;
+    }
+  }
+  if (n_done) *n_done = ndone;
+  if (n_resident) *n_resident = resident;
+  if (n_queued) *n_queued = (int32_t)srv->queue.size();
+  return IMLOC_OK;
+}
+
+int imloc_server_poll(imloc_server* srv, int64_t ticket, imloc_pose* pose, imloc_stats* stats) {
+  if (!srv || !pose) return IMLOC_EINVAL;
+  auto it = srv->done.find(ticket);
+  if (it == srv->done.end()) {
+    if (ticket < 0 || ticket >= srv->next_ticket) return set_err(srv->ctx, IMLOC_EINVAL, "unknown ticket");
+    return IMLOC_PENDING;
+  }
+  *pose = it->second.pose;
+  if (stats) *stats = it->second.stats;
+  const int st = it->second.status;
+  srv->done.erase(it);
+  return st;
+}
+
+int imloc_server_usage(const imloc_server* srv, int64_t* candidate_slots_used, int64_t* bytes_used) {
+  if (!srv || !candidate_slots_used || !bytes_used) return IMLOC_EINVAL;
+  *candidate_slots_used = srv->cand_pool.used;
+  *bytes_used = srv->bytes_pool.used;
   return IMLOC_OK;
 }
 

@@ -1,6 +1,11 @@
 // score.hip -- hypothesis scoring, the hot loop of LO-RANSAC (ImLoc Sec. 3.3:
 // every pose hypothesis is scored against every scored correspondence by a
-// confidence-weighted truncated squared reprojection error).
+// confidence-weighted truncated squared reprojection error), and the
+// per-query top-k selection of the candidates to refine.
+//
+// Work decomposition: a work item is (query, tile of CT candidates, chunk of
+// 256 * PPL correspondences); persistent workgroups walk a device-side work
+// list, so one launch covers any mix of queries.
 //
 // Layout: one lane per correspondence (PPL correspondences per lane kept in
 // registers, coalesced structure-of-arrays loads), candidates wave-uniform so
@@ -12,10 +17,14 @@
 //   e' = du'^2 + dv'^2                   MUL + FMA    (= e / tau^2)
 //   inlier iff e' < w |w|                MUL + CMP    (division-free; rejects w <= 0)
 // The inlier count is a wave ballot + popcount (scalar unit).  The truncated
-// cost is accumulated as MSAC = tau^2 (sum_i w_i - sum_in w_i (1 - e'/(w |w|))),
-// so only inlier lanes of a wave with at least one inlier pay a reciprocal.
-// Partial sums are written per (candidate, point chunk) and reduced in chunk
-// order, so results do not depend on scheduling.
+// cost is MSAC = tau^2 (sum_i w_i - G), G = sum_in w_i (1 - e'/(w |w|)), so
+// only inlier lanes of a wave with at least one inlier pay a reciprocal.
+//
+// Accumulation: each wave's partial G (a float sum over its fixed set of
+// 64 * PPL correspondences) is converted once to fixed point (2^-32) and all
+// partials are added with integer atomics, as are the counts.  Integer sums
+// do not depend on the order, so a candidate's score is the same for any
+// tiling, grid size or mix of queries.
 #include "imloc_device.h"
 #include "imloc_kernels.h"
 
@@ -32,36 +41,80 @@ __device__ inline float to_vgpr(float x) {
   return r;
 }
 
-// Projection rows are stored pre-divided by tau in their first two rows
-// (a' = a / tau, b' = b / tau), and the observations enter as u / tau, v / tau:
-// then e' = du'^2 + dv'^2 = e / tau^2 and the inlier test is e' < w |w|.
-template <int PPL, int CT>
-__global__ __launch_bounds__(kScoreBlock) void score_f32_kernel(
-    const float* __restrict__ U, const float* __restrict__ V, const float* __restrict__ X,
-    const float* __restrict__ Y, const float* __restrict__ Z, const float* __restrict__ W, int64_t m,
-    const float* __restrict__ P, const int32_t* __restrict__ n_cand, float inv_tau, int64_t cap,
-    uint32_t* __restrict__ part_cnt, float* __restrict__ part_gain) {
-  const int ncand = *n_cand;
-  const int tile0 = blockIdx.y * CT;
-  if (tile0 >= ncand) return;
+__device__ inline int ppl_of(const QueryDesc& d) { return d.precision ? kScorePPL64 : kScorePPL32; }
+__device__ inline int64_t chunks_of(const QueryDesc& d) {
+  const int64_t per = (int64_t)kScoreBlock * ppl_of(d);
+  const int64_t c = (d.m + per - 1) / per;
+  return c > 0 ? c : 1;
+}
+
+// Work list: items_q = tiles_q * chunks_q for queries sampling this round;
+// item_off = exclusive prefix, item_off[nq] = total (one workgroup).
+__global__ __launch_bounds__(1024) void worklist_kernel(const QueryDesc* __restrict__ qd,
+                                                        const int32_t* __restrict__ n_cand, int nq, int ct,
+                                                        int64_t* __restrict__ item_off) {
+  __shared__ long long s[1024];
+  const int seg = (nq + 1023) / 1024;
+  const int q0 = threadIdx.x * seg, q1 = min(nq, q0 + seg);
+  long long sum = 0;
+  for (int q = q0; q < q1; ++q) {
+    const QueryDesc& d = qd[q];
+    if (d.B > 0) sum += (long long)((n_cand[q] + ct - 1) / ct) * chunks_of(d);
+  }
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const long long v = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += v;
+    __syncthreads();
+  }
+  long long run = s[threadIdx.x] - sum;
+  for (int q = q0; q < q1; ++q) {
+    item_off[q] = run;
+    const QueryDesc& d = qd[q];
+    if (d.B > 0) run += (long long)((n_cand[q] + ct - 1) / ct) * chunks_of(d);
+  }
+  if (threadIdx.x == 1023) item_off[nq] = s[1023];
+}
+
+hipError_t launch_worklist(const QueryDesc* qd, CandBuf cb, int nq, int ct, int64_t* item_off, hipStream_t s) {
+  hipLaunchKernelGGL(worklist_kernel, dim3(1), dim3(1024), 0, s, qd, cb.n, nq, ct, item_off);
+  return hipGetLastError();
+}
+
+template <int CT>
+__device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* __restrict__ proj,
+                                               uint32_t* __restrict__ ccnt, unsigned long long* __restrict__ cgain,
+                                               BestState* st, int64_t tile, int64_t chunk, int ncand,
+                                               uint32_t (*s_cnt)[kScoreWaves],
+                                               unsigned long long (*s_gain)[kScoreWaves]) {
+  constexpr int PPL = kScorePPL32;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int64_t base = (int64_t)blockIdx.x * (kScoreBlock * PPL) + wave * (kWave * PPL) + lane;
+  const float inv_tau = (float)(1.0 / d.tau);
+  const int64_t base = chunk * (kScoreBlock * PPL) + wave * (kWave * PPL) + lane;
+  const auto U = gmem(d.S.u);
+  const auto V = gmem(d.S.v);
+  const auto X = gmem(d.S.X);
+  const auto Y = gmem(d.S.Y);
+  const auto Z = gmem(d.S.Z);
+  const auto W = gmem(d.S.w);
   float pu[PPL], pv[PPL], px[PPL], py[PPL], pz[PPL], pw[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int64_t i = base + (int64_t)k * kWave;
-    if (i < m) {
+    if (i < d.m) {
       pu[k] = U[i] * inv_tau; pv[k] = V[i] * inv_tau; px[k] = X[i]; py[k] = Y[i]; pz[k] = Z[i];
       pw[k] = W ? W[i] : 1.0f;
     } else {  // a NaN residual is never an inlier
       pu[k] = __builtin_nanf(""); pv[k] = 0.f; px[k] = 0.f; py[k] = 0.f; pz[k] = 0.f; pw[k] = 0.f;
     }
   }
-  __shared__ uint32_t s_cnt[CT][kScoreWaves];
-  __shared__ float s_gain[CT][kScoreWaves];
-  const int cend = min(CT, ncand - tile0);
-  const float4* pc = reinterpret_cast<const float4*>(P + 16 * (int64_t)tile0);
+  const int c0 = (int)(tile * CT);
+  const int cend = min(CT, ncand - c0);
+  const float4* __restrict__ pc = reinterpret_cast<const float4*>(proj + 16 * (d.cand_off + c0));
   float4 n0 = pc[0], n1 = pc[1], n2 = pc[2];
+  uint32_t item_cnt = 0;
   for (int c = 0; c < cend; ++c) {
     const float4 r0 = n0, r1 = n1, r2 = n2;
     if (c + 1 < cend) {  // prefetch the next candidate's rows
@@ -83,59 +136,66 @@ __global__ __launch_bounds__(kScoreBlock) void score_f32_kernel(
       cnt += (uint32_t)__popcll(bal);
       any |= bal;
     }
-    float gain = 0.f;
+    unsigned long long gfx = 0;
     if (any) {
+      float gain = 0.f;
 #pragma unroll
       for (int k = 0; k < PPL; ++k)
         if (e[k] < t[k]) gain = fmaf(pw[k], fmaf(-e[k], __builtin_amdgcn_rcpf(t[k]), 1.0f), gain);
       gain = wave_sum(gain);
+      gfx = (unsigned long long)((double)gain * kGainScale);
     }
+    item_cnt += cnt;
     if (lane == 0) {
       s_cnt[c][wave] = cnt;
-      s_gain[c][wave] = gain;
+      s_gain[c][wave] = gfx;
     }
   }
   __syncthreads();
   if ((int)threadIdx.x < cend) {
     const int c = threadIdx.x;
     uint32_t cnt = 0;
-    float gain = 0.f;
+    unsigned long long g = 0;
 #pragma unroll
-    for (int w = 0; w < kScoreWaves; ++w) { cnt += s_cnt[c][w]; gain += s_gain[c][w]; }
-    part_cnt[(int64_t)blockIdx.x * cap + tile0 + c] = cnt;
-    part_gain[(int64_t)blockIdx.x * cap + tile0 + c] = gain;
+    for (int w = 0; w < kScoreWaves; ++w) { cnt += s_cnt[c][w]; g += s_gain[c][w]; }
+    const int64_t slot = d.cand_off + c0 + c;
+    if (cnt) atomicAdd(&ccnt[slot], cnt);
+    if (g) atomicAdd(&cgain[slot], g);
   }
+  if (lane == 0 && item_cnt) atomicAdd((unsigned long long*)&st->inlier_residuals, (unsigned long long)item_cnt);
+  __syncthreads();
 }
 
 // Float64 scoring (every step in double; the projection rows are formed from
 // the float64 pose per candidate).
-template <int PPL, int CT>
-__global__ __launch_bounds__(kScoreBlock) void score_f64_kernel(
-    const float* __restrict__ U, const float* __restrict__ V, const float* __restrict__ X,
-    const float* __restrict__ Y, const float* __restrict__ Z, const float* __restrict__ W, int64_t m,
-    const double* __restrict__ poses, const int32_t* __restrict__ n_cand, Cam K, double tau2, int64_t cap,
-    uint32_t* __restrict__ part_cnt, double* __restrict__ part_gain) {
-  const int ncand = *n_cand;
-  const int tile0 = blockIdx.y * CT;
-  if (tile0 >= ncand) return;
+template <int CT>
+__device__ __forceinline__ void score_item_f64(const QueryDesc& d, const double* __restrict__ pose,
+                                               uint32_t* __restrict__ ccnt, unsigned long long* __restrict__ cgain,
+                                               BestState* st, int64_t tile, int64_t chunk, int ncand,
+                                               uint32_t (*s_cnt)[kScoreWaves],
+                                               unsigned long long (*s_gain)[kScoreWaves]) {
+  constexpr int PPL = kScorePPL64;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int64_t base = (int64_t)blockIdx.x * (kScoreBlock * PPL) + wave * (kWave * PPL) + lane;
+  const int64_t base = chunk * (kScoreBlock * PPL) + wave * (kWave * PPL) + lane;
+  const Cam K{d.fx, d.fy, d.cx, d.cy};
+  const double tau2 = d.tau * d.tau;
   double pu[PPL], pv[PPL], px[PPL], py[PPL], pz[PPL], pw[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int64_t i = base + (int64_t)k * kWave;
-    if (i < m) {
-      pu[k] = U[i]; pv[k] = V[i]; px[k] = X[i]; py[k] = Y[i]; pz[k] = Z[i];
-      pw[k] = W ? W[i] : 1.0;
+    if (i < d.m) {
+      pu[k] = gmem(d.S.u)[i]; pv[k] = gmem(d.S.v)[i]; px[k] = gmem(d.S.X)[i]; py[k] = gmem(d.S.Y)[i];
+      pz[k] = gmem(d.S.Z)[i];
+      pw[k] = d.S.w ? gmem(d.S.w)[i] : 1.0;
     } else {
       pu[k] = __builtin_nan(""); pv[k] = 0.0; px[k] = 0.0; py[k] = 0.0; pz[k] = 0.0; pw[k] = 0.0;
     }
   }
-  __shared__ uint32_t s_cnt[CT][kScoreWaves];
-  __shared__ double s_gain[CT][kScoreWaves];
-  const int cend = min(CT, ncand - tile0);
+  const int c0 = (int)(tile * CT);
+  const int cend = min(CT, ncand - c0);
+  uint32_t item_cnt = 0;
   for (int c = 0; c < cend; ++c) {
-    const double* q = poses + 12 * (int64_t)(tile0 + c);
+    const double* q = pose + 12 * (d.cand_off + c0 + c);
     Pose Pp;
     for (int e = 0; e < 9; ++e) Pp.R[e] = q[e];
     for (int e = 0; e < 3; ++e) Pp.t[e] = q[9 + e];
@@ -158,192 +218,275 @@ __global__ __launch_bounds__(kScoreBlock) void score_f64_kernel(
         if (in) gain += pw[k] * (1.0 - e / t);
       }
     }
-    if (cnt) gain = wave_sum(gain);
+    unsigned long long gfx = 0;
+    if (cnt) {
+      gain = wave_sum(gain);
+      gfx = (unsigned long long)(gain * kGainScale);
+    }
+    item_cnt += cnt;
     if (lane == 0) {
       s_cnt[c][wave] = cnt;
-      s_gain[c][wave] = gain;
+      s_gain[c][wave] = gfx;
     }
   }
   __syncthreads();
   if ((int)threadIdx.x < cend) {
     const int c = threadIdx.x;
     uint32_t cnt = 0;
-    double gain = 0.0;
+    unsigned long long g = 0;
 #pragma unroll
-    for (int w = 0; w < kScoreWaves; ++w) { cnt += s_cnt[c][w]; gain += s_gain[c][w]; }
-    part_cnt[(int64_t)blockIdx.x * cap + tile0 + c] = cnt;
-    part_gain[(int64_t)blockIdx.x * cap + tile0 + c] = gain;
+    for (int w = 0; w < kScoreWaves; ++w) { cnt += s_cnt[c][w]; g += s_gain[c][w]; }
+    const int64_t slot = d.cand_off + c0 + c;
+    if (cnt) atomicAdd(&ccnt[slot], cnt);
+    if (g) atomicAdd(&cgain[slot], g);
   }
-}
-
-ScorePlan plan_score(int64_t m, int64_t cand_cap, int precision) {
-  ScorePlan p;
-  if (precision == 0) {
-    p.ppl = m > 65536 ? 8 : m > 16384 ? 4 : m > 4096 ? 2 : 1;
-  } else {
-    p.ppl = m > 65536 ? 4 : m > 8192 ? 2 : 1;
-  }
-  p.ct = 32;
-  const int64_t per_block = (int64_t)kScoreBlock * p.ppl;
-  p.chunks = (int)((m + per_block - 1) / per_block);
-  if (p.chunks < 1) p.chunks = 1;
-  p.tiles = (int)((cand_cap + p.ct - 1) / p.ct);
-  if (p.tiles < 1) p.tiles = 1;
-  p.cap = cand_cap;
-  return p;
-}
-
-size_t score_partial_bytes(const ScorePlan& p) {
-  return (size_t)p.chunks * (size_t)p.cap * (sizeof(uint32_t) + sizeof(double));
-}
-
-template <int PPL>
-static void launch_f32(const CorrF32& c, int64_t m, float inv_tau, const ScorePlan& pl, const CandBuf& cb,
-                       uint32_t* pc, float* pg, hipStream_t s) {
-  hipLaunchKernelGGL((score_f32_kernel<PPL, 32>), dim3(pl.chunks, pl.tiles), dim3(kScoreBlock), 0, s, c.u, c.v, c.X,
-                     c.Y, c.Z, c.w, m, cb.proj, cb.n, inv_tau, pl.cap, pc, pg);
-}
-template <int PPL>
-static void launch_f64(const CorrF32& c, int64_t m, Cam K, double tau2, const ScorePlan& pl, const CandBuf& cb,
-                       uint32_t* pc, double* pg, hipStream_t s) {
-  hipLaunchKernelGGL((score_f64_kernel<PPL, 32>), dim3(pl.chunks, pl.tiles), dim3(kScoreBlock), 0, s, c.u, c.v, c.X,
-                     c.Y, c.Z, c.w, m, cb.pose, cb.n, K, tau2, pl.cap, pc, pg);
-}
-
-hipError_t launch_score(const CorrF32& c, int64_t m, CamH Kh, double tau, int precision, const ScorePlan& pl,
-                        const CandBuf& cb, uint32_t* part_cnt, float* part_gain, double* part_gain64,
-                        hipStream_t s) {
-  if (precision == 0) {
-    const float inv_tau = (float)(1.0 / tau);
-    switch (pl.ppl) {
-      case 1: launch_f32<1>(c, m, inv_tau, pl, cb, part_cnt, part_gain, s); break;
-      case 2: launch_f32<2>(c, m, inv_tau, pl, cb, part_cnt, part_gain, s); break;
-      case 4: launch_f32<4>(c, m, inv_tau, pl, cb, part_cnt, part_gain, s); break;
-      default: launch_f32<8>(c, m, inv_tau, pl, cb, part_cnt, part_gain, s); break;
-    }
-  } else {
-    Cam K{Kh.fx, Kh.fy, Kh.cx, Kh.cy};
-    const double tau2 = tau * tau;
-    switch (pl.ppl) {
-      case 1: launch_f64<1>(c, m, K, tau2, pl, cb, part_cnt, part_gain64, s); break;
-      case 2: launch_f64<2>(c, m, K, tau2, pl, cb, part_cnt, part_gain64, s); break;
-      default: launch_f64<4>(c, m, K, tau2, pl, cb, part_cnt, part_gain64, s); break;
-    }
-  }
-  return hipGetLastError();
-}
-
-// One thread per candidate: partials summed in chunk order (float64).
-__global__ void reduce_scores_kernel(const int32_t* __restrict__ n_cand, int chunks, int64_t cap,
-                                     const uint32_t* __restrict__ part_cnt, const float* __restrict__ part_gain,
-                                     const double* __restrict__ part_gain64, double tau2, BestState* st,
-                                     int32_t* __restrict__ count, double* __restrict__ msac) {
-  const int nc = *n_cand;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  long long cnt = 0;
-  if (c < nc) {
-    double g = 0.0;
-    for (int ch = 0; ch < chunks; ++ch) {
-      cnt += part_cnt[(int64_t)ch * cap + c];
-      g += part_gain64 ? part_gain64[(int64_t)ch * cap + c] : (double)part_gain[(int64_t)ch * cap + c];
-    }
-    count[c] = (int32_t)cnt;
-    msac[c] = tau2 * (st->weight_sum - g);
-  }
-  const long long tot = wave_sum(cnt);
-  if ((threadIdx.x & (kWave - 1)) == 0 && tot) atomicAdd((unsigned long long*)&st->inlier_residuals, (unsigned long long)tot);
-  if (c == 0) atomicAdd((unsigned long long*)&st->candidates, (unsigned long long)nc);
-}
-
-hipError_t launch_reduce_scores(const ScorePlan& pl, const CandBuf& cb, double tau, const uint32_t* part_cnt,
-                                const float* part_gain, const double* part_gain64, int precision, BestState* st,
-                                hipStream_t s) {
-  const int64_t n = pl.cap;
-  hipLaunchKernelGGL(reduce_scores_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cb.n, pl.chunks,
-                     pl.cap, part_cnt, part_gain, precision == 0 ? nullptr : part_gain64, tau * tau, st, cb.count,
-                     cb.msac);
-  return hipGetLastError();
-}
-
-// Sum of weights over the scoring set, float64, fixed order (one workgroup).
-__global__ __launch_bounds__(1024) void weight_sum_kernel(const float* __restrict__ W, int64_t m, BestState* st) {
-  double s = 0.0;
-  if (W) {
-    for (int64_t i = threadIdx.x; i < m; i += 1024) s += W[i];
-  } else {
-    for (int64_t i = threadIdx.x; i < m; i += 1024) s += 1.0;
-  }
-  s = wave_sum(s);
-  __shared__ double sw[16];
-  if ((threadIdx.x & 63) == 0) sw[threadIdx.x / 64] = s;
+  if (lane == 0 && item_cnt) atomicAdd((unsigned long long*)&st->inlier_residuals, (unsigned long long)item_cnt);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < 16; ++w) t += sw[w];
-    st->weight_sum = t;
+}
+
+// Persistent workgroups over the work list; every workgroup exits once the
+// item index passes the device-side total.
+template <int CT>
+__global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __restrict__ qd,
+                                                            const float* __restrict__ proj,
+                                                            const double* __restrict__ pose,
+                                                            const int32_t* __restrict__ ncand,
+                                                            uint32_t* __restrict__ ccnt,
+                                                            unsigned long long* __restrict__ cgain,
+                                                            BestState* __restrict__ st, int nq,
+                                                            const int64_t* __restrict__ item_off) {
+  __shared__ uint32_t s_cnt[CT][kScoreWaves];
+  __shared__ unsigned long long s_gain[CT][kScoreWaves];
+  const int64_t total = item_off[nq];
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    int lo = 0, hi = nq - 1;  // the query owning item w: last q with item_off[q] <= w
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (item_off[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    const QueryDesc& d = qd[lo];
+    const int64_t chunks = chunks_of(d);
+    const int64_t local = w - item_off[lo];
+    const int64_t tile = local / chunks, chunk = local - tile * chunks;
+    const int nc = ncand[lo];
+    if (d.precision == 0)
+      score_item_f32<CT>(d, proj, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain);
+    else
+      score_item_f64<CT>(d, pose, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain);
   }
 }
 
-hipError_t launch_weight_sum(const CorrF32& c, int64_t m, BestState* st, hipStream_t s) {
-  hipLaunchKernelGGL(weight_sum_kernel, dim3(1), dim3(1024), 0, s, c.w, m, st);
+hipError_t launch_score(const QueryDesc* qd, CandBuf cb, BestState* st, int nq, const int64_t* item_off,
+                        ScoreTune tune, int precision, hipStream_t s) {
+  (void)precision;
+  const dim3 grid(tune.blocks > 0 ? tune.blocks : 2048), block(kScoreBlock);
+  unsigned long long* g = reinterpret_cast<unsigned long long*>(cb.gain);
+  switch (tune.ct) {
+    case 128:
+      hipLaunchKernelGGL(score_kernel<128>, grid, block, 0, s, qd, cb.proj, cb.pose, cb.n, cb.cnt, g, st, nq, item_off);
+      break;
+    case 64:
+      hipLaunchKernelGGL(score_kernel<64>, grid, block, 0, s, qd, cb.proj, cb.pose, cb.n, cb.cnt, g, st, nq, item_off);
+      break;
+    default:
+      hipLaunchKernelGGL(score_kernel<32>, grid, block, 0, s, qd, cb.proj, cb.pose, cb.n, cb.cnt, g, st, nq, item_off);
+      break;
+  }
   return hipGetLastError();
 }
 
-// Top-k of the batch by (msac asc, count desc, h asc, j asc) among candidates
-// whose truncated cost beats the running best; k rounds of a workgroup argmin.
-__device__ inline bool cand_less(int a, int b, const int32_t* cnt, const double* ms, const int64_t* h, const int32_t* j) {
-  if (ms[a] != ms[b]) return ms[a] < ms[b];
-  if (cnt[a] != cnt[b]) return cnt[a] > cnt[b];
-  if (h[a] != h[b]) return h[a] < h[b];
-  return j[a] < j[b];
+__device__ inline double cand_msac(const QueryDesc& d, const BestState& b, uint64_t gain) {
+  return d.tau * d.tau * (b.weight_sum - (double)gain * (1.0 / kGainScale));
 }
 
-constexpr int kSelBlock = 256;
-constexpr int kMaxTopK = 32;
+__global__ void candidate_costs_kernel(const QueryDesc* __restrict__ qd, const BestState* __restrict__ st, CandBuf cb,
+                                       int64_t np, int32_t* __restrict__ count, double* __restrict__ msac) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const int64_t o = qd[0].cand_off + i;
+  count[i] = (int32_t)cb.cnt[o];
+  msac[i] = cand_msac(qd[0], st[0], cb.gain[o]);
+}
 
-__global__ __launch_bounds__(kSelBlock) void select_kernel(const int32_t* __restrict__ n_cand,
-                                                           const int32_t* __restrict__ cnt,
-                                                           const double* __restrict__ ms,
-                                                           const int64_t* __restrict__ ch,
-                                                           const int32_t* __restrict__ cj, int k, const BestState* st,
+hipError_t launch_candidate_costs(const QueryDesc* qd, const BestState* st, CandBuf cb, int64_t np, int32_t* count,
+                                  double* msac, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(candidate_costs_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, qd, st, cb, np,
+                     count, msac);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Top-k of a query's batch by (msac asc, count desc, h asc, j asc) among the
+// candidates whose truncated cost beats the running best.  One workgroup per
+// query.
+// ---------------------------------------------------------------------------
+struct Key {
+  double ms;
+  long long hj;   // sample index * 4 + solution index
+  int cnt, idx;
+};
+
+__device__ inline bool key_less(const Key& a, const Key& b) {
+  if (a.ms != b.ms) return a.ms < b.ms;
+  if (a.cnt != b.cnt) return a.cnt > b.cnt;
+  return a.hj < b.hj;
+}
+
+__device__ inline Key key_none() { return Key{__builtin_inf(), 0x7fffffffffffffffll, -1, -1}; }
+
+__device__ inline Key shfl_key(const Key& k, int lane_xor) {
+  Key o;
+  o.ms = __shfl_xor(k.ms, lane_xor, kWave);
+  o.hj = __shfl_xor(k.hj, lane_xor, kWave);
+  o.cnt = __shfl_xor(k.cnt, lane_xor, kWave);
+  o.idx = __shfl_xor(k.idx, lane_xor, kWave);
+  return o;
+}
+
+constexpr int kSelBlock = 1024;
+constexpr int kSelWaves = kSelBlock / kWave;
+constexpr int kSelList = 8;    // per-thread list of the fast path
+
+__device__ inline Key load_key(const QueryDesc& d, const BestState& b, const CandBuf& cb, int c) {
+  const int64_t o = d.cand_off + c;
+  return Key{cand_msac(d, b, cb.gain[o]), (long long)cb.h[o] * 4 + cb.j[o], (int)cb.cnt[o], c};
+}
+
+// Fast path (k <= 8): every thread keeps its best kSelList candidates sorted in
+// registers; then k rounds pick the smallest list head across the workgroup.
+__global__ __launch_bounds__(kSelBlock) void select_kernel(const QueryDesc* __restrict__ qd,
+                                                           BestState* __restrict__ st, CandBuf cb,
                                                            int32_t* __restrict__ sel, int32_t* __restrict__ n_sel) {
-  const int nc = *n_cand;
-  const double gate = st->cost;
-  __shared__ int s_sel[kMaxTopK];
-  __shared__ int s_red[kSelBlock];
+  const int q = blockIdx.x;
+  const QueryDesc& d = qd[q];
+  if (d.B <= 0) {
+    if (threadIdx.x == 0) n_sel[q] = 0;
+    return;
+  }
+  const int nc = cb.n[q];
+  const int k = d.k;
+  const BestState& b = st[q];
+  const double gate = b.cost;
+  Key list[kSelList];
+#pragma unroll
+  for (int e = 0; e < kSelList; ++e) list[e] = key_none();
+  for (int c = threadIdx.x; c < nc; c += kSelBlock) {
+    Key x = load_key(d, b, cb, c);
+    if (!(x.ms < gate)) continue;
+    if (!key_less(x, list[kSelList - 1])) continue;
+    // sorted insertion as a compare-and-swap pass (static register indices)
+#pragma unroll
+    for (int e = 0; e < kSelList; ++e) {
+      if (key_less(x, list[e])) {
+        const Key t = list[e];
+        list[e] = x;
+        x = t;
+      }
+    }
+  }
+  __shared__ Key s_w[kSelWaves];
+  __shared__ int s_wt[kSelWaves];
+  __shared__ int s_win_thread;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   int r = 0;
   for (; r < k; ++r) {
-    int bi = -1;
-    for (int c = threadIdx.x; c < nc; c += kSelBlock) {
-      if (!(ms[c] < gate)) continue;
+    Key best = list[0];  // the head; popped entries shift the list down
+    int best_thread = best.idx >= 0 ? (int)threadIdx.x : -1;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const Key o = shfl_key(best, off);
+      const int ot = __shfl_xor(best_thread, off, kWave);
+      if (ot >= 0 && (best_thread < 0 || key_less(o, best))) {
+        best = o;
+        best_thread = ot;
+      }
+    }
+    if (lane == 0) {
+      s_w[wave] = best;
+      s_wt[wave] = best_thread;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int bw = -1;
+      for (int w = 0; w < kSelWaves; ++w)
+        if (s_wt[w] >= 0 && (bw < 0 || key_less(s_w[w], s_w[bw]))) bw = w;
+      s_win_thread = bw < 0 ? -1 : s_wt[bw];
+      if (bw >= 0) sel[q * kMaxTopK + r] = s_w[bw].idx;
+    }
+    __syncthreads();
+    const int wt = s_win_thread;
+    __syncthreads();
+    if (wt < 0) break;
+    if ((int)threadIdx.x == wt) {
+#pragma unroll
+      for (int e = 0; e + 1 < kSelList; ++e) list[e] = list[e + 1];
+      list[kSelList - 1] = key_none();
+    }
+  }
+  if (threadIdx.x == 0) {
+    n_sel[q] = r;
+    st[q].candidates += nc;
+  }
+}
+
+// General path (k up to 32): k rounds of a workgroup argmin over all
+// candidates not yet taken.
+__global__ __launch_bounds__(256) void select_rounds_kernel(const QueryDesc* __restrict__ qd,
+                                                            BestState* __restrict__ st, CandBuf cb,
+                                                            int32_t* __restrict__ sel, int32_t* __restrict__ n_sel) {
+  const int q = blockIdx.x;
+  const QueryDesc& d = qd[q];
+  if (d.B <= 0) {
+    if (threadIdx.x == 0) n_sel[q] = 0;
+    return;
+  }
+  const int nc = cb.n[q];
+  const int k = d.k;
+  const BestState& b = st[q];
+  const double gate = b.cost;
+  __shared__ int s_sel[kMaxTopK];
+  __shared__ Key s_red[256];
+  int r = 0;
+  for (; r < k; ++r) {
+    Key bi = key_none();
+    for (int c = threadIdx.x; c < nc; c += 256) {
+      const Key x = load_key(d, b, cb, c);
+      if (!(x.ms < gate)) continue;
       bool taken = false;
-      for (int q = 0; q < r; ++q) taken |= (s_sel[q] == c);
+      for (int t = 0; t < r; ++t) taken |= (s_sel[t] == c);
       if (taken) continue;
-      if (bi < 0 || cand_less(c, bi, cnt, ms, ch, cj)) bi = c;
+      if (bi.idx < 0 || key_less(x, bi)) bi = x;
     }
     s_red[threadIdx.x] = bi;
     __syncthreads();
-    for (int off = kSelBlock / 2; off > 0; off >>= 1) {
+    for (int off = 128; off > 0; off >>= 1) {
       if ((int)threadIdx.x < off) {
-        const int a = s_red[threadIdx.x], b = s_red[threadIdx.x + off];
-        if (a < 0 || (b >= 0 && cand_less(b, a, cnt, ms, ch, cj))) s_red[threadIdx.x] = b;
+        const Key a = s_red[threadIdx.x], bb = s_red[threadIdx.x + off];
+        if (a.idx < 0 || (bb.idx >= 0 && key_less(bb, a))) s_red[threadIdx.x] = bb;
       }
       __syncthreads();
     }
-    const int win = s_red[0];
+    const int win = s_red[0].idx;
     __syncthreads();
     if (win < 0) break;
-    if (threadIdx.x == 0) { s_sel[r] = win; sel[r] = win; }
+    if (threadIdx.x == 0) { s_sel[r] = win; sel[q * kMaxTopK + r] = win; }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *n_sel = r;
+  if (threadIdx.x == 0) {
+    n_sel[q] = r;
+    st[q].candidates += nc;
+  }
 }
 
-hipError_t launch_select(const CandBuf& cb, int32_t k, const BestState* st, int32_t* sel, int32_t* n_sel,
-                         hipStream_t s) {
-  if (k > kMaxTopK) k = kMaxTopK;
-  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelBlock), 0, s, cb.n, cb.count, cb.msac, cb.h, cb.j, k, st, sel,
-                     n_sel);
+hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int kmax, int32_t* sel,
+                         int32_t* n_sel, hipStream_t s) {
+  BestState* stw = const_cast<BestState*>(st);
+  if (kmax <= kSelList) {
+    hipLaunchKernelGGL(select_kernel, dim3(nq), dim3(kSelBlock), 0, s, qd, stw, cb, sel, n_sel);
+  } else {
+    hipLaunchKernelGGL(select_rounds_kernel, dim3(nq), dim3(256), 0, s, qd, stw, cb, sel, n_sel);
+  }
   return hipGetLastError();
 }
 

@@ -39,8 +39,8 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(imloc_ransac_params), sizeof(imloc_stats), sizeof(imloc_camera),
          sizeof(imloc_pose), sizeof(imloc_corr), sizeof(imloc_corr_out), sizeof(imloc_matches));
-  printf("%zu %zu %zu %zu\n", offsetof(imloc_ransac_params, precision), offsetof(imloc_ransac_params, seed),
-         offsetof(imloc_stats, score_launches), offsetof(imloc_stats, ms_total));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(imloc_ransac_params, precision), offsetof(imloc_ransac_params, seed),
+         offsetof(imloc_stats, score_launches), offsetof(imloc_stats, ms_total), sizeof(imloc_server_config));
   return 0;
 }
 ''')
@@ -51,7 +51,7 @@ int main(void) {
     want = [C.sizeof(pk.RansacParams), C.sizeof(pk.Stats), C.sizeof(pk.Camera), C.sizeof(pk.Pose),
             C.sizeof(pk.Corr), C.sizeof(pk.CorrOut), C.sizeof(pk.Matches),
             pk.RansacParams.precision.offset, pk.RansacParams.seed.offset, pk.Stats.score_launches.offset,
-            pk.Stats.ms_total.offset]
+            pk.Stats.ms_total.offset, C.sizeof(pk.ServerConfig)]
     assert got == want
 
 
@@ -72,4 +72,9 @@ def test_host_side_checks_without_device():
     assert L.imloc_score_workspace_bytes(1000, 10, 0) > 0
     assert L.imloc_lift_workspace_bytes(160000, 20) > 0
     ns = (C.c_int64 * 3)(100, 5000, 200)
-    assert L.imloc_batch_workspace_bytes(3, ns, C.byref(p)) >= L.imloc_workspace_bytes(5000, C.byref(p))
+    assert L.imloc_batch_workspace_bytes(3, ns, C.byref(p), 1) >= L.imloc_workspace_bytes(5000, C.byref(p))
+    assert L.imloc_sample_workspace_bytes(2000, 1024) > 0
+    cfg = pk.ServerConfig(64, 8, 200000, 64 * 4096, 64 * 200256)
+    assert L.imloc_server_workspace_bytes(C.byref(cfg)) > 0
+    bad = pk.ServerConfig(0, 8, 200000, 64 * 4096, 64 * 200256)
+    assert L.imloc_server_workspace_bytes(C.byref(bad)) == 0
