@@ -90,6 +90,13 @@ def lib():
         L.orc_lift.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp, i32, i32, i32, vp, vp, C.c_float,
                                vp, vp, vp, vp, vp, vp, vp]
         L.orc_lift.restype = i64
+        L.orc_lift_log8.argtypes = L.orc_lift.argtypes
+        L.orc_lift_log8.restype = i64
+        L.orc_log8_decode.argtypes = [C.c_uint8]
+        L.orc_log8_decode.restype = dbl
+        L.orc_log8_encode.argtypes = [C.c_float]
+        L.orc_log8_encode.restype = C.c_uint8
+        L.orc_log8_encode_array.argtypes = [vp, i64, vp]
         L.orc_normal_equations.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
         L.orc_normal_equations.restype = dbl
         L.orc_pose_update.argtypes = [vp, vp, vp]
@@ -273,20 +280,36 @@ def lo_ransac_pnp(corr, K, **params):
 
 def lift(matches, depth, cams, poses, min_conf=0.05, subpixel=True):
     """matches: dict q_u, q_v, db_u, db_v, conf (float32), view (int32).
-    depth: (K, H, W) float32.  cams: (K, 4).  poses: (K, 12) cam_from_world."""
+    depth: (K, H, W) float32 depth maps, or uint8 8-bit log-depth codes.
+    cams: (K, 4).  poses: (K, 12) cam_from_world."""
     f32 = lambda a: np.ascontiguousarray(a, np.float32)
     qu, qv, du, dv, cf = (f32(matches[k]) for k in ("q_u", "q_v", "db_u", "db_v", "conf"))
     vw = np.ascontiguousarray(matches["view"], np.int32)
-    D = f32(depth)
+    codes = np.asarray(depth).dtype == np.uint8
+    D = np.ascontiguousarray(depth, np.uint8) if codes else f32(depth)
     nv, H, W = D.shape
     cams_a = np.ascontiguousarray(np.asarray(cams, np.float64).reshape(nv, 4))
     poses_a = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(nv, 12))
     n = qu.shape[0]
     outs = [np.zeros(max(n, 1), np.float64) for _ in range(6)]
     src = np.zeros(max(n, 1), np.int64)
-    cnt = lib().orc_lift(_p(qu), _p(qv), _p(du), _p(dv), _p(cf), _p(vw), n, 1 if subpixel else 0, _p(D), nv, H, W,
-                         _p(cams_a), _p(poses_a), C.c_float(np.float32(min_conf)), *[_p(o) for o in outs], _p(src))
+    fn = lib().orc_lift_log8 if codes else lib().orc_lift
+    cnt = fn(_p(qu), _p(qv), _p(du), _p(dv), _p(cf), _p(vw), n, 1 if subpixel else 0, _p(D), nv, H, W,
+             _p(cams_a), _p(poses_a), C.c_float(np.float32(min_conf)), *[_p(o) for o in outs], _p(src))
     names = ("u", "v", "X", "Y", "Z", "w")
     res = {k: o[:cnt].copy() for k, o in zip(names, outs)}
     res["src"] = src[:cnt].copy()
     return res
+
+
+def log8_decode(code: int) -> float:
+    """Depth level of an 8-bit log-depth code (0: no depth)."""
+    return float(lib().orc_log8_decode(int(code)))
+
+
+def log8_encode(depth) -> np.ndarray:
+    """8-bit log-depth codes of float32 depths (any shape)."""
+    d = np.ascontiguousarray(depth, np.float32)
+    out = np.zeros(d.shape, np.uint8)
+    lib().orc_log8_encode_array(_p(d), d.size, _p(out))
+    return out

@@ -831,11 +831,54 @@ int orc_lo_ransac_pnp(const orc_corr *c, const orc_camera *K, const orc_params *
 /* ------------------------------------------------------------------------- */
 static int depth_ok(float d) { return isfinite(d) && d > 0.0f; }
 
-int64_t orc_lift(const float *q_u, const float *q_v, const float *db_u, const float *db_v, const float *conf,
-                 const int32_t *view, int64_t n_matches, int32_t subpixel, const float *depth, int32_t n_views,
-                 int32_t H, int32_t W, const orc_camera *cams, const orc_pose *poses, float min_conf,
-                 double *out_u, double *out_v, double *out_X, double *out_Y, double *out_Z, double *out_w,
-                 int64_t *out_src) {
+/* ------------------------------------------------------------------------- */
+/* 8-bit log-depth codes (Sec. 3.1 "Data Compression", Sec. 4 "Depth          */
+/* Quantization"): depth clipped to [0.25, 128] m and quantised uniformly in  */
+/* log depth.  Reading: code 0 marks a pixel without depth; codes 1..255 are  */
+/* the levels d(c) = 0.25 * (128 / 0.25)^((c - 1) / 254), endpoints included; */
+/* encoding rounds log depth to the nearest level (halves away from zero).    */
+/* ------------------------------------------------------------------------- */
+#define ORC_LOG8_DMIN 0.25
+#define ORC_LOG8_DMAX 128.0
+#define ORC_LOG8_STEPS 254.0
+
+double orc_log8_decode(uint8_t c) {
+  if (c == 0) return 0.0;
+  return ORC_LOG8_DMIN * pow(ORC_LOG8_DMAX / ORC_LOG8_DMIN, ((double)c - 1.0) / ORC_LOG8_STEPS);
+}
+
+uint8_t orc_log8_encode(float depth) {
+  double d = depth;
+  if (!(isfinite(d) && d > 0.0)) return 0;
+  if (d < ORC_LOG8_DMIN) d = ORC_LOG8_DMIN;
+  if (d > ORC_LOG8_DMAX) d = ORC_LOG8_DMAX;
+  const double level = ORC_LOG8_STEPS * log(d / ORC_LOG8_DMIN) / log(ORC_LOG8_DMAX / ORC_LOG8_DMIN);
+  return (uint8_t)(1 + (int)round(level));
+}
+
+void orc_log8_encode_array(const float *depth, int64_t n, uint8_t *codes) {
+  for (int64_t i = 0; i < n; ++i) codes[i] = orc_log8_encode(depth[i]);
+}
+
+/* Depth texel idx of the float32 maps or the code maps (exactly one given);
+ * returns 0 if the texel holds no valid depth. */
+static int depth_tap(const float *depth, const uint8_t *codes, int64_t idx, double *d) {
+  if (codes) {
+    if (codes[idx] == 0) return 0;
+    *d = orc_log8_decode(codes[idx]);
+    return 1;
+  }
+  if (!depth_ok(depth[idx])) return 0;
+  *d = depth[idx];
+  return 1;
+}
+
+static int64_t lift_maps(const float *q_u, const float *q_v, const float *db_u, const float *db_v,
+                         const float *conf, const int32_t *view, int64_t n_matches, int32_t subpixel,
+                         const float *depth, const uint8_t *codes, int32_t n_views, int32_t H, int32_t W,
+                         const orc_camera *cams, const orc_pose *poses, float min_conf, double *out_u,
+                         double *out_v, double *out_X, double *out_Y, double *out_Z, double *out_w,
+                         int64_t *out_src) {
   int64_t nout = 0;
   for (int64_t mi = 0; mi < n_matches; ++mi) {
     if (!(conf[mi] > min_conf)) continue;
@@ -843,24 +886,24 @@ int64_t orc_lift(const float *q_u, const float *q_v, const float *db_u, const fl
     if (k < 0 || k >= n_views) continue;
     double qu = q_u[mi], qv = q_v[mi], du = db_u[mi], dv = db_v[mi];
     if (!isfinite(qu) || !isfinite(qv) || !isfinite(du) || !isfinite(dv)) continue;
-    const float *D = depth + (int64_t)k * H * W;
+    const int64_t base = (int64_t)k * H * W;
     double d;
     if (subpixel) {
       double x = du - 0.5, y = dv - 0.5;
       double x0 = floor(x), y0 = floor(y);
       if (x0 < 0.0 || y0 < 0.0 || x0 + 1.0 > (double)(W - 1) || y0 + 1.0 > (double)(H - 1)) continue;
       int64_t c0 = (int64_t)x0, r0 = (int64_t)y0;
-      float d00 = D[r0 * W + c0], d01 = D[r0 * W + c0 + 1];
-      float d10 = D[(r0 + 1) * W + c0], d11 = D[(r0 + 1) * W + c0 + 1];
-      if (!depth_ok(d00) || !depth_ok(d01) || !depth_ok(d10) || !depth_ok(d11)) continue;
+      double d00, d01, d10, d11;
+      if (!depth_tap(depth, codes, base + r0 * W + c0, &d00) || !depth_tap(depth, codes, base + r0 * W + c0 + 1, &d01) ||
+          !depth_tap(depth, codes, base + (r0 + 1) * W + c0, &d10) ||
+          !depth_tap(depth, codes, base + (r0 + 1) * W + c0 + 1, &d11))
+        continue;
       double ax = x - x0, ay = y - y0;
       d = (1.0 - ay) * ((1.0 - ax) * d00 + ax * d01) + ay * ((1.0 - ax) * d10 + ax * d11);
     } else {
       double cf = floor(du), rf = floor(dv);
       if (cf < 0.0 || rf < 0.0 || cf > (double)(W - 1) || rf > (double)(H - 1)) continue;
-      float dd = D[(int64_t)rf * W + (int64_t)cf];
-      if (!depth_ok(dd)) continue;
-      d = dd;
+      if (!depth_tap(depth, codes, base + (int64_t)rf * W + (int64_t)cf, &d)) continue;
     }
     const orc_camera *Kc = &cams[k];
     const orc_pose *T = &poses[k];
@@ -876,4 +919,22 @@ int64_t orc_lift(const float *q_u, const float *q_v, const float *db_u, const fl
     ++nout;
   }
   return nout;
+}
+
+int64_t orc_lift(const float *q_u, const float *q_v, const float *db_u, const float *db_v, const float *conf,
+                 const int32_t *view, int64_t n_matches, int32_t subpixel, const float *depth, int32_t n_views,
+                 int32_t H, int32_t W, const orc_camera *cams, const orc_pose *poses, float min_conf,
+                 double *out_u, double *out_v, double *out_X, double *out_Y, double *out_Z, double *out_w,
+                 int64_t *out_src) {
+  return lift_maps(q_u, q_v, db_u, db_v, conf, view, n_matches, subpixel, depth, NULL, n_views, H, W, cams, poses,
+                   min_conf, out_u, out_v, out_X, out_Y, out_Z, out_w, out_src);
+}
+
+int64_t orc_lift_log8(const float *q_u, const float *q_v, const float *db_u, const float *db_v, const float *conf,
+                      const int32_t *view, int64_t n_matches, int32_t subpixel, const uint8_t *codes,
+                      int32_t n_views, int32_t H, int32_t W, const orc_camera *cams, const orc_pose *poses,
+                      float min_conf, double *out_u, double *out_v, double *out_X, double *out_Y, double *out_Z,
+                      double *out_w, int64_t *out_src) {
+  return lift_maps(q_u, q_v, db_u, db_v, conf, view, n_matches, subpixel, NULL, codes, n_views, H, W, cams, poses,
+                   min_conf, out_u, out_v, out_X, out_Y, out_Z, out_w, out_src);
 }

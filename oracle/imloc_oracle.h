@@ -144,6 +144,23 @@ int64_t orc_lift(const float *q_u, const float *q_v, const float *db_u, const fl
                  double *out_u, double *out_v, double *out_X, double *out_Y, double *out_Z,
                  double *out_w, int64_t *out_src);
 
+/* 8-bit log-depth codes (Sec. 3.1 "Data Compression"; Sec. 4 "Depth
+ * Quantization"): depth clipped to [0.25, 128] m, quantised uniformly in log
+ * depth.  Code 0: no depth (not finite or <= 0); codes 1..255: levels
+ * 0.25 * 512^((c - 1) / 254), the nearest level in log depth is chosen. */
+double orc_log8_decode(uint8_t c);
+uint8_t orc_log8_encode(float depth);
+void orc_log8_encode_array(const float *depth, int64_t n, uint8_t *codes);
+
+/* orc_lift on code maps codes[k*H*W + row*W + col]; a tap holding code 0 is
+ * invalid, any other decodes to its level (float64) before interpolation. */
+int64_t orc_lift_log8(const float *q_u, const float *q_v, const float *db_u, const float *db_v,
+                      const float *conf, const int32_t *view, int64_t n_matches, int32_t subpixel,
+                      const uint8_t *codes, int32_t n_views, int32_t H, int32_t W,
+                      const orc_camera *cams, const orc_pose *poses, float min_conf,
+                      double *out_u, double *out_v, double *out_X, double *out_Y, double *out_Z,
+                      double *out_w, int64_t *out_src);
+
 #ifdef __cplusplus
 }
 #endif
