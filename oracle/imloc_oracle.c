@@ -832,7 +832,7 @@ int orc_lo_ransac_pnp(const orc_corr *c, const orc_camera *K, const orc_params *
 static int depth_ok(float d) { return isfinite(d) && d > 0.0f; }
 
 /* ------------------------------------------------------------------------- */
-/* 8-bit log-depth codes (Sec. 3.1 "Data Compression", Sec. 4 "Depth          */
+/* 8-bit log-depth codes (Sec. 3.3 "Data Compression", Sec. 4.3 "Depth       */
 /* Quantization"): depth clipped to [0.25, 128] m and quantised uniformly in  */
 /* log depth.  Reading: code 0 marks a pixel without depth; codes 1..255 are  */
 /* the levels d(c) = 0.25 * (128 / 0.25)^((c - 1) / 254), endpoints included; */

@@ -144,7 +144,7 @@ int64_t orc_lift(const float *q_u, const float *q_v, const float *db_u, const fl
                  double *out_u, double *out_v, double *out_X, double *out_Y, double *out_Z,
                  double *out_w, int64_t *out_src);
 
-/* 8-bit log-depth codes (Sec. 3.1 "Data Compression"; Sec. 4 "Depth
+/* 8-bit log-depth codes (Sec. 3.3 "Data Compression"; Sec. 4.3 "Depth
  * Quantization"): depth clipped to [0.25, 128] m, quantised uniformly in log
  * depth.  Code 0: no depth (not finite or <= 0); codes 1..255: levels
  * 0.25 * 512^((c - 1) / 254), the nearest level in log depth is chosen. */

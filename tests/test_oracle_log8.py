@@ -1,6 +1,6 @@
-"""Pins of the oracle's 8-bit log-depth codes (Sec. 3.1 "Data Compression":
+"""Pins of the oracle's 8-bit log-depth codes (Sec. 3.3 "Data Compression":
 depth clipped to [0.25, 128] m and quantised in log space with 256 levels;
-Sec. 4 "Depth Quantization": the relative quantisation error stays below
+Sec. 4.3 "Depth Quantization": the relative quantisation error stays below
 1.4 %) and of lifting through code maps.
 
 Reading: code 0 marks a pixel without depth, codes 1..255 are the levels
