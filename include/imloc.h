@@ -132,7 +132,8 @@ size_t imloc_batch_workspace_bytes(int32_t nq, const int64_t *n, const imloc_ran
 /* Workspace bytes of the stage entry points: imloc_score for n
  * correspondences and np poses, imloc_local_optimize for n correspondences
  * and np start poses, imloc_refine for n correspondences, imloc_sample_p3p
- * for count samples of n correspondences, imloc_lift for n_matches matches over n_views views. */
+ * for count samples of n correspondences, imloc_lift and imloc_lift_log8 for n_matches matches over
+ * n_views views. */
 size_t imloc_score_workspace_bytes(int64_t n, int64_t np, int32_t precision);
 size_t imloc_sample_workspace_bytes(int64_t n, int64_t count);
 size_t imloc_lo_workspace_bytes(int64_t n, int32_t np);
@@ -175,6 +176,26 @@ int imloc_get_score_tuning(const imloc_ctx *ctx, int32_t *candidates_per_item, i
 int imloc_lift(imloc_ctx *ctx, const imloc_matches *m, int64_t n_matches, const float *depth, int32_t n_views,
                int32_t H, int32_t W, const imloc_camera *cams, const imloc_pose *poses, int32_t subpixel,
                float min_conf, const imloc_corr_out *out, int64_t capacity, int32_t *n_out);
+
+/* 8-bit log-depth codes of stored depth maps (Sec. 3.3 "Data Compression":
+ * depth clipped to [0.25, 128] m and quantised uniformly in log depth, 256
+ * codes; Sec. 4.3 "Depth Quantization" bounds the relative error by 1.4 %).
+ * Code 0 = no depth (depth not finite or <= 0); code c in 1..255 = the level
+ * 0.25 * 512^((c - 1) / 254) m; a depth gets its nearest level in log depth
+ * (halves away from zero), so the relative error is at most
+ * exp(ln 512 / 508) - 1 = 1.24 %.
+ *   depth: device float32 [count]; codes: device uint8 [count] (caller-owned).
+ *   Asynchronous on the context's stream.  Returns IMLOC_EINVAL for a
+ *   negative count or null arrays. */
+int imloc_depth_encode_log8(imloc_ctx *ctx, const float *depth, int64_t count, uint8_t *codes);
+
+/* imloc_lift on code maps: codes is device uint8 [n_views][H][W]; a tap with
+ * code 0 is invalid, any other is decoded to its level (float64) before the
+ * interpolation.  Every other argument, rule and the output are those of
+ * imloc_lift; the maps take a quarter of the float32 maps' memory. */
+int imloc_lift_log8(imloc_ctx *ctx, const imloc_matches *m, int64_t n_matches, const uint8_t *codes,
+                    int32_t n_views, int32_t H, int32_t W, const imloc_camera *cams, const imloc_pose *poses,
+                    int32_t subpixel, float min_conf, const imloc_corr_out *out, int64_t capacity, int32_t *n_out);
 
 /* LO-RANSAC PnP for one query (Sec. 3.3 "Pose Estimation").  Minimal sample
  * h draws three distinct indices of the scoring set from Philox4x64-10 with

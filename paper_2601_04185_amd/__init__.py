@@ -34,7 +34,7 @@ EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_err
             "imloc_set_graphs", "imloc_graph_counters", "imloc_server_workspace_bytes", "imloc_server_create",
             "imloc_server_destroy", "imloc_server_submit", "imloc_server_step", "imloc_server_poll",
             "imloc_server_usage",
-            "imloc_lift",
+            "imloc_lift", "imloc_lift_log8", "imloc_depth_encode_log8",
             "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score",
             "imloc_local_optimize", "imloc_refine"]
 
@@ -125,6 +125,8 @@ def lib():
             "imloc_refine_workspace_bytes": ([i64], C.c_size_t),
             "imloc_set_timing": ([vp, C.c_int], C.c_int),
             "imloc_lift": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
+            "imloc_lift_log8": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
+            "imloc_depth_encode_log8": ([vp, vp, i64, vp], C.c_int),
             "imloc_lo_ransac_pnp": ([vp, vp, i64, vp, vp, vp, vp, vp], C.c_int),
             "imloc_lo_ransac_pnp_batch": ([vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp], C.c_int),
             "imloc_sample_p3p": ([vp, vp, i64, vp, u64, u64, i32, i64, i64, vp, vp, vp, vp, vp], C.c_int),
@@ -259,7 +261,8 @@ def imloc_lo_ransac_pnp_batch(ctx: Context, corrs: list, Ks: list, params, masks
 
 def imloc_lift(ctx: Context, matches: dict, depth, cams, poses, subpixel=True, min_conf=0.05, capacity=None):
     """matches: dict of cuda tensors q_u, q_v, db_u, db_v, conf (float32), view (int32).
-    depth: cuda float32 (K, H, W).  cams: (K, 4) host; poses: (K, 12) host.
+    depth: cuda float32 (K, H, W) depth maps, or cuda uint8 (K, H, W) 8-bit
+    log-depth codes (imloc_lift_log8).  cams: (K, 4) host; poses: (K, 12) host.
     Returns dict of cuda tensors u, v, X, Y, Z, w (float32), src (int32) and n (int)."""
     torch = ctx.torch
     n = int(matches["q_u"].numel())
@@ -275,12 +278,26 @@ def imloc_lift(ctx: Context, matches: dict, depth, cams, poses, subpixel=True, m
     P = np.asarray(poses, np.float64).reshape(nv, 12)
     poses_a = (Pose * nv)(*[Pose((C.c_double * 9)(*P[k, :9]), (C.c_double * 3)(*P[k, 9:])) for k in range(nv)])
     ctx.ensure_workspace(lib().imloc_lift_workspace_bytes(n, nv))
-    ctx.check(lib().imloc_lift(ctx.h, C.byref(m), n, C.c_void_p(depth.data_ptr()), nv, H, W, cams_a, poses_a,
-                               1 if subpixel else 0, C.c_float(min_conf), C.byref(co), cap, C.c_void_p(n_out.data_ptr())))
+    fn = lib().imloc_lift_log8 if depth.dtype == torch.uint8 else lib().imloc_lift
+    if depth.dtype not in (torch.uint8, torch.float32) or not depth.is_contiguous():
+        raise ValueError("depth must be contiguous float32 maps or uint8 code maps")
+    ctx.check(fn(ctx.h, C.byref(m), n, C.c_void_p(depth.data_ptr()), nv, H, W, cams_a, poses_a,
+                 1 if subpixel else 0, C.c_float(min_conf), C.byref(co), cap, C.c_void_p(n_out.data_ptr())))
     k = int(n_out.item())
     res = {key: v[:min(k, cap)] for key, v in out.items()}
     res["n"] = k
     return res
+
+
+def imloc_depth_encode_log8(ctx: Context, depth):
+    """8-bit log-depth codes (cuda uint8, same shape) of cuda float32 depths."""
+    torch = ctx.torch
+    d = depth.contiguous()
+    if d.dtype != torch.float32:
+        raise ValueError("depth must be float32")
+    codes = torch.empty(d.shape, dtype=torch.uint8, device=d.device)
+    ctx.check(lib().imloc_depth_encode_log8(ctx.h, _ptr(d), d.numel(), _ptr(codes)))
+    return codes
 
 
 def imloc_sample_p3p(ctx: Context, corr: dict, K, seed: int, query_id: int, h0: int, count: int, exhaustive=0,

@@ -1,0 +1,45 @@
+"""Autotuner of the scoring kernel's launch shape.
+
+The persistent scoring kernel takes two free parameters: candidates per work
+item (32, 64 or 128) and the number of persistent workgroups.  Neither changes
+a result (per-candidate scores are integer-accumulated), so the tuner simply
+times each shape on the caller's own workload with HIP events (the library's
+per-stage timing) and keeps the fastest on the context.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import Context, lib
+
+
+def candidate_shapes(cus: int):
+    for ct in (32, 64, 128):
+        for per_cu in (2, 4, 8, 16, 32):
+            yield ct, per_cu * cus
+
+
+def tune_scoring(ctx: Context, run, reps: int = 2, cus: int | None = None) -> dict:
+    """run(ctx) must execute the workload once and return imloc stats (a dict,
+    or a list of dicts for a batch).  Returns the timing table and leaves the
+    fastest shape set on ctx."""
+    if cus is None:
+        import torch
+        cus = torch.cuda.get_device_properties(ctx.device).multi_processor_count
+    lib().imloc_set_timing(ctx.h, 1)
+    table = []
+    try:
+        for ct, wg in candidate_shapes(cus):
+            ctx.set_score_tuning(ct, wg)
+            best = None
+            for _ in range(reps):
+                st = run(ctx)
+                st0 = st[0] if isinstance(st, (list, tuple)) else st
+                ms = st0["ms_score"]
+                best = ms if best is None else min(best, ms)
+            table.append(dict(candidates_per_item=ct, workgroups=wg, score_ms=best))
+    finally:
+        lib().imloc_set_timing(ctx.h, 0)
+    win = min(table, key=lambda r: r["score_ms"])
+    ctx.set_score_tuning(win["candidates_per_item"], win["workgroups"])
+    return dict(best=win, table=table)

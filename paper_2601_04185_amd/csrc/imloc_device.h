@@ -190,39 +190,45 @@ __device__ inline bool chol6_solve_packed(const double Hp[21], const double b[6]
 // follows from the three camera-frame points l_i y_i.
 // ---------------------------------------------------------------------------
 
-// Real roots of c3 x^3 + c2 x^2 + c1 x + c0 on [lo, hi]: split at the
-// critical points and bisect every sign change.
-__device__ inline int cubic_roots_in(double c0, double c1, double c2, double c3, double lo, double hi, double r[3]) {
-  double pts[4];
-  int np = 0;
-  pts[np++] = lo;
+// Real roots of c3 x^3 + c2 x^2 + c1 x + c0 on [lo, hi], ascending, each
+// passed to emit(root): split at the critical points and bisect every sign
+// change.  No arrays: the (at most three) intervals are walked with a
+// running left end so that everything stays in registers.
+template <class Emit>
+__device__ inline void cubic_roots_in(double c0, double c1, double c2, double c3, double lo, double hi, Emit&& emit) {
   // critical points: 3 c3 x^2 + 2 c2 x + c1 = 0
   const double qa = 3.0 * c3, qb = 2.0 * c2, qc = c1;
-  double cr[2];
-  int nc = 0;
+  double x1 = 0.0, x2 = 0.0;
+  bool u1 = false, u2 = false;
   const double scale = fabs(qa) + fabs(qb) + fabs(qc);
   if (fabs(qa) > 1e-300 + 1e-15 * scale) {
     const double disc = qb * qb - 4.0 * qa * qc;
     if (disc > 0.0) {
       const double q = -0.5 * (qb + copysign(sqrt(disc), qb));
-      double x1 = q / qa, x2 = (q != 0.0) ? qc / q : x1;
-      if (x1 > x2) { double tt = x1; x1 = x2; x2 = tt; }
-      cr[nc++] = x1;
-      cr[nc++] = x2;
+      x1 = q / qa;
+      x2 = (q != 0.0) ? qc / q : x1;
+      if (x1 > x2) { const double tt = x1; x1 = x2; x2 = tt; }
+      u1 = true;
+      u2 = true;
     }
   } else if (fabs(qb) > 0.0) {
-    cr[nc++] = -qc / qb;
+    x1 = -qc / qb;
+    u1 = true;
   }
-  for (int i = 0; i < nc; ++i)
-    if (cr[i] > lo && cr[i] < hi) pts[np++] = cr[i];
-  pts[np++] = hi;
-  int nr = 0;
-  for (int i = 0; i + 1 < np; ++i) {
-    double a = pts[i], b = pts[i + 1];
+  u1 = u1 && x1 > lo && x1 < hi;
+  u2 = u2 && x2 > lo && x2 < hi;
+  double a0 = lo;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const bool use = t == 0 ? u1 : (t == 1 ? u2 : true);
+    if (!use) continue;
+    const double b0 = t == 0 ? x1 : (t == 1 ? x2 : hi);
+    double a = a0, b = b0;
+    a0 = b0;
     double fa = ((c3 * a + c2) * a + c1) * a + c0;
-    double fb = ((c3 * b + c2) * b + c1) * b + c0;
-    if (fa == 0.0) { r[nr++] = a; continue; }
-    if (fb == 0.0 && i + 2 == np) { r[nr++] = b; continue; }
+    const double fb = ((c3 * b + c2) * b + c1) * b + c0;
+    if (fa == 0.0) { emit(a); continue; }
+    if (fb == 0.0 && t == 2) { emit(b); continue; }
     if ((fa < 0.0) == (fb < 0.0)) continue;
     for (int it = 0; it < 200; ++it) {
       const double m = 0.5 * (a + b);
@@ -231,9 +237,8 @@ __device__ inline int cubic_roots_in(double c0, double c1, double c2, double c3,
       if (fm == 0.0) { a = b = m; break; }
       if ((fm < 0.0) == (fa < 0.0)) { a = m; fa = fm; } else { b = m; }
     }
-    r[nr++] = 0.5 * (a + b);
+    emit(0.5 * (a + b));
   }
-  return nr;
 }
 
 // Eigenvector of symmetric M for eigenvalue s: the longest cross product of
@@ -279,17 +284,37 @@ __device__ inline void polish_depths(double l[3], double a12, double a13, double
   }
 }
 
-// y: unit bearings (row per point), x: world points.  Returns the number of
-// solutions (<= 4) written to out, in canonical order (camera depth of point
-// 0 ascending, then of point 1).
-__device__ inline int p3p_pencil(const double y[3][3], const double x[3][3], Pose out[4]) {
+// Depths of the P3P solutions: at most four, one per (line, intersection)
+// slot, held in fixed slots so that no array is indexed at run time.
+struct P3PDepths {
+  double l[4][3];
+  int n;  // solutions; slots [0, n) hold them in canonical order
+};
+
+// Conditional exchange of two depth slots, ordered by (camera depth of point
+// 0, camera depth of point 1, slot); invalid slots sort last.
+__device__ inline void p3p_order(double la[3], double& ka0, double& ka1, int& ia, double lb[3], double& kb0,
+                                 double& kb1, int& ib) {
+  const bool sw = kb0 < ka0 || (kb0 == ka0 && (kb1 < ka1 || (kb1 == ka1 && ib < ia)));
+  if (!sw) return;
+  for (int c = 0; c < 3; ++c) { const double t = la[c]; la[c] = lb[c]; lb[c] = t; }
+  double t = ka0; ka0 = kb0; kb0 = t;
+  t = ka1; ka1 = kb1; kb1 = t;
+  const int ti = ia; ia = ib; ib = ti;
+}
+
+// y: unit bearings (row per point), x: world points.  Fills the solution
+// depths (all > 0, deduplicated) in canonical order: camera depth of point 0
+// ascending, then of point 1.
+__device__ inline void p3p_pencil(const double y[3][3], const double x[3][3], P3PDepths& out) {
+  out.n = 0;
   double d12[3], d13[3], d23[3];
   for (int k = 0; k < 3; ++k) { d12[k] = x[0][k] - x[1][k]; d13[k] = x[0][k] - x[2][k]; d23[k] = x[1][k] - x[2][k]; }
   const double a12 = dot3(d12, d12), a13 = dot3(d13, d13), a23 = dot3(d23, d23);
   double crs[3];
   cross3(d12, d13, crs);
-  if (!(a12 > 0.0 && a13 > 0.0 && a23 > 0.0)) return 0;
-  if (!(sqrt(dot3(crs, crs)) > 1e-9 * (a12 + a13 + a23))) return 0;
+  if (!(a12 > 0.0 && a13 > 0.0 && a23 > 0.0)) return;
+  if (!(sqrt(dot3(crs, crs)) > 1e-9 * (a12 + a13 + a23))) return;
   const double b12 = -dot3(y[0], y[1]), b13 = -dot3(y[0], y[2]), b23 = -dot3(y[1], y[2]);
   const double r12 = a12 / a23, r13 = a13 / a23;
   const double D1[9] = {1.0, b12, 0.0, b12, 1.0 - r12, -r12 * b23, 0.0, -r12 * b23, -r12};
@@ -299,41 +324,34 @@ __device__ inline int p3p_pencil(const double y[3][3], const double x[3][3], Pos
   adj3(D2, A2);
   const double c0 = det3(D1), c1 = trace_prod(A1, D2), c2 = trace_prod(D1, A2), c3 = det3(D2);
 
-  // degenerate pencil members: D1 + g D2 for |g| <= 1, e D1 + D2 for |e| < 1
-  double roots[6];
-  int from_f[6];
-  int nr = 0;
-  double rr[3];
-  int k = cubic_roots_in(c0, c1, c2, c3, -1.0, 1.0, rr);
-  for (int i = 0; i < k; ++i) { roots[nr] = rr[i]; from_f[nr++] = 1; }
-  k = cubic_roots_in(c3, c2, c1, c0, -1.0, 1.0, rr);
-  for (int i = 0; i < k; ++i)
-    if (fabs(rr[i]) < 1.0) { roots[nr] = rr[i]; from_f[nr++] = 0; }
-
+  // degenerate pencil members: D1 + g D2 for |g| <= 1, e D1 + D2 for |e| < 1;
+  // keep the first one of best quality -S / (T^2 - 2 S)
   double D0[9];
   double best_q = 0.0, bestT = 0.0, bestS = 0.0;
-  int best = -1;
-  for (int i = 0; i < nr; ++i) {
+  bool have = false, best_f = true;
+  auto consider = [&](double root, bool from_f) {
     double M[9], mx = 0.0;
     for (int e = 0; e < 9; ++e) {
-      M[e] = from_f[i] ? D1[e] + roots[i] * D2[e] : roots[i] * D1[e] + D2[e];
+      M[e] = from_f ? D1[e] + root * D2[e] : root * D1[e] + D2[e];
       mx = fmax(mx, fabs(M[e]));
     }
-    if (!(mx > 0.0)) continue;
+    if (!(mx > 0.0)) return;
     for (int e = 0; e < 9; ++e) M[e] /= mx;
     const double T = M[0] + M[4] + M[8];
     const double S = (M[0] * M[4] - M[1] * M[3]) + (M[0] * M[8] - M[2] * M[6]) + (M[4] * M[8] - M[5] * M[7]);
     const double den = T * T - 2.0 * S;
-    if (!(den > 0.0)) continue;
+    if (!(den > 0.0)) return;
     const double q = -S / den;
     if (q > best_q) {
-      best_q = q; best = i; bestT = T; bestS = S;
+      best_q = q; have = true; best_f = from_f; bestT = T; bestS = S;
       for (int e = 0; e < 9; ++e) D0[e] = M[e];
     }
-  }
-  if (best < 0) return 0;
+  };
+  cubic_roots_in(c0, c1, c2, c3, -1.0, 1.0, [&](double r) { consider(r, true); });
+  cubic_roots_in(c3, c2, c1, c0, -1.0, 1.0, [&](double r) { if (fabs(r) < 1.0) consider(r, false); });
+  if (!have) return;
   // conic restricted to the lines: the pencil member farthest from D0
-  const double* Q = from_f[best] ? D2 : D1;
+  const double* Q = best_f ? D2 : D1;
   const double half = 0.5 * bestT, disc = sqrt(half * half - bestS);
   const double s1 = half + disc, s2 = half - disc;  // s1 > 0 > s2
   double e1[3], e2[3], e3[3];
@@ -342,9 +360,21 @@ __device__ inline int p3p_pencil(const double y[3][3], const double x[3][3], Pos
   cross3(e1, e2, e3);
   const double w1 = sqrt(s1), w2 = sqrt(-s2);
 
-  double lam[4][3];
-  int nl = 0;
-  for (int sgn = -1; sgn <= 1; sgn += 2) {
+  // slot 2 * line + intersection; key0/key1 = camera depths of points 0 and 1
+  double k0[4], k1[4];
+  int id[4];
+  bool ok[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    ok[t] = false;
+    id[t] = t;
+    k0[t] = __builtin_inf();
+    k1[t] = __builtin_inf();
+    out.l[t][0] = out.l[t][1] = out.l[t][2] = 0.0;
+  }
+#pragma unroll
+  for (int line = 0; line < 2; ++line) {
+    const double sgn = line == 0 ? -1.0 : 1.0;
     double nrm[3], m[3];
     for (int c = 0; c < 3; ++c) nrm[c] = w1 * e1[c] + sgn * w2 * e2[c];
     cross3(nrm, e3, m);
@@ -370,7 +400,9 @@ __device__ inline int p3p_pencil(const double y[3][3], const double x[3][3], Pos
     } else {
       for (int c = 0; c < 3; ++c) { dirs[0][c] = e3[c]; dirs[1][c] = m[c]; }
     }
+#pragma unroll
     for (int d = 0; d < 2; ++d) {
+      const int t = 2 * line + d;
       const double* v = dirs[d];
       const double s23 = v[1] * v[1] + v[2] * v[2] + 2.0 * b23 * v[1] * v[2];
       if (!(s23 > 0.0)) continue;
@@ -383,67 +415,67 @@ __device__ inline int p3p_pencil(const double y[3][3], const double x[3][3], Pos
       const double F1 = l[0] * l[0] + l[2] * l[2] + 2.0 * b13 * l[0] * l[2] - a13;
       const double F2 = l[1] * l[1] + l[2] * l[2] + 2.0 * b23 * l[1] * l[2] - a23;
       if (!(fabs(F0) + fabs(F1) + fabs(F2) < 1e-6 * (a12 + a13 + a23))) continue;
+      // a duplicate of an earlier accepted slot is dropped
       bool dup = false;
-      for (int e = 0; e < nl; ++e) {
-        const double dl = fabs(lam[e][0] - l[0]) + fabs(lam[e][1] - l[1]) + fabs(lam[e][2] - l[2]);
-        if (dl <= 1e-9 * (l[0] + l[1] + l[2])) dup = true;
+#pragma unroll
+      for (int e = 0; e < t; ++e) {
+        const double dl = fabs(out.l[e][0] - l[0]) + fabs(out.l[e][1] - l[1]) + fabs(out.l[e][2] - l[2]);
+        if (ok[e] && dl <= 1e-9 * (l[0] + l[1] + l[2])) dup = true;
       }
-      if (dup || nl >= 4) continue;
-      lam[nl][0] = l[0]; lam[nl][1] = l[1]; lam[nl][2] = l[2];
-      ++nl;
+      if (dup) continue;
+      ok[t] = true;
+      out.l[t][0] = l[0]; out.l[t][1] = l[1]; out.l[t][2] = l[2];
+      k0[t] = l[0] * y[0][2];
+      k1[t] = l[1] * y[1][2];
     }
   }
+  out.n = (int)ok[0] + (int)ok[1] + (int)ok[2] + (int)ok[3];
+  // four-input sorting network; ties (never between distinct solutions in
+  // practice) keep the slot order
+  p3p_order(out.l[0], k0[0], k1[0], id[0], out.l[1], k0[1], k1[1], id[1]);
+  p3p_order(out.l[2], k0[2], k1[2], id[2], out.l[3], k0[3], k1[3], id[3]);
+  p3p_order(out.l[0], k0[0], k1[0], id[0], out.l[2], k0[2], k1[2], id[2]);
+  p3p_order(out.l[1], k0[1], k1[1], id[1], out.l[3], k0[3], k1[3], id[3]);
+  p3p_order(out.l[1], k0[1], k1[1], id[1], out.l[2], k0[2], k1[2], id[2]);
+}
 
-  // poses: R maps the world triangle frame [d12, d13, d12 x d13] onto the camera one
+// Pose of one P3P solution: R maps the world triangle frame
+// [x1 - x2, x1 - x3, (x1 - x2) x (x1 - x3)] onto the camera one (one
+// Newton-Schulz step towards the nearest rotation), t = l1 y1 - R x1.
+__device__ inline void p3p_pose(const double l[3], const double y[3][3], const double x[3][3], Pose& P) {
+  double d12[3], d13[3], crs[3];
+  for (int k = 0; k < 3; ++k) { d12[k] = x[0][k] - x[1][k]; d13[k] = x[0][k] - x[2][k]; }
+  cross3(d12, d13, crs);
   double X[9];
   for (int r = 0; r < 3; ++r) { X[3 * r] = d12[r]; X[3 * r + 1] = d13[r]; X[3 * r + 2] = crs[r]; }
   double Xa[9];
   adj3(X, Xa);
   const double Xdet = det3(X);
-  int ns = 0;
-  for (int s = 0; s < nl; ++s) {
-    double z[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int c = 0; c < 3; ++c) z[i][c] = lam[s][i] * y[i][c];
-    double e12[3], e13[3], ec[3];
-    for (int c = 0; c < 3; ++c) { e12[c] = z[0][c] - z[1][c]; e13[c] = z[0][c] - z[2][c]; }
-    cross3(e12, e13, ec);
-    double Y[9];
-    for (int r = 0; r < 3; ++r) { Y[3 * r] = e12[r]; Y[3 * r + 1] = e13[r]; Y[3 * r + 2] = ec[r]; }
-    Pose P;
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c)
-        P.R[3 * r + c] = (Y[3 * r] * Xa[c] + Y[3 * r + 1] * Xa[3 + c] + Y[3 * r + 2] * Xa[6 + c]) / Xdet;
-    // one Newton-Schulz step towards the nearest rotation: R <- R (3 I - R^T R) / 2
-    double RtR[9], Rn[9];
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c)
-        RtR[3 * r + c] = P.R[r] * P.R[c] + P.R[3 + r] * P.R[3 + c] + P.R[6 + r] * P.R[6 + c];
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) {
-        double s2 = 0.0;
-        for (int m = 0; m < 3; ++m) s2 += P.R[3 * r + m] * ((m == c ? 3.0 : 0.0) - RtR[3 * m + c]);
-        Rn[3 * r + c] = 0.5 * s2;
-      }
-    for (int e = 0; e < 9; ++e) P.R[e] = Rn[e];
-    for (int r = 0; r < 3; ++r)
-      P.t[r] = z[0][r] - (P.R[3 * r] * x[0][0] + P.R[3 * r + 1] * x[0][1] + P.R[3 * r + 2] * x[0][2]);
-    out[ns++] = P;
-  }
-  // canonical order by (depth of point 0, depth of point 1) = (l1 y1_z, l2 y2_z)
-  double key0[4], key1[4];
-  for (int s = 0; s < ns; ++s) { key0[s] = lam[s][0] * y[0][2]; key1[s] = lam[s][1] * y[1][2]; }
-  for (int a = 1; a < ns; ++a) {
-    Pose kp = out[a];
-    const double ka = key0[a], kb = key1[a];
-    int b = a - 1;
-    while (b >= 0 && (key0[b] > ka || (key0[b] == ka && key1[b] > kb))) {
-      out[b + 1] = out[b]; key0[b + 1] = key0[b]; key1[b + 1] = key1[b];
-      --b;
+  double z[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int c = 0; c < 3; ++c) z[i][c] = l[i] * y[i][c];
+  double e12[3], e13[3], ec[3];
+  for (int c = 0; c < 3; ++c) { e12[c] = z[0][c] - z[1][c]; e13[c] = z[0][c] - z[2][c]; }
+  cross3(e12, e13, ec);
+  double Y[9];
+  for (int r = 0; r < 3; ++r) { Y[3 * r] = e12[r]; Y[3 * r + 1] = e13[r]; Y[3 * r + 2] = ec[r]; }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      P.R[3 * r + c] = (Y[3 * r] * Xa[c] + Y[3 * r + 1] * Xa[3 + c] + Y[3 * r + 2] * Xa[6 + c]) / Xdet;
+  // R <- R (3 I - R^T R) / 2
+  double RtR[9], Rn[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      RtR[3 * r + c] = P.R[r] * P.R[c] + P.R[3 + r] * P.R[3 + c] + P.R[6 + r] * P.R[6 + c];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s2 = 0.0;
+      for (int m = 0; m < 3; ++m) s2 += P.R[3 * r + m] * ((m == c ? 3.0 : 0.0) - RtR[3 * m + c]);
+      Rn[3 * r + c] = 0.5 * s2;
     }
-    out[b + 1] = kp; key0[b + 1] = ka; key1[b + 1] = kb;
-  }
-  return ns;
+  for (int e = 0; e < 9; ++e) P.R[e] = Rn[e];
+  for (int r = 0; r < 3; ++r)
+    P.t[r] = z[0][r] - (P.R[3 * r] * x[0][0] + P.R[3 * r + 1] * x[0][1] + P.R[3 * r + 2] * x[0][2]);
 }
 
 // Folded projection P = K [R | t] rows (a, b, w) = P [X, 1].

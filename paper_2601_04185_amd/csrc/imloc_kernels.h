@@ -87,7 +87,8 @@ struct LiftArgs {
   const float *q_u, *q_v, *db_u, *db_v, *conf;
   const int32_t* view;
   int64_t n;
-  const float* depth;
+  const float* depth;     // float32 maps, or
+  const uint8_t* codes;   // 8-bit log-depth code maps (exactly one is set)
   int32_t n_views, H, W;
   const double* cams;   // device [n_views][4]
   const double* poses;  // device [n_views][12]
@@ -101,6 +102,8 @@ struct LiftArgs {
 };
 int lift_blocks(int64_t n);
 hipError_t launch_lift(const LiftArgs& a, hipStream_t s);
+// 8-bit log-depth codes of n float32 depths (depth and codes 16- and 4-byte aligned)
+hipError_t launch_log8_encode(const float* depth, int64_t n, uint8_t* codes, hipStream_t s);
 
 // --- small utilities ---------------------------------------------------------
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -141,8 +144,10 @@ hipError_t launch_candidate_costs(const QueryDesc* qd, const BestState* st, Cand
                                   double* msac, hipStream_t s);
 
 // --- selection / local optimisation / refinement ------------------------------
-hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int kmax, int32_t* sel,
-                         int32_t* n_sel, hipStream_t s);
+// scratch: select_scratch_bytes(nq); max_cap bounds the queries' candidate slots
+size_t select_scratch_bytes(int nq);
+hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int kmax, int64_t max_cap,
+                         void* scratch, int32_t* sel, int32_t* n_sel, hipStream_t s);
 
 // Gauss-Newton problems.  LO: problem p = q * kmax + slot starts from the
 // candidate sel[q * kMaxTopK + slot] (or from start_direct[p] when given, all

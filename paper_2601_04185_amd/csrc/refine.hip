@@ -63,18 +63,61 @@ size_t gn_scratch_bytes(int nprob, int chunks_max) {
          (size_t)2 * nprob * chunks_max * kAcc * sizeof(double) + 256;
 }
 
-// Solve from the reduced sums in LDS; thread 0 only.  Returns false if the
-// normal matrix is not positive definite.
-__device__ bool gn_solve_step(const double* tot, const double* cur, double* next) {
-  double b[6], d[6];
-  for (int r = 0; r < 6; ++r) b[r] = -tot[21 + r];
-  if (!chol6_solve_packed(tot, b, d)) return false;
-  Pose P, O;
-  for (int e = 0; e < 9; ++e) P.R[e] = cur[e];
-  for (int e = 0; e < 3; ++e) P.t[e] = cur[9 + e];
-  pose_left_update(P, d, O);
-  for (int e = 0; e < 9; ++e) next[e] = O.R[e];
-  for (int e = 0; e < 3; ++e) next[9 + e] = O.t[e];
+// Packed row-wise index of (r, c), r <= c, in the 21-entry upper triangle.
+__host__ __device__ constexpr int upk(int r, int c) { return r * 6 - (r * (r - 1)) / 2 + (c - r); }
+
+// Solve from the reduced sums (LDS); thread 0 only.  Cholesky H = U^T U in
+// place on the packed upper triangle, then U^T y = -g, U d = y, and the left
+// update.  Every loop has constant bounds and is unrolled, so the factor, the
+// vectors and the rotation stay in registers (about 100 VGPRs, below what the
+// accumulation path needs).  Returns false if H is not positive definite.
+__device__ __forceinline__ bool gn_solve_step(const double* tot, const double* cur, double* next) {
+  double h[21];
+#pragma unroll
+  for (int e = 0; e < 21; ++e) h[e] = tot[e];
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double dsum = h[upk(i, i)];
+#pragma unroll
+    for (int m = 0; m < i; ++m) dsum -= h[upk(m, i)] * h[upk(m, i)];
+    ok = ok && dsum > 0.0;
+    const double uii = sqrt(fmax(dsum, 0.0));
+    h[upk(i, i)] = uii;
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j) {
+      double sum = h[upk(i, j)];
+#pragma unroll
+      for (int m = 0; m < i; ++m) sum -= h[upk(m, i)] * h[upk(m, j)];
+      h[upk(i, j)] = sum / uii;
+    }
+  }
+  if (!ok) return false;
+  double y[6], d[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double sum = -tot[21 + i];
+#pragma unroll
+    for (int m = 0; m < i; ++m) sum -= h[upk(m, i)] * y[m];
+    y[i] = sum / h[upk(i, i)];
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    double sum = y[i];
+#pragma unroll
+    for (int m = i + 1; m < 6; ++m) sum -= h[upk(i, m)] * d[m];
+    d[i] = sum / h[upk(i, i)];
+  }
+  // left update: R' = Exp(dw) R, t' = Exp(dw) t + dt
+  double E[9];
+  so3_exp(d, E);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      next[3 * r + c] = E[3 * r] * cur[c] + E[3 * r + 1] * cur[3 + c] + E[3 * r + 2] * cur[6 + c];
+    next[9 + r] = E[3 * r] * cur[9] + E[3 * r + 1] * cur[10] + E[3 * r + 2] * cur[11] + d[3 + r];
+  }
   return true;
 }
 
@@ -147,8 +190,19 @@ __global__ __launch_bounds__(kGNThreads) void gn_kernel(
     const int v = threadIdx.x % kAcc, g = threadIdx.x / kAcc;
     const bool prev_done = prev->done != 0;
     if (!prev_done && g < 8) {
+      // chunks g, g + 8, ...: loaded four at a time, summed in chunk order
       double sum = 0.0;
-      for (int ch = g; ch < chunks; ch += 8) sum += part_prev[(int64_t)ch * kAcc + v];
+      for (int ch0 = g; ch0 < chunks; ch0 += 32) {
+        double t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ch = ch0 + 8 * u;
+          t[u] = ch < chunks ? part_prev[(int64_t)ch * kAcc + v] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (ch0 + 8 * u < chunks) sum += t[u];
+      }
       s_grp[g][v] = sum;
     }
     if (threadIdx.x < 12) {
@@ -209,20 +263,36 @@ __global__ __launch_bounds__(kGNThreads) void gn_kernel(
 #pragma unroll
   for (int e = 0; e < kAcc; ++e) a[e] = 0.0;
   const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
+  // all loads of the thread's points first (one memory latency, not kGNPPT)
+  float pX[kGNPPT], pY[kGNPPT], pZ[kGNPPT], pu[kGNPPT], pv[kGNPPT], pw[kGNPPT];
+  bool use[kGNPPT];
+#pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
     const int64_t i = base + (int64_t)t * kGNThreads;
-    if (i >= n) break;
-    if (MODE == 1 && k > 0 && !in_set[i]) continue;
-    const double X = gmem(c.X)[i], Y = gmem(c.Y)[i], Z = gmem(c.Z)[i];
-    const double w = c.w ? (double)gmem(c.w)[i] : 1.0;
+    use[t] = i < n;
+    const int64_t ii = use[t] ? i : 0;
+    if (MODE == 1 && k > 0) use[t] = use[t] && in_set[ii] != 0;
+    pX[t] = gmem(c.X)[ii];
+    pY[t] = gmem(c.Y)[ii];
+    pZ[t] = gmem(c.Z)[ii];
+    pu[t] = gmem(c.u)[ii];
+    pv[t] = gmem(c.v)[ii];
+    pw[t] = c.w ? gmem(c.w)[ii] : 1.0f;
+  }
+#pragma unroll
+  for (int t = 0; t < kGNPPT; ++t) {
+    if (!use[t]) continue;
+    const int64_t i = base + (int64_t)t * kGNThreads;
+    const double X = pX[t], Y = pY[t], Z = pZ[t];
+    const double w = pw[t];
     const double x = P[0] * X + P[1] * Y + P[2] * Z + P[9];
     const double y = P[3] * X + P[4] * Y + P[5] * Z + P[10];
     const double z = P[6] * X + P[7] * Y + P[8] * Z + P[11];
     double du = 0.0, dv = 0.0, r2 = 0.0;
     const bool front = z > 0.0;
     if (front) {
-      du = K.fx * x / z + K.cx - (double)gmem(c.u)[i];
-      dv = K.fy * y / z + K.cy - (double)gmem(c.v)[i];
+      du = K.fx * x / z + K.cx - (double)pu[t];
+      dv = K.fy * y / z + K.cy - (double)pv[t];
       r2 = du * du + dv * dv;
     }
     if (MODE == 0) {

@@ -144,6 +144,7 @@ struct Engine {
   int32_t* active_count;
   int32_t* sel;
   int32_t* n_sel;
+  void* sel_part;
   double* lo_pose;
   double* lo_cost;
   int64_t* lo_count;
@@ -200,6 +201,7 @@ void carve_engine(Arena& a, Engine& e) {
   e.active_count = a.take<int32_t>(1);
   e.sel = a.take<int32_t>((size_t)nq * kMaxTopK);
   e.n_sel = a.take<int32_t>(nq);
+  e.sel_part = a.take<char>(select_scratch_bytes(nq));
   e.lo_pose = a.take<double>((size_t)nq * e.kmax * 12);
   e.lo_cost = a.take<double>((size_t)nq * e.kmax);
   e.lo_count = a.take<int64_t>((size_t)nq * e.kmax);
@@ -370,7 +372,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, ctx->tune, 0, st_));
       tm.end(kStScore, e1);
       hipEvent_t e2 = tm.begin();
-      HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, e.kmax, e.sel, e.n_sel, st_));
+      HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, e.kmax, 4 * e.max_batch, e.sel_part, e.sel, e.n_sel, st_));
       tm.end(kStSelect, e2);
       hipEvent_t e3 = tm.begin();
       HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * e.kmax, e.kmax, e.chunks_lo, e.lo_iters,
@@ -571,7 +573,8 @@ int imloc_create(imloc_ctx** out, int device, void* hip_stream) {
   }
   int cus = 256;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-  c->tune.blocks = 8 * (cus > 0 ? cus : 256);
+  c->tune.ct = 128;
+  c->tune.blocks = 16 * (cus > 0 ? cus : 256);
   *out = c;
   return IMLOC_OK;
 }
@@ -693,16 +696,17 @@ size_t imloc_lift_workspace_bytes(int64_t n_matches, int32_t n_views) {
   return a.off + 256;
 }
 
-int imloc_lift(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, const float* depth, int32_t n_views,
-               int32_t H, int32_t W, const imloc_camera* cams, const imloc_pose* poses, int32_t subpixel,
-               float min_conf, const imloc_corr_out* out, int64_t capacity, int32_t* n_out) {
+static int lift_impl(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, const float* depth,
+                     const uint8_t* codes, int32_t n_views, int32_t H, int32_t W, const imloc_camera* cams,
+                     const imloc_pose* poses, int32_t subpixel, float min_conf, const imloc_corr_out* out,
+                     int64_t capacity, int32_t* n_out) {
   if (!ctx) return IMLOC_EINVAL;
   if (n_matches < 0 || n_matches > INT32_MAX) return set_err(ctx, IMLOC_EINVAL, "n_matches out of range");
   if (!n_out || !out) return set_err(ctx, IMLOC_EINVAL, "null output");
   if (n_matches > 0) {
     if (!m || !m->q_u || !m->q_v || !m->db_u || !m->db_v || !m->conf || !m->view)
       return set_err(ctx, IMLOC_EINVAL, "null match array");
-    if (!depth || n_views <= 0 || H < 2 || W < 2 || !cams || !poses)
+    if ((!depth && !codes) || n_views <= 0 || H < 2 || W < 2 || !cams || !poses)
       return set_err(ctx, IMLOC_EINVAL, "bad depth maps / views");
     if ((int64_t)n_views * H * W > ((int64_t)1 << 40)) return set_err(ctx, IMLOC_EINVAL, "depth maps too large");
     if (capacity < 0 || (capacity > 0 && (!out->u || !out->v || !out->X || !out->Y || !out->Z)))
@@ -734,11 +738,34 @@ int imloc_lift(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, const 
   LiftArgs la;
   la.q_u = m ? m->q_u : nullptr; la.q_v = m ? m->q_v : nullptr; la.db_u = m ? m->db_u : nullptr;
   la.db_v = m ? m->db_v : nullptr; la.conf = m ? m->conf : nullptr; la.view = m ? m->view : nullptr;
-  la.n = n_matches; la.depth = depth; la.n_views = n_views; la.H = H; la.W = W;
+  la.n = n_matches; la.depth = depth; la.codes = codes; la.n_views = n_views; la.H = H; la.W = W;
   la.cams = dcams; la.poses = dposes; la.subpixel = subpixel; la.min_conf = min_conf;
   la.out_u = out->u; la.out_v = out->v; la.out_X = out->X; la.out_Y = out->Y; la.out_Z = out->Z;
   la.out_w = out->w; la.out_src = out->src; la.capacity = capacity; la.n_out = n_out; la.block_counts = blk;
   HIP_TRY(ctx, launch_lift(la, ctx->stream));
+  return IMLOC_OK;
+}
+
+int imloc_lift(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, const float* depth, int32_t n_views,
+               int32_t H, int32_t W, const imloc_camera* cams, const imloc_pose* poses, int32_t subpixel,
+               float min_conf, const imloc_corr_out* out, int64_t capacity, int32_t* n_out) {
+  return lift_impl(ctx, m, n_matches, depth, nullptr, n_views, H, W, cams, poses, subpixel, min_conf, out, capacity,
+                   n_out);
+}
+
+int imloc_lift_log8(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, const uint8_t* codes,
+                    int32_t n_views, int32_t H, int32_t W, const imloc_camera* cams, const imloc_pose* poses,
+                    int32_t subpixel, float min_conf, const imloc_corr_out* out, int64_t capacity, int32_t* n_out) {
+  return lift_impl(ctx, m, n_matches, nullptr, codes, n_views, H, W, cams, poses, subpixel, min_conf, out, capacity,
+                   n_out);
+}
+
+int imloc_depth_encode_log8(imloc_ctx* ctx, const float* depth, int64_t count, uint8_t* codes) {
+  if (!ctx) return IMLOC_EINVAL;
+  if (count < 0 || count > ((int64_t)1 << 40)) return set_err(ctx, IMLOC_EINVAL, "count out of range");
+  if (count > 0 && (!depth || !codes)) return set_err(ctx, IMLOC_EINVAL, "null depth or code array");
+  hipSetDevice(ctx->device);
+  HIP_TRY(ctx, launch_log8_encode(depth, count, codes, ctx->stream));
   return IMLOC_OK;
 }
 
@@ -1149,7 +1176,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, max_batch, nullptr, s));
     HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, ctx->tune.ct, e.item_off, s));
     HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, ctx->tune, 0, s));
-    HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, e.sel, e.n_sel, s));
+    HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, 4 * max_batch, e.sel_part, e.sel, e.n_sel, s));
     HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * kmax, kmax, chunks_lo, lo_iters, e.gn_lo,
                            e.lo_pose, e.lo_cost, e.lo_count, s));
     HIP_TRY(ctx, launch_update_best(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, kmax, e.st, s));

@@ -21,8 +21,9 @@ __global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* 
   const int64_t s = s0 + threadIdx.x;
   const int64_t h0 = st[q].drawn;
   const Cam K{d.fx, d.fy, d.cx, d.cy};
-  Pose sol[4];
-  int ns = 0;
+  P3PDepths sol;
+  sol.n = 0;
+  double y[3][3], x[3][3];
   if (s < count) {
     const uint64_t h = (uint64_t)(h0 + s);
     int idx[3] = {-1, -1, -1};
@@ -34,7 +35,6 @@ __global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* 
       triples[3 * s + 2] = ok ? idx[2] : -1;
     }
     if (ok) {
-      double y[3][3], x[3][3];
       for (int k = 0; k < 3; ++k) {
         const int i = idx[k];
         const double bx = ((double)d.S.u[i] - K.cx) / K.fx, by = ((double)d.S.v[i] - K.cy) / K.fy;
@@ -42,9 +42,10 @@ __global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* 
         y[k][0] = bx * inv; y[k][1] = by * inv; y[k][2] = inv;
         x[k][0] = d.S.X[i]; x[k][1] = d.S.Y[i]; x[k][2] = d.S.Z[i];
       }
-      ns = p3p_pencil(y, x, sol);
+      p3p_pencil(y, x, sol);
     }
   }
+  const int ns = sol.n;
   // workgroup-wide exclusive scan of the solution counts (sample order inside
   // the workgroup; workgroups append in completion order -- the order of the
   // candidates never enters a result)
@@ -66,10 +67,12 @@ __global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* 
   for (int j = 0; j < 4; ++j) {
     if (j >= ns) break;
     const int64_t o = d.cand_off + base + j;
-    for (int e = 0; e < 9; ++e) cb.pose[12 * o + e] = sol[j].R[e];
-    for (int e = 0; e < 3; ++e) cb.pose[12 * o + 9 + e] = sol[j].t[e];
+    Pose P;
+    p3p_pose(sol.l[j], y, x, P);
+    for (int e = 0; e < 9; ++e) cb.pose[12 * o + e] = P.R[e];
+    for (int e = 0; e < 3; ++e) cb.pose[12 * o + 9 + e] = P.t[e];
     double M[12];
-    projection_rows(sol[j], K, M);
+    projection_rows(P, K, M);
     float4* pr = reinterpret_cast<float4*>(cb.proj + 16 * o);
     pr[0] = make_float4((float)(M[0] * inv_tau), (float)(M[1] * inv_tau), (float)(M[2] * inv_tau),
                         (float)(M[3] * inv_tau));

@@ -344,90 +344,169 @@ __device__ inline Key shfl_key(const Key& k, int lane_xor) {
   return o;
 }
 
-constexpr int kSelBlock = 1024;
-constexpr int kSelWaves = kSelBlock / kWave;
-constexpr int kSelList = 8;    // per-thread list of the fast path
+constexpr int kSelList = 8;      // per-thread list of the fast path (k <= 8)
+constexpr int kSelUnroll = 4;    // candidates loaded together per thread
+constexpr int kSelThreads = 256;
+constexpr int kSelWaves = kSelThreads / kWave;
+constexpr int kSelGroups = 16;   // phase-1 workgroups per query, at most
+constexpr int kSelPerThread = 4; // phase-1 candidates per thread, about
 
 __device__ inline Key load_key(const QueryDesc& d, const BestState& b, const CandBuf& cb, int c) {
   const int64_t o = d.cand_off + c;
   return Key{cand_msac(d, b, cb.gain[o]), (long long)cb.h[o] * 4 + cb.j[o], (int)cb.cnt[o], c};
 }
 
-// Fast path (k <= 8): every thread keeps its best kSelList candidates sorted in
-// registers; then k rounds pick the smallest list head across the workgroup.
-__global__ __launch_bounds__(kSelBlock) void select_kernel(const QueryDesc* __restrict__ qd,
-                                                           BestState* __restrict__ st, CandBuf cb,
-                                                           int32_t* __restrict__ sel, int32_t* __restrict__ n_sel) {
+// Order-preserving 64-bit image of a double (total order of the non-NaN
+// values): equal images <=> equal values.
+__device__ inline unsigned long long ms_order(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// k rounds of "pop the smallest list head of the workgroup" over per-thread
+// sorted lists of L keys; round r writes its key to out[r] (a workgroup-wide
+// LDS array).  A round takes the minimum of the 64-bit image of msac over
+// each wave (12 lane exchanges); only when several lanes hold that same msac
+// do the full keys decide.  Returns the number of keys popped (< k when the
+// lists run dry).
+template <int L>
+__device__ int block_pop_k(Key (&list)[L], int k, Key* out) {
+  __shared__ Key s_key[kSelWaves];
+  __shared__ int s_lane[kSelWaves];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  int r = 0;
+  for (; r < k; ++r) {
+    const Key head = list[0];
+    const bool valid = head.idx >= 0;
+    const unsigned long long pr = valid ? ms_order(head.ms) : ~0ull;
+    unsigned long long m = pr;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const unsigned long long o = (unsigned long long)__shfl_xor((long long)m, off, kWave);
+      m = o < m ? o : m;
+    }
+    const unsigned long long tie = __ballot(valid && pr == m);
+    int wl = -1;
+    if (tie != 0) {
+      if (__popcll(tie) == 1) {
+        wl = __ffsll((long long)tie) - 1;
+      } else {
+        // several lanes share the smallest msac: full-key argmin among them
+        Key bk = ((tie >> lane) & 1ull) ? head : key_none();
+        int bl = ((tie >> lane) & 1ull) ? lane : -1;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          const Key o = shfl_key(bk, off);
+          const int ol = __shfl_xor(bl, off, kWave);
+          if (ol >= 0 && (bl < 0 || key_less(o, bk))) { bk = o; bl = ol; }
+        }
+        wl = bl;
+      }
+    }
+    if (lane == (wl < 0 ? 0 : wl)) {
+      s_key[wave] = wl < 0 ? key_none() : head;
+      s_lane[wave] = wl;
+    }
+    __syncthreads();
+    int bw = -1;
+#pragma unroll
+    for (int w = 0; w < kSelWaves; ++w)
+      if (s_lane[w] >= 0 && (bw < 0 || key_less(s_key[w], s_key[bw]))) bw = w;
+    if (bw < 0) break;  // uniform: every thread read the same table
+    if (threadIdx.x == 0) out[r] = s_key[bw];
+    if (wave == bw && lane == s_lane[bw]) {
+#pragma unroll
+      for (int e = 0; e + 1 < L; ++e) list[e] = list[e + 1];
+      list[L - 1] = key_none();
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  return r;
+}
+
+__device__ inline void list_insert(Key (&list)[kSelList], Key x) {
+  if (!key_less(x, list[kSelList - 1])) return;
+  // sorted insertion as a compare-and-swap pass (static register indices)
+#pragma unroll
+  for (int e = 0; e < kSelList; ++e) {
+    if (key_less(x, list[e])) {
+      const Key t = list[e];
+      list[e] = x;
+      x = t;
+    }
+  }
+}
+
+__host__ __device__ inline int select_groups(int64_t n_cand) {
+  const int64_t g = (n_cand + kSelThreads * kSelPerThread - 1) / (kSelThreads * kSelPerThread);
+  return g < 1 ? 1 : (g > kSelGroups ? kSelGroups : (int)g);
+}
+
+// Phase 1 (k <= 8): workgroup b of a query scans candidates b * 256 + t + j *
+// G * 256, every thread keeps its best kSelList in registers, and the
+// workgroup's top k go to part[q][b][0..k) (key_none() past the end).
+__global__ __launch_bounds__(kSelThreads) void select_partial_kernel(const QueryDesc* __restrict__ qd,
+                                                                     const BestState* __restrict__ st, CandBuf cb,
+                                                                     Key* __restrict__ part) {
+  const int q = blockIdx.y, b = blockIdx.x;
+  const QueryDesc& d = qd[q];
+  if (d.B <= 0) return;
+  const int nc = cb.n[q];
+  const int G = select_groups(d.cap);
+  if (b >= G) return;
+  const BestState& bs = st[q];
+  const double gate = bs.cost;
+  Key list[kSelList];
+#pragma unroll
+  for (int e = 0; e < kSelList; ++e) list[e] = key_none();
+  const int stride = G * kSelThreads;
+  for (int c0 = b * kSelThreads + threadIdx.x; c0 < nc; c0 += kSelUnroll * stride) {
+    Key xs[kSelUnroll];
+#pragma unroll
+    for (int u = 0; u < kSelUnroll; ++u) {
+      const int c = c0 + u * stride;
+      xs[u] = c < nc ? load_key(d, bs, cb, c) : key_none();
+    }
+#pragma unroll
+    for (int u = 0; u < kSelUnroll; ++u)
+      if (xs[u].idx >= 0 && xs[u].ms < gate) list_insert(list, xs[u]);
+  }
+  __shared__ Key s_out[kSelList];
+  const int got = block_pop_k<kSelList>(list, d.k, s_out);
+  if ((int)threadIdx.x < d.k) part[((int64_t)q * kSelGroups + b) * kSelList + threadIdx.x] =
+      (int)threadIdx.x < got ? s_out[threadIdx.x] : key_none();
+}
+
+// Phase 2: one workgroup per query merges the G * k phase-1 keys (one per
+// thread) into the query's top k.
+__global__ __launch_bounds__(kSelThreads) void select_merge_kernel(const QueryDesc* __restrict__ qd,
+                                                                   BestState* __restrict__ st, CandBuf cb,
+                                                                   const Key* __restrict__ part,
+                                                                   int32_t* __restrict__ sel,
+                                                                   int32_t* __restrict__ n_sel) {
   const int q = blockIdx.x;
   const QueryDesc& d = qd[q];
   if (d.B <= 0) {
     if (threadIdx.x == 0) n_sel[q] = 0;
     return;
   }
-  const int nc = cb.n[q];
+  const int G = select_groups(d.cap);
   const int k = d.k;
-  const BestState& b = st[q];
-  const double gate = b.cost;
-  Key list[kSelList];
-#pragma unroll
-  for (int e = 0; e < kSelList; ++e) list[e] = key_none();
-  for (int c = threadIdx.x; c < nc; c += kSelBlock) {
-    Key x = load_key(d, b, cb, c);
-    if (!(x.ms < gate)) continue;
-    if (!key_less(x, list[kSelList - 1])) continue;
-    // sorted insertion as a compare-and-swap pass (static register indices)
-#pragma unroll
-    for (int e = 0; e < kSelList; ++e) {
-      if (key_less(x, list[e])) {
-        const Key t = list[e];
-        list[e] = x;
-        x = t;
-      }
-    }
+  Key list[1];
+  const int t = threadIdx.x;
+  list[0] = t < G * k ? part[((int64_t)q * kSelGroups + t / k) * kSelList + t % k] : key_none();
+  __shared__ Key s_out[kSelList];
+  const int got = block_pop_k<1>(list, k, s_out);
+  if (t < got) sel[q * kMaxTopK + t] = s_out[t].idx;
+  if (t == 0) {
+    n_sel[q] = got;
+    st[q].candidates += cb.n[q];
   }
-  __shared__ Key s_w[kSelWaves];
-  __shared__ int s_wt[kSelWaves];
-  __shared__ int s_win_thread;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  int r = 0;
-  for (; r < k; ++r) {
-    Key best = list[0];  // the head; popped entries shift the list down
-    int best_thread = best.idx >= 0 ? (int)threadIdx.x : -1;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const Key o = shfl_key(best, off);
-      const int ot = __shfl_xor(best_thread, off, kWave);
-      if (ot >= 0 && (best_thread < 0 || key_less(o, best))) {
-        best = o;
-        best_thread = ot;
-      }
-    }
-    if (lane == 0) {
-      s_w[wave] = best;
-      s_wt[wave] = best_thread;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int bw = -1;
-      for (int w = 0; w < kSelWaves; ++w)
-        if (s_wt[w] >= 0 && (bw < 0 || key_less(s_w[w], s_w[bw]))) bw = w;
-      s_win_thread = bw < 0 ? -1 : s_wt[bw];
-      if (bw >= 0) sel[q * kMaxTopK + r] = s_w[bw].idx;
-    }
-    __syncthreads();
-    const int wt = s_win_thread;
-    __syncthreads();
-    if (wt < 0) break;
-    if ((int)threadIdx.x == wt) {
-#pragma unroll
-      for (int e = 0; e + 1 < kSelList; ++e) list[e] = list[e + 1];
-      list[kSelList - 1] = key_none();
-    }
-  }
-  if (threadIdx.x == 0) {
-    n_sel[q] = r;
-    st[q].candidates += nc;
-  }
+}
+
+size_t select_scratch_bytes(int nq) {
+  return (size_t)(nq > 0 ? nq : 1) * kSelGroups * kSelList * sizeof(Key);
 }
 
 // General path (k up to 32): k rounds of a workgroup argmin over all
@@ -479,11 +558,14 @@ __global__ __launch_bounds__(256) void select_rounds_kernel(const QueryDesc* __r
   }
 }
 
-hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int kmax, int32_t* sel,
-                         int32_t* n_sel, hipStream_t s) {
+hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int kmax, int64_t max_cap,
+                         void* scratch, int32_t* sel, int32_t* n_sel, hipStream_t s) {
   BestState* stw = const_cast<BestState*>(st);
   if (kmax <= kSelList) {
-    hipLaunchKernelGGL(select_kernel, dim3(nq), dim3(kSelBlock), 0, s, qd, stw, cb, sel, n_sel);
+    Key* part = reinterpret_cast<Key*>(scratch);
+    hipLaunchKernelGGL(select_partial_kernel, dim3(select_groups(max_cap), nq), dim3(kSelThreads), 0, s, qd, st, cb,
+                       part);
+    hipLaunchKernelGGL(select_merge_kernel, dim3(nq), dim3(kSelThreads), 0, s, qd, stw, cb, part, sel, n_sel);
   } else {
     hipLaunchKernelGGL(select_rounds_kernel, dim3(nq), dim3(256), 0, s, qd, stw, cb, sel, n_sel);
   }

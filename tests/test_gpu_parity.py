@@ -253,6 +253,22 @@ def test_ransac_subsample_and_weights(pk, ctx, orc):
     assert pose_close(R, t, ref["R"], ref["t"])[0]
 
 
+def test_ransac_paper_mode(pk, ctx, orc):
+    """The paper's own settings (Sec. 3.3 "Pose Estimation"): stride subsample
+    to at most 10,000 scoring points, batches of 1,000 minimal sets, local
+    optimisation of a new best, stop at 100,000 samples or when the chance of
+    missing the best model is below 1e-4, confidence-weighted costs, final
+    Cauchy refinement over the full set."""
+    q = synth.make_query(120, 50000, 0.25, 1.5, weights="conf", n_views=10)
+    rc, R, t, st, mask, ref = _run_both(pk, ctx, orc, q, threshold_px=6.0, batch=1000, min_iters=1000,
+                                        max_iters=100000, confidence=0.9999, max_score_points=10000, lo_top_k=1)
+    assert rc == 0 and ref["status"] == 0
+    assert st["samples"] == ref["samples"] and st["batches"] == ref["batches"]
+    assert st["residuals"] == ref["residuals"] == st["candidates"] * 10000
+    assert pose_close(R, t, ref["R"], ref["t"])[0]
+    assert np.degrees(rot_angle(R, q.R)) < 2.0 and np.linalg.norm(t - q.t) < 0.25
+
+
 @pytest.mark.parametrize("n", [0, 1, 2])
 def test_ransac_too_few_points(pk, ctx, orc, n):
     import torch
