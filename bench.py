@@ -58,18 +58,23 @@ def _file_hash(path):
 
 
 def _traffic(kernel_src, workload):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current source of the kernel and this workload."""
-    p = os.path.join(ROOT, "profiles", "score_f32_single_large_traffic.json")
+    """HBM bytes per launch from the committed counter summary (key: value
+    lines), if it was taken on the current source of the kernel and this
+    workload."""
+    p = os.path.join(ROOT, "profiles", "score_single_large_traffic.txt")
     if not os.path.exists(p):
         return None
-    try:
-        d = json.load(open(p))
-    except Exception:
-        return None
+    d = {}
+    for line in open(p):
+        if ":" in line and not line.startswith(("#", " ")):
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.strip()
     if d.get("workload") != workload or d.get("kernel_src_sha256_16") != _file_hash(kernel_src):
         return None
-    return d.get("hbm_bytes_per_launch")
+    try:
+        return float(d["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def _rot_deg(Ra, Rb):
@@ -306,6 +311,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default scoring launch shape")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="first run 3 plain device copies of MB MiB (a known-size reference for HBM counters)")
     ap.add_argument("--score-shape", default=None,
                     help="CT,WG: scoring launch shape (candidates per item, workgroups) instead of autotuning")
     ap.add_argument("--no-e2e", action="store_true", help="skip the lifting + RANSAC leg")
@@ -320,6 +327,14 @@ def main():
     import torch
     import paper_2601_04185_amd as pk
     from paper_2601_04185_amd import synth
+
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     wl = WORKLOADS[args.workload]
     q = getattr(synth, wl["make"])()
