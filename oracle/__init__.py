@@ -30,10 +30,10 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (plain C11 + OpenMP)."""
     if force or not os.path.exists(_SO):
-        src = os.path.join(_HERE, "imloc_oracle.c")
+        srcs = [os.path.join(_HERE, f) for f in ("imloc_oracle.c", "triangulate.c")]
         tmp = _SO + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-std=gnu11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-               "-Wno-unused-parameter", src, "-o", tmp, "-lm"]
+               "-Wno-unused-parameter", *srcs, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _SO)
     return _SO
@@ -97,6 +97,13 @@ def lib():
         L.orc_log8_encode.argtypes = [C.c_float]
         L.orc_log8_encode.restype = C.c_uint8
         L.orc_log8_encode_array.argtypes = [vp, i64, vp]
+        L.orc_triangulate.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_tri_angle.argtypes = [vp, vp, dbl, vp, vp]
+        L.orc_tri_angle.restype = dbl
+        L.orc_tri_hypothesis.argtypes = [vp, vp, vp, vp, vp]
+        L.orc_tri_hypothesis.restype = C.c_int
+        L.orc_tri_refine.argtypes = [vp, vp, dbl, C.c_int, vp, vp, vp, C.c_int]
+        L.orc_tri_refine.restype = dbl
         L.orc_normal_equations.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
         L.orc_normal_equations.restype = dbl
         L.orc_pose_update.argtypes = [vp, vp, vp]
@@ -313,3 +320,60 @@ def log8_encode(depth) -> np.ndarray:
     out = np.zeros(d.shape, np.uint8)
     lib().orc_log8_encode_array(_p(d), d.size, _p(out))
     return out
+
+
+class TriParams(C.Structure):
+    _fields_ = [("min_conf", C.c_double), ("angle_deg", C.c_double), ("min_inliers", C.c_int32),
+                ("max_refine_iters", C.c_int32)]
+
+
+def _cams(Ks):
+    Ks = np.asarray(Ks, np.float64).reshape(-1, 4)
+    return (Camera * len(Ks))(*[Camera(*map(float, k)) for k in Ks])
+
+
+def _poses(Ts):
+    Ts = np.ascontiguousarray(np.asarray(Ts, np.float64).reshape(-1, 12))
+    return Ts
+
+
+def triangulate(K0, T0, Ks, Ts, mu, mv, conf, min_conf=0.05, angle_deg=2.0, min_inliers=4, max_refine_iters=50):
+    """Depth of every pixel of a mapping image (H x W) from dense matches
+    mu, mv, conf of shape (V, H, W).  T0, Ts: cam_from_world as 12 numbers
+    (R row-major, t).  Returns dict depth (H, W) float64, inliers, best_view,
+    ambiguous."""
+    mu = np.ascontiguousarray(mu, np.float32)
+    mv = np.ascontiguousarray(mv, np.float32)
+    cf = np.ascontiguousarray(conf, np.float32)
+    V, H, W = mu.shape
+    depth = np.zeros((H, W), np.float64)
+    inl = np.zeros((H, W), np.int32)
+    bv = np.zeros((H, W), np.int32)
+    amb = np.zeros((H, W), np.uint8)
+    T0a = _poses(T0)
+    Tsa = _poses(Ts)
+    prm = TriParams(float(min_conf), float(angle_deg), int(min_inliers), int(max_refine_iters))
+    lib().orc_triangulate(H, W, _cams([K0]), _p(T0a), V, _cams(Ks), _p(Tsa), _p(mu), _p(mv), _p(cf),
+                          C.byref(prm), _p(depth), _p(inl), _p(bv), _p(amb))
+    return dict(depth=depth, inliers=inl, best_view=bv, ambiguous=amb.astype(bool))
+
+
+def tri_angle(C0, r0, l, Ck, rk) -> float:
+    a = [np.ascontiguousarray(x, np.float64) for x in (C0, r0, Ck, rk)]
+    return float(lib().orc_tri_angle(_p(a[0]), _p(a[1]), float(l), _p(a[2]), _p(a[3])))
+
+
+def tri_hypothesis(C0, r0, Ck, rk):
+    a = [np.ascontiguousarray(x, np.float64) for x in (C0, r0, Ck, rk)]
+    out = np.zeros(1)
+    ok = lib().orc_tri_hypothesis(_p(a[0]), _p(a[1]), _p(a[2]), _p(a[3]), _p(out))
+    return float(out[0]) if ok else None
+
+
+def tri_refine(C0, r0, l0, Ck, rk, w, max_iters=50) -> float:
+    Ck = np.ascontiguousarray(Ck, np.float64).reshape(-1, 3)
+    rk = np.ascontiguousarray(rk, np.float64).reshape(-1, 3)
+    w = np.ascontiguousarray(w, np.float64)
+    C0 = np.ascontiguousarray(C0, np.float64)
+    r0 = np.ascontiguousarray(r0, np.float64)
+    return float(lib().orc_tri_refine(_p(C0), _p(r0), float(l0), len(w), _p(Ck), _p(rk), _p(w), int(max_iters)))

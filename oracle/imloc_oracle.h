@@ -161,6 +161,32 @@ int64_t orc_lift_log8(const float *q_u, const float *q_v, const float *db_u, con
                       double *out_u, double *out_v, double *out_X, double *out_Y, double *out_Z,
                       double *out_w, int64_t *out_src);
 
+/* Depth of every pixel of a mapping image by 1-DoF triangulation of dense
+ * matches (Sec. 3.3 "Depth Estimation by Dense Matching"; triangulate.c).
+ * Matches mu, mv, conf: [V][H][W] float32, pixel (row i, col j) of the
+ * mapping image matched to (mu, mv) of covisible view k.  Outputs [H][W]:
+ * depth (z-depth, 0 = none), inliers of the winning hypothesis, the view
+ * whose match gave it (-1 = none) and whether some angular test of the pixel
+ * lay within 1e-9 rad of the threshold (then float rounding may decide). */
+typedef struct {
+  double min_conf;         /* a match is used iff conf >= min_conf (float32 comparison) */
+  double angle_deg;        /* inlier iff angular error < angle_deg */
+  int32_t min_inliers;     /* the depth is kept iff the inlier set has at least this many */
+  int32_t max_refine_iters;
+} orc_tri_params;
+
+void orc_triangulate(int32_t H, int32_t W, const orc_camera *K0, const orc_pose *T0, int32_t V,
+                     const orc_camera *Kv, const orc_pose *Tv, const float *mu, const float *mv,
+                     const float *conf, const orc_tri_params *p, double *depth, int32_t *inliers,
+                     int32_t *best_view, uint8_t *ambiguous);
+/* The pieces, for the tests: angle of depth l for one observation (C0 + l r0
+ * seen from Ck along unit rk), the depth minimising it (0 if none), and the
+ * refinement of l0 over n weighted observations. */
+double orc_tri_angle(const double C0[3], const double r0[3], double l, const double Ck[3], const double rk[3]);
+int orc_tri_hypothesis(const double C0[3], const double r0[3], const double Ck[3], const double rk[3], double *l);
+double orc_tri_refine(const double C0[3], const double r0[3], double l0, int n, const double (*Ck)[3],
+                      const double (*rk)[3], const double *w, int max_iters);
+
 #ifdef __cplusplus
 }
 #endif

@@ -327,3 +327,83 @@ def config4_lift_scene(n_views: int = 20, per_view: int = 8000, correct_frac: fl
     matches = dict(q_u=f(cat(q_u)), q_v=f(cat(q_v)), db_u=f(cat(db_u)), db_v=f(cat(db_v)), conf=conf,
                    view=np.ascontiguousarray(cat(view), np.int32))
     return LiftWorkload(depth, cams, poses, matches, K, Rq, tq, cat(corr))
+
+
+# ---------------------------------------------------------------------------
+# Dense matches of a mapping image against its covisible views (mapping-time
+# depth estimation workload).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class DenseMatchWorkload:
+    K0: tuple
+    T0: np.ndarray        # (12,) cam_from_world of the mapping image
+    Ks: np.ndarray        # (V, 4)
+    Ts: np.ndarray        # (V, 12)
+    mu: np.ndarray        # (V, H, W) float32 matched column coordinate in view k
+    mv: np.ndarray        # (V, H, W) float32
+    conf: np.ndarray      # (V, H, W) float32
+    depth_true: np.ndarray  # (H, W) float64 z-depth of the mapping image (inf: nothing hit)
+    correct: np.ndarray   # (V, H, W) bool: generated as a correct match
+
+
+def dense_match_scene(n_views: int = 10, width: int = 560, height: int = 560, correct_frac: float = 0.7,
+                      noise_px: float = 0.5, seed: int = 1006, f: float | None = None) -> DenseMatchWorkload:
+    """A box-and-plane scene seen by one mapping camera and n_views covisible
+    cameras (0.5-3 m away, looking at nearby targets).  For every pixel of the
+    mapping image and every view: where the pixel's surface point is visible
+    in the view (in the image, not occluded), with probability correct_frac
+    the match is its true projection plus Gaussian noise (noise_px) with
+    confidence U(0.3, 1]; every other match is a uniformly random pixel with
+    confidence U(0, 0.6]."""
+    rng = rng_for(seed)
+    f = 0.8 * width if f is None else f
+    K = (f, f, width / 2.0, height / 2.0)
+    scene = make_scene(rng)
+    ang = rng.uniform(0, 2 * np.pi)
+    c0 = np.array([14.0 * np.cos(ang), 14.0 * np.sin(ang), 1.6])
+    target = np.array([0.0, 0.0, 1.0]) + rng.normal(0, 1.0, 3)
+    R0, t0 = look_at(c0, target)
+    Rs, ts = [], []
+    for _ in range(n_views):
+        off = rng.normal(0, 1.0, 3)
+        off *= rng.uniform(0.5, 3.0) / np.linalg.norm(off)
+        off[2] = 0.3 * off[2]
+        Rk, tk = look_at(c0 + off, target + rng.normal(0, 0.5, 3))
+        Rs.append(Rk)
+        ts.append(tk)
+    d0 = render_depth(scene, R0, t0, K, width, height)
+    fx, fy, cx, cy = K
+    jj, ii = np.meshgrid(np.arange(width) + 0.5, np.arange(height) + 0.5)
+    ok0 = np.isfinite(d0)
+    dd = np.where(ok0, d0, 1.0)
+    Xc = np.stack([(jj - cx) / fx * dd, (ii - cy) / fy * dd, dd], -1).reshape(-1, 3)
+    Xw = (Xc - t0) @ R0  # R0^T (x_c - t0)
+    V = n_views
+    mu = np.empty((V, height, width), np.float32)
+    mv = np.empty((V, height, width), np.float32)
+    conf = np.empty((V, height, width), np.float32)
+    correct = np.zeros((V, height, width), bool)
+    for k in range(V):
+        xk = Xw @ Rs[k].T + ts[k]
+        zk = xk[:, 2]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            uk = fx * xk[:, 0] / zk + cx
+            vk = fy * xk[:, 1] / zk + cy
+        vis = ok0.reshape(-1) & (zk > 0.1) & (uk >= 0) & (uk < width) & (vk >= 0) & (vk < height)
+        dk = render_depth(scene, Rs[k], ts[k], K, width, height)
+        ci = np.clip(np.floor(np.nan_to_num(uk)).astype(int), 0, width - 1)
+        ri = np.clip(np.floor(np.nan_to_num(vk)).astype(int), 0, height - 1)
+        vis &= np.abs(dk[ri, ci] - zk) < 0.02 * np.abs(zk)
+        good = vis & (rng.random(vis.shape[0]) < correct_frac)
+        n = vis.shape[0]
+        u = np.where(good, uk + rng.normal(0, noise_px, n), rng.random(n) * width)
+        v = np.where(good, vk + rng.normal(0, noise_px, n), rng.random(n) * height)
+        c = np.where(good, 1.0 - 0.7 * rng.random(n), 0.6 * rng.random(n))
+        mu[k] = u.reshape(height, width)
+        mv[k] = v.reshape(height, width)
+        conf[k] = c.reshape(height, width)
+        correct[k] = good.reshape(height, width)
+    pose = lambda R, t: np.concatenate([R.reshape(9), t])
+    return DenseMatchWorkload(K, pose(R0, t0), np.tile(np.array(K), (V, 1)), np.stack([pose(R, t) for R, t in zip(Rs, ts)]),
+                              mu, mv, conf, np.where(ok0, d0, np.inf), correct)
