@@ -197,6 +197,45 @@ int imloc_lift_log8(imloc_ctx *ctx, const imloc_matches *m, int64_t n_matches, c
                     int32_t n_views, int32_t H, int32_t W, const imloc_camera *cams, const imloc_pose *poses,
                     int32_t subpixel, float min_conf, const imloc_corr_out *out, int64_t capacity, int32_t *n_out);
 
+/* Dense matches of a mapping image against n_views covisible views, device
+ * arrays [n_views][H][W]: pixel (row, col) of the mapping image matched to
+ * (u, v) of view k with confidence conf. */
+typedef struct {
+  const float *u, *v, *conf;
+} imloc_dense_matches;
+
+typedef struct {
+  double min_conf;           /* a match is used iff conf >= min_conf (float32 comparison; the paper: 0.05) */
+  double angle_deg;          /* a match is an inlier of a depth iff its angular error < angle_deg (2) */
+  int32_t min_inliers;       /* the depth is kept iff the winning inlier set has >= min_inliers (4: "more than 3") */
+  int32_t max_refine_iters;  /* Newton steps of the refinement, at most (50) */
+} imloc_triangulation_params;
+
+/* Mapping-time depth of every pixel by 1-DoF triangulation of dense matches
+ * (Sec. 3.3 "Depth Estimation by Dense Matching").  With known poses the
+ * pixel's point is X(l) = C0 + l R0^T K0^-1 [col + 0.5, row + 0.5, 1]^T (l =
+ * z-depth); a match in view k is the unit ray r_k from its centre C_k, and the
+ * angular error of depth l for it is the angle between X(l) - C_k and r_k.
+ * Each used match gives one hypothesis, the depth minimising its own angular
+ * error (when that minimum lies at a finite l > 0); the hypothesis with the
+ * most matches within angle_deg wins (ties: lowest view); its depth is refined
+ * by minimising the confidence-weighted sum of squared angular errors over
+ * its inliers (a fixed set; Newton's method to a step below 1e-12 l) and kept
+ * iff it has at least min_inliers inliers, else the depth is 0.
+ *   K_map, T_map: the mapping camera (host); K_views, T_views: host arrays of
+ *   n_views (1..32) entries, cam_from_world.  m: device arrays.  Outputs
+ *   (device [H][W], each may be NULL): depth (float32 z-depth in metres, 0 =
+ *   none), inliers (int32, the winning set's size), codes (uint8 8-bit
+ *   log-depth codes of depth, as imloc_depth_encode_log8).  Asynchronous on
+ *   the context's stream; needs imloc_triangulate_workspace_bytes(n_views) of
+ *   workspace.  IMLOC_EINVAL for n_views outside 1..32, H or W < 1, null
+ *   inputs or bad intrinsics. */
+size_t imloc_triangulate_workspace_bytes(int32_t n_views);
+int imloc_triangulate_depth(imloc_ctx *ctx, int32_t H, int32_t W, const imloc_camera *K_map,
+                            const imloc_pose *T_map, int32_t n_views, const imloc_camera *K_views,
+                            const imloc_pose *T_views, const imloc_dense_matches *m,
+                            const imloc_triangulation_params *p, float *depth, int32_t *inliers, uint8_t *codes);
+
 /* LO-RANSAC PnP for one query (Sec. 3.3 "Pose Estimation").  Minimal sample
  * h draws three distinct indices of the scoring set from Philox4x64-10 with
  * key (seed, 0) and counter (h, query_id, attempt, 0), index = floor(word *

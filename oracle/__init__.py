@@ -327,12 +327,12 @@ class TriParams(C.Structure):
                 ("max_refine_iters", C.c_int32)]
 
 
-def _cams(Ks):
+def _tri_cams(Ks):
     Ks = np.asarray(Ks, np.float64).reshape(-1, 4)
     return (Camera * len(Ks))(*[Camera(*map(float, k)) for k in Ks])
 
 
-def _poses(Ts):
+def _tri_poses(Ts):
     Ts = np.ascontiguousarray(np.asarray(Ts, np.float64).reshape(-1, 12))
     return Ts
 
@@ -350,10 +350,10 @@ def triangulate(K0, T0, Ks, Ts, mu, mv, conf, min_conf=0.05, angle_deg=2.0, min_
     inl = np.zeros((H, W), np.int32)
     bv = np.zeros((H, W), np.int32)
     amb = np.zeros((H, W), np.uint8)
-    T0a = _poses(T0)
-    Tsa = _poses(Ts)
+    T0a = _tri_poses(T0)
+    Tsa = _tri_poses(Ts)
     prm = TriParams(float(min_conf), float(angle_deg), int(min_inliers), int(max_refine_iters))
-    lib().orc_triangulate(H, W, _cams([K0]), _p(T0a), V, _cams(Ks), _p(Tsa), _p(mu), _p(mv), _p(cf),
+    lib().orc_triangulate(H, W, _tri_cams([K0]), _p(T0a), V, _tri_cams(Ks), _p(Tsa), _p(mu), _p(mv), _p(cf),
                           C.byref(prm), _p(depth), _p(inl), _p(bv), _p(amb))
     return dict(depth=depth, inliers=inl, best_view=bv, ambiguous=amb.astype(bool))
 

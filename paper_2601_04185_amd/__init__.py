@@ -34,7 +34,8 @@ EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_err
             "imloc_set_graphs", "imloc_graph_counters", "imloc_server_workspace_bytes", "imloc_server_create",
             "imloc_server_destroy", "imloc_server_submit", "imloc_server_step", "imloc_server_poll",
             "imloc_server_usage",
-            "imloc_lift", "imloc_lift_log8", "imloc_depth_encode_log8",
+            "imloc_lift", "imloc_lift_log8", "imloc_depth_encode_log8", "imloc_triangulate_workspace_bytes",
+            "imloc_triangulate_depth",
             "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score",
             "imloc_local_optimize", "imloc_refine"]
 
@@ -127,6 +128,8 @@ def lib():
             "imloc_lift": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_lift_log8": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_depth_encode_log8": ([vp, vp, i64, vp], C.c_int),
+            "imloc_triangulate_workspace_bytes": ([i32], C.c_size_t),
+            "imloc_triangulate_depth": ([vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "imloc_lo_ransac_pnp": ([vp, vp, i64, vp, vp, vp, vp, vp], C.c_int),
             "imloc_lo_ransac_pnp_batch": ([vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp], C.c_int),
             "imloc_sample_p3p": ([vp, vp, i64, vp, u64, u64, i32, i64, i64, vp, vp, vp, vp, vp], C.c_int),
@@ -298,6 +301,49 @@ def imloc_depth_encode_log8(ctx: Context, depth):
     codes = torch.empty(d.shape, dtype=torch.uint8, device=d.device)
     ctx.check(lib().imloc_depth_encode_log8(ctx.h, _ptr(d), d.numel(), _ptr(codes)))
     return codes
+
+
+class DenseMatches(C.Structure):
+    _fields_ = [("u", C.c_void_p), ("v", C.c_void_p), ("conf", C.c_void_p)]
+
+
+class TriangulationParams(C.Structure):
+    _fields_ = [("min_conf", C.c_double), ("angle_deg", C.c_double), ("min_inliers", C.c_int32),
+                ("max_refine_iters", C.c_int32)]
+
+
+def _pose12(T) -> Pose:
+    T = np.asarray(T, np.float64).reshape(12)
+    return Pose((C.c_double * 9)(*T[:9]), (C.c_double * 3)(*T[9:]))
+
+
+def imloc_triangulate_depth(ctx: Context, K_map, T_map, K_views, T_views, mu, mv, conf, min_conf=0.05,
+                            angle_deg=2.0, min_inliers=4, max_refine_iters=50, want_codes=False):
+    """mu, mv, conf: cuda float32 (V, H, W) dense matches of the mapping image
+    in its V covisible views.  K_*: (fx, fy, cx, cy); T_*: 12 numbers
+    cam_from_world.  Returns dict of cuda tensors depth (H, W) float32,
+    inliers (H, W) int32 and, if asked, codes (H, W) uint8."""
+    torch = ctx.torch
+    V, H, W = (int(x) for x in mu.shape)
+    dev = mu.device
+    depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+    inl = torch.empty((H, W), dtype=torch.int32, device=dev)
+    codes = torch.empty((H, W), dtype=torch.uint8, device=dev) if want_codes else None
+    Kv = np.asarray(K_views, np.float64).reshape(V, 4)
+    Tv = np.asarray(T_views, np.float64).reshape(V, 12)
+    cams = (Camera * V)(*[_cam(k) for k in Kv])
+    poses = (Pose * V)(*[_pose12(t) for t in Tv])
+    m = DenseMatches(mu.contiguous().data_ptr(), mv.contiguous().data_ptr(), conf.contiguous().data_ptr())
+    prm = TriangulationParams(float(min_conf), float(angle_deg), int(min_inliers), int(max_refine_iters))
+    ctx.ensure_workspace(lib().imloc_triangulate_workspace_bytes(V))
+    k0 = _cam(K_map)
+    t0 = _pose12(T_map)
+    ctx.check(lib().imloc_triangulate_depth(ctx.h, H, W, C.byref(k0), C.byref(t0), V, cams, poses, C.byref(m),
+                                            C.byref(prm), _ptr(depth), _ptr(inl), _ptr(codes)))
+    out = dict(depth=depth, inliers=inl)
+    if want_codes:
+        out["codes"] = codes
+    return out
 
 
 def imloc_sample_p3p(ctx: Context, corr: dict, K, seed: int, query_id: int, h0: int, count: int, exhaustive=0,

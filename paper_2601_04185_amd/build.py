@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libimloc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["rounds.hip", "sample_p3p.hip", "score.hip", "refine.hip", "lift.hip", "runtime.cpp"]
+SOURCES = ["rounds.hip", "sample_p3p.hip", "score.hip", "refine.hip", "lift.hip", "triangulate.hip", "runtime.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-result"]
 

@@ -230,14 +230,22 @@ __device__ inline void cubic_roots_in(double c0, double c1, double c2, double c3
     if (fa == 0.0) { emit(a); continue; }
     if (fb == 0.0 && t == 2) { emit(b); continue; }
     if ((fa < 0.0) == (fb < 0.0)) continue;
-    for (int it = 0; it < 200; ++it) {
-      const double m = 0.5 * (a + b);
-      if (m <= a || m >= b) break;
-      const double fm = ((c3 * m + c2) * m + c1) * m + c0;
-      if (fm == 0.0) { a = b = m; break; }
-      if ((fm < 0.0) == (fa < 0.0)) { a = m; fa = fm; } else { b = m; }
+    // safeguarded Newton: the cubic is monotone on the bracket; a Newton step
+    // that leaves the bracket, or that shrinks it by less than half, is
+    // replaced by bisection; the bracket shrinks every step
+    double x = 0.5 * (a + b), dx_old = b - a;
+    for (int it = 0; it < 100; ++it) {
+      const double fx = ((c3 * x + c2) * x + c1) * x + c0;
+      if (fx == 0.0) { a = b = x; break; }
+      if ((fx < 0.0) == (fa < 0.0)) { a = x; fa = fx; } else { b = x; }
+      const double dfx = (3.0 * c3 * x + 2.0 * c2) * x + c1;
+      double xn = x - fx / dfx;
+      if (!(xn > a && xn < b) || !(fabs(xn - x) < 0.5 * dx_old)) xn = 0.5 * (a + b);
+      dx_old = fabs(xn - x);
+      if (xn == x || xn <= a || xn >= b) break;
+      x = xn;
     }
-    emit(0.5 * (a + b));
+    emit(a == b ? a : x);
   }
 }
 
@@ -476,6 +484,26 @@ __device__ inline void p3p_pose(const double l[3], const double y[3][3], const d
   for (int e = 0; e < 9; ++e) P.R[e] = Rn[e];
   for (int r = 0; r < 3; ++r)
     P.t[r] = z[0][r] - (P.R[3 * r] * x[0][0] + P.R[3 * r + 1] * x[0][1] + P.R[3 * r + 2] * x[0][2]);
+}
+
+// 8-bit log-depth codes (ImLoc Sec. 3.3 "Data Compression"): depth clipped to
+// [0.25, 128] m and quantised uniformly in log depth; code 0 = no depth,
+// code c >= 1 = 0.25 * 512^((c - 1) / 254).
+constexpr double kLog8DMin = 0.25;            // metres, level of code 1
+constexpr double kLog8Log2Range = 9.0;        // log2(128 / 0.25)
+constexpr double kLog8Steps = 254.0;          // levels 1..255
+
+__device__ inline double log8_level(int c) {
+  return c == 0 ? 0.0 : kLog8DMin * exp2(((double)(c - 1) * kLog8Log2Range) / kLog8Steps);
+}
+
+// nearest level in log depth (halves away from zero); 0 for depth not finite or <= 0
+__device__ inline uint8_t log8_code(float f) {
+  double d = f;
+  if (!(d > 0.0 && d <= 3.4028234663852886e38)) return 0;
+  d = fmin(fmax(d, kLog8DMin), kLog8DMin * 512.0);
+  const double level = kLog8Steps * log2(d / kLog8DMin) / kLog8Log2Range;
+  return (uint8_t)(1 + (int)round(level));
 }
 
 // Folded projection P = K [R | t] rows (a, b, w) = P [X, 1].

@@ -20,7 +20,7 @@ struct CorrF32 {
 struct CamH { double fx, fy, cx, cy; };
 
 constexpr int kMaxTopK = 32;       // local optimisations per query and batch, at most
-constexpr int kScorePPL32 = 4;     // correspondences per lane, float32 scoring (fixes the summation order)
+constexpr int kScorePPL32 = 8;     // correspondences per lane, float32 scoring (fixes the summation order)
 constexpr int kScorePPL64 = 2;     // correspondences per lane, float64 scoring
 constexpr double kGainScale = 4294967296.0;  // fixed-point scale of the accumulated truncated-cost gain
 
@@ -104,6 +104,20 @@ int lift_blocks(int64_t n);
 hipError_t launch_lift(const LiftArgs& a, hipStream_t s);
 // 8-bit log-depth codes of n float32 depths (depth and codes 16- and 4-byte aligned)
 hipError_t launch_log8_encode(const float* depth, int64_t n, uint8_t* codes, hipStream_t s);
+
+// --- mapping-time depth by 1-DoF triangulation ------------------------------
+struct TriArgs {
+  int32_t H, W, V;               // mapping image size, covisible views (<= 32)
+  const double* views;           // device [V + 1][16]: fx, fy, cx, cy, R^T (9), C0 - Ck (3); entry 0 = mapping camera
+  const float *mu, *mv, *conf;   // device [V][H][W]
+  float min_conf;
+  double cos2_thr;               // cos^2 of the angular threshold
+  int32_t min_inliers, max_iters;
+  float* depth;                  // device [H][W] or null
+  int32_t* inliers;              // device [H][W] or null
+  uint8_t* codes;                // device [H][W] 8-bit log-depth codes, or null
+};
+hipError_t launch_triangulate(const TriArgs& a, hipStream_t s);
 
 // --- small utilities ---------------------------------------------------------
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -23,14 +23,6 @@ constexpr int kLiftBlock = 256;
 
 __device__ inline bool depth_ok(float d) { return d > 0.0f && d <= 3.402823466e38f; }  // finite and positive
 
-constexpr double kLog8DMin = 0.25;            // metres, level of code 1
-constexpr double kLog8Log2Range = 9.0;        // log2(128 / 0.25)
-constexpr double kLog8Steps = 254.0;          // levels 1..255
-
-__device__ inline double log8_level(int c) {
-  return c == 0 ? 0.0 : kLog8DMin * exp2(((double)(c - 1) * kLog8Log2Range) / kLog8Steps);
-}
-
 // Depth texel idx of view map D; false if it holds no valid depth.
 template <bool kCodes>
 __device__ inline bool tap(const LiftArgs& a, int64_t idx, const double* lut, double& d) {
@@ -187,14 +179,6 @@ hipError_t launch_lift(const LiftArgs& a, hipStream_t s) {
 // Four depths per thread (one float4 load, one 32-bit store) over the first
 // 4 * n4 entries, one per thread over the rest (n4 = 0 when the arrays are
 // not 16- and 4-byte aligned).
-__device__ inline uint8_t log8_code(float f) {
-  double d = f;
-  if (!(d > 0.0 && d <= 3.4028234663852886e38)) return 0;
-  d = fmin(fmax(d, kLog8DMin), kLog8DMin * 512.0);
-  const double level = kLog8Steps * log2(d / kLog8DMin) / kLog8Log2Range;
-  return (uint8_t)(1 + (int)round(level));
-}
-
 __global__ __launch_bounds__(256) void log8_encode_kernel(const float* __restrict__ depth, int64_t n, int64_t n4,
                                                            uint8_t* __restrict__ codes) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;

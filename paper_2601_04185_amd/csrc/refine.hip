@@ -67,12 +67,12 @@ size_t gn_scratch_bytes(int nprob, int chunks_max) {
 __host__ __device__ constexpr int upk(int r, int c) { return r * 6 - (r * (r - 1)) / 2 + (c - r); }
 
 // Solve from the reduced sums (LDS); thread 0 only.  Cholesky H = U^T U in
-// place on the packed upper triangle, then U^T y = -g, U d = y, and the left
-// update.  Every loop has constant bounds and is unrolled, so the factor, the
+// place on the packed upper triangle (pivot reciprocals computed once), then
+// U^T y = -g, U d = y, and the left update.  Every loop has constant bounds and is unrolled, so the factor, the
 // vectors and the rotation stay in registers (about 100 VGPRs, below what the
 // accumulation path needs).  Returns false if H is not positive definite.
 __device__ __forceinline__ bool gn_solve_step(const double* tot, const double* cur, double* next) {
-  double h[21];
+  double h[21], inv[6];
 #pragma unroll
   for (int e = 0; e < 21; ++e) h[e] = tot[e];
   bool ok = true;
@@ -83,13 +83,14 @@ __device__ __forceinline__ bool gn_solve_step(const double* tot, const double* c
     for (int m = 0; m < i; ++m) dsum -= h[upk(m, i)] * h[upk(m, i)];
     ok = ok && dsum > 0.0;
     const double uii = sqrt(fmax(dsum, 0.0));
+    inv[i] = 1.0 / uii;
     h[upk(i, i)] = uii;
 #pragma unroll
     for (int j = i + 1; j < 6; ++j) {
       double sum = h[upk(i, j)];
 #pragma unroll
       for (int m = 0; m < i; ++m) sum -= h[upk(m, i)] * h[upk(m, j)];
-      h[upk(i, j)] = sum / uii;
+      h[upk(i, j)] = sum * inv[i];
     }
   }
   if (!ok) return false;
@@ -99,14 +100,14 @@ __device__ __forceinline__ bool gn_solve_step(const double* tot, const double* c
     double sum = -tot[21 + i];
 #pragma unroll
     for (int m = 0; m < i; ++m) sum -= h[upk(m, i)] * y[m];
-    y[i] = sum / h[upk(i, i)];
+    y[i] = sum * inv[i];
   }
 #pragma unroll
   for (int i = 5; i >= 0; --i) {
     double sum = y[i];
 #pragma unroll
     for (int m = i + 1; m < 6; ++m) sum -= h[upk(i, m)] * d[m];
-    d[i] = sum / h[upk(i, i)];
+    d[i] = sum * inv[i];
   }
   // left update: R' = Exp(dw) R, t' = Exp(dw) t + dt
   double E[9];
@@ -162,11 +163,35 @@ __global__ __launch_bounds__(kGNThreads) void gn_kernel(
   const int chunks = chunks_for(n);
   if (chunk >= chunks) return;
   uint8_t* in_set = MODE == 1 ? in_set_all + d.in_set_off : nullptr;
-
   GNState* prev = gst + (int64_t)((k + 1) & 1) * nprob + p;
   GNState* next = gst + (int64_t)(k & 1) * nprob + p;
   const double* part_prev = part + ((int64_t)((k + 1) & 1) * nprob + p) * chunks_max * kAcc;
   double* part_next = part + ((int64_t)(k & 1) * nprob + p) * chunks_max * kAcc;
+  const bool prev_done = k > 0 && prev->done != 0;
+
+  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
+  // the chunk's points of a live problem are loaded first: one memory latency
+  // per launch, overlapping the reduction of the previous partial sums and
+  // the solve
+  float pX[kGNPPT], pY[kGNPPT], pZ[kGNPPT], pu[kGNPPT], pv[kGNPPT], pw[kGNPPT];
+  bool use[kGNPPT];
+#pragma unroll
+  for (int t = 0; t < kGNPPT; ++t) {
+    const int64_t i = base + (int64_t)t * kGNThreads;
+    use[t] = !prev_done && i < n;
+    pX[t] = pY[t] = pZ[t] = pu[t] = pv[t] = 0.0f;
+    pw[t] = 1.0f;
+    if (MODE == 1 && k > 0 && use[t]) use[t] = in_set[i] != 0;
+    if (use[t]) {
+      pX[t] = gmem(c.X)[i];
+      pY[t] = gmem(c.Y)[i];
+      pZ[t] = gmem(c.Z)[i];
+      pu[t] = gmem(c.u)[i];
+      pv[t] = gmem(c.v)[i];
+      if (c.w) pw[t] = gmem(c.w)[i];
+    }
+  }
+
 
   __shared__ double s_grp[8][kAcc];
   __shared__ double s_tot[kAcc];
@@ -188,7 +213,6 @@ __global__ __launch_bounds__(kGNThreads) void gn_kernel(
   } else {
     // partial sums of launch k-1 in chunk order: thread (v, g) sums chunks g, g+8, ...
     const int v = threadIdx.x % kAcc, g = threadIdx.x / kAcc;
-    const bool prev_done = prev->done != 0;
     if (!prev_done && g < 8) {
       // chunks g, g + 8, ...: loaded four at a time, summed in chunk order
       double sum = 0.0;
@@ -262,23 +286,6 @@ __global__ __launch_bounds__(kGNThreads) void gn_kernel(
   double a[kAcc];
 #pragma unroll
   for (int e = 0; e < kAcc; ++e) a[e] = 0.0;
-  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
-  // all loads of the thread's points first (one memory latency, not kGNPPT)
-  float pX[kGNPPT], pY[kGNPPT], pZ[kGNPPT], pu[kGNPPT], pv[kGNPPT], pw[kGNPPT];
-  bool use[kGNPPT];
-#pragma unroll
-  for (int t = 0; t < kGNPPT; ++t) {
-    const int64_t i = base + (int64_t)t * kGNThreads;
-    use[t] = i < n;
-    const int64_t ii = use[t] ? i : 0;
-    if (MODE == 1 && k > 0) use[t] = use[t] && in_set[ii] != 0;
-    pX[t] = gmem(c.X)[ii];
-    pY[t] = gmem(c.Y)[ii];
-    pZ[t] = gmem(c.Z)[ii];
-    pu[t] = gmem(c.u)[ii];
-    pv[t] = gmem(c.v)[ii];
-    pw[t] = c.w ? gmem(c.w)[ii] : 1.0f;
-  }
 #pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
     if (!use[t]) continue;

@@ -769,6 +769,63 @@ int imloc_depth_encode_log8(imloc_ctx* ctx, const float* depth, int64_t count, u
   return IMLOC_OK;
 }
 
+size_t imloc_triangulate_workspace_bytes(int32_t n_views) {
+  const int v = n_views < 0 ? 0 : n_views;
+  return ((size_t)(v + 1) * 16 * sizeof(double) + 255) & ~size_t(255);
+}
+
+int imloc_triangulate_depth(imloc_ctx* ctx, int32_t H, int32_t W, const imloc_camera* K_map, const imloc_pose* T_map,
+                            int32_t n_views, const imloc_camera* K_views, const imloc_pose* T_views,
+                            const imloc_dense_matches* m, const imloc_triangulation_params* p, float* depth,
+                            int32_t* inliers, uint8_t* codes) {
+  if (!ctx) return IMLOC_EINVAL;
+  if (H < 1 || W < 1 || (int64_t)H * W > INT32_MAX) return set_err(ctx, IMLOC_EINVAL, "bad image size");
+  if (n_views < 1 || n_views > 32) return set_err(ctx, IMLOC_EINVAL, "n_views must be in 1..32");
+  if (!K_map || !T_map || !K_views || !T_views || !m || !p) return set_err(ctx, IMLOC_EINVAL, "null argument");
+  if (!m->u || !m->v || !m->conf) return set_err(ctx, IMLOC_EINVAL, "null match array");
+  if (!cam_ok(K_map)) return set_err(ctx, IMLOC_EINVAL, "bad intrinsics of the mapping camera");
+  for (int k = 0; k < n_views; ++k)
+    if (!cam_ok(&K_views[k])) return set_err(ctx, IMLOC_EINVAL, "view %d: bad intrinsics", k);
+  if (!(p->angle_deg > 0.0 && p->angle_deg < 90.0)) return set_err(ctx, IMLOC_EINVAL, "angle_deg must be in (0, 90)");
+  if (p->max_refine_iters < 0) return set_err(ctx, IMLOC_EINVAL, "max_refine_iters < 0");
+  hipSetDevice(ctx->device);
+  Arena a{ctx->ws, ctx->ws_bytes};
+  double* dviews = a.take<double>((size_t)(n_views + 1) * 16);
+  if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small for triangulation: need %zu bytes", a.off);
+  const size_t hb = (size_t)(n_views + 1) * 16 * sizeof(double);
+  if (!ensure_pinned(ctx, hb + 512)) return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the staging buffer may still feed an earlier copy
+  double* h = reinterpret_cast<double*>(ctx->pinned);
+  auto centre = [](const imloc_pose& T, double C[3]) {
+    for (int r = 0; r < 3; ++r) C[r] = -(T.R[r] * T.t[0] + T.R[3 + r] * T.t[1] + T.R[6 + r] * T.t[2]);
+  };
+  double C0[3];
+  centre(*T_map, C0);
+  for (int e = 0; e <= n_views; ++e) {
+    const imloc_camera& K = e == 0 ? *K_map : K_views[e - 1];
+    const imloc_pose& T = e == 0 ? *T_map : T_views[e - 1];
+    double* o = h + 16 * e;
+    o[0] = K.fx; o[1] = K.fy; o[2] = K.cx; o[3] = K.cy;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) o[4 + 3 * r + c] = T.R[3 * c + r];  // R^T
+    double C[3];
+    centre(T, C);
+    for (int c = 0; c < 3; ++c) o[13 + c] = e == 0 ? 0.0 : C0[c] - C[c];
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(dviews, h, hb, hipMemcpyHostToDevice, ctx->stream));
+  TriArgs ta;
+  ta.H = H; ta.W = W; ta.V = n_views; ta.views = dviews;
+  ta.mu = m->u; ta.mv = m->v; ta.conf = m->conf;
+  ta.min_conf = (float)p->min_conf;
+  const double th = p->angle_deg * (3.14159265358979323846 / 180.0);
+  ta.cos2_thr = cos(th) * cos(th);
+  ta.min_inliers = p->min_inliers;
+  ta.max_iters = p->max_refine_iters;
+  ta.depth = depth; ta.inliers = inliers; ta.codes = codes;
+  HIP_TRY(ctx, launch_triangulate(ta, ctx->stream));
+  return IMLOC_OK;
+}
+
 int imloc_lo_ransac_pnp(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K,
                         const imloc_ransac_params* p, imloc_pose* pose_out, uint8_t* mask, imloc_stats* stats) {
   if (!ctx) return IMLOC_EINVAL;

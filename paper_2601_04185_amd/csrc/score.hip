@@ -41,6 +41,23 @@ __device__ inline float to_vgpr(float x) {
   return r;
 }
 
+// Sum over the 64 lanes of a full wave with DPP lane moves (pairs, quads,
+// rows of 16 by shifts, then the row broadcasts 15 and 31), total read from
+// lane 63 (wave-uniform).  Every lane must be active.
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ inline float wave_total_dpp(float x) {
+  x += dpp_move<0xb1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_move<0x4e>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_move<0x114>(x);  // row_shr:4
+  x += dpp_move<0x118>(x);  // row_shr:8
+  x += dpp_move<0x142>(x);  // row_bcast:15
+  x += dpp_move<0x143>(x);  // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
 __device__ inline int ppl_of(const QueryDesc& d) { return d.precision ? kScorePPL64 : kScorePPL32; }
 __device__ inline int64_t chunks_of(const QueryDesc& d) {
   const int64_t per = (int64_t)kScoreBlock * ppl_of(d);
@@ -115,6 +132,7 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
   const float4* __restrict__ pc = reinterpret_cast<const float4*>(proj + 16 * (d.cand_off + c0));
   float4 n0 = pc[0], n1 = pc[1], n2 = pc[2];
   uint32_t item_cnt = 0;
+#pragma unroll 2
   for (int c = 0; c < cend; ++c) {
     const float4 r0 = n0, r1 = n1, r2 = n2;
     if (c + 1 < cend) {  // prefetch the next candidate's rows
@@ -142,7 +160,7 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
 #pragma unroll
       for (int k = 0; k < PPL; ++k)
         if (e[k] < t[k]) gain = fmaf(pw[k], fmaf(-e[k], __builtin_amdgcn_rcpf(t[k]), 1.0f), gain);
-      gain = wave_sum(gain);
+      gain = wave_total_dpp(gain);
       gfx = (unsigned long long)((double)gain * kGainScale);
     }
     item_cnt += cnt;

@@ -41,6 +41,8 @@ int main(void) {
          sizeof(imloc_pose), sizeof(imloc_corr), sizeof(imloc_corr_out), sizeof(imloc_matches));
   printf("%zu %zu %zu %zu %zu\n", offsetof(imloc_ransac_params, precision), offsetof(imloc_ransac_params, seed),
          offsetof(imloc_stats, score_launches), offsetof(imloc_stats, ms_total), sizeof(imloc_server_config));
+  printf("%zu %zu %zu\n", sizeof(imloc_dense_matches), sizeof(imloc_triangulation_params),
+         offsetof(imloc_triangulation_params, max_refine_iters));
   return 0;
 }
 ''')
@@ -51,7 +53,8 @@ int main(void) {
     want = [C.sizeof(pk.RansacParams), C.sizeof(pk.Stats), C.sizeof(pk.Camera), C.sizeof(pk.Pose),
             C.sizeof(pk.Corr), C.sizeof(pk.CorrOut), C.sizeof(pk.Matches),
             pk.RansacParams.precision.offset, pk.RansacParams.seed.offset, pk.Stats.score_launches.offset,
-            pk.Stats.ms_total.offset, C.sizeof(pk.ServerConfig)]
+            pk.Stats.ms_total.offset, C.sizeof(pk.ServerConfig), C.sizeof(pk.DenseMatches),
+            C.sizeof(pk.TriangulationParams), pk.TriangulationParams.max_refine_iters.offset]
     assert got == want
 
 
