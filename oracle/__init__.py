@@ -30,7 +30,7 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (plain C11 + OpenMP)."""
     if force or not os.path.exists(_SO):
-        srcs = [os.path.join(_HERE, f) for f in ("imloc_oracle.c", "triangulate.c")]
+        srcs = [os.path.join(_HERE, f) for f in ("imloc_oracle.c", "triangulate.c", "rig.c")]
         tmp = _SO + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-std=gnu11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
                "-Wno-unused-parameter", *srcs, "-o", tmp, "-lm"]
@@ -97,6 +97,15 @@ def lib():
         L.orc_log8_encode.argtypes = [C.c_float]
         L.orc_log8_encode.restype = C.c_uint8
         L.orc_log8_encode_array.argtypes = [vp, i64, vp]
+        L.orc_gp3p.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.orc_gp3p.restype = C.c_int
+        L.orc_rig_score.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
+        L.orc_rig_lo.argtypes = [vp, vp, vp, dbl, i32, vp, vp, vp]
+        L.orc_rig_lo.restype = C.c_int
+        L.orc_rig_refine.argtypes = [vp, vp, vp, dbl, dbl, i32, vp, vp, vp]
+        L.orc_rig_refine.restype = C.c_int
+        L.orc_rig_lo_ransac.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+        L.orc_rig_lo_ransac.restype = C.c_int
         L.orc_triangulate.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_tri_angle.argtypes = [vp, vp, dbl, vp, vp]
         L.orc_tri_angle.restype = dbl
@@ -377,3 +386,95 @@ def tri_refine(C0, r0, l0, Ck, rk, w, max_iters=50) -> float:
     C0 = np.ascontiguousarray(C0, np.float64)
     r0 = np.ascontiguousarray(r0, np.float64)
     return float(lib().orc_tri_refine(_p(C0), _p(r0), float(l0), len(w), _p(Ck), _p(rk), _p(w), int(max_iters)))
+
+
+class RigCamera(C.Structure):
+    _fields_ = [("K", Camera), ("R", C.c_double * 9), ("t", C.c_double * 3)]
+
+
+class RigCorr(C.Structure):
+    _fields_ = [("u", C.c_void_p), ("v", C.c_void_p), ("X", C.c_void_p), ("Y", C.c_void_p), ("Z", C.c_void_p),
+                ("w", C.c_void_p), ("cam", C.c_void_p), ("n", C.c_int64)]
+
+
+def _rig_cams(rig):
+    """rig: sequence of (K (4,), cam_from_rig (12,))."""
+    out = (RigCamera * len(rig))()
+    for k, (K, T) in enumerate(rig):
+        T = np.asarray(T, np.float64).reshape(12)
+        out[k] = RigCamera(Camera(*map(float, K)), (C.c_double * 9)(*T[:9]), (C.c_double * 3)(*T[9:]))
+    return out
+
+
+class _RigCorrHold(_CorrHold):
+    def __init__(self, corr):
+        super().__init__(corr)
+        self.cam = np.ascontiguousarray(corr["cam"], np.int32)
+        a = self.arrs
+        self.rc = RigCorr(*[a[k].ctypes.data for k in ("u", "v", "X", "Y", "Z")],
+                          None if a["w"] is None else a["w"].ctypes.data, self.cam.ctypes.data, self.c.n)
+
+
+def gp3p(o, f, Xw):
+    """Generalised P3P: rays (origins o (3, 3), directions f (3, 3)) in the rig
+    frame through world points Xw (3, 3).  -> (list of (R, t) rig_from_world,
+    depths (k, 3), ill)."""
+    o = np.ascontiguousarray(o, np.float64).reshape(9)
+    f = np.ascontiguousarray(f, np.float64).reshape(9)
+    X = np.ascontiguousarray(Xw, np.float64).reshape(9)
+    out = np.zeros((8, 12))
+    dep = np.zeros((8, 3))
+    ill = np.zeros(1, np.int32)
+    n = lib().orc_gp3p(_p(o), _p(f), _p(X), _p(out), _p(dep), _p(ill))
+    return [split_pose(out[k]) for k in range(n)], dep[:n].copy(), bool(ill[0])
+
+
+def rig_score(poses, corr, rig, tau):
+    P = _poses(poses)
+    h = _RigCorrHold(corr)
+    cams = _rig_cams(rig)
+    cnt = np.zeros(max(len(P), 1), np.int32)
+    ms = np.zeros(max(len(P), 1), np.float64)
+    lib().orc_rig_score(_p(P), len(P), C.byref(h.rc), cams, float(tau), _p(cnt), _p(ms))
+    return cnt[:len(P)], ms[:len(P)]
+
+
+def rig_lo(start, corr, rig, tau, iters=10):
+    s = np.ascontiguousarray(start, np.float64).reshape(12)
+    h = _RigCorrHold(corr)
+    out = np.zeros(12)
+    cost = np.zeros(1)
+    cnt = np.zeros(1, np.int64)
+    acc = lib().orc_rig_lo(_p(s), C.byref(h.rc), _rig_cams(rig), float(tau), int(iters), _p(out), _p(cost), _p(cnt))
+    return dict(pose=out, cost=float(cost[0]), count=int(cnt[0]), accepted=int(acc))
+
+
+def rig_refine(start, corr, rig, tau, s=None, iters=10):
+    st = np.ascontiguousarray(start, np.float64).reshape(12)
+    h = _RigCorrHold(corr)
+    out = np.zeros(12)
+    cost = np.zeros(1)
+    ni = np.zeros(1, np.int64)
+    s = 0.5 * tau if s is None else s
+    acc = lib().orc_rig_refine(_p(st), C.byref(h.rc), _rig_cams(rig), float(tau), float(s), int(iters), _p(out),
+                               _p(cost), _p(ni))
+    return dict(pose=out, cost=float(cost[0]), n_inliers=int(ni[0]), accepted=int(acc))
+
+
+def rig_lo_ransac(corr, rig, **params):
+    """LO-RANSAC for a multi-camera rig query: corr has u, v, X, Y, Z, (w) and
+    cam (int32 camera index); rig: list of (K, cam_from_rig).  -> dict(R, t
+    (rig_from_world), mask, status, stats...)."""
+    h = _RigCorrHold(corr)
+    n = h.c.n
+    prm = make_params(**params)
+    pose = np.zeros(12, np.float64)
+    mask = np.zeros(max(n, 1), np.uint8)
+    st = Stats()
+    status = lib().orc_rig_lo_ransac(C.byref(h.rc), _rig_cams(rig), len(rig), C.byref(prm), _p(pose), _p(mask),
+                                     C.byref(st))
+    R, t = split_pose(pose)
+    out = dict(R=R, t=t, mask=mask[:n].copy(), status=int(status))
+    for f_, _ in Stats._fields_:
+        out[f_] = getattr(st, f_)
+    return out

@@ -187,6 +187,35 @@ int orc_tri_hypothesis(const double C0[3], const double r0[3], const double Ck[3
 double orc_tri_refine(const double C0[3], const double r0[3], double l0, int n, const double (*Ck)[3],
                       const double (*rk)[3], const double *w, int max_iters);
 
+/* Multi-camera rig (generalised absolute pose; rig.c).  A rig camera has
+ * intrinsics K and cam_from_rig (R, t); poses are rig_from_world; a world
+ * point X seen by camera c projects through x_c = R_c (R X + t) + t_c. */
+typedef struct {
+  orc_camera K;
+  double R[9], t[3];
+} orc_rig_camera;
+
+typedef struct {
+  const float *u, *v, *X, *Y, *Z, *w;  /* as orc_corr (w may be NULL) */
+  const int32_t *cam;                  /* camera of each correspondence */
+  int64_t n;
+} orc_rig_corr;
+
+/* Generalised P3P: rays (origins o[3*i..], directions f[3*i..], rig frame)
+ * through world points Xw.  Up to 8 rig poses, ordered by the depth along ray
+ * 0, then ray 1; depths (3 per pose) if non-NULL.  *ill = 1 for near-double
+ * roots or near-zero depths (another correct formulation may then differ). */
+int orc_gp3p(const double o[9], const double f[9], const double Xw[9], orc_pose out[8], double depths[24],
+             int32_t *ill);
+void orc_rig_score(const orc_pose *poses, int64_t np, const orc_rig_corr *c, const orc_rig_camera *cams,
+                   double tau, int32_t *count, double *msac);
+int orc_rig_lo(const orc_pose *start, const orc_rig_corr *c, const orc_rig_camera *cams, double tau, int32_t iters,
+               orc_pose *out, double *cost, int64_t *count);
+int orc_rig_refine(const orc_pose *start, const orc_rig_corr *c, const orc_rig_camera *cams, double tau, double s,
+                   int32_t iters, orc_pose *out, double *cost, int64_t *n_inl);
+int orc_rig_lo_ransac(const orc_rig_corr *c, const orc_rig_camera *cams, int32_t n_cams, const orc_params *p,
+                      orc_pose *pose, uint8_t *mask, orc_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

@@ -407,3 +407,91 @@ def dense_match_scene(n_views: int = 10, width: int = 560, height: int = 560, co
     pose = lambda R, t: np.concatenate([R.reshape(9), t])
     return DenseMatchWorkload(K, pose(R0, t0), np.tile(np.array(K), (V, 1)), np.stack([pose(R, t) for R, t in zip(Rs, ts)]),
                               mu, mv, conf, np.where(ok0, d0, np.inf), correct)
+
+
+# ---------------------------------------------------------------------------
+# Multi-camera rig queries (generalised absolute pose workload).
+# ---------------------------------------------------------------------------
+
+def _yaw(deg: float) -> np.ndarray:
+    a = np.radians(deg)
+    return np.array([[np.cos(a), 0.0, np.sin(a)], [0.0, 1.0, 0.0], [-np.sin(a), 0.0, np.cos(a)]])
+
+
+def head_rig(n_cams: int = 4, K=(380.0, 380.0, 320.0, 240.0)):
+    """A head-mounted rig: cameras yawed -80, -20, 20, 80 degrees (first
+    n_cams of them), centres about 10 cm apart.  Returns a list of
+    (K, cam_from_rig 12-vector)."""
+    yaws = [-80.0, -20.0, 20.0, 80.0, -140.0, 140.0, 0.0, 180.0][:n_cams]
+    rig = []
+    for k, y in enumerate(yaws):
+        Rc = _yaw(y).T                  # cam_from_rig rotation: the camera looks along yaw y
+        centre = np.array([0.05 * np.sin(np.radians(y)), -0.02 * (k % 2), 0.05 * np.cos(np.radians(y))])
+        tc = -Rc @ centre
+        rig.append((tuple(K), np.concatenate([Rc.reshape(9), tc])))
+    return rig
+
+
+@dataclass
+class RigQuery:
+    u: np.ndarray
+    v: np.ndarray
+    X: np.ndarray
+    Y: np.ndarray
+    Z: np.ndarray
+    w: np.ndarray | None
+    cam: np.ndarray            # int32 camera of each correspondence (grouped: non-decreasing)
+    rig: list                  # [(K, cam_from_rig)]
+    R: np.ndarray              # rig_from_world
+    t: np.ndarray
+    is_inlier: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.u.shape[0])
+
+    def corr(self) -> dict:
+        return dict(u=self.u, v=self.v, X=self.X, Y=self.Y, Z=self.Z, w=self.w, cam=self.cam)
+
+    def cam_start(self) -> np.ndarray:
+        return np.searchsorted(self.cam, np.arange(len(self.rig) + 1)).astype(np.int64)
+
+
+def make_rig_query(seed: int, n: int, inlier_ratio: float, sigma_px: float, n_cams: int = 4,
+                   width: int = DEFAULT_W, height: int = DEFAULT_H, zmin: float = 2.0, zmax: float = 20.0,
+                   tmax: float = 5.0, weights: str = "ones") -> RigQuery:
+    """A rig query: random rig_from_world pose; the correspondences split evenly
+    over the cameras (grouped by camera), in each camera inliers seen through
+    the true pose with Gaussian pixel noise and outliers with a uniform pixel
+    and an independent point from that camera's frustum."""
+    rng = rng_for(seed)
+    rig = head_rig(n_cams)
+    R = random_rotation(rng)
+    t = random_translation(rng, tmax)
+    us, vs, Xs, cams, inls = [], [], [], [], []
+    for c, (K, T) in enumerate(rig):
+        Rc, tc = T[:9].reshape(3, 3), T[9:]
+        nc = n // n_cams + (1 if c < n % n_cams else 0)
+        n_in = int(round(nc * inlier_ratio))
+        n_out = nc - n_in
+        px, py, Xc = _frustum_points(rng, n_in, K, width, height, zmin, zmax)
+        Xr = (Xc - tc) @ Rc                # rig frame
+        Xw_in = (Xr - t) @ R               # world
+        ou = rng.random(n_out) * width
+        ov = rng.random(n_out) * height
+        _, _, Xc_o = _frustum_points(rng, n_out, K, width, height, zmin, zmax)
+        Xw_out = ((Xc_o - tc) @ Rc - t) @ R
+        u = np.concatenate([px + rng.standard_normal(n_in) * sigma_px, ou])
+        v = np.concatenate([py + rng.standard_normal(n_in) * sigma_px, ov])
+        X = np.concatenate([Xw_in, Xw_out])
+        inl = np.concatenate([np.ones(n_in, bool), np.zeros(n_out, bool)])
+        perm = rng.permutation(nc)
+        us.append(u[perm]); vs.append(v[perm]); Xs.append(X[perm]); inls.append(inl[perm])
+        cams.append(np.full(nc, c, np.int32))
+    f = lambda a: np.ascontiguousarray(np.concatenate(a) if isinstance(a, list) else a, np.float32)
+    Xw = np.concatenate(Xs)
+    w = None
+    if weights != "ones":
+        w = np.maximum((0.05 + 0.95 * rng.random(n)).astype(np.float32), np.float32(0.0500001))
+    return RigQuery(f(us), f(vs), f(Xw[:, 0]), f(Xw[:, 1]), f(Xw[:, 2]), w, np.concatenate(cams), rig, R, t,
+                    np.concatenate(inls))
