@@ -317,6 +317,36 @@ def mapping_depth_leg(pk, steps=10):
                               "context, not a target")
 
 
+def rig_leg(pk, steps=10):
+    """Multi-camera rig queries (generalised absolute pose): a 4-camera head
+    rig, 20,000 correspondences (5,000 per camera), 35% inliers, sigma 1 px,
+    2,048 samples, tau 4 px, LO on the top 8, float32 scoring."""
+    import numpy as np
+    import oracle
+    from paper_2601_04185_amd import synth
+    q = synth.make_rig_query(1007, 20000, 0.35, 1.0)
+    d = pk.to_device(q)
+    prm = pk.make_params(threshold_px=4.0, fixed_samples=2048, batch=2048, lo_top_k=8)
+    ctx = pk.Context(0)
+    for _ in range(2):
+        pk.imloc_rig_lo_ransac_pnp(ctx, d, q.rig, q.cam_start(), prm)
+    lat = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        rc, R, t, st = pk.imloc_rig_lo_ransac_pnp(ctx, d, q.rig, q.cam_start(), prm)
+        lat.append(time.perf_counter() - t0)
+    ref = oracle.rig_lo_ransac(q.corr(), q.rig, threshold_px=4.0, fixed_samples=2048, batch=2048, lo_top_k=8)
+    return dict(workload="4-camera head rig, 20,000 correspondences (5,000 per camera), 35% inliers, sigma 1 px, "
+                         "2,048 generalised-P3P samples, tau 4 px, LO top-8, float32 scoring, float64 solves",
+                status=int(rc), p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
+                p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3), queries_per_s=round(steps / sum(lat), 2),
+                candidates=st["candidates"], residuals=st["residuals"],
+                residuals_per_s=round(st["residuals"] / float(np.median(lat)), 1),
+                rot_err_vs_oracle_deg=_rot_deg(R, ref["R"]),
+                t_rel_err_vs_oracle=float(np.linalg.norm(t - ref["t"]) / max(1.0, np.linalg.norm(ref["t"]))),
+                rot_err_vs_truth_deg=_rot_deg(R, q.R), t_err_vs_truth_m=float(np.linalg.norm(t - q.t)))
+
+
 def cpu_baseline(q, params, reps):
     """The oracle as it stands, on the host cores, on the same query."""
     import oracle
@@ -352,6 +382,7 @@ def main():
     ap.add_argument("--no-e2e", action="store_true", help="skip the lifting + RANSAC leg")
     ap.add_argument("--no-paper-mode", action="store_true", help="skip the paper-settings leg")
     ap.add_argument("--no-mapping", action="store_true", help="skip the mapping-time depth leg")
+    ap.add_argument("--no-rig", action="store_true", help="skip the multi-camera rig leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported (queries are independent, "
@@ -451,6 +482,8 @@ def main():
         out["paper_mode"] = paper_mode_leg(pk)
     if not args.no_mapping:
         out["mapping_depth"] = mapping_depth_leg(pk)
+    if not args.no_rig:
+        out["rig"] = rig_leg(pk)
     print(json.dumps(out))
 
 

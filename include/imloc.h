@@ -197,6 +197,47 @@ int imloc_lift_log8(imloc_ctx *ctx, const imloc_matches *m, int64_t n_matches, c
                     int32_t n_views, int32_t H, int32_t W, const imloc_camera *cams, const imloc_pose *poses,
                     int32_t subpixel, float min_conf, const imloc_corr_out *out, int64_t capacity, int32_t *n_out);
 
+/* A camera of a multi-camera rig: intrinsics and the camera's pose in the
+ * rig frame (cam_from_rig: x_cam = R x_rig + t). */
+typedef struct {
+  imloc_camera K;
+  imloc_pose cam_from_rig;
+} imloc_rig_camera;
+
+/* LO-RANSAC for a multi-camera rig query: generalised absolute pose (the
+ * appendix on LaMAR HoloLens rig queries, with the LO-RANSAC of Sec. 3.3
+ * "Pose Estimation").  The unknown is rig_from_world (R, t); a world point X
+ * seen by camera c projects through x_c = R_c (R X + t) + t_c and K_c.
+ * Minimal samples are drawn as in imloc_lo_ransac_pnp; each yields up to 8
+ * candidates from the generalised P3P (the distance equations of the three
+ * rays of the sampled points in the rig frame, reduced to a degree-8
+ * polynomial in the first depth); scoring, selection, local optimisation,
+ * stopping and the final Cauchy refinement are those of imloc_lo_ransac_pnp
+ * with every residual taken through its point's camera.
+ *   pts: device arrays of n correspondences GROUPED BY CAMERA: camera c owns
+ *   [cam_start[c], cam_start[c + 1]) (host array of n_cams + 1, from 0 to n).
+ *   cams: host array of n_cams (1..8).  pose_out: rig_from_world.  mask,
+ *   stats: as imloc_lo_ransac_pnp (mask in the caller's point order).
+ *   Needs imloc_rig_workspace_bytes(n, n_cams, p) of workspace. */
+size_t imloc_rig_workspace_bytes(int64_t n, int32_t n_cams, const imloc_ransac_params *p);
+int imloc_rig_lo_ransac_pnp(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_rig_camera *cams,
+                            int32_t n_cams, const int64_t *cam_start, const imloc_ransac_params *p,
+                            imloc_pose *pose_out, uint8_t *mask, imloc_stats *stats);
+
+/* Rig stages for the parity tests, as imloc_sample_p3p and imloc_score:
+ * sampling + generalised P3P of `count` samples (up to 8 candidates each, in
+ * order of the depth along the first ray, then the second), and scoring of np
+ * rig poses.  Workspace: imloc_rig_stage_workspace_bytes(n, n_cams, count)
+ * with count = samples or poses. */
+size_t imloc_rig_stage_workspace_bytes(int64_t n, int32_t n_cams, int64_t count);
+int imloc_rig_sample_gp3p(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_rig_camera *cams,
+                          int32_t n_cams, const int64_t *cam_start, uint64_t seed, uint64_t query_id,
+                          int32_t exhaustive, int64_t h0, int64_t count, double *poses, int64_t *h_out,
+                          int32_t *j_out, int32_t *n_cand, int32_t *triples);
+int imloc_rig_score(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_rig_camera *cams, int32_t n_cams,
+                    const int64_t *cam_start, const double *poses, int64_t np, double tau, int32_t precision,
+                    int32_t *count, double *msac);
+
 /* Dense matches of a mapping image against n_views covisible views, device
  * arrays [n_views][H][W]: pixel (row, col) of the mapping image matched to
  * (u, v) of view k with confidence conf. */

@@ -106,7 +106,7 @@ def lib():
         L.orc_rig_refine.restype = C.c_int
         L.orc_rig_lo_ransac.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.orc_rig_lo_ransac.restype = C.c_int
-        L.orc_triangulate.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_triangulate.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_tri_angle.argtypes = [vp, vp, dbl, vp, vp]
         L.orc_tri_angle.restype = dbl
         L.orc_tri_hypothesis.argtypes = [vp, vp, vp, vp, vp]
@@ -359,12 +359,14 @@ def triangulate(K0, T0, Ks, Ts, mu, mv, conf, min_conf=0.05, angle_deg=2.0, min_
     inl = np.zeros((H, W), np.int32)
     bv = np.zeros((H, W), np.int32)
     amb = np.zeros((H, W), np.uint8)
+    cost = np.zeros((H, W), np.float64)
+    curv = np.zeros((H, W), np.float64)
     T0a = _tri_poses(T0)
     Tsa = _tri_poses(Ts)
     prm = TriParams(float(min_conf), float(angle_deg), int(min_inliers), int(max_refine_iters))
     lib().orc_triangulate(H, W, _tri_cams([K0]), _p(T0a), V, _tri_cams(Ks), _p(Tsa), _p(mu), _p(mv), _p(cf),
-                          C.byref(prm), _p(depth), _p(inl), _p(bv), _p(amb))
-    return dict(depth=depth, inliers=inl, best_view=bv, ambiguous=amb.astype(bool))
+                          C.byref(prm), _p(depth), _p(inl), _p(bv), _p(amb), _p(cost), _p(curv))
+    return dict(depth=depth, inliers=inl, best_view=bv, ambiguous=amb.astype(bool), cost=cost, curv=curv)
 
 
 def tri_angle(C0, r0, l, Ck, rk) -> float:

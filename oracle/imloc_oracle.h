@@ -178,7 +178,9 @@ typedef struct {
 void orc_triangulate(int32_t H, int32_t W, const orc_camera *K0, const orc_pose *T0, int32_t V,
                      const orc_camera *Kv, const orc_pose *Tv, const float *mu, const float *mv,
                      const float *conf, const orc_tri_params *p, double *depth, int32_t *inliers,
-                     int32_t *best_view, uint8_t *ambiguous);
+                     int32_t *best_view, uint8_t *ambiguous, double *cost, double *curv);
+/* (cost, curv: optional [H][W] outputs, the refinement cost at the kept depth
+ * and its second derivative in l, 0 where no depth is kept) */
 /* The pieces, for the tests: angle of depth l for one observation (C0 + l r0
  * seen from Ck along unit rk), the depth minimising it (0 if none), and the
  * refinement of l0 over n weighted observations. */

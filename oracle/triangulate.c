@@ -125,8 +125,20 @@ static double tri_grad(const tri_pixel *px, double l, int n, const double (*Ck)[
  * difference, the Gauss-Newton curvature where that is not positive), a step
  * that raises the cost halved up to 30 times, until the step is below 1e-12 l
  * or max_iters steps. */
+static double tri_refine_full(const double C0[3], const double r0[3], double l0, int n, const double (*Ck)[3],
+                              const double (*rk)[3], const double *w, int max_iters, double *cost_out,
+                              double *curv_out);
+
 double orc_tri_refine(const double C0[3], const double r0[3], double l0, int n, const double (*Ck)[3],
                       const double (*rk)[3], const double *w, int max_iters) {
+  return tri_refine_full(C0, r0, l0, n, Ck, rk, w, max_iters, NULL, NULL);
+}
+
+/* The refinement, and the cost and its second derivative at the result (the
+ * derivative of the cost's derivative by the same central difference). */
+static double tri_refine_full(const double C0[3], const double r0[3], double l0, int n, const double (*Ck)[3],
+                              const double (*rk)[3], const double *w, int max_iters, double *cost_out,
+                              double *curv_out) {
   tri_pixel px;
   for (int c = 0; c < 3; ++c) { px.C0[c] = C0[c]; px.r0[c] = r0[c]; }
   double l = l0, e = tri_cost(&px, l, n, Ck, rk, w);
@@ -155,13 +167,19 @@ double orc_tri_refine(const double C0[3], const double r0[3], double l0, int n, 
     }
     if (!moved || fabs(step) <= 1e-12 * l) break;
   }
+  if (cost_out) *cost_out = e;
+  if (curv_out) {
+    const double dl = 1e-6 * l;
+    /* d(cost)/dl = 2 g, so d2(cost)/dl2 = 2 dg/dl */
+    *curv_out = 2.0 * (tri_grad(&px, l + dl, n, Ck, rk, w, NULL) - tri_grad(&px, l - dl, n, Ck, rk, w, NULL)) / (2.0 * dl);
+  }
   return l;
 }
 
 void orc_triangulate(int32_t H, int32_t W, const orc_camera *K0, const orc_pose *T0, int32_t V,
                      const orc_camera *Kv, const orc_pose *Tv, const float *mu, const float *mv, const float *conf,
                      const orc_tri_params *p, double *depth, int32_t *inliers, int32_t *best_view,
-                     uint8_t *ambiguous) {
+                     uint8_t *ambiguous, double *cost, double *curv) {
   const double thr = p->angle_deg * (M_PI / 180.0);
   const float min_conf = (float)p->min_conf;
   double (*Cv)[3] = malloc(sizeof(double[3]) * (V > 0 ? V : 1));
@@ -203,6 +221,8 @@ void orc_triangulate(int32_t H, int32_t W, const orc_camera *K0, const orc_pose 
       }
       depth[pix] = 0.0;
       inliers[pix] = best_n;
+      if (cost) cost[pix] = 0.0;
+      if (curv) curv[pix] = 0.0;
       if (best_view) best_view[pix] = best;
       if (ambiguous) ambiguous[pix] = margin < 1e-9;
       if (best < 0 || best_n < p->min_inliers) continue;
@@ -212,8 +232,11 @@ void orc_triangulate(int32_t H, int32_t W, const orc_camera *K0, const orc_pose 
         for (int c = 0; c < 3; ++c) { Cs[n][c] = Cv[k][c]; rs[n][c] = rk[k][c]; }
         ws[n++] = wk[k];
       }
-      const double l = orc_tri_refine(px.C0, px.r0, best_l, n, (const double (*)[3])Cs, (const double (*)[3])rs, ws,
-                                      p->max_refine_iters);
+      double ce = 0.0, cc = 0.0;
+      const double l = tri_refine_full(px.C0, px.r0, best_l, n, (const double (*)[3])Cs, (const double (*)[3])rs, ws,
+                                       p->max_refine_iters, &ce, &cc);
+      if (cost) cost[pix] = ce;
+      if (curv) curv[pix] = cc;
       depth[pix] = l > 0.0 ? l : 0.0;
     }
   }

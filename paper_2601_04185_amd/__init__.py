@@ -35,7 +35,8 @@ EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_err
             "imloc_server_destroy", "imloc_server_submit", "imloc_server_step", "imloc_server_poll",
             "imloc_server_usage",
             "imloc_lift", "imloc_lift_log8", "imloc_depth_encode_log8", "imloc_triangulate_workspace_bytes",
-            "imloc_triangulate_depth",
+            "imloc_triangulate_depth", "imloc_rig_workspace_bytes", "imloc_rig_lo_ransac_pnp",
+            "imloc_rig_stage_workspace_bytes", "imloc_rig_sample_gp3p", "imloc_rig_score",
             "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score",
             "imloc_local_optimize", "imloc_refine"]
 
@@ -129,6 +130,11 @@ def lib():
             "imloc_lift_log8": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_depth_encode_log8": ([vp, vp, i64, vp], C.c_int),
             "imloc_triangulate_workspace_bytes": ([i32], C.c_size_t),
+            "imloc_rig_workspace_bytes": ([i64, i32, vp], C.c_size_t),
+            "imloc_rig_lo_ransac_pnp": ([vp, vp, i64, vp, i32, vp, vp, vp, vp, vp], C.c_int),
+            "imloc_rig_stage_workspace_bytes": ([i64, i32, i64], C.c_size_t),
+            "imloc_rig_sample_gp3p": ([vp, vp, i64, vp, i32, vp, u64, u64, i32, i64, i64, vp, vp, vp, vp, vp], C.c_int),
+            "imloc_rig_score": ([vp, vp, i64, vp, i32, vp, vp, i64, C.c_double, i32, vp, vp], C.c_int),
             "imloc_triangulate_depth": ([vp, i32, i32, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "imloc_lo_ransac_pnp": ([vp, vp, i64, vp, vp, vp, vp, vp], C.c_int),
             "imloc_lo_ransac_pnp_batch": ([vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp], C.c_int),
@@ -260,6 +266,79 @@ def imloc_lo_ransac_pnp_batch(ctx: Context, corrs: list, Ks: list, params, masks
     ctx.check(lib().imloc_lo_ransac_pnp_batch(ctx.h, cs, ns, cams, nq, pa, len(plist), poses, mk, stats, status))
     out = [(np.array(p.R[:]).reshape(3, 3), np.array(p.t[:])) for p in poses]
     return list(status), out, [s.as_dict() for s in stats]
+
+
+class RigCamera(C.Structure):
+    _fields_ = [("K", Camera), ("cam_from_rig", Pose)]
+
+
+def rig_struct(rig):
+    """rig: list of (K (fx, fy, cx, cy), cam_from_rig as 12 numbers R row-major, t)."""
+    out = (RigCamera * len(rig))()
+    for k, (K, T) in enumerate(rig):
+        T = np.asarray(T, np.float64).reshape(12)
+        out[k] = RigCamera(_cam(K), Pose((C.c_double * 9)(*T[:9]), (C.c_double * 3)(*T[9:])))
+    return out
+
+
+def _cam_start(cam_start):
+    a = np.ascontiguousarray(np.asarray(cam_start, np.int64))
+    return (C.c_int64 * len(a))(*a.tolist())
+
+
+def imloc_rig_lo_ransac_pnp(ctx: Context, corr: dict, rig, cam_start, params: RansacParams, mask=None):
+    """LO-RANSAC for a multi-camera rig query.  corr: dict of float32 cuda
+    tensors grouped by camera (camera c owns [cam_start[c], cam_start[c+1])).
+    Returns (status, R, t (rig_from_world), stats dict)."""
+    n = int(corr["u"].numel())
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    cams = rig_struct(rig)
+    starts = _cam_start(cam_start)
+    ctx.ensure_workspace(lib().imloc_rig_workspace_bytes(n, len(rig), C.byref(params)))
+    pose = Pose()
+    st = Stats()
+    rc = ctx.check(lib().imloc_rig_lo_ransac_pnp(ctx.h, C.byref(cs), n, cams, len(rig), starts, C.byref(params),
+                                                 C.byref(pose), _ptr(mask), C.byref(st)))
+    return rc, np.array(pose.R[:]).reshape(3, 3), np.array(pose.t[:]), st.as_dict()
+
+
+def imloc_rig_sample_gp3p(ctx: Context, corr: dict, rig, cam_start, seed: int, query_id: int, h0: int, count: int,
+                          exhaustive=0, want_triples=False):
+    """-> dict of cuda tensors poses (nc, 12) float64 (rig_from_world), h (nc,), j (nc,) and triples."""
+    torch = ctx.torch
+    dev = corr["u"].device
+    n = int(corr["u"].numel())
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    cap = 8 * max(count, 1)
+    poses = torch.empty((cap, 12), dtype=torch.float64, device=dev)
+    h = torch.empty(cap, dtype=torch.int64, device=dev)
+    j = torch.empty(cap, dtype=torch.int32, device=dev)
+    nc = torch.zeros(1, dtype=torch.int32, device=dev)
+    tri = torch.empty((max(count, 1), 3), dtype=torch.int32, device=dev) if want_triples else None
+    ctx.ensure_workspace(lib().imloc_rig_stage_workspace_bytes(n, len(rig), count))
+    ctx.check(lib().imloc_rig_sample_gp3p(ctx.h, C.byref(cs), n, rig_struct(rig), len(rig), _cam_start(cam_start),
+                                          seed, query_id, exhaustive, h0, count, _ptr(poses), _ptr(h), _ptr(j),
+                                          _ptr(nc), _ptr(tri)))
+    k = int(nc.item())
+    out = dict(poses=poses[:k], h=h[:k], j=j[:k])
+    if want_triples:
+        out["triples"] = tri[:count]
+    return out
+
+
+def imloc_rig_score(ctx: Context, corr: dict, rig, cam_start, poses, threshold_px: float, precision=IMLOC_FP32_SCORE):
+    """poses: cuda float64 (np, 12) rig_from_world -> (count int32, msac float64) cuda tensors."""
+    torch = ctx.torch
+    n = int(corr["u"].numel())
+    npz = int(poses.shape[0])
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    cnt = torch.empty(max(npz, 1), dtype=torch.int32, device=poses.device)
+    ms = torch.empty(max(npz, 1), dtype=torch.float64, device=poses.device)
+    ctx.ensure_workspace(lib().imloc_rig_stage_workspace_bytes(n, len(rig), npz))
+    ctx.check(lib().imloc_rig_score(ctx.h, C.byref(cs), n, rig_struct(rig), len(rig), _cam_start(cam_start),
+                                    _ptr(poses.contiguous()), npz, float(threshold_px), int(precision), _ptr(cnt),
+                                    _ptr(ms)))
+    return cnt[:npz], ms[:npz]
 
 
 def imloc_lift(ctx: Context, matches: dict, depth, cams, poses, subpixel=True, min_conf=0.05, capacity=None):

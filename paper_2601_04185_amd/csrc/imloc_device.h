@@ -78,17 +78,17 @@ __device__ inline bool unrank_triple(uint64_t h, uint64_t n, int idx[3]) {
 // ---------------------------------------------------------------------------
 // Small dense algebra (float64).
 // ---------------------------------------------------------------------------
-__device__ inline double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
-__device__ inline void cross3(const double a[3], const double b[3], double o[3]) {
+__host__ __device__ inline double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__host__ __device__ inline void cross3(const double a[3], const double b[3], double o[3]) {
   o[0] = a[1] * b[2] - a[2] * b[1];
   o[1] = a[2] * b[0] - a[0] * b[2];
   o[2] = a[0] * b[1] - a[1] * b[0];
 }
-__device__ inline double det3(const double M[9]) {
+__host__ __device__ inline double det3(const double M[9]) {
   return M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) + M[2] * (M[3] * M[7] - M[4] * M[6]);
 }
 // adjugate (transpose of the cofactor matrix)
-__device__ inline void adj3(const double M[9], double A[9]) {
+__host__ __device__ inline void adj3(const double M[9], double A[9]) {
   A[0] = M[4] * M[8] - M[5] * M[7];
   A[1] = M[2] * M[7] - M[1] * M[8];
   A[2] = M[1] * M[5] - M[2] * M[4];
@@ -243,6 +243,7 @@ __device__ inline void cubic_roots_in(double c0, double c1, double c2, double c3
       if (!(xn > a && xn < b) || !(fabs(xn - x) < 0.5 * dx_old)) xn = 0.5 * (a + b);
       dx_old = fabs(xn - x);
       if (xn == x || xn <= a || xn >= b) break;
+      if (dx_old <= 2e-16 * fabs(x)) { x = xn; break; }  // converged to rounding level
       x = xn;
     }
     emit(a == b ? a : x);

@@ -20,6 +20,7 @@ struct CorrF32 {
 struct CamH { double fx, fy, cx, cy; };
 
 constexpr int kMaxTopK = 32;       // local optimisations per query and batch, at most
+constexpr int kMaxCams = 8;        // cameras of a rig query, at most
 constexpr int kScorePPL32 = 8;     // correspondences per lane, float32 scoring (fixes the summation order)
 constexpr int kScorePPL64 = 2;     // correspondences per lane, float64 scoring
 constexpr double kGainScale = 4294967296.0;  // fixed-point scale of the accumulated truncated-cost gain
@@ -68,13 +69,28 @@ struct QueryDesc {
   int64_t B;             // samples of the current round (0: inactive)
   uint8_t* mask;         // inlier mask output (device) or null
   int32_t fresh;         // 1: admitted with this table upload (initialise, gather its subset)
-  int32_t pad_;
+  int32_t ncam;          // 0: one camera (fx, fy, cx, cy; poses cam_from_world); 1..kMaxCams: a rig
+  const double* rig;     // rig cameras (device) [ncam][16]: fx, fy, cx, cy, cam_from_rig R (9), t (3)
+  int64_t proj_off;      // first float of this query's projection rows: 16 per camera per candidate slot
+  int64_t segS[kMaxCams + 1];  // rig: camera c owns scoring-set points [segS[c], segS[c + 1])
+  int64_t segF[kMaxCams + 1];  // rig: camera c owns full-set points [segF[c], segF[c + 1])
 };
+
+// Camera of point i of a rig query (segments seg[0..ncam]); 0 for one camera.
+__host__ __device__ inline int cam_of(const int64_t* seg, int ncam, int64_t i) {
+  int c = 0;
+  while (c + 1 < ncam && i >= seg[c + 1]) ++c;
+  return c;
+}
+
+// Rows per candidate slot: one set of 16 floats per camera.
+__host__ __device__ inline int rows_per_slot(const QueryDesc& d) { return d.ncam > 0 ? d.ncam : 1; }
 
 // Candidate arrays of all queries of a batch (device), indexed by slot.
 struct CandBuf {
   double* pose;      // [slots][12]
-  float* proj;       // [slots][16] float32 rows of K [R | t], rows a and b divided by tau (12 used)
+  float* proj;       // per query from proj_off: [slots][cameras][16] float32 rows of K [R | t] (rig: of
+                     // K_c [R_c R | R_c t + t_c]), rows a and b divided by tau (12 used)
   int64_t* h;        // [slots] sample index
   int32_t* j;        // [slots] solution index
   uint32_t* cnt;     // [slots] inlier count (accumulated by scoring)
@@ -142,6 +158,10 @@ hipError_t launch_end_round(const QueryDesc* qd, BestState* st, int nq, int32_t*
 // Samples [drawn, drawn + B) of every query; max_b bounds B.
 hipError_t launch_sample_p3p(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int64_t max_b,
                              int32_t* triples, hipStream_t s);
+// Rig queries of the batch (the one-camera ones are skipped): generalised P3P,
+// up to 8 candidates per sample.
+hipError_t launch_sample_gp3p(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int64_t max_b,
+                              int32_t* triples, hipStream_t s);
 // Candidates from given float64 poses (query 0): projection rows, zeroed accumulators.
 hipError_t launch_set_candidates(const QueryDesc* qd, const double* poses, int64_t np, CandBuf cb, hipStream_t s);
 
@@ -170,15 +190,17 @@ hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, i
 // full set, if the query has just finished sampling.
 int gn_chunks(int64_t n);
 size_t gn_scratch_bytes(int nprob, int chunks_max);
+// any_rig: some problem belongs to a rig query (selects the kernel variant
+// that takes residuals through rig cameras)
 hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
                      const double* start_direct, int nprob, int kmax, int chunks_max, int iters_max, void* scratch,
-                     double* out_pose, double* out_cost, int64_t* out_count, hipStream_t s);
+                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, hipStream_t s);
 hipError_t launch_update_best(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
                               const double* lo_pose, const double* lo_cost, const int64_t* lo_count, int nq,
                               int kmax, BestState* st, hipStream_t s);
 hipError_t launch_refine(const QueryDesc* qd, BestState* st, const double* start_direct, int nq, int chunks_max,
                          int iters_max, uint8_t* in_set, void* scratch, double* out_pose, double* out_cost,
-                         hipStream_t s);
+                         bool any_rig, hipStream_t s);
 // mask and inlier count of the final pose of every query that just finished
 // (all != 0: of every query, each with a pose)
 hipError_t launch_mask(const QueryDesc* qd, BestState* st, const double* fin_pose, int nq, int64_t max_n, int all,

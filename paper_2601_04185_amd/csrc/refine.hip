@@ -39,6 +39,34 @@ __device__ inline void acc_point(double* a, const Cam& K, double x, double y, do
   for (int r = 0; r < 6; ++r) a[21 + r] = fma(wt, J0[r] * du + J1[r] * dv, a[21 + r]);
 }
 
+// The same for a rig camera: x_c = R_c x_r + t_c with the rig-frame point x_r
+// moving under the left update of the rig pose, so the rows of d(pixel)/dx_c
+// are carried through R_c: J = [x_r x r, r] for each row r of d(pixel)/dx_c R_c.
+__device__ inline void acc_point_rig(double* a, const Cam& K, const double xr[3], double x, double y, double z,
+                                     const double* Rc, double du, double dv, double wt) {
+  const double iz = 1.0 / z;
+  const double p0[3] = {K.fx * iz, 0.0, -K.fx * x * iz * iz};
+  const double p1[3] = {0.0, K.fy * iz, -K.fy * y * iz * iz};
+  double r0[3], r1[3];
+  for (int c = 0; c < 3; ++c) {
+    r0[c] = p0[0] * Rc[c] + p0[1] * Rc[3 + c] + p0[2] * Rc[6 + c];
+    r1[c] = p1[0] * Rc[c] + p1[1] * Rc[3 + c] + p1[2] * Rc[6 + c];
+  }
+  double w0[3], w1[3];
+  cross3(xr, r0, w0);
+  cross3(xr, r1, w1);
+  const double J0[6] = {w0[0], w0[1], w0[2], r0[0], r0[1], r0[2]};
+  const double J1[6] = {w1[0], w1[1], w1[2], r1[0], r1[1], r1[2]};
+  int k = 0;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+#pragma unroll
+    for (int c = r; c < 6; ++c) { a[k] = fma(wt, J0[r] * J0[c] + J1[r] * J1[c], a[k]); ++k; }
+  }
+#pragma unroll
+  for (int r = 0; r < 6; ++r) a[21 + r] = fma(wt, J0[r] * du + J1[r] * dv, a[21 + r]);
+}
+
 // Per-problem Gauss-Newton state, double-buffered across launches.
 struct GNState {
   double cur[12];      // accepted pose
@@ -133,7 +161,7 @@ __device__ __forceinline__ bool gn_solve_step(const double* tot, const double* c
 // MODE 0 (local optimisation): truncated cost over the scoring set.
 // MODE 1 (final refinement): Cauchy cost over the in-set, which launch 0
 // marks as the inliers (tau) of the start pose.
-template <int MODE>
+template <int MODE, bool RIG>
 __global__ __launch_bounds__(kGNThreads) void gn_kernel(
     const QueryDesc* __restrict__ qd, CandBuf cb, const int32_t* __restrict__ sel, const int32_t* __restrict__ n_sel,
     const double* __restrict__ start_direct, BestState* __restrict__ bst, int kmax, int k, GNState* __restrict__ gst,
@@ -193,6 +221,11 @@ __global__ __launch_bounds__(kGNThreads) void gn_kernel(
   }
 
 
+  __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
+  const bool rig = RIG && d.ncam > 0;  // the RIG = false variant runs batches without rig queries
+  const int64_t* seg = MODE == 0 ? d.segS : d.segF;
+  if (rig)
+    for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
   __shared__ double s_grp[8][kAcc];
   __shared__ double s_tot[kAcc];
   __shared__ double s_cur[12], s_eval[12];
@@ -292,21 +325,33 @@ __global__ __launch_bounds__(kGNThreads) void gn_kernel(
     const int64_t i = base + (int64_t)t * kGNThreads;
     const double X = pX[t], Y = pY[t], Z = pZ[t];
     const double w = pw[t];
-    const double x = P[0] * X + P[1] * Y + P[2] * Z + P[9];
-    const double y = P[3] * X + P[4] * Y + P[5] * Z + P[10];
-    const double z = P[6] * X + P[7] * Y + P[8] * Z + P[11];
+    double x = P[0] * X + P[1] * Y + P[2] * Z + P[9];
+    double y = P[3] * X + P[4] * Y + P[5] * Z + P[10];
+    double z = P[6] * X + P[7] * Y + P[8] * Z + P[11];
+    Cam Kp = K;
+    const double* Rc = nullptr;
+    const double xr[3] = {x, y, z};
+    if (rig) {  // through the point's camera: x_c = R_c x_r + t_c
+      const double* rc = s_rig + 16 * cam_of(seg, d.ncam, i);
+      Kp = Cam{rc[0], rc[1], rc[2], rc[3]};
+      Rc = rc + 4;
+      x = Rc[0] * xr[0] + Rc[1] * xr[1] + Rc[2] * xr[2] + rc[13];
+      y = Rc[3] * xr[0] + Rc[4] * xr[1] + Rc[5] * xr[2] + rc[14];
+      z = Rc[6] * xr[0] + Rc[7] * xr[1] + Rc[8] * xr[2] + rc[15];
+    }
     double du = 0.0, dv = 0.0, r2 = 0.0;
     const bool front = z > 0.0;
     if (front) {
-      du = K.fx * x / z + K.cx - (double)pu[t];
-      dv = K.fy * y / z + K.cy - (double)pv[t];
+      du = Kp.fx * x / z + Kp.cx - (double)pu[t];
+      dv = Kp.fy * y / z + Kp.cy - (double)pv[t];
       r2 = du * du + dv * dv;
     }
     if (MODE == 0) {
       if (front && r2 < tau2) {
         a[27] += w * r2;
         a[28] += 1.0;
-        acc_point(a, K, x, y, z, du, dv, w);
+        if (rig) acc_point_rig(a, Kp, xr, x, y, z, Rc, du, dv, w);
+        else acc_point(a, K, x, y, z, du, dv, w);
       } else {
         a[27] += w * tau2;
       }
@@ -322,7 +367,8 @@ __global__ __launch_bounds__(kGNThreads) void gn_kernel(
         continue;
       }
       a[27] += w * s2 * log1p(r2 / s2);
-      acc_point(a, K, x, y, z, du, dv, w / (1.0 + r2 / s2));
+      if (rig) acc_point_rig(a, Kp, xr, x, y, z, Rc, du, dv, w / (1.0 + r2 / s2));
+      else acc_point(a, K, x, y, z, du, dv, w / (1.0 + r2 / s2));
     }
   }
   __shared__ double s_part[kGNWaves][kAcc];
@@ -349,13 +395,14 @@ static void split_scratch(void* scratch, int nprob, GNState** st, double** part)
 
 hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
                      const double* start_direct, int nprob, int kmax, int chunks_max, int iters_max, void* scratch,
-                     double* out_pose, double* out_cost, int64_t* out_count, hipStream_t s) {
+                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   GNState* st;
   double* part;
   split_scratch(scratch, nprob, &st, &part);
+  auto kern = any_rig ? gn_kernel<0, true> : gn_kernel<0, false>;
   for (int k = 0; k <= iters_max + 1; ++k)
-    hipLaunchKernelGGL(gn_kernel<0>, dim3(chunks_max, nprob), dim3(kGNThreads), 0, s, qd, cb, sel, n_sel,
+    hipLaunchKernelGGL(kern, dim3(chunks_max, nprob), dim3(kGNThreads), 0, s, qd, cb, sel, n_sel,
                        start_direct, (BestState*)nullptr, kmax, k, st, part, chunks_max, nprob, (uint8_t*)nullptr,
                        out_pose, out_cost, out_count);
   return hipGetLastError();
@@ -363,14 +410,15 @@ hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const 
 
 hipError_t launch_refine(const QueryDesc* qd, BestState* bst, const double* start_direct, int nq, int chunks_max,
                          int iters_max, uint8_t* in_set, void* scratch, double* out_pose, double* out_cost,
-                         hipStream_t s) {
+                         bool any_rig, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   GNState* st;
   double* part;
   split_scratch(scratch, nq, &st, &part);
   CandBuf none{};
+  auto kern = any_rig ? gn_kernel<1, true> : gn_kernel<1, false>;
   for (int k = 0; k <= iters_max + 1; ++k)
-    hipLaunchKernelGGL(gn_kernel<1>, dim3(chunks_max, nq), dim3(kGNThreads), 0, s, qd, none,
+    hipLaunchKernelGGL(kern, dim3(chunks_max, nq), dim3(kGNThreads), 0, s, qd, none,
                        (const int32_t*)nullptr, (const int32_t*)nullptr, start_direct, bst, 1, k, st, part, chunks_max,
                        nq, in_set, out_pose, out_cost, (int64_t*)nullptr);
   return hipGetLastError();
@@ -423,12 +471,22 @@ __global__ void mask_kernel(const QueryDesc* __restrict__ qd, BestState* __restr
   long long in = 0;
   if (i < d.n && have) {
     const double X = gmem(d.full.X)[i], Y = gmem(d.full.Y)[i], Z = gmem(d.full.Z)[i];
-    const double x = pose[0] * X + pose[1] * Y + pose[2] * Z + pose[9];
-    const double y = pose[3] * X + pose[4] * Y + pose[5] * Z + pose[10];
-    const double z = pose[6] * X + pose[7] * Y + pose[8] * Z + pose[11];
+    double x = pose[0] * X + pose[1] * Y + pose[2] * Z + pose[9];
+    double y = pose[3] * X + pose[4] * Y + pose[5] * Z + pose[10];
+    double z = pose[6] * X + pose[7] * Y + pose[8] * Z + pose[11];
+    double fx = d.fx, fy = d.fy, cx = d.cx, cy = d.cy;
+    if (d.ncam > 0) {  // through the point's rig camera
+      const double* rc = d.rig + 16 * cam_of(d.segF, d.ncam, i);
+      const double* Rc = rc + 4;
+      const double xr[3] = {x, y, z};
+      x = Rc[0] * xr[0] + Rc[1] * xr[1] + Rc[2] * xr[2] + rc[13];
+      y = Rc[3] * xr[0] + Rc[4] * xr[1] + Rc[5] * xr[2] + rc[14];
+      z = Rc[6] * xr[0] + Rc[7] * xr[1] + Rc[8] * xr[2] + rc[15];
+      fx = rc[0]; fy = rc[1]; cx = rc[2]; cy = rc[3];
+    }
     if (z > 0.0) {
-      const double du = d.fx * x / z + d.cx - (double)gmem(d.full.u)[i];
-      const double dv = d.fy * y / z + d.cy - (double)gmem(d.full.v)[i];
+      const double du = fx * x / z + cx - (double)gmem(d.full.u)[i];
+      const double dv = fy * y / z + cy - (double)gmem(d.full.v)[i];
       in = (du * du + dv * dv < d.tau * d.tau) ? 1 : 0;
     }
   }

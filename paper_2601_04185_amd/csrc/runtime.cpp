@@ -116,10 +116,37 @@ struct QPlan {
   bool subset;
   int64_t total, batch, cap;
   int k;
+  int ncam = 0;  // 0: one camera; else the cameras of a rig
 };
 
-QPlan plan_query(int64_t n, const imloc_ransac_params* p) {
+// Host view of a rig query (ncam == 0: a one-camera query).
+struct RigHost {
+  int32_t ncam;
+  const imloc_rig_camera* cams;  // [ncam]
+  const int64_t* cam_start;      // [ncam + 1], correspondences grouped by camera
+};
+
+int rig_check(imloc_ctx* ctx, const RigHost& r, int64_t n) {
+  if (r.ncam < 1 || r.ncam > kMaxCams) return set_err(ctx, IMLOC_EINVAL, "n_cams must be in 1..%d", kMaxCams);
+  if (!r.cams || !r.cam_start) return set_err(ctx, IMLOC_EINVAL, "null rig arrays");
+  if (r.cam_start[0] != 0 || r.cam_start[r.ncam] != n)
+    return set_err(ctx, IMLOC_EINVAL, "cam_start must run from 0 to n");
+  for (int c = 0; c < r.ncam; ++c) {
+    if (r.cam_start[c + 1] < r.cam_start[c]) return set_err(ctx, IMLOC_EINVAL, "cam_start must not decrease");
+    const imloc_rig_camera& k = r.cams[c];
+    if (!(k.K.fx > 0.0 && k.K.fy > 0.0 && std::isfinite(k.K.cx) && std::isfinite(k.K.cy)))
+      return set_err(ctx, IMLOC_EINVAL, "rig camera %d: bad intrinsics", c);
+    for (int e = 0; e < 9; ++e)
+      if (!std::isfinite(k.cam_from_rig.R[e])) return set_err(ctx, IMLOC_EINVAL, "rig camera %d: bad pose", c);
+    for (int e = 0; e < 3; ++e)
+      if (!std::isfinite(k.cam_from_rig.t[e])) return set_err(ctx, IMLOC_EINVAL, "rig camera %d: bad pose", c);
+  }
+  return IMLOC_OK;
+}
+
+QPlan plan_query(int64_t n, const imloc_ransac_params* p, int ncam = 0) {
   QPlan s;
+  s.ncam = ncam;
   s.n = n;
   s.subset = p->max_score_points > 0 && n > p->max_score_points;
   s.m = s.subset ? p->max_score_points : n;
@@ -127,7 +154,7 @@ QPlan plan_query(int64_t n, const imloc_ransac_params* p) {
   s.batch = p->batch > 0 ? p->batch : 1024;
   if (s.batch > s.total) s.batch = s.total;
   if (s.batch < 1) s.batch = 1;
-  s.cap = 4 * s.batch;
+  s.cap = (ncam > 0 ? 8 : 4) * s.batch;  // P3P gives at most 4 candidates, generalised P3P 8
   s.k = p->lo_top_k < 1 ? 1 : (p->lo_top_k > kMaxTopK ? kMaxTopK : p->lo_top_k);
   return s;
 }
@@ -137,7 +164,10 @@ struct Engine {
   int nq = 0, kmax = 1, chunks_lo = 1, chunks_fin = 1, lo_iters = 0, fin_iters = 0;
   int64_t max_batch = 1, max_n = 0, slots = 0, max_rounds = 0;
   bool all_fixed = true;
+  bool any_rig = false;
+  int64_t max_cap = 4, proj_floats = 16, rig_doubles = 0;
   QueryDesc* qd;
+  double* rig;
   BestState* st;
   CandBuf cb;
   int64_t* item_off;
@@ -154,7 +184,7 @@ struct Engine {
   void* gn_lo;
   void* gn_fin;
   float* subset;
-  std::vector<int64_t> cand_off, in_set_off, subset_off;
+  std::vector<int64_t> cand_off, in_set_off, subset_off, proj_off, rig_off;
 };
 
 void plan_engine(Engine& e, int nq, const QPlan* pl, const imloc_ransac_params* const* pp) {
@@ -162,10 +192,18 @@ void plan_engine(Engine& e, int nq, const QPlan* pl, const imloc_ransac_params* 
   e.cand_off.resize(nq);
   e.in_set_off.resize(nq);
   e.subset_off.resize(nq);
-  int64_t slots = 0, in_bytes = 0, sub = 0;
+  e.proj_off.resize(nq);
+  e.rig_off.resize(nq);
+  int64_t slots = 0, in_bytes = 0, sub = 0, proj = 0, rigd = 0;
   for (int q = 0; q < nq; ++q) {
     e.cand_off[q] = slots;
     slots += pl[q].cap;
+    e.proj_off[q] = proj;
+    proj += 16 * pl[q].cap * std::max(1, pl[q].ncam);
+    e.rig_off[q] = rigd;
+    rigd += 16 * pl[q].ncam;
+    e.max_cap = std::max(e.max_cap, pl[q].cap);
+    if (pl[q].ncam > 0) e.any_rig = true;
     e.in_set_off[q] = in_bytes;
     in_bytes += (pl[q].n + 255) & ~int64_t(255);
     e.subset_off[q] = sub;
@@ -181,6 +219,8 @@ void plan_engine(Engine& e, int nq, const QPlan* pl, const imloc_ransac_params* 
     if (pp[q]->fixed_samples <= 0) e.all_fixed = false;
   }
   e.slots = std::max<int64_t>(slots, 1);
+  e.proj_floats = std::max<int64_t>(proj, 16);
+  e.rig_doubles = rigd;
   e.in_set_off.push_back(in_bytes);
   e.subset_off.push_back(sub);
 }
@@ -191,7 +231,8 @@ void carve_engine(Arena& a, Engine& e) {
   e.qd = a.take<QueryDesc>(nq);
   e.st = a.take<BestState>(nq);
   e.cb.pose = a.take<double>(12 * S);
-  e.cb.proj = a.take<float>(16 * S);
+  e.cb.proj = a.take<float>((size_t)e.proj_floats);
+  e.rig = a.take<double>((size_t)std::max<int64_t>(e.rig_doubles, 16));
   e.cb.h = a.take<int64_t>(S);
   e.cb.j = a.take<int32_t>(S);
   e.cb.cnt = a.take<uint32_t>(S);
@@ -279,7 +320,7 @@ void identity_pose(imloc_pose* p) {
 }
 
 QueryDesc make_desc(const imloc_corr* pts, int64_t n, const imloc_camera* K, const imloc_ransac_params* p,
-                    const QPlan& pl, const Engine& e, int q, uint8_t* mask) {
+                    const QPlan& pl, const Engine& e, int q, uint8_t* mask, const RigHost* rig = nullptr) {
   QueryDesc d;
   std::memset(&d, 0, sizeof(d));
   d.full = n > 0 ? to_corr(pts) : kNoCorr;
@@ -292,7 +333,7 @@ QueryDesc make_desc(const imloc_corr* pts, int64_t n, const imloc_camera* K, con
   }
   d.n = n;
   d.m = pl.m;
-  d.fx = K->fx; d.fy = K->fy; d.cx = K->cx; d.cy = K->cy;
+  if (K) { d.fx = K->fx; d.fy = K->fy; d.cx = K->cx; d.cy = K->cy; }
   d.tau = p->threshold_px;
   d.cauchy_s = p->cauchy_scale_px > 0.0 ? p->cauchy_scale_px : 1.0;
   d.confidence = p->confidence;
@@ -313,13 +354,40 @@ QueryDesc make_desc(const imloc_corr* pts, int64_t n, const imloc_camera* K, con
   d.B = 0;
   d.mask = mask;
   d.fresh = 1;
+  d.proj_off = e.proj_off[q];
+  d.ncam = 0;
+  if (rig && rig->ncam > 0) {
+    d.ncam = rig->ncam;
+    d.rig = e.rig + e.rig_off[q];
+    for (int c = 0; c <= rig->ncam; ++c) {
+      d.segF[c] = rig->cam_start[c];
+      // stride subset j -> point floor(j n / m): camera c starts at j = ceil(start_c m / n)
+      d.segS[c] = pl.subset ? (int64_t)(((unsigned __int128)rig->cam_start[c] * (uint64_t)pl.m + (uint64_t)n - 1) /
+                                        (uint64_t)n)
+                            : rig->cam_start[c];
+    }
+  }
   return d;
+}
+
+// Rig tables of a batch in host staging: per camera fx, fy, cx, cy, R (9), t (3).
+void fill_rig_tables(double* h, int nq, const RigHost* rigs, const Engine& e) {
+  if (!rigs) return;
+  for (int q = 0; q < nq; ++q) {
+    for (int c = 0; c < rigs[q].ncam; ++c) {
+      double* o = h + e.rig_off[q] + 16 * c;
+      const imloc_rig_camera& k = rigs[q].cams[c];
+      o[0] = k.K.fx; o[1] = k.K.fy; o[2] = k.K.cx; o[3] = k.K.cy;
+      for (int x = 0; x < 9; ++x) o[4 + x] = k.cam_from_rig.R[x];
+      for (int x = 0; x < 3; ++x) o[13 + x] = k.cam_from_rig.t[x];
+    }
+  }
 }
 
 // Validate, plan, carve and run a batch.  Outputs are host arrays of nq.
 int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, const imloc_camera* K,
               const imloc_ransac_params* params, int n_params, imloc_pose* poses, uint8_t* const* masks,
-              imloc_stats* stats, int32_t* status) {
+              imloc_stats* stats, int32_t* status, const RigHost* rigs = nullptr) {
   std::vector<const imloc_ransac_params*> pp(nq);
   std::vector<QPlan> pl(nq);
   for (int q = 0; q < nq; ++q) {
@@ -328,8 +396,14 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
     if (rc) return rc;
     if (n[q] < 0 || n[q] > INT32_MAX) return set_err(ctx, IMLOC_EINVAL, "query %d: n out of range", q);
     if (n[q] > 0 && !corr_ok(&pts[q])) return set_err(ctx, IMLOC_EINVAL, "query %d: null correspondence array", q);
-    if (!cam_ok(&K[q])) return set_err(ctx, IMLOC_EINVAL, "query %d: bad intrinsics", q);
-    pl[q] = plan_query(n[q], pp[q]);
+    const int ncam = rigs ? rigs[q].ncam : 0;
+    if (ncam > 0) {
+      rc = rig_check(ctx, rigs[q], n[q]);
+      if (rc) return rc;
+    } else if (!cam_ok(&K[q])) {
+      return set_err(ctx, IMLOC_EINVAL, "query %d: bad intrinsics", q);
+    }
+    pl[q] = plan_query(n[q], pp[q], ncam);
   }
   hipSetDevice(ctx->device);
   hipStream_t s = ctx->stream;
@@ -340,9 +414,14 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
   if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes, have %zu", a.off, ctx->ws_bytes);
   const size_t tab = (size_t)nq * sizeof(QueryDesc);
   const size_t outb = (size_t)nq * sizeof(BestState) + (size_t)nq * 13 * sizeof(double) + 64;
-  if (!ensure_pinned(ctx, tab + outb + 512)) return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
+  const size_t rigb = (size_t)e.rig_doubles * sizeof(double);
+  if (!ensure_pinned(ctx, tab + outb + 512 + rigb)) return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
   QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
-  for (int q = 0; q < nq; ++q) htab[q] = make_desc(&pts[q], n[q], &K[q], pp[q], pl[q], e, q, masks ? masks[q] : nullptr);
+  for (int q = 0; q < nq; ++q)
+    htab[q] = make_desc(&pts[q], n[q], rigs && rigs[q].ncam > 0 ? nullptr : &K[q], pp[q], pl[q], e, q,
+                        masks ? masks[q] : nullptr, rigs ? &rigs[q] : nullptr);
+  double* hrig = reinterpret_cast<double*>(ctx->pinned + tab + outb + 512);
+  fill_rig_tables(hrig, nq, rigs, e);
 
   BestState* hst = reinterpret_cast<BestState*>(ctx->pinned + tab);
   double* hfin = reinterpret_cast<double*>(ctx->pinned + tab + (size_t)nq * sizeof(BestState));
@@ -359,6 +438,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
   auto enqueue = [&](hipStream_t st_, bool sync) -> int {
     hipEvent_t ev_total = tm.begin();
     HIP_TRY(ctx, hipMemcpyAsync(e.qd, htab, tab, hipMemcpyHostToDevice, st_));
+    if (rigb) HIP_TRY(ctx, hipMemcpyAsync(e.rig, hrig, rigb, hipMemcpyHostToDevice, st_));
     HIP_TRY(ctx, launch_gather_subsets(e.qd, nq, max_m_sub, st_));
     HIP_TRY(ctx, launch_init_queries(e.qd, e.st, nq, st_));
     rounds = 0;
@@ -366,17 +446,18 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       hipEvent_t e0 = tm.begin();
       HIP_TRY(ctx, launch_begin_round(e.qd, e.st, e.cb, nq, st_));
       HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
+      if (e.any_rig) HIP_TRY(ctx, launch_sample_gp3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
       tm.end(kStSample, e0);
       hipEvent_t e1 = tm.begin();
       HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, ctx->tune.ct, e.item_off, st_));
       HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, ctx->tune, 0, st_));
       tm.end(kStScore, e1);
       hipEvent_t e2 = tm.begin();
-      HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, e.kmax, 4 * e.max_batch, e.sel_part, e.sel, e.n_sel, st_));
+      HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, e.kmax, e.max_cap, e.sel_part, e.sel, e.n_sel, st_));
       tm.end(kStSelect, e2);
       hipEvent_t e3 = tm.begin();
       HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * e.kmax, e.kmax, e.chunks_lo, e.lo_iters,
-                             e.gn_lo, e.lo_pose, e.lo_cost, e.lo_count, st_));
+                             e.gn_lo, e.lo_pose, e.lo_cost, e.lo_count, e.any_rig, st_));
       HIP_TRY(ctx, launch_update_best(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, e.kmax, e.st,
                                       st_));
       HIP_TRY(ctx, launch_end_round(e.qd, e.st, nq, e.active_count, st_));
@@ -390,7 +471,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
     }
     hipEvent_t e4 = tm.begin();
     HIP_TRY(ctx, launch_refine(e.qd, e.st, nullptr, nq, e.chunks_fin, e.fin_iters, e.in_set, e.gn_fin, e.fin_pose,
-                               e.fin_cost, st_));
+                               e.fin_cost, e.any_rig, st_));
     HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, e.max_n, 0, st_));
     tm.end(kStRefine, e4);
     tm.end(kStTotal, ev_total);
@@ -408,8 +489,8 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
              ctx->tune.blocks, e.lo_iters, e.fin_iters);
     key += buf;
     for (int q = 0; q < nq; ++q) {
-      snprintf(buf, sizeof(buf), "%lld,%lld,%d,%lld,%lld,%d;", (long long)pl[q].n, (long long)pl[q].m,
-               (int)pl[q].subset, (long long)pl[q].total, (long long)pl[q].batch, pl[q].k);
+      snprintf(buf, sizeof(buf), "%lld,%lld,%d,%lld,%lld,%d,%d;", (long long)pl[q].n, (long long)pl[q].m,
+               (int)pl[q].subset, (long long)pl[q].total, (long long)pl[q].batch, pl[q].k, pl[q].ncam);
       key += buf;
     }
     if (!ctx->gstream) {
@@ -482,12 +563,13 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
   return IMLOC_OK;
 }
 
-size_t batch_bytes(int nq, const int64_t* n, const imloc_ransac_params* params, int n_params) {
+size_t batch_bytes(int nq, const int64_t* n, const imloc_ransac_params* params, int n_params,
+                   const int32_t* ncam = nullptr) {
   std::vector<const imloc_ransac_params*> pp(nq);
   std::vector<QPlan> pl(nq);
   for (int q = 0; q < nq; ++q) {
     pp[q] = &params[n_params == 1 ? 0 : q];
-    pl[q] = plan_query(n[q] < 0 ? 0 : n[q], pp[q]);
+    pl[q] = plan_query(n[q] < 0 ? 0 : n[q], pp[q], ncam ? ncam[q] : 0);
   }
   Engine e;
   plan_engine(e, nq, pl.data(), pp.data());
@@ -505,7 +587,7 @@ struct StageQuery {
 };
 
 void stage_setup(StageQuery& sq, int64_t n, int64_t cap, double tau, int precision, int lo_iters, int final_iters,
-                 double cauchy_s, int nprob_lo) {
+                 double cauchy_s, int nprob_lo, int ncam = 0) {
   std::memset(&sq.p, 0, sizeof(sq.p));
   sq.p.threshold_px = tau;
   sq.p.fixed_samples = 1;
@@ -515,7 +597,7 @@ void stage_setup(StageQuery& sq, int64_t n, int64_t cap, double tau, int precisi
   sq.p.final_iters = final_iters;
   sq.p.cauchy_scale_px = cauchy_s;
   sq.p.precision = precision;
-  sq.pl = plan_query(n, &sq.p);
+  sq.pl = plan_query(n, &sq.p, ncam);
   sq.pl.cap = std::max<int64_t>(cap, 1);
   const imloc_ransac_params* pp = &sq.p;
   plan_engine(sq.e, 1, &sq.pl, &pp);
@@ -534,13 +616,21 @@ size_t stage_bytes(StageQuery& sq, int nprob_lo) {
 // Upload the one-query table (and optionally an initial state) and return the
 // device pointers.
 int stage_upload(imloc_ctx* ctx, StageQuery& sq, const imloc_corr* pts, int64_t n, const imloc_camera* K,
-                 int64_t B, int64_t drawn, uint8_t* mask) {
-  if (!ensure_pinned(ctx, sizeof(QueryDesc) + sizeof(BestState) + 512))
+                 int64_t B, int64_t drawn, uint8_t* mask, const RigHost* rig = nullptr) {
+  const size_t rig_at = 256 * ((sizeof(QueryDesc) + sizeof(BestState) + 512 + 255) / 256);
+  if (!ensure_pinned(ctx, rig_at + (size_t)sq.e.rig_doubles * sizeof(double)))
     return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the staging buffer may still feed an earlier copy
   QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
-  htab[0] = make_desc(pts, n, K, &sq.p, sq.pl, sq.e, 0, mask);
+  htab[0] = make_desc(pts, n, K, &sq.p, sq.pl, sq.e, 0, mask, rig);
   htab[0].B = B;
   HIP_TRY(ctx, hipMemcpyAsync(sq.e.qd, htab, sizeof(QueryDesc), hipMemcpyHostToDevice, ctx->stream));
+  if (rig && sq.e.rig_doubles) {
+    double* hrig = reinterpret_cast<double*>(ctx->pinned + rig_at);
+    fill_rig_tables(hrig, 1, rig, sq.e);
+    HIP_TRY(ctx, hipMemcpyAsync(sq.e.rig, hrig, (size_t)sq.e.rig_doubles * sizeof(double), hipMemcpyHostToDevice,
+                                ctx->stream));
+  }
   HIP_TRY(ctx, launch_init_queries(sq.e.qd, sq.e.st, 1, ctx->stream));
   if (drawn) {
     BestState* hb = reinterpret_cast<BestState*>(ctx->pinned + 256 * ((sizeof(QueryDesc) + 255) / 256));
@@ -656,6 +746,18 @@ size_t imloc_workspace_bytes(int64_t n, const imloc_ransac_params* p) {
 size_t imloc_batch_workspace_bytes(int32_t nq, const int64_t* n, const imloc_ransac_params* p, int32_t n_params) {
   if (nq <= 0 || !n || !p || (n_params != 1 && n_params != nq)) return 0;
   return batch_bytes(nq, n, p, n_params);
+}
+
+size_t imloc_rig_workspace_bytes(int64_t n, int32_t n_cams, const imloc_ransac_params* p) {
+  if (!p || n < 0 || n_cams < 1 || n_cams > kMaxCams) return 0;
+  return batch_bytes(1, &n, p, 1, &n_cams);
+}
+
+size_t imloc_rig_stage_workspace_bytes(int64_t n, int32_t n_cams, int64_t count) {
+  if (n < 0 || count < 0 || n_cams < 1 || n_cams > kMaxCams) return 0;
+  StageQuery sq;
+  stage_setup(sq, n, 8 * std::max<int64_t>(count, 1), 1.0, 1, 0, 0, 1.0, 1, n_cams);
+  return stage_bytes(sq, 1);
 }
 
 size_t imloc_score_workspace_bytes(int64_t n, int64_t np, int32_t precision) {
@@ -880,6 +982,82 @@ int imloc_sample_p3p(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const iml
   return IMLOC_OK;
 }
 
+int imloc_rig_sample_gp3p(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_rig_camera* cams,
+                          int32_t n_cams, const int64_t* cam_start, uint64_t seed, uint64_t query_id, int32_t exhaustive,
+                          int64_t h0, int64_t count, double* poses, int64_t* h_out, int32_t* j_out, int32_t* n_cand,
+                          int32_t* triples) {
+  if (!ctx) return IMLOC_EINVAL;
+  if (n < 0 || n > INT32_MAX || count < 0 || count > INT32_MAX || h0 < 0)
+    return set_err(ctx, IMLOC_EINVAL, "bad sizes");
+  if (n > 0 && !corr_ok(pts)) return set_err(ctx, IMLOC_EINVAL, "null correspondence array");
+  const RigHost rig{n_cams, cams, cam_start};
+  int rc = rig_check(ctx, rig, n);
+  if (rc) return rc;
+  if (!poses || !h_out || !j_out || !n_cand) return set_err(ctx, IMLOC_EINVAL, "null output");
+  hipSetDevice(ctx->device);
+  StageQuery sq;
+  stage_setup(sq, n, 8 * std::max<int64_t>(count, 1), 1.0, 0, 0, 0, 1.0, 1, n_cams);
+  sq.p.seed = seed;
+  sq.p.query_id = query_id;
+  sq.p.exhaustive = exhaustive;
+  Arena a{ctx->ws, ctx->ws_bytes};
+  carve_engine(a, sq.e);
+  if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes", a.off);
+  sq.e.cb.pose = poses;
+  sq.e.cb.h = h_out;
+  sq.e.cb.j = j_out;
+  sq.e.cb.n = n_cand;
+  rc = stage_upload(ctx, sq, pts, n, nullptr, count, h0, nullptr, &rig);
+  if (rc) return rc;
+  HIP_TRY(ctx, launch_fill_i32(n_cand, 1, 0, ctx->stream));
+  HIP_TRY(ctx, launch_sample_gp3p(sq.e.qd, sq.e.st, sq.e.cb, 1, count, triples, ctx->stream));
+  return IMLOC_OK;
+}
+
+int imloc_rig_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_rig_camera* cams, int32_t n_cams,
+                    const int64_t* cam_start, const double* poses, int64_t np, double tau, int32_t precision,
+                    int32_t* count, double* msac) {
+  if (!ctx) return IMLOC_EINVAL;
+  if (n < 0 || n > INT32_MAX || np < 0 || np > INT32_MAX) return set_err(ctx, IMLOC_EINVAL, "bad sizes");
+  if (n > 0 && !corr_ok(pts)) return set_err(ctx, IMLOC_EINVAL, "null correspondence array");
+  const RigHost rig{n_cams, cams, cam_start};
+  int rc = rig_check(ctx, rig, n);
+  if (rc) return rc;
+  if (!(tau > 0.0)) return set_err(ctx, IMLOC_EINVAL, "threshold must be > 0");
+  if (precision != IMLOC_FP32_SCORE && precision != IMLOC_FP64_ALL) return set_err(ctx, IMLOC_EINVAL, "bad precision");
+  if (np == 0) return IMLOC_OK;
+  if (!poses || !count || !msac) return set_err(ctx, IMLOC_EINVAL, "null pose / output array");
+  hipSetDevice(ctx->device);
+  StageQuery sq;
+  stage_setup(sq, n, np, tau, precision, 0, 0, 1.0, 1, n_cams);
+  Arena a{ctx->ws, ctx->ws_bytes};
+  carve_engine(a, sq.e);
+  if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes", a.off);
+  rc = stage_upload(ctx, sq, pts, n, nullptr, 1, 0, nullptr, &rig);
+  if (rc) return rc;
+  hipStream_t s = ctx->stream;
+  HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
+  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, ctx->tune.ct, sq.e.item_off, s));
+  HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, ctx->tune, precision, s));
+  HIP_TRY(ctx, launch_candidate_costs(sq.e.qd, sq.e.st, sq.e.cb, np, count, msac, s));
+  return IMLOC_OK;
+}
+
+int imloc_rig_lo_ransac_pnp(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_rig_camera* cams,
+                            int32_t n_cams, const int64_t* cam_start, const imloc_ransac_params* p,
+                            imloc_pose* pose_out, uint8_t* mask, imloc_stats* stats) {
+  if (!ctx) return IMLOC_EINVAL;
+  if (!pose_out) return set_err(ctx, IMLOC_EINVAL, "pose_out is null");
+  if (!p) return set_err(ctx, IMLOC_EINVAL, "params is null");
+  imloc_corr none{};
+  int32_t status = 0;
+  uint8_t* masks[1] = {mask};
+  const RigHost rig{n_cams, cams, cam_start};
+  imloc_camera unused{1.0, 1.0, 0.0, 0.0};
+  int rc = run_batch(ctx, 1, pts ? pts : &none, &n, &unused, p, 1, pose_out, masks, stats, &status, &rig);
+  return rc < 0 ? rc : status;
+}
+
 int imloc_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K, const double* poses,
                 int64_t np, double tau, int32_t precision, int32_t* count, double* msac) {
   if (!ctx) return IMLOC_EINVAL;
@@ -926,7 +1104,7 @@ int imloc_local_optimize(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const
   int rc = stage_upload(ctx, sq, pts, n, K, 0, 0, nullptr);
   if (rc) return rc;
   HIP_TRY(ctx, launch_lo(sq.e.qd, sq.e.cb, nullptr, nullptr, start, np, 1, sq.e.chunks_lo, iters, scratch, out_poses,
-                         cost, count, ctx->stream));
+                         cost, count, false, ctx->stream));
   return IMLOC_OK;
 }
 
@@ -947,7 +1125,7 @@ int imloc_refine(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_c
   int rc = stage_upload(ctx, sq, pts, n, K, 0, 0, mask);
   if (rc) return rc;
   HIP_TRY(ctx, launch_refine(sq.e.qd, sq.e.st, start, 1, sq.e.chunks_fin, iters, sq.e.in_set, sq.e.gn_fin, out_pose,
-                             cost, ctx->stream));
+                             cost, false, ctx->stream));
   if (mask) HIP_TRY(ctx, launch_mask(sq.e.qd, sq.e.st, out_pose, 1, n, 1, ctx->stream));
   return IMLOC_OK;
 }
@@ -1056,8 +1234,12 @@ void server_engine(Engine& e, const imloc_server_config* c) {
   e.chunks_lo = gn_chunks(c->max_n);
   e.chunks_fin = gn_chunks(c->max_n);
   e.slots = c->candidate_pool;
+  e.proj_floats = 16 * std::max<int64_t>(c->candidate_pool, 1);
+  e.rig_doubles = 0;
   e.in_set_off.assign(1, 0);
   e.subset_off.assign(1, 0);
+  e.proj_off.assign(1, 0);
+  e.rig_off.assign(1, 0);
 }
 
 size_t server_carve(Arena& a, Engine& e, const imloc_server_config* c, char** byte_pool) {
@@ -1210,6 +1392,8 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
       }
       // per-slot view of the pools
       e.cand_off.assign(1, sl.cand_off);
+      e.proj_off.assign(1, 16 * sl.cand_off);
+      e.rig_off.assign(1, 0);
       e.in_set_off.assign(1, 0);
       e.subset_off.assign(1, 0);
       QueryDesc d = make_desc(&sl.q.pts, sl.q.n, &sl.q.K, &sl.q.p, sl.pl, e, 0, sl.q.mask);
@@ -1235,11 +1419,11 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, ctx->tune, 0, s));
     HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, 4 * max_batch, e.sel_part, e.sel, e.n_sel, s));
     HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * kmax, kmax, chunks_lo, lo_iters, e.gn_lo,
-                           e.lo_pose, e.lo_cost, e.lo_count, s));
+                           e.lo_pose, e.lo_cost, e.lo_count, false, s));
     HIP_TRY(ctx, launch_update_best(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, kmax, e.st, s));
     HIP_TRY(ctx, launch_end_round(e.qd, e.st, nq, e.active_count, s));
     HIP_TRY(ctx, launch_refine(e.qd, e.st, nullptr, nq, chunks_fin, fin_iters, e.in_set, e.gn_fin, e.fin_pose,
-                               e.fin_cost, s));
+                               e.fin_cost, false, s));
     HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, max_n, 0, s));
     HIP_TRY(ctx, launch_retire(e.st, nq, s));
     BestState* hst = reinterpret_cast<BestState*>(ctx->pinned + tab);

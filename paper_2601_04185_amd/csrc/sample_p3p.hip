@@ -1,8 +1,10 @@
 // sample_p3p.hip -- minimal sampling (Philox4x64-10) and float64 P3P, one
 // lane per sample, candidates compacted per workgroup (ImLoc Sec. 3.3, "Pose
 // Estimation": batches of minimal sets, P3P hypotheses).
+#include "gp3p_device.h"
 #include "imloc_device.h"
 #include "imloc_kernels.h"
+#include "query_device.h"
 
 namespace imloc {
 
@@ -15,6 +17,7 @@ __global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* 
                                                                int32_t* __restrict__ triples) {
   const int q = blockIdx.y;
   const QueryDesc& d = qd[q];
+  if (d.ncam > 0) return;  // rig queries: sample_gp3p_kernel
   const int64_t count = d.B;
   const int64_t s0 = (int64_t)blockIdx.x * kP3PBlock;
   if (s0 >= count) return;
@@ -62,24 +65,104 @@ __global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* 
   if (threadIdx.x == kP3PBlock - 1) s_base = s_scan[kP3PBlock - 1] > 0 ? atomicAdd(&cb.n[q], s_scan[kP3PBlock - 1]) : 0;
   __syncthreads();
   const int base = s_base + s_scan[threadIdx.x] - ns;
-  const double inv_tau = 1.0 / d.tau;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (j >= ns) break;
-    const int64_t o = d.cand_off + base + j;
+    const int64_t local = base + j;
+    const int64_t o = d.cand_off + local;
     Pose P;
     p3p_pose(sol.l[j], y, x, P);
     for (int e = 0; e < 9; ++e) cb.pose[12 * o + e] = P.R[e];
     for (int e = 0; e < 3; ++e) cb.pose[12 * o + 9 + e] = P.t[e];
-    double M[12];
-    projection_rows(P, K, M);
-    float4* pr = reinterpret_cast<float4*>(cb.proj + 16 * o);
-    pr[0] = make_float4((float)(M[0] * inv_tau), (float)(M[1] * inv_tau), (float)(M[2] * inv_tau),
-                        (float)(M[3] * inv_tau));
-    pr[1] = make_float4((float)(M[4] * inv_tau), (float)(M[5] * inv_tau), (float)(M[6] * inv_tau),
-                        (float)(M[7] * inv_tau));
-    pr[2] = make_float4((float)M[8], (float)M[9], (float)M[10], (float)M[11]);
-    pr[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+    write_candidate_rows(d, cb.proj, local, P);
+    cb.h[o] = h0 + s;
+    cb.j[o] = j;
+    cb.cnt[o] = 0;
+    cb.gain[o] = 0;
+  }
+}
+
+// Rig queries: the same sampling, generalised P3P on the three rays of the
+// sampled points (origin and direction of each point's camera in the rig
+// frame), up to 8 candidates per sample with rows for every camera.
+__global__ __launch_bounds__(kP3PBlock) void sample_gp3p_kernel(const QueryDesc* __restrict__ qd,
+                                                                const BestState* __restrict__ st, CandBuf cb,
+                                                                int32_t* __restrict__ triples) {
+  const int q = blockIdx.y;
+  const QueryDesc& d = qd[q];
+  if (d.ncam == 0) return;
+  const int64_t count = d.B;
+  const int64_t s0 = (int64_t)blockIdx.x * kP3PBlock;
+  if (s0 >= count) return;
+  const int64_t s = s0 + threadIdx.x;
+  const int64_t h0 = st[q].drawn;
+  GP3PIn g;
+  double X[3][3];
+  double dep[8][3];
+  int ns = 0;
+  if (s < count) {
+    const uint64_t h = (uint64_t)(h0 + s);
+    int idx[3] = {-1, -1, -1};
+    const bool ok = d.exhaustive ? unrank_triple(h, (uint64_t)d.m, idx)
+                                 : sample_triple(d.seed, d.qid, h, (uint64_t)d.m, idx);
+    if (triples) {
+      triples[3 * s] = ok ? idx[0] : -1;
+      triples[3 * s + 1] = ok ? idx[1] : -1;
+      triples[3 * s + 2] = ok ? idx[2] : -1;
+    }
+    if (ok) {
+      for (int k = 0; k < 3; ++k) {
+        const int i = idx[k];
+        const double* rc = d.rig + 16 * cam_of(d.segS, d.ncam, i);
+        const double* Rc = rc + 4;
+        const double* tc = rc + 13;
+        const double bx = ((double)d.S.u[i] - rc[2]) / rc[0], by = ((double)d.S.v[i] - rc[3]) / rc[1];
+        double f[3];
+        for (int c = 0; c < 3; ++c) {
+          g.o[k][c] = -(Rc[c] * tc[0] + Rc[3 + c] * tc[1] + Rc[6 + c] * tc[2]);
+          f[c] = Rc[c] * bx + Rc[3 + c] * by + Rc[6 + c];
+        }
+        const double inv = 1.0 / sqrt(dot3(f, f));
+        for (int c = 0; c < 3; ++c) g.f[k][c] = f[c] * inv;
+        X[k][0] = d.S.X[i]; X[k][1] = d.S.Y[i]; X[k][2] = d.S.Z[i];
+      }
+      const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+      for (int e = 0; e < 3; ++e) {
+        double v[3];
+        for (int c = 0; c < 3; ++c) v[c] = X[pa[e]][c] - X[pb[e]][c];
+        g.d2[e] = dot3(v, v);
+      }
+      ns = gp3p_depths(g, dep);
+    }
+  }
+  __shared__ int s_scan[kP3PBlock];
+  __shared__ int s_base;
+  s_scan[threadIdx.x] = ns;
+  __syncthreads();
+  for (int off = 1; off < kP3PBlock; off <<= 1) {
+    const int v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0;
+    __syncthreads();
+    s_scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  if (threadIdx.x == kP3PBlock - 1) s_base = s_scan[kP3PBlock - 1] > 0 ? atomicAdd(&cb.n[q], s_scan[kP3PBlock - 1]) : 0;
+  __syncthreads();
+  const int base = s_base + s_scan[threadIdx.x] - ns;
+  for (int j = 0; j < ns; ++j) {
+    const int64_t local = base + j;
+    const int64_t o = d.cand_off + local;
+    double P[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c < 3; ++c) P[i][c] = g.o[i][c] + dep[j][i] * g.f[i][c];
+    Pose pose;
+    if (!gp3p_pose(P, X, pose)) {  // degenerate triangle: an identity placeholder never wins a score
+      for (int e = 0; e < 9; ++e) pose.R[e] = (e % 4 == 0) ? 1.0 : 0.0;
+      pose.t[0] = pose.t[1] = 0.0;
+      pose.t[2] = -1e30;
+    }
+    for (int e = 0; e < 9; ++e) cb.pose[12 * o + e] = pose.R[e];
+    for (int e = 0; e < 3; ++e) cb.pose[12 * o + 9 + e] = pose.t[e];
+    write_candidate_rows(d, cb.proj, local, pose);
     cb.h[o] = h0 + s;
     cb.j[o] = j;
     cb.cnt[o] = 0;
@@ -95,6 +178,14 @@ hipError_t launch_sample_p3p(const QueryDesc* qd, const BestState* st, CandBuf c
   return hipGetLastError();
 }
 
+hipError_t launch_sample_gp3p(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int64_t max_b,
+                              int32_t* triples, hipStream_t s) {
+  if (nq <= 0 || max_b <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((max_b + kP3PBlock - 1) / kP3PBlock);
+  hipLaunchKernelGGL(sample_gp3p_kernel, dim3(blocks, nq), dim3(kP3PBlock), 0, s, qd, st, cb, triples);
+  return hipGetLastError();
+}
+
 // Candidates from given float64 poses (query 0).
 __global__ void set_candidates_kernel(const QueryDesc* __restrict__ qd, const double* __restrict__ poses, int64_t np,
                                       CandBuf cb) {
@@ -102,17 +193,12 @@ __global__ void set_candidates_kernel(const QueryDesc* __restrict__ qd, const do
   if (i == 0) cb.n[0] = (int32_t)np;
   if (i >= np) return;
   const QueryDesc& d = qd[0];
-  const Cam K{d.fx, d.fy, d.cx, d.cy};
   const int64_t o = d.cand_off + i;
   Pose P;
   for (int e = 0; e < 9; ++e) P.R[e] = poses[12 * i + e];
   for (int e = 0; e < 3; ++e) P.t[e] = poses[12 * i + 9 + e];
   for (int e = 0; e < 12; ++e) cb.pose[12 * o + e] = poses[12 * i + e];
-  double M[12];
-  projection_rows(P, K, M);
-  const double inv_tau = 1.0 / d.tau;
-  for (int e = 0; e < 12; ++e) cb.proj[16 * o + e] = (float)(e < 8 ? M[e] * inv_tau : M[e]);
-  for (int e = 12; e < 16; ++e) cb.proj[16 * o + e] = 0.f;
+  write_candidate_rows(d, cb.proj, i, P);
   cb.h[o] = i;
   cb.j[o] = 0;
   cb.cnt[o] = 0;

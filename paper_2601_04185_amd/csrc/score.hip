@@ -27,6 +27,7 @@
 // tiling, grid size or mix of queries.
 #include "imloc_device.h"
 #include "imloc_kernels.h"
+#include "query_device.h"
 
 namespace imloc {
 
@@ -61,9 +62,31 @@ __device__ inline float wave_total_dpp(float x) {
 __device__ inline int ppl_of(const QueryDesc& d) { return d.precision ? kScorePPL64 : kScorePPL32; }
 __device__ inline int64_t chunks_of(const QueryDesc& d) {
   const int64_t per = (int64_t)kScoreBlock * ppl_of(d);
-  const int64_t c = (d.m + per - 1) / per;
+  int64_t c = 0;
+  if (d.ncam == 0) {
+    c = (d.m + per - 1) / per;
+  } else {  // a rig: every camera's segment is chunked on its own
+    for (int k = 0; k < d.ncam; ++k) c += (d.segS[k + 1] - d.segS[k] + per - 1) / per;
+  }
   return c > 0 ? c : 1;
 }
+
+// Points [begin, end) and camera of chunk `chunk` of the scoring set.
+struct ChunkRange {
+  int64_t begin, end;
+  int cam;
+};
+__device__ inline ChunkRange chunk_range(const QueryDesc& d, int64_t chunk) {
+  const int64_t per = (int64_t)kScoreBlock * ppl_of(d);
+  if (d.ncam == 0) return ChunkRange{chunk * per, d.m, 0};
+  for (int k = 0; k < d.ncam; ++k) {
+    const int64_t nch = (d.segS[k + 1] - d.segS[k] + per - 1) / per;
+    if (chunk < nch) return ChunkRange{d.segS[k] + chunk * per, d.segS[k + 1], k};
+    chunk -= nch;
+  }
+  return ChunkRange{0, 0, 0};
+}
+
 
 // Work list: items_q = tiles_q * chunks_q for queries sampling this round;
 // item_off = exclusive prefix, item_off[nq] = total (one workgroup).
@@ -109,7 +132,8 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
   constexpr int PPL = kScorePPL32;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const float inv_tau = (float)(1.0 / d.tau);
-  const int64_t base = chunk * (kScoreBlock * PPL) + wave * (kWave * PPL) + lane;
+  const ChunkRange rg = chunk_range(d, chunk);
+  const int64_t base = rg.begin + wave * (kWave * PPL) + lane;
   const auto U = gmem(d.S.u);
   const auto V = gmem(d.S.v);
   const auto X = gmem(d.S.X);
@@ -120,7 +144,7 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int64_t i = base + (int64_t)k * kWave;
-    if (i < d.m) {
+    if (i < rg.end) {
       pu[k] = U[i] * inv_tau; pv[k] = V[i] * inv_tau; px[k] = X[i]; py[k] = Y[i]; pz[k] = Z[i];
       pw[k] = W ? W[i] : 1.0f;
     } else {  // a NaN residual is never an inlier
@@ -129,14 +153,17 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
   }
   const int c0 = (int)(tile * CT);
   const int cend = min(CT, ncand - c0);
-  const float4* __restrict__ pc = reinterpret_cast<const float4*>(proj + 16 * (d.cand_off + c0));
+  const int rows = rows_per_slot(d);
+  const float4* __restrict__ pc =
+      reinterpret_cast<const float4*>(proj + d.proj_off + 16 * ((int64_t)rows * c0 + rg.cam));
+  const int stride = 4 * rows;  // float4s from one candidate's rows to the next one's
   float4 n0 = pc[0], n1 = pc[1], n2 = pc[2];
   uint32_t item_cnt = 0;
 #pragma unroll 2
   for (int c = 0; c < cend; ++c) {
     const float4 r0 = n0, r1 = n1, r2 = n2;
     if (c + 1 < cend) {  // prefetch the next candidate's rows
-      n0 = pc[4 * (c + 1)]; n1 = pc[4 * (c + 1) + 1]; n2 = pc[4 * (c + 1) + 2];
+      n0 = pc[stride * (c + 1)]; n1 = pc[stride * (c + 1) + 1]; n2 = pc[stride * (c + 1) + 2];
     }
     const float o0 = to_vgpr(r0.w), o1 = to_vgpr(r1.w), o2 = to_vgpr(r2.w);
     uint32_t cnt = 0;
@@ -194,14 +221,14 @@ __device__ __forceinline__ void score_item_f64(const QueryDesc& d, const double*
                                                unsigned long long (*s_gain)[kScoreWaves]) {
   constexpr int PPL = kScorePPL64;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int64_t base = chunk * (kScoreBlock * PPL) + wave * (kWave * PPL) + lane;
-  const Cam K{d.fx, d.fy, d.cx, d.cy};
+  const ChunkRange rg = chunk_range(d, chunk);
+  const int64_t base = rg.begin + wave * (kWave * PPL) + lane;
   const double tau2 = d.tau * d.tau;
   double pu[PPL], pv[PPL], px[PPL], py[PPL], pz[PPL], pw[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int64_t i = base + (int64_t)k * kWave;
-    if (i < d.m) {
+    if (i < rg.end) {
       pu[k] = gmem(d.S.u)[i]; pv[k] = gmem(d.S.v)[i]; px[k] = gmem(d.S.X)[i]; py[k] = gmem(d.S.Y)[i];
       pz[k] = gmem(d.S.Z)[i];
       pw[k] = d.S.w ? gmem(d.S.w)[i] : 1.0;
@@ -214,11 +241,13 @@ __device__ __forceinline__ void score_item_f64(const QueryDesc& d, const double*
   uint32_t item_cnt = 0;
   for (int c = 0; c < cend; ++c) {
     const double* q = pose + 12 * (d.cand_off + c0 + c);
-    Pose Pp;
+    Pose Pp, Pc;
     for (int e = 0; e < 9; ++e) Pp.R[e] = q[e];
     for (int e = 0; e < 3; ++e) Pp.t[e] = q[9 + e];
+    Cam K;
+    camera_pose(d, rg.cam, Pp, Pc, K);
     double M[12];
-    projection_rows(Pp, K, M);
+    projection_rows(Pc, K, M);
     uint32_t cnt = 0;
     double gain = 0.0;
 #pragma unroll

@@ -43,6 +43,7 @@ int main(void) {
          offsetof(imloc_stats, score_launches), offsetof(imloc_stats, ms_total), sizeof(imloc_server_config));
   printf("%zu %zu %zu\n", sizeof(imloc_dense_matches), sizeof(imloc_triangulation_params),
          offsetof(imloc_triangulation_params, max_refine_iters));
+  printf("%zu %zu\n", sizeof(imloc_rig_camera), offsetof(imloc_rig_camera, cam_from_rig));
   return 0;
 }
 ''')
@@ -54,7 +55,8 @@ int main(void) {
             C.sizeof(pk.Corr), C.sizeof(pk.CorrOut), C.sizeof(pk.Matches),
             pk.RansacParams.precision.offset, pk.RansacParams.seed.offset, pk.Stats.score_launches.offset,
             pk.Stats.ms_total.offset, C.sizeof(pk.ServerConfig), C.sizeof(pk.DenseMatches),
-            C.sizeof(pk.TriangulationParams), pk.TriangulationParams.max_refine_iters.offset]
+            C.sizeof(pk.TriangulationParams), pk.TriangulationParams.max_refine_iters.offset,
+            C.sizeof(pk.RigCamera), pk.RigCamera.cam_from_rig.offset]
     assert got == want
 
 

@@ -194,3 +194,39 @@ def test_wrong_matches_do_not_move_the_depth(orc):
     assert m.mean() > 0.3
     rel = np.abs(r["depth"][m] / w.depth_true[m] - 1)
     assert np.median(rel) < 1e-6 and np.mean(rel < 1e-4) > 0.98
+
+
+def test_reported_cost_and_curvature(orc):
+    """The reported refinement cost is sum w angle^2 over the winning
+    hypothesis' inliers at the kept depth (numpy), and the reported second
+    derivative is positive there (a minimum)."""
+    w = synth.dense_match_scene(n_views=6, width=40, height=30, correct_frac=0.8, noise_px=0.5, seed=23)
+    r = orc.triangulate(w.K0, w.T0, w.Ks, w.Ts, w.mu, w.mv, w.conf)
+    T0 = np.asarray(w.T0)
+    R0, t0 = T0[:9].reshape(3, 3), T0[9:]
+    C0 = -R0.T @ t0
+    K0 = w.K0
+    checked = 0
+    for i, j in np.argwhere(r["depth"] > 0)[:40]:
+        r0 = R0.T @ np.array([(j + 0.5 - K0[2]) / K0[0], (i + 0.5 - K0[3]) / K0[1], 1.0])
+        rays, cents, ws = [], [], []
+        for k in range(len(w.Ks)):
+            if not (w.conf[k, i, j] >= np.float32(0.05)):
+                continue
+            Kk, Tk = w.Ks[k], np.asarray(w.Ts[k])
+            Rk, tk = Tk[:9].reshape(3, 3), Tk[9:]
+            d = Rk.T @ np.array([(float(w.mu[k, i, j]) - Kk[2]) / Kk[0], (float(w.mv[k, i, j]) - Kk[3]) / Kk[1], 1.0])
+            rays.append(d / np.linalg.norm(d))
+            cents.append(-Rk.T @ tk)
+            ws.append(float(w.conf[k, i, j]))
+        hv = int(r["best_view"][i, j])
+        used = [k for k in range(len(w.Ks)) if w.conf[k, i, j] >= np.float32(0.05)]
+        h = orc.tri_hypothesis(C0, r0, cents[used.index(hv)], rays[used.index(hv)])
+        inl = [m for m in range(len(rays)) if _angle_np(C0, r0, h, cents[m], rays[m]) < math.radians(2.0)]
+        assert len(inl) == r["inliers"][i, j]
+        l = r["depth"][i, j]
+        cost = sum(ws[m] * _angle_np(C0, r0, l, cents[m], rays[m]) ** 2 for m in inl)
+        assert abs(cost - r["cost"][i, j]) <= 1e-9 * cost + 1e-18
+        assert r["curv"][i, j] > 0
+        checked += 1
+    assert checked >= 20
