@@ -230,23 +230,16 @@ __device__ inline void cubic_roots_in(double c0, double c1, double c2, double c3
     if (fa == 0.0) { emit(a); continue; }
     if (fb == 0.0 && t == 2) { emit(b); continue; }
     if ((fa < 0.0) == (fb < 0.0)) continue;
-    // safeguarded Newton: the cubic is monotone on the bracket; a Newton step
-    // that leaves the bracket, or that shrinks it by less than half, is
-    // replaced by bisection; the bracket shrinks every step
-    double x = 0.5 * (a + b), dx_old = b - a;
-    for (int it = 0; it < 100; ++it) {
-      const double fx = ((c3 * x + c2) * x + c1) * x + c0;
-      if (fx == 0.0) { a = b = x; break; }
-      if ((fx < 0.0) == (fa < 0.0)) { a = x; fa = fx; } else { b = x; }
-      const double dfx = (3.0 * c3 * x + 2.0 * c2) * x + c1;
-      double xn = x - fx / dfx;
-      if (!(xn > a && xn < b) || !(fabs(xn - x) < 0.5 * dx_old)) xn = 0.5 * (a + b);
-      dx_old = fabs(xn - x);
-      if (xn == x || xn <= a || xn >= b) break;
-      if (dx_old <= 2e-16 * fabs(x)) { x = xn; break; }  // converged to rounding level
-      x = xn;
+    // bisection to full precision: every lane of a wave runs the same short
+    // loop body (a Newton step would cost a float64 division per iteration)
+    for (int it = 0; it < 200; ++it) {
+      const double m = 0.5 * (a + b);
+      if (m <= a || m >= b) break;
+      const double fm = ((c3 * m + c2) * m + c1) * m + c0;
+      if (fm == 0.0) { a = b = m; break; }
+      if ((fm < 0.0) == (fa < 0.0)) { a = m; fa = fm; } else { b = m; }
     }
-    emit(a == b ? a : x);
+    emit(0.5 * (a + b));
   }
 }
 
