@@ -260,8 +260,7 @@ def paper_mode_leg(pk, steps=10):
     from paper_2601_04185_amd import synth
     q = synth.make_query(1002, 50000, 0.25, 1.5, weights="conf", n_views=10)
     d = pk.to_device(q)
-    prm = pk.make_params(threshold_px=6.0, batch=1000, min_iters=1000, max_iters=100000, confidence=0.9999,
-                         max_score_points=10000, lo_top_k=1)
+    prm = pk.paper_params(6.0)
     ctx = pk.Context(0)
     for _ in range(2):
         pk.imloc_lo_ransac_pnp(ctx, d, q.K, prm)

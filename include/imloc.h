@@ -109,6 +109,17 @@ typedef struct {
   float ms_sample, ms_score, ms_select, ms_lo, ms_refine, ms_total;  /* device time, if timing is on */
 } imloc_stats;
 
+/* Fill *p with the LO-RANSAC settings of Sec. 3.3 "Pose Estimation": batches
+ * of 1,000 minimal sets, adaptive stop once the chance of having missed the
+ * best model is below 1e-4 (at least one batch, at most 100,000 samples),
+ * scoring on a uniform subsample of at most 10,000 points, local optimisation
+ * (10 Gauss-Newton iterations) of a batch's best candidate when it beats the
+ * running best, 10 Cauchy refinement iterations over the full set with
+ * s = threshold_px / 2, float32 scoring, seed 0.  The paper states no pixel
+ * threshold, so the caller gives it.  Host-only; touches no device.  Returns
+ * IMLOC_EINVAL for a null p or a threshold that is not finite and > 0. */
+int imloc_paper_params(double threshold_px, imloc_ransac_params *p);
+
 /* ---- context ----------------------------------------------------------- */
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;

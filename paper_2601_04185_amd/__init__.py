@@ -38,7 +38,7 @@ EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_err
             "imloc_triangulate_depth", "imloc_rig_workspace_bytes", "imloc_rig_lo_ransac_pnp",
             "imloc_rig_stage_workspace_bytes", "imloc_rig_sample_gp3p", "imloc_rig_score",
             "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score",
-            "imloc_local_optimize", "imloc_refine"]
+            "imloc_local_optimize", "imloc_refine", "imloc_paper_params"]
 
 
 class ImlocError(RuntimeError):
@@ -126,6 +126,7 @@ def lib():
             "imloc_lo_workspace_bytes": ([i64, i32], C.c_size_t),
             "imloc_refine_workspace_bytes": ([i64], C.c_size_t),
             "imloc_set_timing": ([vp, C.c_int], C.c_int),
+            "imloc_paper_params": ([dbl, vp], C.c_int),
             "imloc_lift": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_lift_log8": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_depth_encode_log8": ([vp, vp, i64, vp], C.c_int),
@@ -167,6 +168,22 @@ def make_params(threshold_px=4.0, fixed_samples=0, batch=1024, min_iters=1024, m
     return RansacParams(float(threshold_px), int(fixed_samples), int(batch), int(min_iters), int(max_iters),
                         float(confidence), int(lo_top_k), int(lo_iters), int(max_score_points), int(final_iters),
                         float(cauchy_scale_px), int(exhaustive), int(precision), int(seed), int(query_id))
+
+
+def paper_params(threshold_px=6.0, **overrides) -> RansacParams:
+    """The LO-RANSAC settings of Sec. 3.3 "Pose Estimation" as filled in by
+    imloc_paper_params (batches of 1,000, subsample 10,000, confidence
+    1 - 1e-4, cap 100,000, top-1 local optimisation); keyword arguments
+    override single fields afterwards."""
+    p = RansacParams()
+    rc = lib().imloc_paper_params(float(threshold_px), C.byref(p))
+    if rc != IMLOC_OK:
+        raise ImlocError(f"imloc_paper_params failed ({rc})")
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
 
 
 class Context:

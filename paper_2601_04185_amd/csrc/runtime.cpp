@@ -738,6 +738,27 @@ int imloc_get_score_tuning(const imloc_ctx* c, int32_t* candidates_per_item, int
   return IMLOC_OK;
 }
 
+int imloc_paper_params(double threshold_px, imloc_ransac_params* p) {
+  if (!p || !(threshold_px > 0.0) || !std::isfinite(threshold_px)) return IMLOC_EINVAL;
+  *p = imloc_ransac_params{};
+  p->threshold_px = threshold_px;
+  p->fixed_samples = 0;
+  p->batch = 1000;
+  p->min_iters = 1000;
+  p->max_iters = 100000;
+  p->confidence = 1.0 - 1e-4;
+  p->lo_top_k = 1;
+  p->lo_iters = 10;
+  p->max_score_points = 10000;
+  p->final_iters = 10;
+  p->cauchy_scale_px = 0.5 * threshold_px;
+  p->exhaustive = 0;
+  p->precision = IMLOC_FP32_SCORE;
+  p->seed = 0;
+  p->query_id = 0;
+  return IMLOC_OK;
+}
+
 size_t imloc_workspace_bytes(int64_t n, const imloc_ransac_params* p) {
   if (!p || n < 0) return 0;
   return batch_bytes(1, &n, p, 1);

@@ -83,3 +83,24 @@ def test_host_side_checks_without_device():
     assert L.imloc_server_workspace_bytes(C.byref(cfg)) > 0
     bad = pk.ServerConfig(0, 8, 200000, 64 * 4096, 64 * 200256)
     assert L.imloc_server_workspace_bytes(C.byref(bad)) == 0
+
+
+def test_paper_params():
+    """imloc_paper_params fills the settings Sec. 3.3 "Pose Estimation" gives:
+    batches of 1,000, scoring subsample of at most 10,000, stop at a 1e-4
+    chance of having missed the best model or 100,000 samples, local
+    optimisation of a new best (top 1), Cauchy refinement over the full set."""
+    import paper_2601_04185_amd as pk
+    p = pk.paper_params(6.0)
+    assert p.threshold_px == 6.0 and p.fixed_samples == 0
+    assert p.batch == 1000 and p.min_iters == 1000 and p.max_iters == 100000
+    assert abs((1.0 - p.confidence) - 1e-4) < 1e-15
+    assert p.max_score_points == 10000 and p.lo_top_k == 1
+    assert p.final_iters > 0 and p.cauchy_scale_px == 3.0 and p.exhaustive == 0
+    assert pk.paper_params(4.0, seed=7).seed == 7
+    L = pk.lib()
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        assert L.imloc_paper_params(bad, C.byref(pk.RansacParams())) == pk.IMLOC_EINVAL
+    assert L.imloc_paper_params(4.0, None) == pk.IMLOC_EINVAL
+    with pytest.raises(TypeError):
+        pk.paper_params(4.0, no_such_field=1)

@@ -267,6 +267,10 @@ def test_ransac_paper_mode(pk, ctx, orc):
     assert st["residuals"] == ref["residuals"] == st["candidates"] * 10000
     assert pose_close(R, t, ref["R"], ref["t"])[0]
     assert np.degrees(rot_angle(R, q.R)) < 2.0 and np.linalg.norm(t - q.t) < 0.25
+    # the library's own paper settings run the same query to the same result
+    rc2, R2, t2, st2 = pk.imloc_lo_ransac_pnp(ctx, _dev(q), q.K, pk.paper_params(6.0))
+    assert rc2 == 0 and st2["samples"] == st["samples"] and st2["best_h"] == st["best_h"]
+    assert np.array_equal(R2, R) and np.array_equal(t2, t)
 
 
 @pytest.mark.parametrize("n", [0, 1, 2])
