@@ -168,6 +168,15 @@ int imloc_graph_counters(const imloc_ctx *ctx, int64_t *captures, int64_t *launc
 int imloc_set_score_tuning(imloc_ctx *ctx, int32_t candidates_per_item, int32_t workgroups);
 int imloc_get_score_tuning(const imloc_ctx *ctx, int32_t *candidates_per_item, int32_t *workgroups);
 
+/* Launch form of the Gauss-Newton runs (local optimisation and final
+ * refinement): 0 (default) picks by size, 1 = one launch per iteration in
+ * which every workgroup of a problem re-reduces the previous partial sums,
+ * 2 = an evaluation launch and a one-workgroup-per-problem decision launch
+ * per iteration.  Every form sums the same 512-point chunk partials in the
+ * same order, so results are identical; only the speed differs.  Returns
+ * IMLOC_EINVAL for another value. */
+int imloc_set_gn_mode(imloc_ctx *ctx, int32_t mode);
+
 /* ---- the hot path -------------------------------------------------------- */
 
 /* Lift 2D-2D matches to 2D-3D correspondences (Sec. 3.3 "Query Time Matching

@@ -38,7 +38,8 @@ EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_err
             "imloc_triangulate_depth", "imloc_rig_workspace_bytes", "imloc_rig_lo_ransac_pnp",
             "imloc_rig_stage_workspace_bytes", "imloc_rig_sample_gp3p", "imloc_rig_score",
             "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score",
-            "imloc_local_optimize", "imloc_refine", "imloc_paper_params"]
+            "imloc_local_optimize", "imloc_refine", "imloc_paper_params",
+            "imloc_set_gn_mode"]
 
 
 class ImlocError(RuntimeError):
@@ -127,6 +128,7 @@ def lib():
             "imloc_refine_workspace_bytes": ([i64], C.c_size_t),
             "imloc_set_timing": ([vp, C.c_int], C.c_int),
             "imloc_paper_params": ([dbl, vp], C.c_int),
+            "imloc_set_gn_mode": ([vp, i32], C.c_int),
             "imloc_lift": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_lift_log8": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_depth_encode_log8": ([vp, vp, i64, vp], C.c_int),
@@ -230,6 +232,10 @@ class Context:
 
     def set_score_tuning(self, candidates_per_item: int, workgroups: int):
         self.check(lib().imloc_set_score_tuning(self.h, int(candidates_per_item), int(workgroups)))
+
+    def set_gn_mode(self, mode: int):
+        """Gauss-Newton launch form: 0 by size, 1 fused, 2 split (identical results)."""
+        self.check(lib().imloc_set_gn_mode(self.h, int(mode)))
 
     def score_tuning(self):
         a, b = C.c_int32(), C.c_int32()

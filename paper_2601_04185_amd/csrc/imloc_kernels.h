@@ -191,16 +191,19 @@ hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, i
 int gn_chunks(int64_t n);
 size_t gn_scratch_bytes(int nprob, int chunks_max);
 // any_rig: some problem belongs to a rig query (selects the kernel variant
-// that takes residuals through rig cameras)
+// that takes residuals through rig cameras).  gn_mode: 0 = pick the launch
+// form by size, 1 = fused (one launch per iteration), 2 = split (evaluation
+// and decision launches); every form gives identical results.
 hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
                      const double* start_direct, int nprob, int kmax, int chunks_max, int iters_max, void* scratch,
-                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, hipStream_t s);
+                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, int gn_mode,
+                     hipStream_t s);
 hipError_t launch_update_best(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
                               const double* lo_pose, const double* lo_cost, const int64_t* lo_count, int nq,
                               int kmax, BestState* st, hipStream_t s);
 hipError_t launch_refine(const QueryDesc* qd, BestState* st, const double* start_direct, int nq, int chunks_max,
                          int iters_max, uint8_t* in_set, void* scratch, double* out_pose, double* out_cost,
-                         bool any_rig, hipStream_t s);
+                         bool any_rig, int gn_mode, hipStream_t s);
 // mask and inlier count of the final pose of every query that just finished
 // (all != 0: of every query, each with a pose)
 hipError_t launch_mask(const QueryDesc* qd, BestState* st, const double* fin_pose, int nq, int64_t max_n, int all,

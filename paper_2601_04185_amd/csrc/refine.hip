@@ -5,11 +5,13 @@
 //   final refinement: robust Cauchy loss, weighted by the confidences, over
 //     all inliers of the full set at the best pose (held fixed).
 // Each Gauss-Newton iteration is one launch over (point chunk x problem)
-// workgroups for every problem of a batch of queries.  A workgroup
-// accumulates the 6x6 normal equations (upper triangle), the gradient, the
-// cost and the inlier count in float64 with a fixed thread-to-point map and
-// reduction tree; partial sums are combined in chunk order, so the result is
-// deterministic.  Residual r = pi(R X + t) - x; left update on SO(3).
+// workgroups for every problem of a batch of queries (or, for large batches,
+// an evaluation launch and a decision launch).  A workgroup accumulates the
+// 6x6 normal equations (upper triangle), the gradient, the cost and the
+// inlier count of a 512-point chunk in float64 with a fixed thread-to-point
+// map and reduction tree; partial sums are combined in chunk order, so the
+// result depends on the problem alone, not on the batch around it or the
+// launch form.  Residual r = pi(R X + t) - x; left update on SO(3).
 #include "imloc_device.h"
 #include "imloc_kernels.h"
 
@@ -17,13 +19,13 @@ namespace imloc {
 
 constexpr int kAcc = 29;  // 21 (H upper) + 6 (g) + cost + count
 constexpr int kGNThreads = 256;
-constexpr int kGNWaves = kGNThreads / kWave;
-constexpr int kGNPPT = 8;                       // points per thread per chunk
-constexpr int kGNChunk = kGNThreads * kGNPPT;   // points per workgroup
+constexpr int kGNPPT = 2;                       // points per thread per chunk
+constexpr int kGNChunk = kGNThreads * kGNPPT;   // points per chunk (fixed: the summation order depends on n only)
+constexpr int kGNRows = kGNThreads / 16;        // 16-lane rows of a workgroup
 
-__device__ inline void acc_point(double* a, const Cam& K, double x, double y, double z, double du, double dv,
-                                 double wt) {
-  const double iz = 1.0 / z;
+// Normal equations of one point, given iz = 1 / z of its camera coordinates.
+__device__ inline void acc_point(double* a, const Cam& K, double x, double y, double z, double iz, double du,
+                                 double dv, double wt) {
   const double a00 = K.fx * iz, a02 = -K.fx * x * iz * iz;
   const double a11 = K.fy * iz, a12 = -K.fy * y * iz * iz;
   // d x_c / d(dw, dt) rows: (0, z, -y, 1, 0, 0), (-z, 0, x, 0, 1, 0), (y, -x, 0, 0, 0, 1)
@@ -42,9 +44,8 @@ __device__ inline void acc_point(double* a, const Cam& K, double x, double y, do
 // The same for a rig camera: x_c = R_c x_r + t_c with the rig-frame point x_r
 // moving under the left update of the rig pose, so the rows of d(pixel)/dx_c
 // are carried through R_c: J = [x_r x r, r] for each row r of d(pixel)/dx_c R_c.
-__device__ inline void acc_point_rig(double* a, const Cam& K, const double xr[3], double x, double y, double z,
+__device__ inline void acc_point_rig(double* a, const Cam& K, const double xr[3], double x, double y, double iz,
                                      const double* Rc, double du, double dv, double wt) {
-  const double iz = 1.0 / z;
   const double p0[3] = {K.fx * iz, 0.0, -K.fx * x * iz * iz};
   const double p1[3] = {0.0, K.fy * iz, -K.fy * y * iz * iz};
   double r0[3], r1[3];
@@ -67,10 +68,10 @@ __device__ inline void acc_point_rig(double* a, const Cam& K, const double xr[3]
   for (int r = 0; r < 6; ++r) a[21 + r] = fma(wt, J0[r] * du + J1[r] * dv, a[21 + r]);
 }
 
-// Per-problem Gauss-Newton state, double-buffered across launches.
+// Per-problem Gauss-Newton state after a decision, double-buffered.
 struct GNState {
   double cur[12];      // accepted pose
-  double eval[12];     // pose evaluated by the launch that wrote this state
+  double eval[12];     // pose the next evaluation runs at
   double cur_cost;
   double cur_count;
   int32_t done;
@@ -97,8 +98,7 @@ __host__ __device__ constexpr int upk(int r, int c) { return r * 6 - (r * (r - 1
 // Solve from the reduced sums (LDS); thread 0 only.  Cholesky H = U^T U in
 // place on the packed upper triangle (pivot reciprocals computed once), then
 // U^T y = -g, U d = y, and the left update.  Every loop has constant bounds and is unrolled, so the factor, the
-// vectors and the rotation stay in registers (about 100 VGPRs, below what the
-// accumulation path needs).  Returns false if H is not positive definite.
+// vectors and the rotation stay in registers.  Returns false if H is not positive definite.
 __device__ __forceinline__ bool gn_solve_step(const double* tot, const double* cur, double* next) {
   double h[21], inv[6];
 #pragma unroll
@@ -150,181 +150,199 @@ __device__ __forceinline__ bool gn_solve_step(const double* tot, const double* c
   return true;
 }
 
-// One launch of a batched multi-workgroup Gauss-Newton run.  Launch k of a
-// problem:
-//   k = 0: evaluate the start pose;
-//   k >= 1: reduce the partial sums of launch k-1 (every workgroup of the
-//     problem, in chunk order, so all take the same decision), accept the
-//     evaluated pose if its cost did not rise (at k = 1 it is the start),
-//     solve the normal equations of the accepted pose for the next pose
-//     (unless the iteration budget is spent), and evaluate that.
-// MODE 0 (local optimisation): truncated cost over the scoring set.
-// MODE 1 (final refinement): Cauchy cost over the in-set, which launch 0
-// marks as the inliers (tau) of the start pose.
-template <int MODE, bool RIG>
-__global__ __launch_bounds__(kGNThreads) void gn_kernel(
-    const QueryDesc* __restrict__ qd, CandBuf cb, const int32_t* __restrict__ sel, const int32_t* __restrict__ n_sel,
-    const double* __restrict__ start_direct, BestState* __restrict__ bst, int kmax, int k, GNState* __restrict__ gst,
-    double* __restrict__ part, int chunks_max, int nprob, uint8_t* __restrict__ in_set_all,
-    double* __restrict__ out_pose, double* __restrict__ out_cost, int64_t* __restrict__ out_count) {
-  const int p = blockIdx.y;
-  const int chunk = blockIdx.x;
-  int q;
-  const double* start;
+// A double moved across lanes by a DPP control (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each row of 16 lanes (pairs, quads, then the four quads by row
+// rotations); lane 0 of a row holds (q0 + q3) + (q2 + q1) of its quads.
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_f64<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x124>(v);  // row_ror 4
+  v += dpp_f64<0x128>(v);  // row_ror 8
+  return v;
+}
+
+struct GNArgs {
+  const QueryDesc* qd;
+  CandBuf cb;
+  const int32_t* sel;
+  const int32_t* n_sel;
+  const double* start_direct;
+  BestState* bst;
+  GNState* gst;
+  double* part;
+  uint8_t* in_set_all;
+  double* out_pose;
+  double* out_cost;
+  int64_t* out_count;
+  int kmax, cmax, nprob;
+};
+
+// Problem p's query and start pose; false if the problem has no work.
+// LO (MODE 0): problem p = q * kmax + slot starts from the selected
+// candidate; refinement (MODE 1): problem q starts from the query's best pose
+// once it has finished sampling.
+template <int MODE>
+__device__ __forceinline__ bool gn_problem(const GNArgs& g, int p, int& q, const double*& start) {
   if (MODE == 0) {
-    q = start_direct ? 0 : p / kmax;
-    const int slot = p - q * kmax;
-    if (!start_direct && slot >= n_sel[q]) return;
-    start = start_direct ? start_direct + 12 * (int64_t)p
-                         : cb.pose + 12 * (qd[q].cand_off + sel[q * kMaxTopK + slot]);
+    q = g.start_direct ? 0 : p / g.kmax;
+    const int slot = p - q * g.kmax;
+    if (!g.start_direct && slot >= g.n_sel[q]) return false;
+    start = g.start_direct ? g.start_direct + 12 * (int64_t)p
+                           : g.cb.pose + 12 * (g.qd[q].cand_off + g.sel[q * kMaxTopK + slot]);
   } else {
     q = p;
-    if (!start_direct && !(bst[q].finished == 1 && bst[q].have)) return;
-    start = start_direct ? start_direct + 12 * (int64_t)q : bst[q].pose;
+    if (!g.start_direct && !(g.bst[q].finished == 1 && g.bst[q].have)) return false;
+    start = g.start_direct ? g.start_direct + 12 * (int64_t)q : g.bst[q].pose;
   }
-  const QueryDesc& d = qd[q];
-  const CorrF32 c = MODE == 0 ? d.S : d.full;
-  const int64_t n = MODE == 0 ? d.m : d.n;
-  const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
-  const double tau2 = d.tau * d.tau, s2 = d.cauchy_s * d.cauchy_s;
-  const Cam K{d.fx, d.fy, d.cx, d.cy};
-  const int chunks = chunks_for(n);
-  if (chunk >= chunks) return;
-  uint8_t* in_set = MODE == 1 ? in_set_all + d.in_set_off : nullptr;
-  GNState* prev = gst + (int64_t)((k + 1) & 1) * nprob + p;
-  GNState* next = gst + (int64_t)(k & 1) * nprob + p;
-  const double* part_prev = part + ((int64_t)((k + 1) & 1) * nprob + p) * chunks_max * kAcc;
-  double* part_next = part + ((int64_t)(k & 1) * nprob + p) * chunks_max * kAcc;
-  const bool prev_done = k > 0 && prev->done != 0;
+  return true;
+}
 
-  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
-  // the chunk's points of a live problem are loaded first: one memory latency
-  // per launch, overlapping the reduction of the previous partial sums and
-  // the solve
-  float pX[kGNPPT], pY[kGNPPT], pZ[kGNPPT], pu[kGNPPT], pv[kGNPPT], pw[kGNPPT];
+__device__ __forceinline__ const double* gn_part(const GNArgs& g, int buf, int p) {
+  return g.part + ((int64_t)buf * g.nprob + p) * g.cmax * kAcc;
+}
+
+// The C chunk partial sums of one problem in a fixed order: thread (v, grp)
+// adds chunks grp, grp + 8, ... of entry v in chunk order, then the eight
+// group sums are added in group order.  Every thread calls it.
+__device__ void gn_reduce(const double* part, int C, double (*s_grp)[kAcc], double* s_tot) {
+  const int v = threadIdx.x % kAcc, grp = threadIdx.x / kAcc;
+  if (grp < 8) {
+    double sum = 0.0;
+    for (int c0 = grp; c0 < C; c0 += 64) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + 8 * u;
+        x[u] = c < C ? part[(int64_t)c * kAcc + v] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + 8 * u < C) sum += x[u];
+    }
+    s_grp[grp][v] = sum;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < kAcc) {
+    double t = 0.0;
+#pragma unroll
+    for (int gg = 0; gg < 8; ++gg) t += s_grp[gg][threadIdx.x];
+    s_tot[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// Decision j of a run (thread 0), on the sums of evaluation j at s.eval:
+// the evaluated pose becomes the accepted one if its cost did not rise (at
+// j = 0 it is the start); unless the iteration budget is spent, the normal
+// equations at the accepted pose give the pose of evaluation j + 1.  A
+// cost-raising step ends the run with the accepted pose.  Returns true when
+// this decision ends the run.
+struct GNShared {
+  double cur[12], eval[12];
+  double cost, count;
+  int done, accepted;
+};
+
+__device__ __forceinline__ bool gn_decide(int j, int iters, const double* tot, GNShared& s) {
+  if (s.done) return false;
+  if (j == 0 || tot[27] <= s.cost) {
+    for (int e = 0; e < 12; ++e) s.cur[e] = s.eval[e];
+    s.cost = tot[27];
+    s.count = tot[28];
+    if (j > 0) s.accepted += 1;
+    if (j >= iters || !gn_solve_step(tot, s.cur, s.eval)) s.done = 1;
+  } else {
+    s.done = 1;
+  }
+  return s.done != 0;
+}
+
+__device__ __forceinline__ void gn_load_state(GNShared& s, const GNState* st, const double* start) {
+  if (threadIdx.x < 12) {
+    s.cur[threadIdx.x] = st ? st->cur[threadIdx.x] : start[threadIdx.x];
+    s.eval[threadIdx.x] = st ? st->eval[threadIdx.x] : start[threadIdx.x];
+  }
+  if (threadIdx.x == 0) {
+    s.cost = st ? st->cur_cost : __builtin_inf();
+    s.count = st ? st->cur_count : 0.0;
+    s.done = st ? st->done : 0;
+    s.accepted = st ? st->accepted : 0;
+  }
+}
+
+__device__ __forceinline__ void gn_store_state(const GNShared& s, GNState* st) {
+  if (threadIdx.x < 12) {
+    st->cur[threadIdx.x] = s.cur[threadIdx.x];
+    st->eval[threadIdx.x] = s.eval[threadIdx.x];
+  }
+  if (threadIdx.x == 0) {
+    st->cur_cost = s.cost;
+    st->cur_count = s.count;
+    st->done = s.done;
+    st->accepted = s.accepted;
+  }
+}
+
+__device__ __forceinline__ void gn_outputs(const GNArgs& g, const GNShared& s, int p) {
+  if (threadIdx.x < 12 && g.out_pose) g.out_pose[12 * (int64_t)p + threadIdx.x] = s.cur[threadIdx.x];
+  if (threadIdx.x == 0) {
+    if (g.out_cost) g.out_cost[p] = s.cost;
+    if (g.out_count) g.out_count[p] = (int64_t)s.count;
+  }
+}
+
+// A chunk's points, loaded into registers.
+struct GNPoints {
+  float X[kGNPPT], Y[kGNPPT], Z[kGNPPT], u[kGNPPT], v[kGNPPT], w[kGNPPT];
   bool use[kGNPPT];
+};
+
+// MODE 1 reads the in-set flags from evaluation 1 on (evaluation 0 writes them).
+template <int MODE>
+__device__ __forceinline__ void gn_load_points(const CorrF32& c, int64_t n, int64_t base, const uint8_t* in_set,
+                                               bool read_in_set, GNPoints& pt) {
 #pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
     const int64_t i = base + (int64_t)t * kGNThreads;
-    use[t] = !prev_done && i < n;
-    pX[t] = pY[t] = pZ[t] = pu[t] = pv[t] = 0.0f;
-    pw[t] = 1.0f;
-    if (MODE == 1 && k > 0 && use[t]) use[t] = in_set[i] != 0;
-    if (use[t]) {
-      pX[t] = gmem(c.X)[i];
-      pY[t] = gmem(c.Y)[i];
-      pZ[t] = gmem(c.Z)[i];
-      pu[t] = gmem(c.u)[i];
-      pv[t] = gmem(c.v)[i];
-      if (c.w) pw[t] = gmem(c.w)[i];
-    }
+    const bool ok = i < n;
+    pt.X[t] = ok ? gmem(c.X)[i] : 0.0f;
+    pt.Y[t] = ok ? gmem(c.Y)[i] : 0.0f;
+    pt.Z[t] = ok ? gmem(c.Z)[i] : 0.0f;
+    pt.u[t] = ok ? gmem(c.u)[i] : 0.0f;
+    pt.v[t] = ok ? gmem(c.v)[i] : 0.0f;
+    pt.w[t] = ok && c.w ? gmem(c.w)[i] : 1.0f;
+    pt.use[t] = ok && (MODE == 0 || !read_in_set || in_set[i] != 0);
   }
+}
 
-
-  __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
-  const bool rig = RIG && d.ncam > 0;  // the RIG = false variant runs batches without rig queries
+// Accumulate one chunk at pose P and store its partial sums: per thread in
+// point order, then the 16-lane rows by DPP, then the rows in row order.
+template <int MODE, bool RIG>
+__device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* s_rig, const double* P, int j,
+                                              int64_t base, const GNPoints& pt, uint8_t* in_set,
+                                              double (*s_rows)[kAcc], double* part_out) {
+  const double tau2 = d.tau * d.tau, s2 = d.cauchy_s * d.cauchy_s;
+  const double inv_s2 = 1.0 / s2;
+  const Cam K{d.fx, d.fy, d.cx, d.cy};
+  const bool rig = RIG && d.ncam > 0;
   const int64_t* seg = MODE == 0 ? d.segS : d.segF;
-  if (rig)
-    for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
-  __shared__ double s_grp[8][kAcc];
-  __shared__ double s_tot[kAcc];
-  __shared__ double s_cur[12], s_eval[12];
-  __shared__ double s_cost, s_count;
-  __shared__ int s_done, s_accepted;
-  if (k == 0) {
-    if (threadIdx.x < 12) {
-      s_cur[threadIdx.x] = start[threadIdx.x];
-      s_eval[threadIdx.x] = start[threadIdx.x];
-    }
-    if (threadIdx.x == 0) {
-      s_cost = __builtin_inf();
-      s_count = 0.0;
-      s_done = 0;
-      s_accepted = 0;
-    }
-    __syncthreads();
-  } else {
-    // partial sums of launch k-1 in chunk order: thread (v, g) sums chunks g, g+8, ...
-    const int v = threadIdx.x % kAcc, g = threadIdx.x / kAcc;
-    if (!prev_done && g < 8) {
-      // chunks g, g + 8, ...: loaded four at a time, summed in chunk order
-      double sum = 0.0;
-      for (int ch0 = g; ch0 < chunks; ch0 += 32) {
-        double t[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int ch = ch0 + 8 * u;
-          t[u] = ch < chunks ? part_prev[(int64_t)ch * kAcc + v] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (ch0 + 8 * u < chunks) sum += t[u];
-      }
-      s_grp[g][v] = sum;
-    }
-    if (threadIdx.x < 12) {
-      s_cur[threadIdx.x] = prev->cur[threadIdx.x];
-      s_eval[threadIdx.x] = prev->eval[threadIdx.x];
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < kAcc && !prev_done) {
-      double t = 0.0;
-      for (int gg = 0; gg < 8; ++gg) t += s_grp[gg][threadIdx.x];
-      s_tot[threadIdx.x] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      s_cost = prev->cur_cost;
-      s_count = prev->cur_count;
-      s_done = prev->done;
-      s_accepted = prev->accepted;
-      if (!s_done) {
-        // the evaluated pose becomes the accepted one if its cost did not rise
-        if (k == 1 || s_tot[27] <= s_cost) {
-          for (int e = 0; e < 12; ++e) s_cur[e] = s_eval[e];
-          s_cost = s_tot[27];
-          s_count = s_tot[28];
-          if (k > 1) s_accepted += 1;
-          if (k - 1 >= iters || !gn_solve_step(s_tot, s_cur, s_eval)) s_done = 1;
-        } else {
-          s_done = 1;  // the step raised the cost: keep the accepted pose
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // workgroup (0, p) records the state for the next launch and the outputs
-  if (chunk == 0) {
-    if (threadIdx.x < 12) {
-      next->cur[threadIdx.x] = s_cur[threadIdx.x];
-      next->eval[threadIdx.x] = s_eval[threadIdx.x];
-      if (s_done && out_pose) out_pose[12 * (int64_t)p + threadIdx.x] = s_cur[threadIdx.x];
-    }
-    if (threadIdx.x == 0) {
-      next->cur_cost = s_cost;
-      next->cur_count = s_count;
-      next->done = s_done;
-      next->accepted = s_accepted;
-      if (s_done) {
-        if (out_cost) out_cost[p] = s_cost;
-        if (out_count) out_count[p] = (int64_t)s_count;
-      }
-    }
-  }
-  if (s_done) return;
-
-  // accumulate this chunk at the evaluated pose
-  double P[12];
-  for (int e = 0; e < 12; ++e) P[e] = s_eval[e];
   double a[kAcc];
 #pragma unroll
   for (int e = 0; e < kAcc; ++e) a[e] = 0.0;
 #pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
-    if (!use[t]) continue;
+    if (!pt.use[t]) continue;
     const int64_t i = base + (int64_t)t * kGNThreads;
-    const double X = pX[t], Y = pY[t], Z = pZ[t];
-    const double w = pw[t];
+    const double X = pt.X[t], Y = pt.Y[t], Z = pt.Z[t];
+    const double w = pt.w[t];
     double x = P[0] * X + P[1] * Y + P[2] * Z + P[9];
     double y = P[3] * X + P[4] * Y + P[5] * Z + P[10];
     double z = P[6] * X + P[7] * Y + P[8] * Z + P[11];
@@ -339,52 +357,161 @@ __global__ __launch_bounds__(kGNThreads) void gn_kernel(
       y = Rc[3] * xr[0] + Rc[4] * xr[1] + Rc[5] * xr[2] + rc[14];
       z = Rc[6] * xr[0] + Rc[7] * xr[1] + Rc[8] * xr[2] + rc[15];
     }
-    double du = 0.0, dv = 0.0, r2 = 0.0;
+    double du = 0.0, dv = 0.0, r2 = 0.0, iz = 0.0;
     const bool front = z > 0.0;
     if (front) {
-      du = Kp.fx * x / z + Kp.cx - (double)pu[t];
-      dv = Kp.fy * y / z + Kp.cy - (double)pv[t];
+      iz = 1.0 / z;
+      du = Kp.fx * x * iz + Kp.cx - (double)pt.u[t];
+      dv = Kp.fy * y * iz + Kp.cy - (double)pt.v[t];
       r2 = du * du + dv * dv;
     }
     if (MODE == 0) {
       if (front && r2 < tau2) {
         a[27] += w * r2;
         a[28] += 1.0;
-        if (rig) acc_point_rig(a, Kp, xr, x, y, z, Rc, du, dv, w);
-        else acc_point(a, K, x, y, z, du, dv, w);
+        if (rig) acc_point_rig(a, Kp, xr, x, y, iz, Rc, du, dv, w);
+        else acc_point(a, K, x, y, z, iz, du, dv, w);
       } else {
         a[27] += w * tau2;
       }
     } else {
-      if (k == 0) {
+      if (j == 0) {
         const bool in = front && r2 < tau2;
         in_set[i] = in ? 1 : 0;
         if (!in) continue;
       }
       a[28] += 1.0;
       if (!front) {
-        a[27] += w * s2 * log1p(tau2 / s2);
+        a[27] += w * s2 * log1p(tau2 * inv_s2);
         continue;
       }
-      a[27] += w * s2 * log1p(r2 / s2);
-      if (rig) acc_point_rig(a, Kp, xr, x, y, z, Rc, du, dv, w / (1.0 + r2 / s2));
-      else acc_point(a, K, x, y, z, du, dv, w / (1.0 + r2 / s2));
+      const double q = r2 * inv_s2;
+      a[27] += w * s2 * log1p(q);
+      if (rig) acc_point_rig(a, Kp, xr, x, y, iz, Rc, du, dv, w / (1.0 + q));
+      else acc_point(a, K, x, y, z, iz, du, dv, w / (1.0 + q));
     }
   }
-  __shared__ double s_part[kGNWaves][kAcc];
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int row = threadIdx.x >> 4;
 #pragma unroll
   for (int e = 0; e < kAcc; ++e) {
-    const double v = wave_sum(a[e]);
-    if (lane == 0) s_part[wave][e] = v;
+    const double v = row_sum16(a[e]);
+    if ((threadIdx.x & 15) == 0) s_rows[row][e] = v;
   }
   __syncthreads();
   if ((int)threadIdx.x < kAcc) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < kGNWaves; ++w) t += s_part[w][threadIdx.x];
-    part_next[(int64_t)chunk * kAcc + threadIdx.x] = t;
+    for (int r = 0; r < kGNRows; ++r) t += s_rows[r][threadIdx.x];
+    part_out[threadIdx.x] = t;
   }
+}
+
+// Fused launch k of a run (one launch per iteration): decision k - 1 on the
+// partial sums of launch k - 1, taken redundantly by every workgroup of the
+// problem (so no workgroup waits for another), then evaluation k.  Launch 0
+// only evaluates the start pose; the last launch only decides.  Workgroup
+// (0, p) records the state for the next launch and, when the run ends, the
+// outputs.
+template <int MODE, bool RIG>
+__global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
+  const int p = blockIdx.y;
+  const int chunk = blockIdx.x;
+  int q;
+  const double* start;
+  if (!gn_problem<MODE>(g, p, q, start)) return;
+  const QueryDesc& d = g.qd[q];
+  const CorrF32 c = MODE == 0 ? d.S : d.full;
+  const int64_t n = MODE == 0 ? d.m : d.n;
+  const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
+  const int C = chunks_for(n);
+  if (chunk >= C) return;
+  uint8_t* in_set = MODE == 1 ? g.in_set_all + d.in_set_off : nullptr;
+  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
+  // the points are loaded first: their latency overlaps the reduction and the decision
+  GNPoints pt;
+  gn_load_points<MODE>(c, n, base, in_set, k > 0, pt);
+
+  __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
+  if (RIG && d.ncam > 0)
+    for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
+  __shared__ double s_grp[8][kAcc];
+  __shared__ double s_tot[kAcc];
+  __shared__ double s_rows[kGNRows][kAcc];
+  __shared__ GNShared s;
+  __shared__ int s_end;
+  if (k == 0) {
+    gn_load_state(s, nullptr, start);
+    __syncthreads();
+  } else {
+    gn_reduce(gn_part(g, (k - 1) & 1, p), C, s_grp, s_tot);
+    gn_load_state(s, k >= 2 ? g.gst + (int64_t)(k & 1) * g.nprob + p : nullptr, start);
+    __syncthreads();
+    if (threadIdx.x == 0) s_end = gn_decide(k - 1, iters, s_tot, s);
+    __syncthreads();
+    if (chunk == 0) {
+      gn_store_state(s, g.gst + (int64_t)((k - 1) & 1) * g.nprob + p);
+      if (s_end) gn_outputs(g, s, p);
+    }
+  }
+  if (s.done) return;
+  gn_accumulate<MODE, RIG>(d, s_rig, s.eval, k, base, pt, in_set, s_rows,
+                           const_cast<double*>(gn_part(g, k & 1, p)) + (int64_t)chunk * kAcc);
+}
+
+// Split form, for batches where the redundant reduction of the fused form
+// would read too much: evaluation j (one workgroup per chunk) ...
+template <int MODE, bool RIG>
+__global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
+  const int p = blockIdx.y;
+  const int chunk = blockIdx.x;
+  int q;
+  const double* start;
+  if (!gn_problem<MODE>(g, p, q, start)) return;
+  const QueryDesc& d = g.qd[q];
+  const CorrF32 c = MODE == 0 ? d.S : d.full;
+  const int64_t n = MODE == 0 ? d.m : d.n;
+  const int C = chunks_for(n);
+  if (chunk >= C) return;
+  const GNState* st = j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr;
+  if (st && st->done) return;
+  uint8_t* in_set = MODE == 1 ? g.in_set_all + d.in_set_off : nullptr;
+  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
+  GNPoints pt;
+  gn_load_points<MODE>(c, n, base, in_set, j > 0, pt);
+  __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
+  if (RIG && d.ncam > 0)
+    for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
+  __shared__ double s_eval[12];
+  __shared__ double s_rows[kGNRows][kAcc];
+  if (threadIdx.x < 12) s_eval[threadIdx.x] = st ? st->eval[threadIdx.x] : start[threadIdx.x];
+  __syncthreads();
+  gn_accumulate<MODE, RIG>(d, s_rig, s_eval, j, base, pt, in_set, s_rows,
+                           const_cast<double*>(gn_part(g, j & 1, p)) + (int64_t)chunk * kAcc);
+}
+
+// ... then decision j (one workgroup per problem), with the same reduction
+// order and decision as the fused form, so both give identical results.
+template <int MODE>
+__global__ __launch_bounds__(kGNThreads) void gn_decide_kernel(GNArgs g, int j) {
+  const int p = blockIdx.x;
+  int q;
+  const double* start;
+  if (!gn_problem<MODE>(g, p, q, start)) return;
+  const QueryDesc& d = g.qd[q];
+  const int64_t n = MODE == 0 ? d.m : d.n;
+  const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
+  const int C = chunks_for(n);
+  __shared__ double s_grp[8][kAcc];
+  __shared__ double s_tot[kAcc];
+  __shared__ GNShared s;
+  __shared__ int s_end;
+  gn_reduce(gn_part(g, j & 1, p), C, s_grp, s_tot);
+  gn_load_state(s, j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr, start);
+  __syncthreads();
+  if (threadIdx.x == 0) s_end = gn_decide(j, iters, s_tot, s);
+  __syncthreads();
+  gn_store_state(s, g.gst + (int64_t)(j & 1) * g.nprob + p);
+  if (s_end) gn_outputs(g, s, p);
 }
 
 static void split_scratch(void* scratch, int nprob, GNState** st, double** part) {
@@ -393,34 +520,71 @@ static void split_scratch(void* scratch, int nprob, GNState** st, double** part)
                                     (((size_t)2 * nprob * sizeof(GNState) + 255) & ~size_t(255)));
 }
 
+// The fused form reads every problem's partial sums once per workgroup:
+// nprob * C^2 * 232 bytes per launch.  Above 32 MiB the split form (one more
+// launch per iteration, partials read once) is faster.
+static bool use_fused(int gn_mode, int nprob, int chunks_max) {
+  if (gn_mode == 1) return true;
+  if (gn_mode == 2) return false;
+  return (double)nprob * chunks_max * chunks_max * kAcc * sizeof(double) <= 32.0 * 1024 * 1024;
+}
+
+template <int MODE, bool RIG>
+static void launch_gn(const GNArgs& g, int iters_max, bool fused, hipStream_t s) {
+  const dim3 grid(g.cmax, g.nprob);
+  if (fused) {
+    for (int k = 0; k <= iters_max + 1; ++k)
+      hipLaunchKernelGGL((gn_fused_kernel<MODE, RIG>), grid, dim3(kGNThreads), 0, s, g, k);
+  } else {
+    for (int j = 0; j <= iters_max; ++j) {
+      hipLaunchKernelGGL((gn_eval_kernel<MODE, RIG>), grid, dim3(kGNThreads), 0, s, g, j);
+      hipLaunchKernelGGL((gn_decide_kernel<MODE>), dim3(g.nprob), dim3(kGNThreads), 0, s, g, j);
+    }
+  }
+}
+
 hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
                      const double* start_direct, int nprob, int kmax, int chunks_max, int iters_max, void* scratch,
-                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, hipStream_t s) {
+                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, int gn_mode,
+                     hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  GNState* st;
-  double* part;
-  split_scratch(scratch, nprob, &st, &part);
-  auto kern = any_rig ? gn_kernel<0, true> : gn_kernel<0, false>;
-  for (int k = 0; k <= iters_max + 1; ++k)
-    hipLaunchKernelGGL(kern, dim3(chunks_max, nprob), dim3(kGNThreads), 0, s, qd, cb, sel, n_sel,
-                       start_direct, (BestState*)nullptr, kmax, k, st, part, chunks_max, nprob, (uint8_t*)nullptr,
-                       out_pose, out_cost, out_count);
+  GNArgs g{};
+  split_scratch(scratch, nprob, &g.gst, &g.part);
+  g.qd = qd;
+  g.cb = cb;
+  g.sel = sel;
+  g.n_sel = n_sel;
+  g.start_direct = start_direct;
+  g.out_pose = out_pose;
+  g.out_cost = out_cost;
+  g.out_count = out_count;
+  g.kmax = kmax;
+  g.cmax = chunks_max;
+  g.nprob = nprob;
+  const bool fused = use_fused(gn_mode, nprob, chunks_max);
+  if (any_rig) launch_gn<0, true>(g, iters_max, fused, s);
+  else launch_gn<0, false>(g, iters_max, fused, s);
   return hipGetLastError();
 }
 
 hipError_t launch_refine(const QueryDesc* qd, BestState* bst, const double* start_direct, int nq, int chunks_max,
                          int iters_max, uint8_t* in_set, void* scratch, double* out_pose, double* out_cost,
-                         bool any_rig, hipStream_t s) {
+                         bool any_rig, int gn_mode, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
-  GNState* st;
-  double* part;
-  split_scratch(scratch, nq, &st, &part);
-  CandBuf none{};
-  auto kern = any_rig ? gn_kernel<1, true> : gn_kernel<1, false>;
-  for (int k = 0; k <= iters_max + 1; ++k)
-    hipLaunchKernelGGL(kern, dim3(chunks_max, nq), dim3(kGNThreads), 0, s, qd, none,
-                       (const int32_t*)nullptr, (const int32_t*)nullptr, start_direct, bst, 1, k, st, part, chunks_max,
-                       nq, in_set, out_pose, out_cost, (int64_t*)nullptr);
+  GNArgs g{};
+  split_scratch(scratch, nq, &g.gst, &g.part);
+  g.qd = qd;
+  g.bst = bst;
+  g.start_direct = start_direct;
+  g.in_set_all = in_set;
+  g.out_pose = out_pose;
+  g.out_cost = out_cost;
+  g.kmax = 1;
+  g.cmax = chunks_max;
+  g.nprob = nq;
+  const bool fused = use_fused(gn_mode, nq, chunks_max);
+  if (any_rig) launch_gn<1, true>(g, iters_max, fused, s);
+  else launch_gn<1, false>(g, iters_max, fused, s);
   return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ struct imloc_ctx {
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   ScoreTune tune{64, 2048};
+  int gn_mode = 0;  // Gauss-Newton launch form: 0 by size, 1 fused, 2 split
   // hipGraph replay of the fixed-sample pipeline
   bool graphs = false;
   hipStream_t gstream = nullptr;
@@ -457,7 +458,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       tm.end(kStSelect, e2);
       hipEvent_t e3 = tm.begin();
       HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * e.kmax, e.kmax, e.chunks_lo, e.lo_iters,
-                             e.gn_lo, e.lo_pose, e.lo_cost, e.lo_count, e.any_rig, st_));
+                             e.gn_lo, e.lo_pose, e.lo_cost, e.lo_count, e.any_rig, ctx->gn_mode, st_));
       HIP_TRY(ctx, launch_update_best(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, e.kmax, e.st,
                                       st_));
       HIP_TRY(ctx, launch_end_round(e.qd, e.st, nq, e.active_count, st_));
@@ -471,7 +472,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
     }
     hipEvent_t e4 = tm.begin();
     HIP_TRY(ctx, launch_refine(e.qd, e.st, nullptr, nq, e.chunks_fin, e.fin_iters, e.in_set, e.gn_fin, e.fin_pose,
-                               e.fin_cost, e.any_rig, st_));
+                               e.fin_cost, e.any_rig, ctx->gn_mode, st_));
     HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, e.max_n, 0, st_));
     tm.end(kStRefine, e4);
     tm.end(kStTotal, ev_total);
@@ -485,8 +486,8 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
     // key of everything a captured graph bakes in: shapes, workspace, staging
     std::string key;
     char buf[160];
-    snprintf(buf, sizeof(buf), "%d|%p|%p|%d|%d|%d|%d|", nq, (void*)ctx->ws, (void*)ctx->pinned, ctx->tune.ct,
-             ctx->tune.blocks, e.lo_iters, e.fin_iters);
+    snprintf(buf, sizeof(buf), "%d|%p|%p|%d|%d|%d|%d|%d|", nq, (void*)ctx->ws, (void*)ctx->pinned, ctx->tune.ct,
+             ctx->tune.blocks, e.lo_iters, e.fin_iters, ctx->gn_mode);
     key += buf;
     for (int q = 0; q < nq; ++q) {
       snprintf(buf, sizeof(buf), "%lld,%lld,%d,%lld,%lld,%d,%d;", (long long)pl[q].n, (long long)pl[q].m,
@@ -728,6 +729,13 @@ int imloc_set_score_tuning(imloc_ctx* c, int32_t candidates_per_item, int32_t wo
   if (workgroups < 1 || workgroups > (1 << 20)) return set_err(c, IMLOC_EINVAL, "workgroups out of range");
   c->tune.ct = candidates_per_item;
   c->tune.blocks = workgroups;
+  return IMLOC_OK;
+}
+
+int imloc_set_gn_mode(imloc_ctx* c, int32_t mode) {
+  if (!c) return IMLOC_EINVAL;
+  if (mode < 0 || mode > 2) return set_err(c, IMLOC_EINVAL, "Gauss-Newton launch form must be 0, 1 or 2");
+  c->gn_mode = mode;
   return IMLOC_OK;
 }
 
@@ -1125,7 +1133,7 @@ int imloc_local_optimize(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const
   int rc = stage_upload(ctx, sq, pts, n, K, 0, 0, nullptr);
   if (rc) return rc;
   HIP_TRY(ctx, launch_lo(sq.e.qd, sq.e.cb, nullptr, nullptr, start, np, 1, sq.e.chunks_lo, iters, scratch, out_poses,
-                         cost, count, false, ctx->stream));
+                         cost, count, false, ctx->gn_mode, ctx->stream));
   return IMLOC_OK;
 }
 
@@ -1146,7 +1154,7 @@ int imloc_refine(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_c
   int rc = stage_upload(ctx, sq, pts, n, K, 0, 0, mask);
   if (rc) return rc;
   HIP_TRY(ctx, launch_refine(sq.e.qd, sq.e.st, start, 1, sq.e.chunks_fin, iters, sq.e.in_set, sq.e.gn_fin, out_pose,
-                             cost, false, ctx->stream));
+                             cost, false, ctx->gn_mode, ctx->stream));
   if (mask) HIP_TRY(ctx, launch_mask(sq.e.qd, sq.e.st, out_pose, 1, n, 1, ctx->stream));
   return IMLOC_OK;
 }
@@ -1440,11 +1448,11 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, ctx->tune, 0, s));
     HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, 4 * max_batch, e.sel_part, e.sel, e.n_sel, s));
     HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * kmax, kmax, chunks_lo, lo_iters, e.gn_lo,
-                           e.lo_pose, e.lo_cost, e.lo_count, false, s));
+                           e.lo_pose, e.lo_cost, e.lo_count, false, ctx->gn_mode, s));
     HIP_TRY(ctx, launch_update_best(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, kmax, e.st, s));
     HIP_TRY(ctx, launch_end_round(e.qd, e.st, nq, e.active_count, s));
     HIP_TRY(ctx, launch_refine(e.qd, e.st, nullptr, nq, chunks_fin, fin_iters, e.in_set, e.gn_fin, e.fin_pose,
-                               e.fin_cost, false, s));
+                               e.fin_cost, false, ctx->gn_mode, s));
     HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, max_n, 0, s));
     HIP_TRY(ctx, launch_retire(e.st, nq, s));
     BestState* hst = reinterpret_cast<BestState*>(ctx->pinned + tab);
