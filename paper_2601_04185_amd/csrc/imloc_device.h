@@ -106,14 +106,34 @@ __device__ inline double trace_prod(const double A[9], const double B[9]) {
   return s;
 }
 
-// Exp on SO(3) (Rodrigues), series for small angles.
+// Exp on SO(3) (Rodrigues): A = sin(th) / th and B = (1 - cos(th)) / th^2;
+// below th = 0.5 their Taylor series in th^2 to 9 terms (truncation below
+// 1e-19), which a Gauss-Newton step almost always is.
 __device__ inline void so3_exp(const double w[3], double E[9]) {
-  const double th2 = dot3(w, w), th = sqrt(th2);
+  const double th2 = dot3(w, w);
   double A, B;
-  if (th < 1e-4) {
-    A = 1.0 - th2 * (1.0 / 6.0) + th2 * th2 * (1.0 / 120.0);
-    B = 0.5 - th2 * (1.0 / 24.0) + th2 * th2 * (1.0 / 720.0);
+  if (th2 < 0.25) {
+    // 1/(2k+1)! and 1/(2k+2)!, k = 8 .. 0, in Horner order
+    A = 1.0 / 355687428096000.0;
+    A = fma(A, -th2, 1.0 / 1307674368000.0);
+    A = fma(A, -th2, 1.0 / 6227020800.0);
+    A = fma(A, -th2, 1.0 / 39916800.0);
+    A = fma(A, -th2, 1.0 / 362880.0);
+    A = fma(A, -th2, 1.0 / 5040.0);
+    A = fma(A, -th2, 1.0 / 120.0);
+    A = fma(A, -th2, 1.0 / 6.0);
+    A = fma(A, -th2, 1.0);
+    B = 1.0 / 6402373705728000.0;
+    B = fma(B, -th2, 1.0 / 20922789888000.0);
+    B = fma(B, -th2, 1.0 / 87178291200.0);
+    B = fma(B, -th2, 1.0 / 479001600.0);
+    B = fma(B, -th2, 1.0 / 3628800.0);
+    B = fma(B, -th2, 1.0 / 40320.0);
+    B = fma(B, -th2, 1.0 / 720.0);
+    B = fma(B, -th2, 1.0 / 24.0);
+    B = fma(B, -th2, 0.5);
   } else {
+    const double th = sqrt(th2);
     double s, c;
     sincos(th, &s, &c);
     A = s / th;
@@ -191,9 +211,16 @@ __device__ inline bool chol6_solve_packed(const double Hp[21], const double b[6]
 // ---------------------------------------------------------------------------
 
 // Real roots of c3 x^3 + c2 x^2 + c1 x + c0 on [lo, hi], ascending, each
-// passed to emit(root): split at the critical points and bisect every sign
-// change.  No arrays: the (at most three) intervals are walked with a
-// running left end so that everything stays in registers.
+// passed to emit(root).  The interval is split at the critical points, so
+// the cubic is monotone on each of the (at most three) brackets; every
+// bracket with a sign change is shrunk by 24 bisection steps and then
+// polished by 4 Newton steps kept inside it.  The brackets are refined
+// together, branch-free, as independent chains (a lone wave per SIMD is
+// bound by instruction issue, so one shared loop beats three divergent ones).
+__device__ inline double cubic_at(double c0, double c1, double c2, double c3, double x) {
+  return ((c3 * x + c2) * x + c1) * x + c0;
+}
+
 template <class Emit>
 __device__ inline void cubic_roots_in(double c0, double c1, double c2, double c3, double lo, double hi, Emit&& emit) {
   // critical points: 3 c3 x^2 + 2 c2 x + c1 = 0
@@ -217,29 +244,51 @@ __device__ inline void cubic_roots_in(double c0, double c1, double c2, double c3
   }
   u1 = u1 && x1 > lo && x1 < hi;
   u2 = u2 && x2 > lo && x2 < hi;
-  double a0 = lo;
+  // brackets [lo, m1], [m1, m2], [m2, hi] over the split points in range
+  const double m1 = u1 ? x1 : (u2 ? x2 : hi);
+  const double m2 = (u1 && u2) ? x2 : hi;
+  const int nb = 1 + (int)u1 + (int)u2;
+  double A[3] = {lo, m1, m2}, B[3] = {m1, m2, hi};
+  bool run[3], neg[3], at_a[3], at_b[3];
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
-    const bool use = t == 0 ? u1 : (t == 1 ? u2 : true);
-    if (!use) continue;
-    const double b0 = t == 0 ? x1 : (t == 1 ? x2 : hi);
-    double a = a0, b = b0;
-    a0 = b0;
-    double fa = ((c3 * a + c2) * a + c1) * a + c0;
-    const double fb = ((c3 * b + c2) * b + c1) * b + c0;
-    if (fa == 0.0) { emit(a); continue; }
-    if (fb == 0.0 && t == 2) { emit(b); continue; }
-    if ((fa < 0.0) == (fb < 0.0)) continue;
-    // bisection to full precision: every lane of a wave runs the same short
-    // loop body (a Newton step would cost a float64 division per iteration)
-    for (int it = 0; it < 200; ++it) {
-      const double m = 0.5 * (a + b);
-      if (m <= a || m >= b) break;
-      const double fm = ((c3 * m + c2) * m + c1) * m + c0;
-      if (fm == 0.0) { a = b = m; break; }
-      if ((fm < 0.0) == (fa < 0.0)) { a = m; fa = fm; } else { b = m; }
+    const double fa = cubic_at(c0, c1, c2, c3, A[t]), fb = cubic_at(c0, c1, c2, c3, B[t]);
+    const bool live = t < nb;
+    at_a[t] = live && fa == 0.0;
+    at_b[t] = live && !at_a[t] && fb == 0.0 && t == nb - 1;
+    run[t] = live && !at_a[t] && !at_b[t] && ((fa < 0.0) != (fb < 0.0));
+    neg[t] = fa < 0.0;
+  }
+  if (run[0] || run[1] || run[2]) {
+    for (int it = 0; it < 24; ++it) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const double m = 0.5 * (A[t] + B[t]);
+        const bool left = (cubic_at(c0, c1, c2, c3, m) < 0.0) == neg[t];
+        A[t] = left ? m : A[t];
+        B[t] = left ? B[t] : m;
+      }
     }
-    emit(0.5 * (a + b));
+    double x[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) x[t] = 0.5 * (A[t] + B[t]);
+    for (int it = 0; it < 4; ++it) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const double f = cubic_at(c0, c1, c2, c3, x[t]);
+        const double df = (qa * x[t] + qb) * x[t] + qc;
+        const double xn = df != 0.0 ? x[t] - f / df : x[t];
+        x[t] = fmin(fmax(xn, A[t]), B[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) A[t] = x[t];
+  }
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (at_a[t]) emit(t == 0 ? lo : (t == 1 ? m1 : m2));
+    else if (run[t]) emit(A[t]);
+    else if (at_b[t]) emit(hi);
   }
 }
 
@@ -276,8 +325,9 @@ __device__ inline void polish_depths(double l[3], double a12, double a13, double
     double A[9];
     adj3(J, A);
     const double F[3] = {F0, F1, F2};
+    const double idet = 1.0 / det;
     double n[3];
-    for (int r = 0; r < 3; ++r) n[r] = l[r] - (A[3 * r] * F[0] + A[3 * r + 1] * F[1] + A[3 * r + 2] * F[2]) / det;
+    for (int r = 0; r < 3; ++r) n[r] = l[r] - (A[3 * r] * F[0] + A[3 * r + 1] * F[1] + A[3 * r + 2] * F[2]) * idet;
     const double G0 = n[0] * n[0] + n[1] * n[1] + 2.0 * b12 * n[0] * n[1] - a12;
     const double G1 = n[0] * n[0] + n[2] * n[2] + 2.0 * b13 * n[0] * n[2] - a13;
     const double G2 = n[1] * n[1] + n[2] * n[2] + 2.0 * b23 * n[1] * n[2] - a23;
@@ -318,7 +368,8 @@ __device__ inline void p3p_pencil(const double y[3][3], const double x[3][3], P3
   if (!(a12 > 0.0 && a13 > 0.0 && a23 > 0.0)) return;
   if (!(sqrt(dot3(crs, crs)) > 1e-9 * (a12 + a13 + a23))) return;
   const double b12 = -dot3(y[0], y[1]), b13 = -dot3(y[0], y[2]), b23 = -dot3(y[1], y[2]);
-  const double r12 = a12 / a23, r13 = a13 / a23;
+  const double ia23 = 1.0 / a23;
+  const double r12 = a12 * ia23, r13 = a13 * ia23;
   const double D1[9] = {1.0, b12, 0.0, b12, 1.0 - r12, -r12 * b23, 0.0, -r12 * b23, -r12};
   const double D2[9] = {1.0, 0.0, b13, 0.0, -r13, -r13 * b23, b13, -r13 * b23, 1.0 - r13};
   double A1[9], A2[9];
@@ -338,7 +389,8 @@ __device__ inline void p3p_pencil(const double y[3][3], const double x[3][3], P3
       mx = fmax(mx, fabs(M[e]));
     }
     if (!(mx > 0.0)) return;
-    for (int e = 0; e < 9; ++e) M[e] /= mx;
+    const double imx = 1.0 / mx;
+    for (int e = 0; e < 9; ++e) M[e] *= imx;
     const double T = M[0] + M[4] + M[8];
     const double S = (M[0] * M[4] - M[1] * M[3]) + (M[0] * M[8] - M[2] * M[6]) + (M[4] * M[8] - M[5] * M[7]);
     const double den = T * T - 2.0 * S;
@@ -382,7 +434,8 @@ __device__ inline void p3p_pencil(const double y[3][3], const double x[3][3], P3
     cross3(nrm, e3, m);
     const double mn = sqrt(dot3(m, m));
     if (!(mn > 0.0)) continue;
-    for (int c = 0; c < 3; ++c) m[c] /= mn;
+    const double imn = 1.0 / mn;
+    for (int c = 0; c < 3; ++c) m[c] *= imn;
     double Qe[3], Qm[3];
     for (int r = 0; r < 3; ++r) {
       Qe[r] = Q[3 * r] * e3[0] + Q[3 * r + 1] * e3[1] + Q[3 * r + 2] * e3[2];
@@ -441,18 +494,24 @@ __device__ inline void p3p_pencil(const double y[3][3], const double x[3][3], P3
   p3p_order(out.l[1], k0[1], k1[1], id[1], out.l[2], k0[2], k1[2], id[2]);
 }
 
-// Pose of one P3P solution: R maps the world triangle frame
-// [x1 - x2, x1 - x3, (x1 - x2) x (x1 - x3)] onto the camera one (one
-// Newton-Schulz step towards the nearest rotation), t = l1 y1 - R x1.
-__device__ inline void p3p_pose(const double l[3], const double y[3][3], const double x[3][3], Pose& P) {
+// Inverse of the world triangle frame X = [x1 - x2, x1 - x3, (x1 - x2) x
+// (x1 - x3)] (columns), shared by all solutions of a sample.
+__device__ inline void p3p_frame_inverse(const double x[3][3], double Xi[9]) {
   double d12[3], d13[3], crs[3];
   for (int k = 0; k < 3; ++k) { d12[k] = x[0][k] - x[1][k]; d13[k] = x[0][k] - x[2][k]; }
   cross3(d12, d13, crs);
   double X[9];
   for (int r = 0; r < 3; ++r) { X[3 * r] = d12[r]; X[3 * r + 1] = d13[r]; X[3 * r + 2] = crs[r]; }
-  double Xa[9];
-  adj3(X, Xa);
-  const double Xdet = det3(X);
+  adj3(X, Xi);
+  const double idet = 1.0 / det3(X);
+  for (int e = 0; e < 9; ++e) Xi[e] *= idet;
+}
+
+// Pose of one P3P solution: R maps the world triangle frame onto the camera
+// one (R = Y X^-1, then one Newton-Schulz step towards the nearest rotation),
+// t = l1 y1 - R x1.  Xi from p3p_frame_inverse.
+__device__ inline void p3p_pose(const double l[3], const double y[3][3], const double x[3][3], const double Xi[9],
+                                Pose& P) {
   double z[3][3];
   for (int i = 0; i < 3; ++i)
     for (int c = 0; c < 3; ++c) z[i][c] = l[i] * y[i][c];
@@ -463,7 +522,7 @@ __device__ inline void p3p_pose(const double l[3], const double y[3][3], const d
   for (int r = 0; r < 3; ++r) { Y[3 * r] = e12[r]; Y[3 * r + 1] = e13[r]; Y[3 * r + 2] = ec[r]; }
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c)
-      P.R[3 * r + c] = (Y[3 * r] * Xa[c] + Y[3 * r + 1] * Xa[3 + c] + Y[3 * r + 2] * Xa[6 + c]) / Xdet;
+      P.R[3 * r + c] = Y[3 * r] * Xi[c] + Y[3 * r + 1] * Xi[3 + c] + Y[3 * r + 2] * Xi[6 + c];
   // R <- R (3 I - R^T R) / 2
   double RtR[9], Rn[9];
   for (int r = 0; r < 3; ++r)

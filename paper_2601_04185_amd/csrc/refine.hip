@@ -19,26 +19,44 @@ namespace imloc {
 
 constexpr int kAcc = 29;  // 21 (H upper) + 6 (g) + cost + count
 constexpr int kGNThreads = 256;
+constexpr int kGNWaves = kGNThreads / kWave;
 constexpr int kGNPPT = 2;                       // points per thread per chunk
 constexpr int kGNChunk = kGNThreads * kGNPPT;   // points per chunk (fixed: the summation order depends on n only)
-constexpr int kGNRows = kGNThreads / 16;        // 16-lane rows of a workgroup
 
 // Normal equations of one point, given iz = 1 / z of its camera coordinates.
+// The rows of d(pixel)/d(dw, dt) are J0 = (a02 y, a00 z - a02 x, -a00 y, a00,
+// 0, a02) and J1 = (a12 y - a11 z, -a12 x, a11 x, 0, a11, a12); the products
+// with their structural zeros are left out (H[3][4] gets nothing).
 __device__ inline void acc_point(double* a, const Cam& K, double x, double y, double z, double iz, double du,
                                  double dv, double wt) {
   const double a00 = K.fx * iz, a02 = -K.fx * x * iz * iz;
   const double a11 = K.fy * iz, a12 = -K.fy * y * iz * iz;
-  // d x_c / d(dw, dt) rows: (0, z, -y, 1, 0, 0), (-z, 0, x, 0, 1, 0), (y, -x, 0, 0, 0, 1)
   const double J0[6] = {a02 * y, a00 * z - a02 * x, -a00 * y, a00, 0.0, a02};
   const double J1[6] = {-a11 * z + a12 * y, -a12 * x, a11 * x, 0.0, a11, a12};
+  double W0[6], W1[6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    W0[r] = wt * J0[r];
+    W1[r] = wt * J1[r];
+  }
   int k = 0;
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
 #pragma unroll
-    for (int c = r; c < 6; ++c) { a[k] = fma(wt, J0[r] * J0[c] + J1[r] * J1[c], a[k]); ++k; }
+    for (int c = r; c < 6; ++c) {
+      const bool z0 = r == 4 || c == 4, z1 = r == 3 || c == 3;
+      if (!z0 && !z1) a[k] = fma(W0[r], J0[c], fma(W1[r], J1[c], a[k]));
+      else if (!z0) a[k] = fma(W0[r], J0[c], a[k]);
+      else if (!z1) a[k] = fma(W1[r], J1[c], a[k]);
+      ++k;
+    }
   }
 #pragma unroll
-  for (int r = 0; r < 6; ++r) a[21 + r] = fma(wt, J0[r] * du + J1[r] * dv, a[21 + r]);
+  for (int r = 0; r < 6; ++r) {
+    if (r == 4) a[21 + r] = fma(W1[r], dv, a[21 + r]);
+    else if (r == 3) a[21 + r] = fma(W0[r], du, a[21 + r]);
+    else a[21 + r] = fma(W0[r], du, fma(W1[r], dv, a[21 + r]));
+  }
 }
 
 // The same for a rig camera: x_c = R_c x_r + t_c with the rig-frame point x_r
@@ -159,14 +177,66 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Sum over each row of 16 lanes (pairs, quads, then the four quads by row
-// rotations); lane 0 of a row holds (q0 + q3) + (q2 + q1) of its quads.
-__device__ __forceinline__ double row_sum16(double v) {
-  v += dpp_f64<0xb1>(v);   // quad_perm [1, 0, 3, 2]
-  v += dpp_f64<0x4e>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp_f64<0x124>(v);  // row_ror 4
-  v += dpp_f64<0x128>(v);  // row_ror 8
-  return v;
+// Exchange of lanes 32..63 of x with lanes 0..31 of y (swap16: odd 16-lane
+// rows of x with even rows of y); then x + y holds, in a lane with that lane
+// bit clear, the pair sum of x, and with it set, the pair sum of y.
+__device__ __forceinline__ void swap32_f64(double& x, double& y) {
+  const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+  x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);
+  y = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+}
+
+__device__ __forceinline__ void swap16_f64(double& x, double& y) {
+  const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+  x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);
+  y = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+}
+
+// One halving level on lane bit B with the partner given by a DPP control:
+// a lane keeps the lower half of the list if its bit is clear, the upper
+// half if set, and adds what the partner (bit flipped) did not keep.
+template <int CTRL, int H>
+__device__ __forceinline__ void halve_dpp(double* v, bool upper) {
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double send = upper ? v[i] : v[i + H];
+    const double keep = upper ? v[i + H] : v[i];
+    v[i] = keep + dpp_f64<CTRL>(send);
+  }
+}
+
+// Wave sums of the 29 accumulators by recursive halving (about 125
+// instructions instead of 29 separate reductions): after the six levels, lane
+// l holds the wave total of entry l >> 1 (entries 29..31 are zero padding).
+// Partners: lane ^ 32 and lane ^ 16 by the swap instructions, lane ^ 8
+// (row_ror 8), lane ^ 7 (row_half_mirror: bit 2 flips, and the lanes already
+// merged on bits 0..1 are all covered after the last two levels), lane ^ 2,
+// lane ^ 1 (quad_perm).  The order of additions depends on the lane only.
+__device__ __forceinline__ double wave_sum29(const double* a) {
+  double v[32];
+#pragma unroll
+  for (int e = 0; e < 32; ++e) v[e] = e < kAcc ? a[e] : 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    double x = v[i], y = v[i + 16];
+    swap32_f64(x, y);
+    v[i] = x + y;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double x = v[i], y = v[i + 8];
+    swap16_f64(x, y);
+    v[i] = x + y;
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  halve_dpp<0x128, 4>(v, (lane & 8) != 0);   // row_ror 8: lane ^ 8
+  halve_dpp<0x141, 2>(v, (lane & 4) != 0);   // row_half_mirror: lane ^ 7
+  halve_dpp<0x4e, 1>(v, (lane & 2) != 0);    // quad_perm [2, 3, 0, 1]: lane ^ 2
+  return v[0] + dpp_f64<0xb1>(v[0]);         // quad_perm [1, 0, 3, 2]: lane ^ 1
 }
 
 struct GNArgs {
@@ -185,24 +255,29 @@ struct GNArgs {
   int kmax, cmax, nprob;
 };
 
-// Problem p's query and start pose; false if the problem has no work.
-// LO (MODE 0): problem p = q * kmax + slot starts from the selected
-// candidate; refinement (MODE 1): problem q starts from the query's best pose
-// once it has finished sampling.
+// Problem p's query.  LO (MODE 0): problem p = q * kmax + slot starts from
+// the slot-th selected candidate of query q; refinement (MODE 1): problem q
+// starts from the query's best pose once it has finished sampling.
 template <int MODE>
-__device__ __forceinline__ bool gn_problem(const GNArgs& g, int p, int& q, const double*& start) {
-  if (MODE == 0) {
-    q = g.start_direct ? 0 : p / g.kmax;
-    const int slot = p - q * g.kmax;
-    if (!g.start_direct && slot >= g.n_sel[q]) return false;
-    start = g.start_direct ? g.start_direct + 12 * (int64_t)p
-                           : g.cb.pose + 12 * (g.qd[q].cand_off + g.sel[q * kMaxTopK + slot]);
-  } else {
-    q = p;
-    if (!g.start_direct && !(g.bst[q].finished == 1 && g.bst[q].have)) return false;
-    start = g.start_direct ? g.start_direct + 12 * (int64_t)q : g.bst[q].pose;
-  }
-  return true;
+__device__ __forceinline__ int gn_query(const GNArgs& g, int p) {
+  return MODE == 0 ? (g.start_direct ? 0 : p / g.kmax) : p;
+}
+
+// Whether problem p has work this round.
+template <int MODE>
+__device__ __forceinline__ bool gn_live(const GNArgs& g, int p, int q) {
+  if (g.start_direct) return true;
+  if (MODE == 0) return p - q * g.kmax < g.n_sel[q];
+  return (g.bst[q].finished == 1) & (g.bst[q].have != 0);
+}
+
+// Start pose of a live problem.
+template <int MODE>
+__device__ __forceinline__ const double* gn_start(const GNArgs& g, int p, int q) {
+  if (MODE == 0)
+    return g.start_direct ? g.start_direct + 12 * (int64_t)p
+                          : g.cb.pose + 12 * (g.qd[q].cand_off + g.sel[q * kMaxTopK + (p - q * g.kmax)]);
+  return g.start_direct ? g.start_direct + 12 * (int64_t)q : g.bst[q].pose;
 }
 
 __device__ __forceinline__ const double* gn_part(const GNArgs& g, int buf, int p) {
@@ -211,20 +286,40 @@ __device__ __forceinline__ const double* gn_part(const GNArgs& g, int buf, int p
 
 // The C chunk partial sums of one problem in a fixed order: thread (v, grp)
 // adds chunks grp, grp + 8, ... of entry v in chunk order, then the eight
-// group sums are added in group order.  Every thread calls it.
-__device__ void gn_reduce(const double* part, int C, double (*s_grp)[kAcc], double* s_tot) {
+// group sums are added in group order.  The first 16 chunks of every thread
+// (128 of the problem) are loaded at kernel entry by gn_part_issue, whose
+// addresses need only the problem index, so their latency overlaps the
+// descriptor loads; gn_part_sum adds them and loads any further ones.
+struct GNPart {
+  double x[16];
+};
+
+__device__ __forceinline__ void gn_part_issue(const double* part, int cmax, GNPart& r) {
+  const int v = threadIdx.x % kAcc, grp = threadIdx.x / kAcc;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int c = grp + 8 * u;
+    r.x[u] = (grp < 8 && c < cmax) ? part[(int64_t)c * kAcc + v] : 0.0;
+  }
+}
+
+// Every thread calls it.
+__device__ void gn_part_sum(const double* part, int C, const GNPart& r, double (*s_grp)[kAcc], double* s_tot) {
   const int v = threadIdx.x % kAcc, grp = threadIdx.x / kAcc;
   if (grp < 8) {
     double sum = 0.0;
-    for (int c0 = grp; c0 < C; c0 += 64) {
-      double x[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u)
+      if (grp + 8 * u < C) sum += r.x[u];
+    for (int c0 = grp + 128; c0 < C; c0 += 128) {
+      double x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
         const int c = c0 + 8 * u;
         x[u] = c < C ? part[(int64_t)c * kAcc + v] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 16; ++u)
         if (c0 + 8 * u < C) sum += x[u];
     }
     s_grp[grp][v] = sum;
@@ -278,6 +373,45 @@ __device__ __forceinline__ void gn_load_state(GNShared& s, const GNState* st, co
   }
 }
 
+// A recorded state read into registers at kernel entry (threads 0..11 hold
+// one element of cur and eval, every thread the scalars), so that its latency
+// overlaps the other loads; gn_state_to_lds then publishes it.
+struct GNStateRegs {
+  double cur, eval, cost, count;
+  int done, accepted;
+};
+
+__device__ __forceinline__ void gn_state_issue(const GNState* st, GNStateRegs& r) {
+  r.cur = r.eval = 0.0;
+  r.cost = __builtin_inf();
+  r.count = 0.0;
+  r.done = r.accepted = 0;
+  if (!st) return;
+  if (threadIdx.x < 12) {
+    r.cur = st->cur[threadIdx.x];
+    r.eval = st->eval[threadIdx.x];
+  }
+  // uniform loads (every thread): no divergent region forces an early wait
+  r.cost = st->cur_cost;
+  r.count = st->cur_count;
+  r.done = st->done;
+  r.accepted = st->accepted;
+}
+
+// From the registers, or (have = false) the initial state at start.
+__device__ __forceinline__ void gn_state_to_lds(GNShared& s, const GNStateRegs& r, bool have, const double* start) {
+  if (threadIdx.x < 12) {
+    s.cur[threadIdx.x] = have ? r.cur : start[threadIdx.x];
+    s.eval[threadIdx.x] = have ? r.eval : start[threadIdx.x];
+  }
+  if (threadIdx.x == 0) {
+    s.cost = have ? r.cost : __builtin_inf();
+    s.count = have ? r.count : 0.0;
+    s.done = have ? r.done : 0;
+    s.accepted = have ? r.accepted : 0;
+  }
+}
+
 __device__ __forceinline__ void gn_store_state(const GNShared& s, GNState* st) {
   if (threadIdx.x < 12) {
     st->cur[threadIdx.x] = s.cur[threadIdx.x];
@@ -303,28 +437,59 @@ __device__ __forceinline__ void gn_outputs(const GNArgs& g, const GNShared& s, i
 struct GNPoints {
   float X[kGNPPT], Y[kGNPPT], Z[kGNPPT], u[kGNPPT], v[kGNPPT], w[kGNPPT];
   bool use[kGNPPT];
+  int in[kGNPPT];  // in-set flag (1 where not read); tested only when accumulating
 };
 
 // MODE 1 reads the in-set flags from evaluation 1 on (evaluation 0 writes them).
+// Lanes past the end load the last point and do not use it: unconditional
+// loads issue back to back instead of one masked load (and wait) at a time.
 template <int MODE>
 __device__ __forceinline__ void gn_load_points(const CorrF32& c, int64_t n, int64_t base, const uint8_t* in_set,
                                                bool read_in_set, GNPoints& pt) {
+  if (n <= 0) {
+#pragma unroll
+    for (int t = 0; t < kGNPPT; ++t) {
+      pt.X[t] = pt.Y[t] = pt.Z[t] = pt.u[t] = pt.v[t] = 0.0f;
+      pt.w[t] = 1.0f;
+      pt.use[t] = false;
+      pt.in[t] = 0;
+    }
+    return;
+  }
+  int64_t ic[kGNPPT];
 #pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
     const int64_t i = base + (int64_t)t * kGNThreads;
-    const bool ok = i < n;
-    pt.X[t] = ok ? gmem(c.X)[i] : 0.0f;
-    pt.Y[t] = ok ? gmem(c.Y)[i] : 0.0f;
-    pt.Z[t] = ok ? gmem(c.Z)[i] : 0.0f;
-    pt.u[t] = ok ? gmem(c.u)[i] : 0.0f;
-    pt.v[t] = ok ? gmem(c.v)[i] : 0.0f;
-    pt.w[t] = ok && c.w ? gmem(c.w)[i] : 1.0f;
-    pt.use[t] = ok && (MODE == 0 || !read_in_set || in_set[i] != 0);
+    ic[t] = i < n ? i : n - 1;
+    pt.use[t] = i < n;
+  }
+#pragma unroll
+  for (int t = 0; t < kGNPPT; ++t) {
+    pt.X[t] = gmem(c.X)[ic[t]];
+    pt.Y[t] = gmem(c.Y)[ic[t]];
+    pt.Z[t] = gmem(c.Z)[ic[t]];
+    pt.u[t] = gmem(c.u)[ic[t]];
+    pt.v[t] = gmem(c.v)[ic[t]];
+  }
+  if (c.w) {
+#pragma unroll
+    for (int t = 0; t < kGNPPT; ++t) pt.w[t] = gmem(c.w)[ic[t]];
+  } else {
+#pragma unroll
+    for (int t = 0; t < kGNPPT; ++t) pt.w[t] = 1.0f;
+  }
+  if (MODE == 1 && read_in_set) {
+#pragma unroll
+    for (int t = 0; t < kGNPPT; ++t) pt.in[t] = gmem(in_set)[ic[t]];
+  } else {
+#pragma unroll
+    for (int t = 0; t < kGNPPT; ++t) pt.in[t] = 1;
   }
 }
 
 // Accumulate one chunk at pose P and store its partial sums: per thread in
-// point order, then the 16-lane rows by DPP, then the rows in row order.
+// point order, then across the wave by recursive halving, then the waves in
+// wave order.
 template <int MODE, bool RIG>
 __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* s_rig, const double* P, int j,
                                               int64_t base, const GNPoints& pt, uint8_t* in_set,
@@ -337,9 +502,16 @@ __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* 
   double a[kAcc];
 #pragma unroll
   for (int e = 0; e < kAcc; ++e) a[e] = 0.0;
+  int in[kGNPPT];
 #pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
-    if (!pt.use[t]) continue;
+    // keeps the test of the in-set byte (and the wait for its load) here
+    in[t] = pt.in[t];
+    asm volatile("" : "+v"(in[t]));
+  }
+#pragma unroll
+  for (int t = 0; t < kGNPPT; ++t) {
+    if (!pt.use[t] || in[t] == 0) continue;
     const int64_t i = base + (int64_t)t * kGNThreads;
     const double X = pt.X[t], Y = pt.Y[t], Z = pt.Z[t];
     const double w = pt.w[t];
@@ -391,17 +563,14 @@ __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* 
       else acc_point(a, K, x, y, z, iz, du, dv, w / (1.0 + q));
     }
   }
-  const int row = threadIdx.x >> 4;
-#pragma unroll
-  for (int e = 0; e < kAcc; ++e) {
-    const double v = row_sum16(a[e]);
-    if ((threadIdx.x & 15) == 0) s_rows[row][e] = v;
-  }
+  const double tot = wave_sum29(a);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if ((lane & 1) == 0 && (lane >> 1) < kAcc) s_rows[wave][lane >> 1] = tot;
   __syncthreads();
   if ((int)threadIdx.x < kAcc) {
     double t = 0.0;
 #pragma unroll
-    for (int r = 0; r < kGNRows; ++r) t += s_rows[r][threadIdx.x];
+    for (int w = 0; w < kGNWaves; ++w) t += s_rows[w][threadIdx.x];
     part_out[threadIdx.x] = t;
   }
 }
@@ -416,35 +585,49 @@ template <int MODE, bool RIG>
 __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
   const int p = blockIdx.y;
   const int chunk = blockIdx.x;
-  int q;
-  const double* start;
-  if (!gn_problem<MODE>(g, p, q, start)) return;
+  asm volatile("" ::"s"(g.qd), "s"(g.part), "s"(g.gst));
+  // loads whose addresses need only the launch: partial sums, descriptor
+  // fields, state -- issued together, so that one round trip covers them (the
+  // compiler would otherwise fetch each field in the branch that first uses it)
+  GNPart pr;
+  if (k > 0) gn_part_issue(gn_part(g, (k - 1) & 1, p), g.cmax, pr);
+  const int q = gn_query<MODE>(g, p);
   const QueryDesc& d = g.qd[q];
   const CorrF32 c = MODE == 0 ? d.S : d.full;
   const int64_t n = MODE == 0 ? d.m : d.n;
-  const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
-  const int C = chunks_for(n);
-  if (chunk >= C) return;
   uint8_t* in_set = MODE == 1 ? g.in_set_all + d.in_set_off : nullptr;
+  GNStateRegs sr;
+  gn_state_issue(k >= 2 ? g.gst + (int64_t)(k & 1) * g.nprob + p : nullptr, sr);
+  asm volatile("" ::"s"(c.X), "s"(c.Y), "s"(c.Z), "s"(c.u), "s"(c.v), "s"(c.w), "s"(n), "s"(in_set));
   const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
-  // the points are loaded first: their latency overlaps the reduction and the decision
+  // the points are loaded before any test (indices are clamped), so that the
+  // descriptor fields are read together and the point latency overlaps the
+  // reduction and the decision
   GNPoints pt;
   gn_load_points<MODE>(c, n, base, in_set, k > 0, pt);
+  const int C = chunks_for(n);
+  if (chunk >= C) return;
+  const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
 
   __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
   if (RIG && d.ncam > 0)
     for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
   __shared__ double s_grp[8][kAcc];
   __shared__ double s_tot[kAcc];
-  __shared__ double s_rows[kGNRows][kAcc];
+  __shared__ double s_rows[kGNWaves][kAcc];
   __shared__ GNShared s;
   __shared__ int s_end;
+  // the partial sums are added before the liveness test, so that their loads
+  // need not wait for it (a problem without work reads harmless stale values)
+  const bool live = gn_live<MODE>(g, p, q);
   if (k == 0) {
-    gn_load_state(s, nullptr, start);
+    if (!live) return;
+    gn_state_to_lds(s, sr, false, gn_start<MODE>(g, p, q));
     __syncthreads();
   } else {
-    gn_reduce(gn_part(g, (k - 1) & 1, p), C, s_grp, s_tot);
-    gn_load_state(s, k >= 2 ? g.gst + (int64_t)(k & 1) * g.nprob + p : nullptr, start);
+    gn_part_sum(gn_part(g, (k - 1) & 1, p), C, pr, s_grp, s_tot);
+    if (!live) return;
+    gn_state_to_lds(s, sr, k >= 2, k >= 2 ? nullptr : gn_start<MODE>(g, p, q));
     __syncthreads();
     if (threadIdx.x == 0) s_end = gn_decide(k - 1, iters, s_tot, s);
     __syncthreads();
@@ -464,9 +647,8 @@ template <int MODE, bool RIG>
 __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
   const int p = blockIdx.y;
   const int chunk = blockIdx.x;
-  int q;
-  const double* start;
-  if (!gn_problem<MODE>(g, p, q, start)) return;
+  const int q = gn_query<MODE>(g, p);
+  if (!gn_live<MODE>(g, p, q)) return;
   const QueryDesc& d = g.qd[q];
   const CorrF32 c = MODE == 0 ? d.S : d.full;
   const int64_t n = MODE == 0 ? d.m : d.n;
@@ -482,7 +664,8 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
   if (RIG && d.ncam > 0)
     for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
   __shared__ double s_eval[12];
-  __shared__ double s_rows[kGNRows][kAcc];
+  __shared__ double s_rows[kGNWaves][kAcc];
+  const double* start = st ? nullptr : gn_start<MODE>(g, p, q);
   if (threadIdx.x < 12) s_eval[threadIdx.x] = st ? st->eval[threadIdx.x] : start[threadIdx.x];
   __syncthreads();
   gn_accumulate<MODE, RIG>(d, s_rig, s_eval, j, base, pt, in_set, s_rows,
@@ -494,9 +677,10 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
 template <int MODE>
 __global__ __launch_bounds__(kGNThreads) void gn_decide_kernel(GNArgs g, int j) {
   const int p = blockIdx.x;
-  int q;
-  const double* start;
-  if (!gn_problem<MODE>(g, p, q, start)) return;
+  GNPart pr;
+  gn_part_issue(gn_part(g, j & 1, p), g.cmax, pr);
+  const int q = gn_query<MODE>(g, p);
+  if (!gn_live<MODE>(g, p, q)) return;
   const QueryDesc& d = g.qd[q];
   const int64_t n = MODE == 0 ? d.m : d.n;
   const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
@@ -505,8 +689,9 @@ __global__ __launch_bounds__(kGNThreads) void gn_decide_kernel(GNArgs g, int j) 
   __shared__ double s_tot[kAcc];
   __shared__ GNShared s;
   __shared__ int s_end;
-  gn_reduce(gn_part(g, j & 1, p), C, s_grp, s_tot);
-  gn_load_state(s, j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr, start);
+  gn_part_sum(gn_part(g, j & 1, p), C, pr, s_grp, s_tot);
+  gn_load_state(s, j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr,
+                j > 0 ? nullptr : gn_start<MODE>(g, p, q));
   __syncthreads();
   if (threadIdx.x == 0) s_end = gn_decide(j, iters, s_tot, s);
   __syncthreads();

@@ -65,13 +65,15 @@ __global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* 
   if (threadIdx.x == kP3PBlock - 1) s_base = s_scan[kP3PBlock - 1] > 0 ? atomicAdd(&cb.n[q], s_scan[kP3PBlock - 1]) : 0;
   __syncthreads();
   const int base = s_base + s_scan[threadIdx.x] - ns;
+  double Xi[9];
+  if (ns > 0) p3p_frame_inverse(x, Xi);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (j >= ns) break;
     const int64_t local = base + j;
     const int64_t o = d.cand_off + local;
     Pose P;
-    p3p_pose(sol.l[j], y, x, P);
+    p3p_pose(sol.l[j], y, x, Xi, P);
     for (int e = 0; e < 9; ++e) cb.pose[12 * o + e] = P.R[e];
     for (int e = 0; e < 3; ++e) cb.pose[12 * o + 9 + e] = P.t[e];
     write_candidate_rows(d, cb.proj, local, P);
