@@ -145,14 +145,18 @@ hipError_t launch_gather_subsets(const QueryDesc* qd, int nq, int64_t max_m, hip
 
 // --- round bookkeeping ---------------------------------------------------------
 // init: state and the weight sum of the scoring set of every fresh query.
-hipError_t launch_init_queries(const QueryDesc* qd, BestState* st, int nq, hipStream_t s);
+// begin: also set up the first round (every query of the table is fresh)
+hipError_t launch_init_queries(QueryDesc* qd, BestState* st, int32_t* n_cand, int nq, bool begin, hipStream_t s);
 // finished queries (final refinement and mask done) leave the round loop
 hipError_t launch_retire(BestState* st, int nq, hipStream_t s);
 // begin: samples of this round per query, zero candidate counts.
 hipError_t launch_begin_round(QueryDesc* qd, const BestState* st, CandBuf cb, int nq, hipStream_t s);
-// end: advance the sample count, apply the stopping rule; *active_count
-// receives the number of queries that keep sampling.
-hipError_t launch_end_round(const QueryDesc* qd, BestState* st, int nq, int32_t* active_count, hipStream_t s);
+// end: take the round's local optimisations into the running best, advance
+// the sample count, apply the stopping rule, and (begin_next) set up the next
+// round; *active_count receives the number of queries that keep sampling.
+hipError_t launch_round_end(QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
+                            const double* lo_pose, const double* lo_cost, const int64_t* lo_count, int nq, int kmax,
+                            BestState* st, int32_t* active_count, bool begin_next, hipStream_t s);
 
 // --- sampling + P3P ----------------------------------------------------------
 // Samples [drawn, drawn + B) of every query; max_b bounds B.
@@ -198,12 +202,9 @@ hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const 
                      const double* start_direct, int nprob, int kmax, int chunks_max, int iters_max, void* scratch,
                      double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, int gn_mode,
                      hipStream_t s);
-hipError_t launch_update_best(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
-                              const double* lo_pose, const double* lo_cost, const int64_t* lo_count, int nq,
-                              int kmax, BestState* st, hipStream_t s);
 hipError_t launch_refine(const QueryDesc* qd, BestState* st, const double* start_direct, int nq, int chunks_max,
                          int iters_max, uint8_t* in_set, void* scratch, double* out_pose, double* out_cost,
-                         bool any_rig, int gn_mode, hipStream_t s);
+                         bool any_rig, int gn_mode, bool fuse_mask, bool* mask_done, hipStream_t s);
 // mask and inlier count of the final pose of every query that just finished
 // (all != 0: of every query, each with a pose)
 hipError_t launch_mask(const QueryDesc* qd, BestState* st, const double* fin_pose, int nq, int64_t max_n, int all,

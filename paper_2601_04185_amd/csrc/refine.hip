@@ -239,6 +239,31 @@ __device__ __forceinline__ double wave_sum29(const double* a) {
   return v[0] + dpp_f64<0xb1>(v[0]);         // quad_perm [1, 0, 3, 2]: lane ^ 1
 }
 
+// Inlier test of point i of the full set at a final pose (float64, through
+// the point's rig camera for a rig query): depth > 0 and squared pixel
+// residual below tau^2.  Shared by the mask kernel and the fused final
+// refinement, so both give the same mask.
+__device__ __forceinline__ bool mask_test(const QueryDesc& d, const double* pose, double X, double Y, double Z,
+                                          double u, double v, int64_t i) {
+  double x = pose[0] * X + pose[1] * Y + pose[2] * Z + pose[9];
+  double y = pose[3] * X + pose[4] * Y + pose[5] * Z + pose[10];
+  double z = pose[6] * X + pose[7] * Y + pose[8] * Z + pose[11];
+  double fx = d.fx, fy = d.fy, cx = d.cx, cy = d.cy;
+  if (d.ncam > 0) {  // through the point's rig camera
+    const double* rc = d.rig + 16 * cam_of(d.segF, d.ncam, i);
+    const double* Rc = rc + 4;
+    const double xr[3] = {x, y, z};
+    x = Rc[0] * xr[0] + Rc[1] * xr[1] + Rc[2] * xr[2] + rc[13];
+    y = Rc[3] * xr[0] + Rc[4] * xr[1] + Rc[5] * xr[2] + rc[14];
+    z = Rc[6] * xr[0] + Rc[7] * xr[1] + Rc[8] * xr[2] + rc[15];
+    fx = rc[0]; fy = rc[1]; cx = rc[2]; cy = rc[3];
+  }
+  if (!(z > 0.0)) return false;
+  const double du = fx * x / z + cx - u;
+  const double dv = fy * y / z + cy - v;
+  return du * du + dv * dv < d.tau * d.tau;
+}
+
 struct GNArgs {
   const QueryDesc* qd;
   CandBuf cb;
@@ -253,6 +278,7 @@ struct GNArgs {
   double* out_cost;
   int64_t* out_count;
   int kmax, cmax, nprob;
+  int fuse_mask;  // final refinement: the launch that ends a run writes the mask of its chunk
 };
 
 // Problem p's query.  LO (MODE 0): problem p = q * kmax + slot starts from
@@ -621,7 +647,15 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
   // need not wait for it (a problem without work reads harmless stale values)
   const bool live = gn_live<MODE>(g, p, q);
   if (k == 0) {
-    if (!live) return;
+    if (!live) {
+      // a finished query without a pose gets an all-zero mask
+      if (MODE == 1 && g.fuse_mask && d.mask && g.bst[q].finished == 1) {
+#pragma unroll
+        for (int t = 0; t < kGNPPT; ++t)
+          if (pt.use[t]) d.mask[base + (int64_t)t * kGNThreads] = 0;
+      }
+      return;
+    }
     gn_state_to_lds(s, sr, false, gn_start<MODE>(g, p, q));
     __syncthreads();
   } else {
@@ -634,6 +668,20 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
     if (chunk == 0) {
       gn_store_state(s, g.gst + (int64_t)((k - 1) & 1) * g.nprob + p);
       if (s_end) gn_outputs(g, s, p);
+    }
+    if (MODE == 1 && g.fuse_mask && s_end) {  // the run ended: mask of this chunk at the final pose
+      long long cnt = 0;
+#pragma unroll
+      for (int t = 0; t < kGNPPT; ++t) {
+        const int64_t i = base + (int64_t)t * kGNThreads;
+        if (!pt.use[t]) continue;
+        const bool in = mask_test(d, s.cur, pt.X[t], pt.Y[t], pt.Z[t], pt.u[t], pt.v[t], i);
+        if (d.mask) d.mask[i] = in ? 1 : 0;
+        cnt += in ? 1 : 0;
+      }
+      cnt = wave_sum(cnt);
+      if ((threadIdx.x & (kWave - 1)) == 0 && cnt)
+        atomicAdd((unsigned long long*)&g.bst[q].full_count, (unsigned long long)cnt);
     }
   }
   if (s.done) return;
@@ -754,7 +802,8 @@ hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const 
 
 hipError_t launch_refine(const QueryDesc* qd, BestState* bst, const double* start_direct, int nq, int chunks_max,
                          int iters_max, uint8_t* in_set, void* scratch, double* out_pose, double* out_cost,
-                         bool any_rig, int gn_mode, hipStream_t s) {
+                         bool any_rig, int gn_mode, bool fuse_mask, bool* mask_done, hipStream_t s) {
+  if (mask_done) *mask_done = false;
   if (nq <= 0) return hipSuccess;
   GNArgs g{};
   split_scratch(scratch, nq, &g.gst, &g.part);
@@ -768,41 +817,10 @@ hipError_t launch_refine(const QueryDesc* qd, BestState* bst, const double* star
   g.cmax = chunks_max;
   g.nprob = nq;
   const bool fused = use_fused(gn_mode, nq, chunks_max);
+  g.fuse_mask = fused && fuse_mask && !start_direct ? 1 : 0;
+  if (mask_done) *mask_done = g.fuse_mask != 0;
   if (any_rig) launch_gn<1, true>(g, iters_max, fused, s);
   else launch_gn<1, false>(g, iters_max, fused, s);
-  return hipGetLastError();
-}
-
-// Running best after a round's local optimisations: in selection order, a
-// strictly lower refined cost replaces the best.  One thread per query.
-__global__ void update_best_kernel(const QueryDesc* __restrict__ qd, CandBuf cb, const int32_t* __restrict__ sel,
-                                   const int32_t* __restrict__ n_sel, const double* __restrict__ lo_pose,
-                                   const double* __restrict__ lo_cost, const int64_t* __restrict__ lo_count, int nq,
-                                   int kmax, BestState* __restrict__ st) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq || qd[q].B <= 0) return;
-  BestState& b = st[q];
-  const int ns = n_sel[q];
-  for (int slot = 0; slot < ns; ++slot) {
-    const int p = q * kmax + slot;
-    if (lo_cost[p] < b.cost) {
-      b.cost = lo_cost[p];
-      b.count = lo_count[p];
-      for (int e = 0; e < 12; ++e) b.pose[e] = lo_pose[12 * (int64_t)p + e];
-      const int64_t o = qd[q].cand_off + sel[q * kMaxTopK + slot];
-      b.h = cb.h[o];
-      b.j = cb.j[o];
-      b.have = 1;
-    }
-  }
-  b.lo_runs += ns;
-}
-
-hipError_t launch_update_best(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
-                              const double* lo_pose, const double* lo_cost, const int64_t* lo_count, int nq,
-                              int kmax, BestState* st, hipStream_t s) {
-  hipLaunchKernelGGL(update_best_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, qd, cb, sel, n_sel, lo_pose,
-                     lo_cost, lo_count, nq, kmax, st);
   return hipGetLastError();
 }
 
@@ -816,29 +834,10 @@ __global__ void mask_kernel(const QueryDesc* __restrict__ qd, BestState* __restr
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((int64_t)blockIdx.x * blockDim.x >= d.n) return;
   const bool have = all || st[q].have != 0;
-  const double* pose = fin_pose + 12 * (int64_t)q;
   long long in = 0;
-  if (i < d.n && have) {
-    const double X = gmem(d.full.X)[i], Y = gmem(d.full.Y)[i], Z = gmem(d.full.Z)[i];
-    double x = pose[0] * X + pose[1] * Y + pose[2] * Z + pose[9];
-    double y = pose[3] * X + pose[4] * Y + pose[5] * Z + pose[10];
-    double z = pose[6] * X + pose[7] * Y + pose[8] * Z + pose[11];
-    double fx = d.fx, fy = d.fy, cx = d.cx, cy = d.cy;
-    if (d.ncam > 0) {  // through the point's rig camera
-      const double* rc = d.rig + 16 * cam_of(d.segF, d.ncam, i);
-      const double* Rc = rc + 4;
-      const double xr[3] = {x, y, z};
-      x = Rc[0] * xr[0] + Rc[1] * xr[1] + Rc[2] * xr[2] + rc[13];
-      y = Rc[3] * xr[0] + Rc[4] * xr[1] + Rc[5] * xr[2] + rc[14];
-      z = Rc[6] * xr[0] + Rc[7] * xr[1] + Rc[8] * xr[2] + rc[15];
-      fx = rc[0]; fy = rc[1]; cx = rc[2]; cy = rc[3];
-    }
-    if (z > 0.0) {
-      const double du = fx * x / z + cx - (double)gmem(d.full.u)[i];
-      const double dv = fy * y / z + cy - (double)gmem(d.full.v)[i];
-      in = (du * du + dv * dv < d.tau * d.tau) ? 1 : 0;
-    }
-  }
+  if (i < d.n && have)
+    in = mask_test(d, fin_pose + 12 * (int64_t)q, gmem(d.full.X)[i], gmem(d.full.Y)[i], gmem(d.full.Z)[i],
+                   gmem(d.full.u)[i], gmem(d.full.v)[i], i) ? 1 : 0;
   if (i < d.n && d.mask) d.mask[i] = (uint8_t)in;
   const long long tot = wave_sum(in);
   if ((threadIdx.x & (kWave - 1)) == 0 && tot)

@@ -76,23 +76,61 @@ hipError_t launch_gather_subset(const CorrF32& c, int64_t n, int64_t m, float* d
   return hipGetLastError();
 }
 
-// One workgroup per query: reset the state and sum the scoring-set weights
-// (float64, fixed order).
-__global__ __launch_bounds__(256) void init_queries_kernel(const QueryDesc* __restrict__ qd, BestState* __restrict__ st) {
+// Samples of the coming round: the rest of the budget, at most one batch;
+// none once the query stopped.
+__device__ inline int64_t round_samples(const QueryDesc& d, const BestState& b) {
+  if (!b.active) return 0;
+  const int64_t left = d.total - b.drawn;
+  return left < d.batch ? left : d.batch;
+}
+
+// One workgroup of 1024 threads per query: reset the state and sum the
+// scoring-set weights in float64 (thread t adds elements t + 1024 (16 k + u)
+// into sixteen partial sums, u = 0..15, so that sixteen loads are in flight;
+// the partials, the waves and the workgroup are combined in a fixed order).
+// With `begin`, also set up the first round (samples, candidate counter).
+constexpr int kInitThreads = 1024;
+
+__global__ __launch_bounds__(kInitThreads) void init_queries_kernel(QueryDesc* __restrict__ qd,
+                                                                    BestState* __restrict__ st,
+                                                                    int32_t* __restrict__ n_cand, int begin) {
   const int q = blockIdx.x;
-  const QueryDesc& d = qd[q];
+  QueryDesc& d = qd[q];
   if (!d.fresh) return;
-  double s = 0.0;
-  if (d.S.w) {
-    for (int64_t i = threadIdx.x; i < d.m; i += 256) s += d.S.w[i];
+  double p[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) p[u] = 0.0;
+  const float* __restrict__ w = d.S.w;
+  const int64_t m = d.m;
+  if (w) {
+    for (int64_t i0 = threadIdx.x; i0 < m; i0 += 16 * kInitThreads) {
+      float x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int64_t i = i0 + (int64_t)kInitThreads * u;
+        x[u] = i < m ? w[i] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) p[u] += (double)x[u];
+    }
   } else {
-    for (int64_t i = threadIdx.x; i < d.m; i += 256) s += 1.0;
+    for (int64_t i0 = threadIdx.x; i0 < m; i0 += 16 * kInitThreads) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) p[u] += i0 + (int64_t)kInitThreads * u < m ? 1.0 : 0.0;
+    }
   }
-  s = wave_sum(s);
-  __shared__ double sw[4];
-  if ((threadIdx.x & 63) == 0) sw[threadIdx.x / 64] = s;
+#pragma unroll
+  for (int h = 8; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int u = 0; u < h; ++u) p[u] += p[u + h];
+  }
+  const double s = wave_sum(p[0]);
+  __shared__ double sw[kInitThreads / kWave];
+  if ((threadIdx.x & (kWave - 1)) == 0) sw[threadIdx.x / kWave] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < kInitThreads / kWave; ++k) tot += sw[k];
     BestState& b = st[q];
     for (int e = 0; e < 12; ++e) b.pose[e] = (e == 0 || e == 4 || e == 8) ? 1.0 : 0.0;
     b.cost = __builtin_inf();
@@ -103,7 +141,7 @@ __global__ __launch_bounds__(256) void init_queries_kernel(const QueryDesc* __re
     b.lo_runs = 0;
     b.candidates = 0;
     b.inlier_residuals = 0;
-    b.weight_sum = ((sw[0] + sw[1]) + sw[2]) + sw[3];
+    b.weight_sum = tot;
     b.final_cost = 0.0;
     b.full_count = 0;
     b.drawn = 0;
@@ -111,12 +149,16 @@ __global__ __launch_bounds__(256) void init_queries_kernel(const QueryDesc* __re
     const bool can = d.m >= 3 && d.total > 0;
     b.active = can ? 1 : 0;
     b.finished = can ? 0 : 1;
+    if (begin) {
+      d.B = round_samples(d, b);
+      n_cand[q] = 0;
+    }
   }
 }
 
-hipError_t launch_init_queries(const QueryDesc* qd, BestState* st, int nq, hipStream_t s) {
+hipError_t launch_init_queries(QueryDesc* qd, BestState* st, int32_t* n_cand, int nq, bool begin, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(init_queries_kernel, dim3(nq), dim3(256), 0, s, qd, st);
+  hipLaunchKernelGGL(init_queries_kernel, dim3(nq), dim3(kInitThreads), 0, s, qd, st, n_cand, begin ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -135,12 +177,7 @@ __global__ void begin_round_kernel(QueryDesc* __restrict__ qd, const BestState* 
                                    int nq) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
-  int64_t B = 0;
-  if (st[q].active) {
-    const int64_t left = qd[q].total - st[q].drawn;
-    B = left < qd[q].batch ? left : qd[q].batch;
-  }
-  qd[q].B = B;
+  qd[q].B = round_samples(qd[q], st[q]);
   n_cand[q] = 0;
 }
 
@@ -161,14 +198,39 @@ __device__ inline int64_t required_samples(double eps, double conf, int64_t cap)
   return (int64_t)k;
 }
 
-__global__ void end_round_kernel(const QueryDesc* __restrict__ qd, BestState* __restrict__ st, int nq,
-                                 int32_t* active_count) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  int act = 0;
-  if (q < nq) {
-    const QueryDesc& d = qd[q];
+// The end of a round for every query, in one workgroup: the round's local
+// optimisations update the running best (in selection order, a strictly
+// lower refined cost replaces it), the sample count advances, the stopping
+// rule runs, and with `begin_next` the next round is set up (samples,
+// candidate counter).  The number of queries still sampling is summed in the
+// workgroup and written to *active_count (nothing to clear beforehand).
+__global__ __launch_bounds__(1024) void round_end_kernel(QueryDesc* __restrict__ qd, CandBuf cb,
+                                                         const int32_t* __restrict__ sel,
+                                                         const int32_t* __restrict__ n_sel,
+                                                         const double* __restrict__ lo_pose,
+                                                         const double* __restrict__ lo_cost,
+                                                         const int64_t* __restrict__ lo_count, int nq, int kmax,
+                                                         BestState* __restrict__ st, int32_t* __restrict__ active_count,
+                                                         int begin_next) {
+  long long act = 0;
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+    QueryDesc& d = qd[q];
     BestState& b = st[q];
     if (d.B > 0) {
+      const int ns = n_sel[q];
+      for (int slot = 0; slot < ns; ++slot) {
+        const int p = q * kmax + slot;
+        if (lo_cost[p] < b.cost) {
+          b.cost = lo_cost[p];
+          b.count = lo_count[p];
+          for (int e = 0; e < 12; ++e) b.pose[e] = lo_pose[12 * (int64_t)p + e];
+          const int64_t o = d.cand_off + sel[q * kMaxTopK + slot];
+          b.h = cb.h[o];
+          b.j = cb.j[o];
+          b.have = 1;
+        }
+      }
+      b.lo_runs += ns;
       b.drawn += d.B;
       b.batches += 1;
       bool more;
@@ -185,15 +247,28 @@ __global__ void end_round_kernel(const QueryDesc* __restrict__ qd, BestState* __
         b.finished = 1;
       }
     }
-    act = b.active;
+    act += b.active;
+    if (begin_next) {
+      d.B = round_samples(d, b);
+      cb.n[q] = 0;
+    }
   }
-  const long long tot = wave_sum((long long)act);
-  if ((threadIdx.x & 63) == 0 && tot) atomicAdd(active_count, (int32_t)tot);
+  act = wave_sum(act);
+  __shared__ long long s_act[1024 / kWave];
+  if ((threadIdx.x & (kWave - 1)) == 0) s_act[threadIdx.x / kWave] = act;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += s_act[w];
+    *active_count = (int32_t)t;
+  }
 }
 
-hipError_t launch_end_round(const QueryDesc* qd, BestState* st, int nq, int32_t* active_count, hipStream_t s) {
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, active_count, (int64_t)1, 0);
-  hipLaunchKernelGGL(end_round_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, qd, st, nq, active_count);
+hipError_t launch_round_end(QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
+                            const double* lo_pose, const double* lo_cost, const int64_t* lo_count, int nq, int kmax,
+                            BestState* st, int32_t* active_count, bool begin_next, hipStream_t s) {
+  hipLaunchKernelGGL(round_end_kernel, dim3(1), dim3(1024), 0, s, qd, cb, sel, n_sel, lo_pose, lo_cost, lo_count, nq,
+                     kmax, st, active_count, begin_next ? 1 : 0);
   return hipGetLastError();
 }
 

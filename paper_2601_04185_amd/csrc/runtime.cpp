@@ -226,11 +226,18 @@ void plan_engine(Engine& e, int nq, const QPlan* pl, const imloc_ransac_params* 
   e.subset_off.push_back(sub);
 }
 
+size_t result_bytes(int nq) { return (size_t)nq * (sizeof(BestState) + 13 * sizeof(double)); }
+
 void carve_engine(Arena& a, Engine& e) {
   const int nq = e.nq;
   const size_t S = (size_t)e.slots;
   e.qd = a.take<QueryDesc>(nq);
-  e.st = a.take<BestState>(nq);
+  // states, final poses and final costs back to back, in the order of the host
+  // staging buffer, so that one copy returns all results
+  char* res = a.take<char>(result_bytes(nq));
+  e.st = reinterpret_cast<BestState*>(res);
+  e.fin_pose = reinterpret_cast<double*>(res + (size_t)nq * sizeof(BestState));
+  e.fin_cost = e.fin_pose + (size_t)nq * 12;
   e.cb.pose = a.take<double>(12 * S);
   e.cb.proj = a.take<float>((size_t)e.proj_floats);
   e.rig = a.take<double>((size_t)std::max<int64_t>(e.rig_doubles, 16));
@@ -247,8 +254,6 @@ void carve_engine(Arena& a, Engine& e) {
   e.lo_pose = a.take<double>((size_t)nq * e.kmax * 12);
   e.lo_cost = a.take<double>((size_t)nq * e.kmax);
   e.lo_count = a.take<int64_t>((size_t)nq * e.kmax);
-  e.fin_pose = a.take<double>((size_t)nq * 12);
-  e.fin_cost = a.take<double>(nq);
   e.in_set = a.take<uint8_t>((size_t)std::max<int64_t>(e.in_set_off.back(), 1));
   e.gn_lo = a.take<char>(gn_scratch_bytes(nq * e.kmax, e.chunks_lo));
   e.gn_fin = a.take<char>(gn_scratch_bytes(nq, e.chunks_fin));
@@ -441,11 +446,10 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
     HIP_TRY(ctx, hipMemcpyAsync(e.qd, htab, tab, hipMemcpyHostToDevice, st_));
     if (rigb) HIP_TRY(ctx, hipMemcpyAsync(e.rig, hrig, rigb, hipMemcpyHostToDevice, st_));
     HIP_TRY(ctx, launch_gather_subsets(e.qd, nq, max_m_sub, st_));
-    HIP_TRY(ctx, launch_init_queries(e.qd, e.st, nq, st_));
+    HIP_TRY(ctx, launch_init_queries(e.qd, e.st, e.cb.n, nq, true, st_));  // and the first round's setup
     rounds = 0;
     for (int64_t r = 0; r < e.max_rounds; ++r) {
       hipEvent_t e0 = tm.begin();
-      HIP_TRY(ctx, launch_begin_round(e.qd, e.st, e.cb, nq, st_));
       HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
       if (e.any_rig) HIP_TRY(ctx, launch_sample_gp3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
       tm.end(kStSample, e0);
@@ -459,9 +463,8 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       hipEvent_t e3 = tm.begin();
       HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * e.kmax, e.kmax, e.chunks_lo, e.lo_iters,
                              e.gn_lo, e.lo_pose, e.lo_cost, e.lo_count, e.any_rig, ctx->gn_mode, st_));
-      HIP_TRY(ctx, launch_update_best(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, e.kmax, e.st,
-                                      st_));
-      HIP_TRY(ctx, launch_end_round(e.qd, e.st, nq, e.active_count, st_));
+      HIP_TRY(ctx, launch_round_end(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, e.kmax, e.st,
+                                    e.active_count, true, st_));
       tm.end(kStLO, e3);
       ++rounds;
       if (sync) {
@@ -471,14 +474,13 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       }
     }
     hipEvent_t e4 = tm.begin();
+    bool mask_done = false;  // the fused final refinement writes the masks itself
     HIP_TRY(ctx, launch_refine(e.qd, e.st, nullptr, nq, e.chunks_fin, e.fin_iters, e.in_set, e.gn_fin, e.fin_pose,
-                               e.fin_cost, e.any_rig, ctx->gn_mode, st_));
-    HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, e.max_n, 0, st_));
+                               e.fin_cost, e.any_rig, ctx->gn_mode, true, &mask_done, st_));
+    if (!mask_done) HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, e.max_n, 0, st_));
     tm.end(kStRefine, e4);
     tm.end(kStTotal, ev_total);
-    HIP_TRY(ctx, hipMemcpyAsync(hst, e.st, (size_t)nq * sizeof(BestState), hipMemcpyDeviceToHost, st_));
-    HIP_TRY(ctx, hipMemcpyAsync(hfin, e.fin_pose, (size_t)nq * 12 * sizeof(double), hipMemcpyDeviceToHost, st_));
-    HIP_TRY(ctx, hipMemcpyAsync(hfin + 12 * nq, e.fin_cost, (size_t)nq * sizeof(double), hipMemcpyDeviceToHost, st_));
+    HIP_TRY(ctx, hipMemcpyAsync(hst, e.st, result_bytes(nq), hipMemcpyDeviceToHost, st_));
     return IMLOC_OK;
   };
 
@@ -632,7 +634,7 @@ int stage_upload(imloc_ctx* ctx, StageQuery& sq, const imloc_corr* pts, int64_t 
     HIP_TRY(ctx, hipMemcpyAsync(sq.e.rig, hrig, (size_t)sq.e.rig_doubles * sizeof(double), hipMemcpyHostToDevice,
                                 ctx->stream));
   }
-  HIP_TRY(ctx, launch_init_queries(sq.e.qd, sq.e.st, 1, ctx->stream));
+  HIP_TRY(ctx, launch_init_queries(sq.e.qd, sq.e.st, sq.e.cb.n, 1, false, ctx->stream));
   if (drawn) {
     BestState* hb = reinterpret_cast<BestState*>(ctx->pinned + 256 * ((sizeof(QueryDesc) + 255) / 256));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1154,7 +1156,7 @@ int imloc_refine(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_c
   int rc = stage_upload(ctx, sq, pts, n, K, 0, 0, mask);
   if (rc) return rc;
   HIP_TRY(ctx, launch_refine(sq.e.qd, sq.e.st, start, 1, sq.e.chunks_fin, iters, sq.e.in_set, sq.e.gn_fin, out_pose,
-                             cost, false, ctx->gn_mode, ctx->stream));
+                             cost, false, ctx->gn_mode, false, nullptr, ctx->stream));
   if (mask) HIP_TRY(ctx, launch_mask(sq.e.qd, sq.e.st, out_pose, 1, n, 1, ctx->stream));
   return IMLOC_OK;
 }
@@ -1319,7 +1321,7 @@ int imloc_server_create(imloc_ctx* ctx, const imloc_server_config* cfg, imloc_se
   for (int q = 0; q < cfg->max_slots; ++q) htab[q].fresh = 1;
   hipStream_t s = ctx->stream;
   if (hipMemcpyAsync(srv->e.qd, htab, tab, hipMemcpyHostToDevice, s) != hipSuccess ||
-      launch_init_queries(srv->e.qd, srv->e.st, cfg->max_slots, s) != hipSuccess ||
+      launch_init_queries(srv->e.qd, srv->e.st, srv->e.cb.n, cfg->max_slots, false, s) != hipSuccess ||
       launch_retire(srv->e.st, cfg->max_slots, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     delete srv;
     return set_err(ctx, IMLOC_EHIP, "server initialisation failed");
@@ -1441,7 +1443,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     Timer tm(ctx);
     HIP_TRY(ctx, hipMemcpyAsync(e.qd, htab, tab, hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, launch_gather_subsets(e.qd, nq, max_m_sub, s));
-    HIP_TRY(ctx, launch_init_queries(e.qd, e.st, nq, s));
+    HIP_TRY(ctx, launch_init_queries(e.qd, e.st, e.cb.n, nq, false, s));
     HIP_TRY(ctx, launch_begin_round(e.qd, e.st, e.cb, nq, s));
     HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, max_batch, nullptr, s));
     HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, ctx->tune.ct, e.item_off, s));
@@ -1449,17 +1451,17 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, 4 * max_batch, e.sel_part, e.sel, e.n_sel, s));
     HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * kmax, kmax, chunks_lo, lo_iters, e.gn_lo,
                            e.lo_pose, e.lo_cost, e.lo_count, false, ctx->gn_mode, s));
-    HIP_TRY(ctx, launch_update_best(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, kmax, e.st, s));
-    HIP_TRY(ctx, launch_end_round(e.qd, e.st, nq, e.active_count, s));
+    HIP_TRY(ctx, launch_round_end(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, kmax, e.st,
+                                  e.active_count, false, s));
+    bool mask_done = false;  // the fused final refinement writes the masks itself
     HIP_TRY(ctx, launch_refine(e.qd, e.st, nullptr, nq, chunks_fin, fin_iters, e.in_set, e.gn_fin, e.fin_pose,
-                               e.fin_cost, false, ctx->gn_mode, s));
-    HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, max_n, 0, s));
+                               e.fin_cost, false, ctx->gn_mode, true, &mask_done, s));
+    if (!mask_done) HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, max_n, 0, s));
     HIP_TRY(ctx, launch_retire(e.st, nq, s));
+    // the results block is laid out for all e.nq slots (the table may be shorter)
     BestState* hst = reinterpret_cast<BestState*>(ctx->pinned + tab);
-    double* hfin = reinterpret_cast<double*>(ctx->pinned + tab + (size_t)nq * sizeof(BestState));
-    HIP_TRY(ctx, hipMemcpyAsync(hst, e.st, (size_t)nq * sizeof(BestState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(hfin, e.fin_pose, (size_t)nq * 12 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(hfin + 12 * nq, e.fin_cost, (size_t)nq * sizeof(double), hipMemcpyDeviceToHost, s));
+    double* hfin = reinterpret_cast<double*>(ctx->pinned + tab + (size_t)e.nq * sizeof(BestState));
+    HIP_TRY(ctx, hipMemcpyAsync(hst, e.st, result_bytes(e.nq), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     srv->rounds++;
     for (int i = 0; i < nq; ++i) {
@@ -1487,7 +1489,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
       f.stats.lo_runs = (int32_t)b.lo_runs;
       f.stats.status = f.status;
       f.stats.best_msac = have ? b.cost : 0.0;
-      f.stats.final_cost = have ? hfin[12 * nq + i] : 0.0;
+      f.stats.final_cost = have ? hfin[12 * e.nq + i] : 0.0;
       f.stats.best_h = have ? b.h : -1;
       f.stats.best_j = have ? b.j : -1;
       f.stats.score_launches = (int32_t)b.batches;
