@@ -113,61 +113,6 @@ size_t gn_scratch_bytes(int nprob, int chunks_max) {
 // Packed row-wise index of (r, c), r <= c, in the 21-entry upper triangle.
 __host__ __device__ constexpr int upk(int r, int c) { return r * 6 - (r * (r - 1)) / 2 + (c - r); }
 
-// Solve from the reduced sums (LDS); thread 0 only.  Cholesky H = U^T U in
-// place on the packed upper triangle (pivot reciprocals computed once), then
-// U^T y = -g, U d = y, and the left update.  Every loop has constant bounds and is unrolled, so the factor, the
-// vectors and the rotation stay in registers.  Returns false if H is not positive definite.
-__device__ __forceinline__ bool gn_solve_step(const double* tot, const double* cur, double* next) {
-  double h[21], inv[6];
-#pragma unroll
-  for (int e = 0; e < 21; ++e) h[e] = tot[e];
-  bool ok = true;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    double dsum = h[upk(i, i)];
-#pragma unroll
-    for (int m = 0; m < i; ++m) dsum -= h[upk(m, i)] * h[upk(m, i)];
-    ok = ok && dsum > 0.0;
-    const double uii = sqrt(fmax(dsum, 0.0));
-    inv[i] = 1.0 / uii;
-    h[upk(i, i)] = uii;
-#pragma unroll
-    for (int j = i + 1; j < 6; ++j) {
-      double sum = h[upk(i, j)];
-#pragma unroll
-      for (int m = 0; m < i; ++m) sum -= h[upk(m, i)] * h[upk(m, j)];
-      h[upk(i, j)] = sum * inv[i];
-    }
-  }
-  if (!ok) return false;
-  double y[6], d[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    double sum = -tot[21 + i];
-#pragma unroll
-    for (int m = 0; m < i; ++m) sum -= h[upk(m, i)] * y[m];
-    y[i] = sum * inv[i];
-  }
-#pragma unroll
-  for (int i = 5; i >= 0; --i) {
-    double sum = y[i];
-#pragma unroll
-    for (int m = i + 1; m < 6; ++m) sum -= h[upk(i, m)] * d[m];
-    d[i] = sum * inv[i];
-  }
-  // left update: R' = Exp(dw) R, t' = Exp(dw) t + dt
-  double E[9];
-  so3_exp(d, E);
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      next[3 * r + c] = E[3 * r] * cur[c] + E[3 * r + 1] * cur[3 + c] + E[3 * r + 2] * cur[6 + c];
-    next[9 + r] = E[3 * r] * cur[9] + E[3 * r + 1] * cur[10] + E[3 * r + 2] * cur[11] + d[3 + r];
-  }
-  return true;
-}
-
 // A double moved across lanes by a DPP control (both 32-bit halves).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -360,30 +305,88 @@ __device__ void gn_part_sum(const double* part, int C, const GNPart& r, double (
   __syncthreads();
 }
 
-// Decision j of a run (thread 0), on the sums of evaluation j at s.eval:
-// the evaluated pose becomes the accepted one if its cost did not rise (at
-// j = 0 it is the start); unless the iteration budget is spent, the normal
-// equations at the accepted pose give the pose of evaluation j + 1.  A
-// cost-raising step ends the run with the accepted pose.  Returns true when
-// this decision ends the run.
+// Decision j of a run, on the sums of evaluation j at s.eval: the evaluated
+// pose becomes the accepted one if its cost did not rise (at j = 0 it is the
+// start); unless the iteration budget is spent, the normal equations at the
+// accepted pose give the pose of evaluation j + 1.  A cost-raising step, or a
+// system that is not positive definite, ends the run with the accepted pose.
+// Run by the 64 lanes of wave 0 (every lane takes the same branches): the
+// 6 x 7 system [H | -g] is reduced by Gauss-Jordan elimination with one row
+// per lane (lanes 0..5) and the pivot row broadcast by readlane -- a positive
+// definite matrix needs no pivoting and has positive pivots -- and lane e < 12
+// forms element e of the next pose.  Returns true when this decision ends the
+// run.
 struct GNShared {
   double cur[12], eval[12];
   double cost, count;
   int done, accepted;
 };
 
-__device__ __forceinline__ bool gn_decide(int j, int iters, const double* tot, GNShared& s) {
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ bool gn_decide_wave(int j, int iters, const double* tot, GNShared& s) {
+  const int lane = threadIdx.x;
   if (s.done) return false;
-  if (j == 0 || tot[27] <= s.cost) {
-    for (int e = 0; e < 12; ++e) s.cur[e] = s.eval[e];
-    s.cost = tot[27];
+  const double cost = tot[27];
+  if (!(j == 0 || cost <= s.cost)) {
+    if (lane == 0) s.done = 1;
+    return true;
+  }
+  // accept the evaluated pose
+  const double acc_e = lane < 12 ? s.eval[lane] : 0.0;
+  if (lane < 12) s.cur[lane] = acc_e;
+  if (lane == 0) {
+    s.cost = cost;
     s.count = tot[28];
     if (j > 0) s.accepted += 1;
-    if (j >= iters || !gn_solve_step(tot, s.cur, s.eval)) s.done = 1;
-  } else {
-    s.done = 1;
   }
-  return s.done != 0;
+  if (j >= iters) {
+    if (lane == 0) s.done = 1;
+    return true;
+  }
+  // Gauss-Jordan on [H | -g]: lane r < 6 holds row r
+  const int r = lane < 6 ? lane : 0;
+  double a[7];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) a[c] = tot[r <= c ? upk(r, c) : upk(c, r)];
+  a[6] = -tot[21 + r];
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const double piv = readlane_f64(a[i], i);
+    ok = ok && piv > 0.0;
+    const double ip = 1.0 / piv;
+    double prow[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) prow[c] = readlane_f64(a[c], i);
+    const double f = a[i] * ip;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) a[c] = lane == i ? a[c] * ip : fma(-f, prow[c], a[c]);
+  }
+  if (!ok) {
+    if (lane == 0) s.done = 1;
+    return true;
+  }
+  double d[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) d[k] = readlane_f64(a[6], k);
+  // left update: R' = Exp(dw) R, t' = Exp(dw) t + dt, element `lane` (< 12)
+  double E[9];
+  so3_exp(d, E);
+  if (lane < 12) {
+    const int rr = lane < 9 ? lane / 3 : lane - 9, cc = lane < 9 ? lane % 3 : 3;
+    const double* cur = s.eval;  // the accepted pose (s.cur holds the same values)
+    const double v = cc < 3 ? E[3 * rr] * cur[cc] + E[3 * rr + 1] * cur[3 + cc] + E[3 * rr + 2] * cur[6 + cc]
+                            : E[3 * rr] * cur[9] + E[3 * rr + 1] * cur[10] + E[3 * rr + 2] * cur[11] + d[3 + rr];
+    __builtin_amdgcn_wave_barrier();
+    s.eval[lane] = v;
+  }
+  return false;
 }
 
 __device__ __forceinline__ void gn_load_state(GNShared& s, const GNState* st, const double* start) {
@@ -463,53 +466,42 @@ __device__ __forceinline__ void gn_outputs(const GNArgs& g, const GNShared& s, i
 struct GNPoints {
   float X[kGNPPT], Y[kGNPPT], Z[kGNPPT], u[kGNPPT], v[kGNPPT], w[kGNPPT];
   bool use[kGNPPT];
-  int in[kGNPPT];  // in-set flag (1 where not read); tested only when accumulating
+  int in[kGNPPT];  // in-set byte (refinement), tested only when accumulating
+  bool has_w;      // confidence weights present (else every weight is 1)
+  bool read_in;    // the in-set bytes are valid (refinement from evaluation 1 on)
 };
 
-// MODE 1 reads the in-set flags from evaluation 1 on (evaluation 0 writes them).
-// Lanes past the end load the last point and do not use it: unconditional
-// loads issue back to back instead of one masked load (and wait) at a time.
+// MODE 1 reads the in-set flags from evaluation 1 on (evaluation 0 writes
+// them).  Branch-free: lanes past the end load the last point (and do not use
+// it), a query without points or weights reads from `safe` (any valid device
+// address), and every select happens where the value is used -- so the loads
+// issue back to back and nothing waits for them before the accumulation.
 template <int MODE>
 __device__ __forceinline__ void gn_load_points(const CorrF32& c, int64_t n, int64_t base, const uint8_t* in_set,
-                                               bool read_in_set, GNPoints& pt) {
-  if (n <= 0) {
-#pragma unroll
-    for (int t = 0; t < kGNPPT; ++t) {
-      pt.X[t] = pt.Y[t] = pt.Z[t] = pt.u[t] = pt.v[t] = 0.0f;
-      pt.w[t] = 1.0f;
-      pt.use[t] = false;
-      pt.in[t] = 0;
-    }
-    return;
-  }
-  int64_t ic[kGNPPT];
+                                               bool read_in_set, const void* safe, GNPoints& pt) {
+  const bool any = n > 0;
+  const float* sf = reinterpret_cast<const float*>(safe);
+  const float* X = any ? c.X : sf;
+  const float* Y = any ? c.Y : sf;
+  const float* Z = any ? c.Z : sf;
+  const float* U = any ? c.u : sf;
+  const float* V = any ? c.v : sf;
+  const float* W = any && c.w ? c.w : X;
+  const uint8_t* IS = MODE == 1 && any ? in_set : reinterpret_cast<const uint8_t*>(safe);
+  pt.has_w = any && c.w != nullptr;
+  pt.read_in = MODE == 1 && read_in_set;
 #pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
     const int64_t i = base + (int64_t)t * kGNThreads;
-    ic[t] = i < n ? i : n - 1;
     pt.use[t] = i < n;
-  }
-#pragma unroll
-  for (int t = 0; t < kGNPPT; ++t) {
-    pt.X[t] = gmem(c.X)[ic[t]];
-    pt.Y[t] = gmem(c.Y)[ic[t]];
-    pt.Z[t] = gmem(c.Z)[ic[t]];
-    pt.u[t] = gmem(c.u)[ic[t]];
-    pt.v[t] = gmem(c.v)[ic[t]];
-  }
-  if (c.w) {
-#pragma unroll
-    for (int t = 0; t < kGNPPT; ++t) pt.w[t] = gmem(c.w)[ic[t]];
-  } else {
-#pragma unroll
-    for (int t = 0; t < kGNPPT; ++t) pt.w[t] = 1.0f;
-  }
-  if (MODE == 1 && read_in_set) {
-#pragma unroll
-    for (int t = 0; t < kGNPPT; ++t) pt.in[t] = gmem(in_set)[ic[t]];
-  } else {
-#pragma unroll
-    for (int t = 0; t < kGNPPT; ++t) pt.in[t] = 1;
+    const int64_t ic = i < n ? i : (any ? n - 1 : 0);
+    pt.X[t] = gmem(X)[ic];
+    pt.Y[t] = gmem(Y)[ic];
+    pt.Z[t] = gmem(Z)[ic];
+    pt.u[t] = gmem(U)[ic];
+    pt.v[t] = gmem(V)[ic];
+    pt.w[t] = gmem(W)[ic];
+    pt.in[t] = MODE == 1 ? (int)gmem(IS)[ic] : 1;
   }
 }
 
@@ -537,10 +529,10 @@ __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* 
   }
 #pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
-    if (!pt.use[t] || in[t] == 0) continue;
+    if (!pt.use[t] || (pt.read_in && in[t] == 0)) continue;
     const int64_t i = base + (int64_t)t * kGNThreads;
     const double X = pt.X[t], Y = pt.Y[t], Z = pt.Z[t];
-    const double w = pt.w[t];
+    const double w = pt.has_w ? (double)pt.w[t] : 1.0;
     double x = P[0] * X + P[1] * Y + P[2] * Z + P[9];
     double y = P[3] * X + P[4] * Y + P[5] * Z + P[10];
     double z = P[6] * X + P[7] * Y + P[8] * Z + P[11];
@@ -630,7 +622,7 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
   // descriptor fields are read together and the point latency overlaps the
   // reduction and the decision
   GNPoints pt;
-  gn_load_points<MODE>(c, n, base, in_set, k > 0, pt);
+  gn_load_points<MODE>(c, n, base, in_set, k > 0, g.part, pt);
   const int C = chunks_for(n);
   if (chunk >= C) return;
   const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
@@ -663,7 +655,10 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
     if (!live) return;
     gn_state_to_lds(s, sr, k >= 2, k >= 2 ? nullptr : gn_start<MODE>(g, p, q));
     __syncthreads();
-    if (threadIdx.x == 0) s_end = gn_decide(k - 1, iters, s_tot, s);
+    if (threadIdx.x < kWave) {
+      const bool end = gn_decide_wave(k - 1, iters, s_tot, s);
+      if (threadIdx.x == 0) s_end = end;
+    }
     __syncthreads();
     if (chunk == 0) {
       gn_store_state(s, g.gst + (int64_t)((k - 1) & 1) * g.nprob + p);
@@ -707,7 +702,7 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
   uint8_t* in_set = MODE == 1 ? g.in_set_all + d.in_set_off : nullptr;
   const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
   GNPoints pt;
-  gn_load_points<MODE>(c, n, base, in_set, j > 0, pt);
+  gn_load_points<MODE>(c, n, base, in_set, j > 0, g.part, pt);
   __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
   if (RIG && d.ncam > 0)
     for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
@@ -741,7 +736,10 @@ __global__ __launch_bounds__(kGNThreads) void gn_decide_kernel(GNArgs g, int j) 
   gn_load_state(s, j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr,
                 j > 0 ? nullptr : gn_start<MODE>(g, p, q));
   __syncthreads();
-  if (threadIdx.x == 0) s_end = gn_decide(j, iters, s_tot, s);
+  if (threadIdx.x < kWave) {
+    const bool end = gn_decide_wave(j, iters, s_tot, s);
+    if (threadIdx.x == 0) s_end = end;
+  }
   __syncthreads();
   gn_store_state(s, g.gst + (int64_t)(j & 1) * g.nprob + p);
   if (s_end) gn_outputs(g, s, p);

@@ -49,18 +49,40 @@ def test_stage_calls_identical_in_both_forms(pk, n):
 
 
 def test_ransac_identical_in_both_forms(pk):
+    """Also the inlier mask: the fused form writes it in the launch that ends
+    the final refinement, the split form with the mask kernel."""
+    import torch
     q = synth.make_query(911, 30000, 0.3, 1.0, weights="conf")
     prm = pk.make_params(threshold_px=4.0, fixed_samples=2048, batch=1024, lo_top_k=8)
-    res = {}
+    res, masks = {}, {}
     for mode in (1, 2):
         ctx = pk.Context(0)
         ctx.set_gn_mode(mode)
-        res[mode] = pk.imloc_lo_ransac_pnp(ctx, pk.to_device(q), q.K, prm)
+        mask = torch.full((q.n,), 7, dtype=torch.uint8, device="cuda")
+        res[mode] = pk.imloc_lo_ransac_pnp(ctx, pk.to_device(q), q.K, prm, mask=mask)
+        masks[mode] = mask.cpu().numpy()
     (rc1, R1, t1, s1), (rc2, R2, t2, s2) = res[1], res[2]
     assert rc1 == rc2 == 0
     assert np.array_equal(R1, R2) and np.array_equal(t1, t2)
     for key in ("samples", "best_count", "full_count", "lo_runs", "best_h", "best_j", "best_msac", "final_cost"):
         assert s1[key] == s2[key], key
+    assert np.array_equal(masks[1], masks[2]) and set(np.unique(masks[1])) <= {0, 1}
+    assert int(masks[1].sum()) == s1["full_count"]
+
+
+def test_mask_of_a_query_without_pose(pk):
+    """A query that cannot sample (two points) finishes without a pose; both
+    forms leave an all-zero mask and a zero inlier count."""
+    import torch
+    q = synth.make_query(912, 2, 0.5, 1.0)
+    prm = pk.make_params(threshold_px=4.0, fixed_samples=64)
+    for mode in (1, 2):
+        ctx = pk.Context(0)
+        ctx.set_gn_mode(mode)
+        mask = torch.full((q.n,), 7, dtype=torch.uint8, device="cuda")
+        rc, R, t, st = pk.imloc_lo_ransac_pnp(ctx, pk.to_device(q), q.K, prm, mask=mask)
+        assert rc == pk.IMLOC_NO_POSE and st["full_count"] == 0
+        assert np.all(mask.cpu().numpy() == 0)
 
 
 def test_batch_identical_in_both_forms(pk):
@@ -78,6 +100,7 @@ def test_batch_identical_in_both_forms(pk):
             assert np.array_equal(res[mode][1][i][0], res[1][1][i][0]), (mode, i)
             assert np.array_equal(res[mode][1][i][1], res[1][1][i][1]), (mode, i)
             assert res[mode][2][i]["final_cost"] == res[1][2][i]["final_cost"]
+            assert res[mode][2][i]["full_count"] == res[1][2][i]["full_count"]
 
 
 def test_invalid_mode(pk):
