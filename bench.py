@@ -405,7 +405,8 @@ def main():
     q = getattr(synth, wl["make"])()
     prm = pk.make_params(**wl["params"])
     d = pk.to_device(q)
-    ctx = pk.Context(0)
+    # fixed-sample queries are captured once and replayed as a hipGraph
+    ctx = pk.Context(0, graphs=prm.fixed_samples > 0)
     tuned = None
     if args.score_shape:
         ct, wg = (int(x) for x in args.score_shape.split(","))
@@ -455,7 +456,8 @@ def main():
                higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f32" if prm.precision == 0 else "f64", dtype_solve="f64", data="synthetic",
                config=dict(workload=wl["desc"], n_correspondences=q.n, samples=prm.fixed_samples,
-                           candidates=st["candidates"], residuals_per_query=residuals, parallelism="1 GPU"),
+                           candidates=st["candidates"], residuals_per_query=residuals, parallelism="1 GPU",
+                           graph_replay=list(ctx.graph_counters())),
                queries_per_s=round(args.steps / total, 3),
                p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 4),
                p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 4),

@@ -518,12 +518,9 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       ctx->gkey = key;
       ctx->graph_captures++;
     }
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_in, s));
-    HIP_TRY(ctx, hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
-    HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, ctx->gstream));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_out, ctx->gstream));
-    HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->ev_out, 0));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->gstream));
+    // captured on the internal stream, replayed on the caller's stream
+    HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
     ctx->graph_launches++;
     rounds = (int)e.max_rounds;
   } else {
