@@ -17,6 +17,17 @@
 // root of the two quadratics, l3 follows; all three depths are Newton-polished
 // on the three distance equations, and the pose aligns the rig-frame triangle
 // with the world triangle.
+//
+// The pieces are written for eight cooperating lanes per sample: at each
+// level of the derivative splitting the monotone pieces are independent, so
+// lane j refines the root of piece j; the per-level bookkeeping (which roots
+// count, where the next level's pieces start and end) is a short scan every
+// lane repeats over the level's results.  Lane j then lifts root j to the
+// three depths, and a second scan removes duplicates and orders the
+// solutions.  Pieces with no root keep their slot and repeat the previous
+// cut point, so the next level's extra pieces are empty: the sequence of
+// non-empty pieces, and every value computed on them, is that of the plain
+// one-lane recursion.
 #pragma once
 
 #include "imloc_device.h"
@@ -36,56 +47,88 @@ __host__ __device__ inline double peval(const double* c, int d, double x) {
   return r;
 }
 
-// Real roots of the degree-d (<= 8) polynomial c on [-1, 1], ascending, by
-// derivative splitting: the roots of each derivative cut the next one into
-// monotone pieces; a piece with a sign change holds exactly one root, found
-// by Newton steps kept inside the shrinking bracket (else bisection).
-__host__ __device__ inline int poly_roots_pm1(const double* c, int d, double* roots) {
-  double der[9][9];  // der[k]: k-th derivative, degree d - k
-  for (int e = 0; e <= d; ++e) der[0][e] = c[e];
-  for (int k = 1; k <= d; ++k)
-    for (int e = 0; e <= d - k; ++e) der[k][e] = der[k - 1][e + 1] * (double)(e + 1);
-  double pts[10];
-  int np = 0;
-  for (int k = d - 1; k >= 0; --k) {
-    // roots of der[k] (degree d - k) on [-1, 1], between the previous level's roots
-    const int deg = d - k;
-    const double* p = der[k];
-    double cut[10];
-    int nc = 0;
-    cut[nc++] = -1.0;
-    for (int i = 0; i < np; ++i) cut[nc++] = pts[i];
-    cut[nc++] = 1.0;
-    int nr = 0;
-    double nxt[10];
-    for (int i = 0; i + 1 < nc; ++i) {
-      double a = cut[i], b = cut[i + 1];
-      if (!(b > a)) continue;
-      double fa = peval(p, deg, a);
-      const double fb = peval(p, deg, b);
-      if (fa == 0.0) { if (nr == 0 || nxt[nr - 1] != a) nxt[nr++] = a; continue; }
-      if (fb == 0.0) { if (i + 2 == nc) nxt[nr++] = b; continue; }
-      if ((fa < 0.0) == (fb < 0.0)) continue;
-      double x = 0.5 * (a + b), dx_old = b - a;
-      for (int it = 0; it < 100; ++it) {
-        const double fx = peval(p, deg, x);
-        if (fx == 0.0) { a = b = x; break; }
-        if ((fx < 0.0) == (fa < 0.0)) { a = x; fa = fx; } else { b = x; }
-        const double dfx = peval(der[k + 1], deg - 1, x);
-        double xn = x - fx / dfx;
-        if (!(xn > a && xn < b) || !(fabs(xn - x) < 0.5 * dx_old)) xn = 0.5 * (a + b);
-        dx_old = fabs(xn - x);
-        if (xn == x || xn <= a || xn >= b) break;
-        if (dx_old <= 2e-16 * fabs(x)) { x = xn; break; }  // converged to rounding level
-        x = xn;
-      }
-      nxt[nr++] = a == b ? a : x;
-    }
-    for (int i = 0; i < nr; ++i) pts[i] = nxt[i];
-    np = nr;
+// Coefficients (degree D - K) of the K-th derivative of the degree-D
+// polynomial c: c[e + K] (e + K) (e + K - 1) ... (e + 1), one rounding per
+// factor, largest factor first (the order of repeated differentiation).
+template <int D, int K>
+__host__ __device__ inline void deriv_coeffs(const double* c, double* o) {
+#pragma unroll
+  for (int e = 0; e <= D - K; ++e) {
+    double v = c[e + K];
+#pragma unroll
+    for (int m = e + K; m > e; --m) v *= (double)m;
+    o[e] = v;
   }
-  for (int i = 0; i < np; ++i) roots[i] = pts[i];
-  return np;
+}
+
+// Root of the degree-DEG polynomial p (derivative dp) on the piece [a, b]
+// of one level of the derivative splitting: p is monotone there, so a sign
+// change brackets exactly one root, found by Newton steps kept inside the
+// shrinking bracket (else bisection) until a step is below kRootStep (s lies
+// in [-1, 1]).  A Newton step that lands on a bracket end counts as kept, so
+// a converged iteration stops at once; a Newton step rejected right after a
+// step below kRootNoise means the iteration has reached the rounding noise of
+// p near the root, and it stops there too (bisecting on would only shrink a
+// bracket Newton approached from one side).  Returns 0 (no root), 1 (root)
+// or 2 (p(a) == 0: the root is a, and counts only if the level's previous
+// root differs from it).  A zero at b counts on the last piece of the level
+// only.
+constexpr double kRootStep = 1e-14;
+constexpr double kRootNoise = 1e-9;
+
+template <int DEG>
+__host__ __device__ inline int piece_root(const double* p, const double* dp, double a, double b, bool last_piece,
+                                          double& root) {
+  if (!(b > a)) return 0;
+  const double fa = peval(p, DEG, a);
+  const double fb = peval(p, DEG, b);
+  if (fa == 0.0) { root = a; return 2; }
+  if (fb == 0.0) {
+    root = b;
+    return last_piece ? 1 : 0;
+  }
+  if ((fa < 0.0) == (fb < 0.0)) return 0;
+  double x = 0.5 * (a + b), dx_old = b - a;
+  for (int it = 0; it < 100; ++it) {
+    const double fx = peval(p, DEG, x);
+    if (fx == 0.0) break;
+    if ((fx < 0.0) == (fa < 0.0)) a = x; else b = x;
+    const double dfx = peval(dp, DEG - 1, x);
+    double xn = x - fx / dfx;
+    if (!(xn >= a && xn <= b) || !(fabs(xn - x) < 0.5 * dx_old)) {
+      if (dx_old <= kRootNoise) break;
+      xn = 0.5 * (a + b);
+    }
+    dx_old = fabs(xn - x);
+    x = xn;
+    if (dx_old <= kRootStep) break;
+  }
+  root = x;
+  return 1;
+}
+
+// Bookkeeping of one level with N pieces, given every piece's result
+// (kind[i], root[i]): the roots that count, in order, and the cut points of
+// the next level, [-1, slot_0, ..., slot_{N-1}, 1], where slot_i is the last
+// counted root of pieces 0..i (-1 if none).  Lane j receives its next piece
+// [a, b] and whether its own root counts.
+template <int N>
+__host__ __device__ inline void level_scan(const int* kind, const double* root, int j, double& a, double& b,
+                                           bool& counted) {
+  double last = -1.0;
+  bool have = false;
+  a = -1.0;
+  b = 1.0;
+  counted = false;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int k = kind[i];
+    const double r = root[i];
+    const bool c = k == 1 || (k == 2 && (!have || last != r));
+    if (c) { last = r; have = true; }
+    if (i == j - 1) a = last;
+    if (i == j) { b = last; counted = c; }
+  }
 }
 
 struct GP3PIn {
@@ -141,14 +184,26 @@ __host__ __device__ inline bool gp3p_interval(const GP3PIn& g, int k, double& lo
   return true;
 }
 
-// Depths of the generalised P3P solutions (<= 8, all > 0, deduplicated),
-// ordered by l1 then l2.  Returns the count.
-__host__ __device__ inline int gp3p_depths(const GP3PIn& g, double (*out)[3]) {
+// The degree-8 resultant of one sample and what lifting its roots to depths
+// needs.  x = l1 = mid + half s maps the feasible interval onto s in [-1, 1];
+// every polynomial is in s, coefficients in increasing degree.
+struct GP3PPoly {
+  double mid, half, bb, dsum;
+  double B12[2], C12[3], B13[2], C13[3], P[2], R[2], Q[3];
+  double A2[3], A1[4], A0[5];
+  double oct[9];  // the resultant, divided by its largest coefficient magnitude
+};
+
+// Builds the resultant of one sample; returns its degree once negligible
+// leading coefficients are dropped (0: no feasible interval or no roots).
+__host__ __device__ inline int gp3p_poly(const GP3PIn& g, GP3PPoly& y) {
   double lo2, hi2, lo3, hi3;
   if (!gp3p_interval(g, 1, lo2, hi2) || !gp3p_interval(g, 2, lo3, hi3)) return 0;
   const double lo = fmax(0.0, fmax(lo2, lo3)), hi = fmin(hi2, hi3);
   if (!(hi > lo)) return 0;
   const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+  y.mid = mid;
+  y.half = half;
   double D12[3], D13[3], D23[3];
   for (int c = 0; c < 3; ++c) {
     D12[c] = g.o[0][c] - g.o[1][c];
@@ -158,7 +213,10 @@ __host__ __device__ inline int gp3p_depths(const GP3PIn& g, double (*out)[3]) {
   const double c12 = dot3(g.f[0], g.f[1]), c13 = dot3(g.f[0], g.f[2]), c23 = dot3(g.f[1], g.f[2]);
   // polynomials in s, x = mid + half s
   const double xs[2] = {mid, half};
-  double B12[2], C12[3], B13[2], C13[3];
+  double(&B12)[2] = y.B12;
+  double(&C12)[3] = y.C12;
+  double(&B13)[2] = y.B13;
+  double(&C13)[3] = y.C13;
   {
     const double e2 = dot3(D12, g.f[1]), g1 = dot3(D12, g.f[0]), k12 = dot3(D12, D12) - g.d2[0];
     const double e3 = dot3(D13, g.f[2]), h1 = dot3(D13, g.f[0]), k13 = dot3(D13, D13) - g.d2[1];
@@ -172,11 +230,19 @@ __host__ __device__ inline int gp3p_depths(const GP3PIn& g, double (*out)[3]) {
   }
   const double bb = -2.0 * c23, c2 = 2.0 * dot3(D23, g.f[1]), c3 = -2.0 * dot3(D23, g.f[2]);
   const double c0 = dot3(D23, D23) - g.d2[2];
-  double P[2] = {c2 - B12[0], -B12[1]};
-  double R[2] = {c3 - B13[0], -B13[1]};
-  double Q[3] = {c0 - C12[0] - C13[0], -C12[1] - C13[1], -C12[2] - C13[2]};
+  y.bb = bb;
+  y.dsum = g.d2[0] + g.d2[1] + g.d2[2];
+  double(&P)[2] = y.P;
+  double(&R)[2] = y.R;
+  double(&Q)[3] = y.Q;
+  P[0] = c2 - B12[0]; P[1] = -B12[1];
+  R[0] = c3 - B13[0]; R[1] = -B13[1];
+  Q[0] = c0 - C12[0] - C13[0]; Q[1] = -C12[1] - C13[1]; Q[2] = -C12[2] - C13[2];
   // A2 = P^2 - b B13 P + b^2 C13
-  double A2[3], A1[4], A0[5], t1[5], t2[5];
+  double(&A2)[3] = y.A2;
+  double(&A1)[4] = y.A1;
+  double(&A0)[5] = y.A0;
+  double t1[5], t2[5];
   pmul(P, 1, P, 1, A2);
   pmul(B13, 1, P, 1, t1);
   for (int e = 0; e <= 2; ++e) A2[e] += -bb * t1[e] + bb * bb * C13[e];
@@ -205,7 +271,8 @@ __host__ __device__ inline int gp3p_depths(const GP3PIn& g, double (*out)[3]) {
   pmul(A1, 3, C12, 2, a1c12);
   pmul(A0, 4, B12, 1, a0b12);
   for (int e = 0; e <= 5; ++e) W[e] = a1c12[e] - a0b12[e];
-  double UU[9], VW[9], oct[9];
+  double UU[9], VW[9];
+  double(&oct)[9] = y.oct;
   pmul(U, 4, U, 4, UU);
   pmul(V, 3, W, 5, VW);
   double scale = 0.0;
@@ -214,56 +281,78 @@ __host__ __device__ inline int gp3p_depths(const GP3PIn& g, double (*out)[3]) {
   for (int e = 0; e <= 8; ++e) oct[e] /= scale;
   int d = 8;
   while (d > 0 && fabs(oct[d]) < 1e-14) --d;
-  if (d == 0) return 0;
-  double sr[8];
-  const int nr = poly_roots_pm1(oct, d, sr);
-  double dsum = g.d2[0] + g.d2[1] + g.d2[2];
-  int nk = 0;
-  for (int r = 0; r < nr; ++r) {
-    const double x = mid + half * sr[r];
-    const double b12 = peval(B12, 1, sr[r]), c12v = peval(C12, 2, sr[r]);
-    const double a2 = peval(A2, 2, sr[r]), a1 = peval(A1, 3, sr[r]), a0 = peval(A0, 4, sr[r]);
-    double l[3] = {x, 0.0, 0.0};
-    // l2: the common root of l2^2 + B12 l2 + C12 and A2 l2^2 + A1 l2 + A0
-    const double den = a2 * b12 - a1;
-    bool ok = false;
-    if (fabs(den) > 1e-300) {
-      l[1] = -(a2 * c12v - a0) / den;
-      ok = true;
-    }
-    // otherwise (or as a check) the root of the (1,2) quadratic closest to satisfying the rest
-    const double disc = b12 * b12 - 4.0 * c12v;
-    if (!ok && disc >= 0.0) { l[1] = 0.5 * (-b12 + sqrt(disc)); ok = true; }
-    if (!ok) continue;
-    const double pv = peval(P, 1, sr[r]), qv = peval(Q, 2, sr[r]), rv = peval(R, 1, sr[r]);
-    const double den3 = bb * l[1] + rv;
-    if (fabs(den3) > 1e-300) {
-      l[2] = -(pv * l[1] + qv) / den3;
-    } else {
-      const double b13 = peval(B13, 1, sr[r]), c13v = peval(C13, 2, sr[r]);
-      const double d3 = b13 * b13 - 4.0 * c13v;
-      if (d3 < 0.0) continue;
-      l[2] = 0.5 * (-b13 + sqrt(d3));
-    }
-    if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) continue;
-    gp3p_polish(g, l);
-    if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) continue;
-    double res[3];
-    gp3p_res(g, l, res);
-    if (!(fabs(res[0]) + fabs(res[1]) + fabs(res[2]) < 1e-6 * dsum)) continue;
-    bool dup = false;
-    for (int e = 0; e < nk; ++e)
-      if (fabs(out[e][0] - l[0]) + fabs(out[e][1] - l[1]) + fabs(out[e][2] - l[2]) <= 1e-9 * (l[0] + l[1] + l[2]))
-        dup = true;
-    if (dup || nk >= 8) continue;
-    out[nk][0] = l[0]; out[nk][1] = l[1]; out[nk][2] = l[2];
-    ++nk;
+  return d;
+}
+
+// Depths (l1, l2, l3) of the root s of the resultant: l2 is the common root
+// of the two quadratics in l2, l3 follows from the bilinear relation; all
+// three are Newton-polished.  False when the root gives no valid solution
+// (a depth not positive, or a residual above 1e-6 of the squared sides).
+__host__ __device__ inline bool gp3p_lift(const GP3PIn& g, const GP3PPoly& y, double s, double l[3]) {
+  const double x = y.mid + y.half * s;
+  const double b12 = peval(y.B12, 1, s), c12v = peval(y.C12, 2, s);
+  const double a2 = peval(y.A2, 2, s), a1 = peval(y.A1, 3, s), a0 = peval(y.A0, 4, s);
+  l[0] = x;
+  l[1] = 0.0;
+  l[2] = 0.0;
+  const double den = a2 * b12 - a1;
+  bool ok = false;
+  if (fabs(den) > 1e-300) {
+    l[1] = -(a2 * c12v - a0) / den;
+    ok = true;
   }
-  // order by l1, then l2
-  for (int a = 1; a < nk; ++a)
-    for (int b = a; b > 0 && (out[b][0] < out[b - 1][0] || (out[b][0] == out[b - 1][0] && out[b][1] < out[b - 1][1])); --b)
-      for (int c = 0; c < 3; ++c) { const double t = out[b][c]; out[b][c] = out[b - 1][c]; out[b - 1][c] = t; }
-  return nk;
+  // otherwise the larger root of the (1,2) quadratic
+  const double disc = b12 * b12 - 4.0 * c12v;
+  if (!ok && disc >= 0.0) { l[1] = 0.5 * (-b12 + sqrt(disc)); ok = true; }
+  if (!ok) return false;
+  const double pv = peval(y.P, 1, s), qv = peval(y.Q, 2, s), rv = peval(y.R, 1, s);
+  const double den3 = y.bb * l[1] + rv;
+  if (fabs(den3) > 1e-300) {
+    l[2] = -(pv * l[1] + qv) / den3;
+  } else {
+    const double b13 = peval(y.B13, 1, s), c13v = peval(y.C13, 2, s);
+    const double d3 = b13 * b13 - 4.0 * c13v;
+    if (d3 < 0.0) return false;
+    l[2] = 0.5 * (-b13 + sqrt(d3));
+  }
+  if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) return false;
+  gp3p_polish(g, l);
+  if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) return false;
+  double res[3];
+  gp3p_res(g, l, res);
+  return fabs(res[0]) + fabs(res[1]) + fabs(res[2]) < 1e-6 * y.dsum;
+}
+
+// Solutions of one sample from its lifted roots (ok[i], depths l0/l1/l2[i],
+// i < N, in root order): a solution within 1e-9 (relative, summed over the
+// depths) of an earlier kept one is a duplicate; the kept ones are ordered by
+// l1, then l2, ties by root order.  Returns whether lane j's solution is kept
+// and its rank among the kept ones.
+template <int N>
+__host__ __device__ inline bool gp3p_keep_rank(const int* ok, const double* l0, const double* l1, const double* l2,
+                                               int j, int& rank) {
+  bool keep[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    bool k = ok[i] != 0;
+    const double tol = 1e-9 * (l0[i] + l1[i] + l2[i]);
+#pragma unroll
+    for (int e = 0; e < i; ++e)
+      if (keep[e] && fabs(l0[e] - l0[i]) + fabs(l1[e] - l1[i]) + fabs(l2[e] - l2[i]) <= tol) k = false;
+    keep[i] = k;
+  }
+  bool mine = false;
+  double m0 = 0.0, m1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (i == j) { mine = keep[i]; m0 = l0[i]; m1 = l1[i]; }
+  rank = 0;
+#pragma unroll
+  for (int e = 0; e < N; ++e) {
+    const bool before = l0[e] < m0 || (l0[e] == m0 && (l1[e] < m1 || (l1[e] == m1 && e < j)));
+    if (keep[e] && e != j && before) ++rank;
+  }
+  return mine;
 }
 
 // Pose with P_i = R X_i + t from the rig-frame triangle P and the world

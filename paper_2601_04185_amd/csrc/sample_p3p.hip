@@ -1,6 +1,7 @@
 // sample_p3p.hip -- minimal sampling (Philox4x64-10) and float64 P3P, one
-// lane per sample, candidates compacted per workgroup (ImLoc Sec. 3.3, "Pose
-// Estimation": batches of minimal sets, P3P hypotheses).
+// lane per sample (generalised P3P of rig queries: eight lanes per sample),
+// candidates compacted per workgroup (ImLoc Sec. 3.3, "Pose Estimation":
+// batches of minimal sets, P3P hypotheses).
 #include "gp3p_device.h"
 #include "imloc_device.h"
 #include "imloc_kernels.h"
@@ -84,9 +85,44 @@ __global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* 
   }
 }
 
-// Rig queries: the same sampling, generalised P3P on the three rays of the
-// sampled points (origin and direction of each point's camera in the rig
-// frame), up to 8 candidates per sample with rows for every camera.
+// Generalised P3P for rig queries: eight lanes per sample (a workgroup of one
+// wave holds eight samples).  The eight lanes of a sample draw the same
+// minimal set and build the same resultant; lane j refines the root of piece j
+// at every level of the derivative splitting, lifts final root j to depths,
+// and writes solution j, the per-level results being exchanged through LDS
+// within the wave.
+constexpr int kGP3PLanes = 8;
+constexpr int kGP3PSamples = kP3PBlock / kGP3PLanes;
+
+// Levels DEG..D of the derivative splitting of the degree-D resultant c on
+// lane j; kind/root: the sample's eight LDS slots.
+template <int D, int DEG>
+__device__ inline void gp3p_levels(const double* c, int j, int* kind, double* root, double& a, double& b,
+                                   bool& counted, double& r) {
+  double p[DEG + 1], dp[DEG];
+  deriv_coeffs<D, D - DEG>(c, p);
+  deriv_coeffs<D, D - DEG + 1>(c, dp);
+  double x = 0.0;
+  const int k = j < DEG ? piece_root<DEG>(p, dp, a, b, j == DEG - 1, x) : 0;
+  kind[j] = k;
+  root[j] = x;
+  __syncwarp();
+  level_scan<DEG>(kind, root, j, a, b, counted);
+  r = x;
+  __syncwarp();
+  if constexpr (DEG < D) gp3p_levels<D, DEG + 1>(c, j, kind, root, a, b, counted, r);
+}
+
+template <int D>
+__device__ inline bool gp3p_root(const double* c, int j, int* kind, double* root, double& r) {
+  double a = -1.0, b = 1.0;
+  bool counted = false;
+  gp3p_levels<D, 1>(c, j, kind, root, a, b, counted, r);
+  return j < D && counted;
+}
+
+// grid (sample blocks, queries): the lanes 8 g .. 8 g + 7 of block b of query
+// q work on sample drawn_q + 8 b + g.
 __global__ __launch_bounds__(kP3PBlock) void sample_gp3p_kernel(const QueryDesc* __restrict__ qd,
                                                                 const BestState* __restrict__ st, CandBuf cb,
                                                                 int32_t* __restrict__ triples) {
@@ -94,24 +130,29 @@ __global__ __launch_bounds__(kP3PBlock) void sample_gp3p_kernel(const QueryDesc*
   const QueryDesc& d = qd[q];
   if (d.ncam == 0) return;
   const int64_t count = d.B;
-  const int64_t s0 = (int64_t)blockIdx.x * kP3PBlock;
+  const int64_t s0 = (int64_t)blockIdx.x * kGP3PSamples;
   if (s0 >= count) return;
-  const int64_t s = s0 + threadIdx.x;
+  const int grp = threadIdx.x / kGP3PLanes, j = threadIdx.x % kGP3PLanes;
+  const int64_t s = s0 + grp;
   const int64_t h0 = st[q].drawn;
+  __shared__ int s_kind[kP3PBlock];
+  __shared__ double s_val[3][kP3PBlock];
+  __shared__ int s_base;
+  int* kind = s_kind + kGP3PLanes * grp;
+  double* v0 = s_val[0] + kGP3PLanes * grp;
+  double* v1 = s_val[1] + kGP3PLanes * grp;
+  double* v2 = s_val[2] + kGP3PLanes * grp;
   GP3PIn g;
   double X[3][3];
-  double dep[8][3];
-  int ns = 0;
-  if (s < count) {
+  double l[3] = {0.0, 0.0, 0.0};
+  bool keep = false;
+  int rank = 0;
+  if (s < count) {  // uniform over the eight lanes of a sample from here on
     const uint64_t h = (uint64_t)(h0 + s);
     int idx[3] = {-1, -1, -1};
     const bool ok = d.exhaustive ? unrank_triple(h, (uint64_t)d.m, idx)
                                  : sample_triple(d.seed, d.qid, h, (uint64_t)d.m, idx);
-    if (triples) {
-      triples[3 * s] = ok ? idx[0] : -1;
-      triples[3 * s + 1] = ok ? idx[1] : -1;
-      triples[3 * s + 2] = ok ? idx[2] : -1;
-    }
+    if (triples && j < 3) triples[3 * s + j] = ok ? idx[j] : -1;
     if (ok) {
       for (int k = 0; k < 3; ++k) {
         const int i = idx[k];
@@ -134,42 +175,54 @@ __global__ __launch_bounds__(kP3PBlock) void sample_gp3p_kernel(const QueryDesc*
         for (int c = 0; c < 3; ++c) v[c] = X[pa[e]][c] - X[pb[e]][c];
         g.d2[e] = dot3(v, v);
       }
-      ns = gp3p_depths(g, dep);
+      GP3PPoly y;
+      const int deg = gp3p_poly(g, y);
+      double r = 0.0;
+      bool valid = false;
+      switch (deg) {  // almost always 8; lower when leading coefficients vanish
+        case 8: valid = gp3p_root<8>(y.oct, j, kind, v0, r); break;
+        case 7: valid = gp3p_root<7>(y.oct, j, kind, v0, r); break;
+        case 6: valid = gp3p_root<6>(y.oct, j, kind, v0, r); break;
+        case 5: valid = gp3p_root<5>(y.oct, j, kind, v0, r); break;
+        case 4: valid = gp3p_root<4>(y.oct, j, kind, v0, r); break;
+        case 3: valid = gp3p_root<3>(y.oct, j, kind, v0, r); break;
+        case 2: valid = gp3p_root<2>(y.oct, j, kind, v0, r); break;
+        case 1: valid = gp3p_root<1>(y.oct, j, kind, v0, r); break;
+        default: break;
+      }
+      const bool lifted = valid && gp3p_lift(g, y, r, l);
+      kind[j] = lifted ? 1 : 0;
+      v0[j] = l[0];
+      v1[j] = l[1];
+      v2[j] = l[2];
+      __syncwarp();
+      keep = gp3p_keep_rank<kGP3PLanes>(kind, v0, v1, v2, j, rank);
     }
   }
-  __shared__ int s_scan[kP3PBlock];
-  __shared__ int s_base;
-  s_scan[threadIdx.x] = ns;
+  // candidate slots: one per kept solution of the workgroup, in lane order
+  const uint64_t kept = __ballot(keep);
+  const int total = __popcll(kept);
+  if (threadIdx.x == 0) s_base = total > 0 ? atomicAdd(&cb.n[q], total) : 0;
   __syncthreads();
-  for (int off = 1; off < kP3PBlock; off <<= 1) {
-    const int v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0;
-    __syncthreads();
-    s_scan[threadIdx.x] += v;
-    __syncthreads();
+  if (!keep) return;
+  const int64_t local = s_base + __popcll(kept & ((1ull << threadIdx.x) - 1ull));
+  const int64_t o = d.cand_off + local;
+  double P[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int c = 0; c < 3; ++c) P[i][c] = g.o[i][c] + l[i] * g.f[i][c];
+  Pose pose;
+  if (!gp3p_pose(P, X, pose)) {  // degenerate triangle: an identity placeholder never wins a score
+    for (int e = 0; e < 9; ++e) pose.R[e] = (e % 4 == 0) ? 1.0 : 0.0;
+    pose.t[0] = pose.t[1] = 0.0;
+    pose.t[2] = -1e30;
   }
-  if (threadIdx.x == kP3PBlock - 1) s_base = s_scan[kP3PBlock - 1] > 0 ? atomicAdd(&cb.n[q], s_scan[kP3PBlock - 1]) : 0;
-  __syncthreads();
-  const int base = s_base + s_scan[threadIdx.x] - ns;
-  for (int j = 0; j < ns; ++j) {
-    const int64_t local = base + j;
-    const int64_t o = d.cand_off + local;
-    double P[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int c = 0; c < 3; ++c) P[i][c] = g.o[i][c] + dep[j][i] * g.f[i][c];
-    Pose pose;
-    if (!gp3p_pose(P, X, pose)) {  // degenerate triangle: an identity placeholder never wins a score
-      for (int e = 0; e < 9; ++e) pose.R[e] = (e % 4 == 0) ? 1.0 : 0.0;
-      pose.t[0] = pose.t[1] = 0.0;
-      pose.t[2] = -1e30;
-    }
-    for (int e = 0; e < 9; ++e) cb.pose[12 * o + e] = pose.R[e];
-    for (int e = 0; e < 3; ++e) cb.pose[12 * o + 9 + e] = pose.t[e];
-    write_candidate_rows(d, cb.proj, local, pose);
-    cb.h[o] = h0 + s;
-    cb.j[o] = j;
-    cb.cnt[o] = 0;
-    cb.gain[o] = 0;
-  }
+  for (int e = 0; e < 9; ++e) cb.pose[12 * o + e] = pose.R[e];
+  for (int e = 0; e < 3; ++e) cb.pose[12 * o + 9 + e] = pose.t[e];
+  write_candidate_rows(d, cb.proj, local, pose);
+  cb.h[o] = h0 + s;
+  cb.j[o] = rank;
+  cb.cnt[o] = 0;
+  cb.gain[o] = 0;
 }
 
 hipError_t launch_sample_p3p(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int64_t max_b,
@@ -183,7 +236,7 @@ hipError_t launch_sample_p3p(const QueryDesc* qd, const BestState* st, CandBuf c
 hipError_t launch_sample_gp3p(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int64_t max_b,
                               int32_t* triples, hipStream_t s) {
   if (nq <= 0 || max_b <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((max_b + kP3PBlock - 1) / kP3PBlock);
+  const unsigned blocks = (unsigned)((max_b + kGP3PSamples - 1) / kGP3PSamples);
   hipLaunchKernelGGL(sample_gp3p_kernel, dim3(blocks, nq), dim3(kP3PBlock), 0, s, qd, st, cb, triples);
   return hipGetLastError();
 }
