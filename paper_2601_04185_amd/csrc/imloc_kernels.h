@@ -96,6 +96,7 @@ struct CandBuf {
   uint32_t* cnt;     // [slots] inlier count (accumulated by scoring)
   uint64_t* gain;    // [slots] sum of w (1 - r^2 / tau^2) over inliers, fixed point 2^-32 (accumulated)
   int32_t* n;        // [queries] candidates of the current round
+  int32_t* sel_done; // [queries] selection workgroups finished (zeroed by the work-list kernel)
 };
 
 // --- lift ------------------------------------------------------------------

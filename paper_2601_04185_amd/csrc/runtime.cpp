@@ -246,6 +246,7 @@ void carve_engine(Arena& a, Engine& e) {
   e.cb.cnt = a.take<uint32_t>(S);
   e.cb.gain = a.take<uint64_t>(S);
   e.cb.n = a.take<int32_t>(nq);
+  e.cb.sel_done = a.take<int32_t>(nq);
   e.item_off = a.take<int64_t>(nq + 1);
   e.active_count = a.take<int32_t>(1);
   e.sel = a.take<int32_t>((size_t)nq * kMaxTopK);

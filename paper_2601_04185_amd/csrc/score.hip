@@ -89,10 +89,11 @@ __device__ inline ChunkRange chunk_range(const QueryDesc& d, int64_t chunk) {
 
 
 // Work list: items_q = tiles_q * chunks_q for queries sampling this round;
-// item_off = exclusive prefix, item_off[nq] = total (one workgroup).
+// item_off = exclusive prefix, item_off[nq] = total (one workgroup).  Also
+// zeroes the round's selection counters (the selection follows the scoring).
 __global__ __launch_bounds__(1024) void worklist_kernel(const QueryDesc* __restrict__ qd,
                                                         const int32_t* __restrict__ n_cand, int nq, int ct,
-                                                        int64_t* __restrict__ item_off) {
+                                                        int64_t* __restrict__ item_off, int32_t* __restrict__ sel_done) {
   __shared__ long long s[1024];
   const int seg = (nq + 1023) / 1024;
   const int q0 = threadIdx.x * seg, q1 = min(nq, q0 + seg);
@@ -112,6 +113,7 @@ __global__ __launch_bounds__(1024) void worklist_kernel(const QueryDesc* __restr
   long long run = s[threadIdx.x] - sum;
   for (int q = q0; q < q1; ++q) {
     item_off[q] = run;
+    sel_done[q] = 0;
     const QueryDesc& d = qd[q];
     if (d.B > 0) run += (long long)((n_cand[q] + ct - 1) / ct) * chunks_of(d);
   }
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(1024) void worklist_kernel(const QueryDesc* __restr
 }
 
 hipError_t launch_worklist(const QueryDesc* qd, CandBuf cb, int nq, int ct, int64_t* item_off, hipStream_t s) {
-  hipLaunchKernelGGL(worklist_kernel, dim3(1), dim3(1024), 0, s, qd, cb.n, nq, ct, item_off);
+  hipLaunchKernelGGL(worklist_kernel, dim3(1), dim3(1024), 0, s, qd, cb.n, nq, ct, item_off, cb.sel_done);
   return hipGetLastError();
 }
 
@@ -410,65 +412,79 @@ __device__ inline unsigned long long ms_order(double v) {
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
-// k rounds of "pop the smallest list head of the workgroup" over per-thread
-// sorted lists of L keys; round r writes its key to out[r] (a workgroup-wide
-// LDS array).  A round takes the minimum of the 64-bit image of msac over
-// each wave (12 lane exchanges); only when several lanes hold that same msac
-// do the full keys decide.  Returns the number of keys popped (< k when the
-// lists run dry).
+// 64-bit unsigned minimum over the wave, received by every lane.  Partners:
+// lane ^ 32 and lane ^ 16 (swap instructions), lane ^ 8 (row_ror 8), lane ^ 7
+// (row_half_mirror), lane ^ 2 and lane ^ 1 (quad_perm); together they cover
+// the 64 lanes.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
+  return a < b ? a : b;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(v >> 32), (unsigned)(v >> 32), false, false);
+    v = umin64(((unsigned long long)hi[0] << 32) | lo[0], ((unsigned long long)hi[1] << 32) | lo[1]);
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(v >> 32), (unsigned)(v >> 32), false, false);
+    v = umin64(((unsigned long long)hi[0] << 32) | lo[0], ((unsigned long long)hi[1] << 32) | lo[1]);
+  }
+  v = umin64(v, dpp_u64<0x128>(v));
+  v = umin64(v, dpp_u64<0x141>(v));
+  v = umin64(v, dpp_u64<0x4e>(v));
+  v = umin64(v, dpp_u64<0xb1>(v));
+  return v;
+}
+
+// k rounds of "pop the smallest list head of the wave" over per-lane sorted
+// lists of L keys; round r writes its key to out[r] (LDS, visible to the wave
+// after a wave barrier).  A round takes the wave minimum of the 64-bit image
+// of msac; only when several lanes hold that same msac do the full keys
+// decide.  Returns the number of keys popped (< k when the lists run dry).
+// Every lane of the wave must be active.
 template <int L>
-__device__ int block_pop_k(Key (&list)[L], int k, Key* out) {
-  __shared__ Key s_key[kSelWaves];
-  __shared__ int s_lane[kSelWaves];
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+__device__ int wave_pop_k(Key (&list)[L], int k, Key* out) {
+  const int lane = threadIdx.x & (kWave - 1);
   int r = 0;
   for (; r < k; ++r) {
     const Key head = list[0];
     const bool valid = head.idx >= 0;
     const unsigned long long pr = valid ? ms_order(head.ms) : ~0ull;
-    unsigned long long m = pr;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const unsigned long long o = (unsigned long long)__shfl_xor((long long)m, off, kWave);
-      m = o < m ? o : m;
-    }
+    const unsigned long long m = wave_min_u64(pr);
     const unsigned long long tie = __ballot(valid && pr == m);
-    int wl = -1;
-    if (tie != 0) {
-      if (__popcll(tie) == 1) {
-        wl = __ffsll((long long)tie) - 1;
-      } else {
-        // several lanes share the smallest msac: full-key argmin among them
-        Key bk = ((tie >> lane) & 1ull) ? head : key_none();
-        int bl = ((tie >> lane) & 1ull) ? lane : -1;
+    if (tie == 0) break;  // uniform: the lists ran dry
+    int wl;
+    if (__popcll(tie) == 1) {
+      wl = __ffsll((long long)tie) - 1;
+    } else {
+      // several lanes share the smallest msac: full-key argmin among them
+      Key bk = ((tie >> lane) & 1ull) ? head : key_none();
+      int bl = ((tie >> lane) & 1ull) ? lane : -1;
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          const Key o = shfl_key(bk, off);
-          const int ol = __shfl_xor(bl, off, kWave);
-          if (ol >= 0 && (bl < 0 || key_less(o, bk))) { bk = o; bl = ol; }
-        }
-        wl = bl;
+      for (int off = 32; off >= 1; off >>= 1) {
+        const Key o = shfl_key(bk, off);
+        const int ol = __shfl_xor(bl, off, kWave);
+        if (ol >= 0 && (bl < 0 || key_less(o, bk))) { bk = o; bl = ol; }
       }
+      wl = __builtin_amdgcn_readfirstlane(bl);
     }
-    if (lane == (wl < 0 ? 0 : wl)) {
-      s_key[wave] = wl < 0 ? key_none() : head;
-      s_lane[wave] = wl;
-    }
-    __syncthreads();
-    int bw = -1;
-#pragma unroll
-    for (int w = 0; w < kSelWaves; ++w)
-      if (s_lane[w] >= 0 && (bw < 0 || key_less(s_key[w], s_key[bw]))) bw = w;
-    if (bw < 0) break;  // uniform: every thread read the same table
-    if (threadIdx.x == 0) out[r] = s_key[bw];
-    if (wave == bw && lane == s_lane[bw]) {
+    if (lane == wl) {
+      out[r] = head;
 #pragma unroll
       for (int e = 0; e + 1 < L; ++e) list[e] = list[e + 1];
       list[L - 1] = key_none();
     }
-    __syncthreads();
   }
-  __syncthreads();
+  __syncwarp();
   return r;
 }
 
@@ -490,18 +506,27 @@ __host__ __device__ inline int select_groups(int64_t n_cand) {
   return g < 1 ? 1 : (g > kSelGroups ? kSelGroups : (int)g);
 }
 
-// Phase 1 (k <= 8): workgroup b of a query scans candidates b * 256 + t + j *
-// G * 256, every thread keeps its best kSelList in registers, and the
-// workgroup's top k go to part[q][b][0..k) (key_none() past the end).
-__global__ __launch_bounds__(kSelThreads) void select_partial_kernel(const QueryDesc* __restrict__ qd,
-                                                                     const BestState* __restrict__ st, CandBuf cb,
-                                                                     Key* __restrict__ part) {
+// Top k (k <= 8) in one launch: workgroup b of a query scans candidates
+// b * 256 + t + j * G * 256, every thread keeps its best kSelList in
+// registers, each wave pops its k smallest, wave 0 pops the workgroup's k
+// smallest from the waves' lists and writes them to part[q][b][0..k)
+// (key_none() past the end).  The last of the query's G workgroups to finish
+// (counted in cb.sel_done) merges the G lists into the query's top k.
+__global__ __launch_bounds__(kSelThreads) void select_kernel(const QueryDesc* __restrict__ qd,
+                                                             BestState* __restrict__ st, CandBuf cb,
+                                                             Key* __restrict__ part, int32_t* __restrict__ sel,
+                                                             int32_t* __restrict__ n_sel) {
   const int q = blockIdx.y, b = blockIdx.x;
   const QueryDesc& d = qd[q];
-  if (d.B <= 0) return;
+  if (d.B <= 0) {
+    if (b == 0 && threadIdx.x == 0) n_sel[q] = 0;
+    return;
+  }
   const int nc = cb.n[q];
   const int G = select_groups(d.cap);
   if (b >= G) return;
+  const int k = d.k;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const BestState& bs = st[q];
   const double gate = bs.cost;
   Key list[kSelList];
@@ -519,36 +544,43 @@ __global__ __launch_bounds__(kSelThreads) void select_partial_kernel(const Query
     for (int u = 0; u < kSelUnroll; ++u)
       if (xs[u].idx >= 0 && xs[u].ms < gate) list_insert(list, xs[u]);
   }
+  __shared__ Key s_wave[kSelWaves][kSelList];
+  __shared__ int s_got[kSelWaves];
   __shared__ Key s_out[kSelList];
-  const int got = block_pop_k<kSelList>(list, d.k, s_out);
-  if ((int)threadIdx.x < d.k) part[((int64_t)q * kSelGroups + b) * kSelList + threadIdx.x] =
-      (int)threadIdx.x < got ? s_out[threadIdx.x] : key_none();
-}
-
-// Phase 2: one workgroup per query merges the G * k phase-1 keys (one per
-// thread) into the query's top k.
-__global__ __launch_bounds__(kSelThreads) void select_merge_kernel(const QueryDesc* __restrict__ qd,
-                                                                   BestState* __restrict__ st, CandBuf cb,
-                                                                   const Key* __restrict__ part,
-                                                                   int32_t* __restrict__ sel,
-                                                                   int32_t* __restrict__ n_sel) {
-  const int q = blockIdx.x;
-  const QueryDesc& d = qd[q];
-  if (d.B <= 0) {
-    if (threadIdx.x == 0) n_sel[q] = 0;
-    return;
+  const int got = wave_pop_k<kSelList>(list, k, s_wave[wave]);
+  if (lane == 0) s_got[wave] = got;
+  __syncthreads();
+  if (wave != 0) return;
+  // wave 0: the workgroup's k smallest from the waves' lists (one key per lane)
+  Key one[1];
+  one[0] = (lane < kSelWaves * k && lane % k < s_got[lane / k]) ? s_wave[lane / k][lane % k] : key_none();
+  const int got_b = wave_pop_k<1>(one, k, s_out);
+  Key* mine = part + ((int64_t)q * kSelGroups + b) * kSelList;
+  if (lane < k) mine[lane] = lane < got_b ? s_out[lane] : key_none();
+  // publish, then count this workgroup; the last one merges
+  __threadfence();
+  int last = 0;
+  if (lane == 0) last = atomicAdd(&cb.sel_done[q], 1) == G - 1;
+  if (!__builtin_amdgcn_readfirstlane(last)) return;
+  __threadfence();
+  // G * k <= 128 keys, two per lane, each pair sorted
+  const Key* all = part + (int64_t)q * kSelGroups * kSelList;
+  Key two[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = lane + u * kWave;
+    two[u] = e < G * k ? all[(e / k) * kSelList + e % k] : key_none();
   }
-  const int G = select_groups(d.cap);
-  const int k = d.k;
-  Key list[1];
-  const int t = threadIdx.x;
-  list[0] = t < G * k ? part[((int64_t)q * kSelGroups + t / k) * kSelList + t % k] : key_none();
-  __shared__ Key s_out[kSelList];
-  const int got = block_pop_k<1>(list, k, s_out);
-  if (t < got) sel[q * kMaxTopK + t] = s_out[t].idx;
-  if (t == 0) {
-    n_sel[q] = got;
-    st[q].candidates += cb.n[q];
+  if (two[1].idx >= 0 && (two[0].idx < 0 || key_less(two[1], two[0]))) {
+    const Key t = two[0];
+    two[0] = two[1];
+    two[1] = t;
+  }
+  const int got_q = wave_pop_k<2>(two, k, s_out);
+  if (lane < got_q) sel[q * kMaxTopK + lane] = s_out[lane].idx;
+  if (lane == 0) {
+    n_sel[q] = got_q;
+    st[q].candidates += nc;
   }
 }
 
@@ -610,9 +642,8 @@ hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, i
   BestState* stw = const_cast<BestState*>(st);
   if (kmax <= kSelList) {
     Key* part = reinterpret_cast<Key*>(scratch);
-    hipLaunchKernelGGL(select_partial_kernel, dim3(select_groups(max_cap), nq), dim3(kSelThreads), 0, s, qd, st, cb,
-                       part);
-    hipLaunchKernelGGL(select_merge_kernel, dim3(nq), dim3(kSelThreads), 0, s, qd, stw, cb, part, sel, n_sel);
+    hipLaunchKernelGGL(select_kernel, dim3(select_groups(max_cap), nq), dim3(kSelThreads), 0, s, qd, stw, cb, part,
+                       sel, n_sel);
   } else {
     hipLaunchKernelGGL(select_rounds_kernel, dim3(nq), dim3(256), 0, s, qd, stw, cb, sel, n_sel);
   }
