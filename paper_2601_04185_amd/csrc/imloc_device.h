@@ -336,162 +336,170 @@ __device__ inline void polish_depths(double l[3], double a12, double a13, double
   }
 }
 
-// Depths of the P3P solutions: at most four, one per (line, intersection)
-// slot, held in fixed slots so that no array is indexed at run time.
-struct P3PDepths {
-  double l[4][3];
-  int n;  // solutions; slots [0, n) hold them in canonical order
+// Shared part of one sample's P3P: squared sides, bearing cosines, the two
+// conics and the coefficients of the cubic det(D1 + g D2).
+struct P3PSetup {
+  double a12, a13, a23, b12, b13, b23;
+  double D1[9], D2[9];
+  double c0, c1, c2, c3;
 };
 
-// Conditional exchange of two depth slots, ordered by (camera depth of point
-// 0, camera depth of point 1, slot); invalid slots sort last.
-__device__ inline void p3p_order(double la[3], double& ka0, double& ka1, int& ia, double lb[3], double& kb0,
-                                 double& kb1, int& ib) {
-  const bool sw = kb0 < ka0 || (kb0 == ka0 && (kb1 < ka1 || (kb1 == ka1 && ib < ia)));
-  if (!sw) return;
-  for (int c = 0; c < 3; ++c) { const double t = la[c]; la[c] = lb[c]; lb[c] = t; }
-  double t = ka0; ka0 = kb0; kb0 = t;
-  t = ka1; ka1 = kb1; kb1 = t;
-  const int ti = ia; ia = ib; ib = ti;
-}
-
-// y: unit bearings (row per point), x: world points.  Fills the solution
-// depths (all > 0, deduplicated) in canonical order: camera depth of point 0
-// ascending, then of point 1.
-__device__ inline void p3p_pencil(const double y[3][3], const double x[3][3], P3PDepths& out) {
-  out.n = 0;
+// y: unit bearings (row per point), x: world points.  False for a degenerate
+// world triangle (no solution).
+__device__ inline bool p3p_setup(const double y[3][3], const double x[3][3], P3PSetup& s) {
   double d12[3], d13[3], d23[3];
   for (int k = 0; k < 3; ++k) { d12[k] = x[0][k] - x[1][k]; d13[k] = x[0][k] - x[2][k]; d23[k] = x[1][k] - x[2][k]; }
-  const double a12 = dot3(d12, d12), a13 = dot3(d13, d13), a23 = dot3(d23, d23);
+  s.a12 = dot3(d12, d12);
+  s.a13 = dot3(d13, d13);
+  s.a23 = dot3(d23, d23);
   double crs[3];
   cross3(d12, d13, crs);
-  if (!(a12 > 0.0 && a13 > 0.0 && a23 > 0.0)) return;
-  if (!(sqrt(dot3(crs, crs)) > 1e-9 * (a12 + a13 + a23))) return;
-  const double b12 = -dot3(y[0], y[1]), b13 = -dot3(y[0], y[2]), b23 = -dot3(y[1], y[2]);
-  const double ia23 = 1.0 / a23;
-  const double r12 = a12 * ia23, r13 = a13 * ia23;
-  const double D1[9] = {1.0, b12, 0.0, b12, 1.0 - r12, -r12 * b23, 0.0, -r12 * b23, -r12};
-  const double D2[9] = {1.0, 0.0, b13, 0.0, -r13, -r13 * b23, b13, -r13 * b23, 1.0 - r13};
+  if (!(s.a12 > 0.0 && s.a13 > 0.0 && s.a23 > 0.0)) return false;
+  if (!(sqrt(dot3(crs, crs)) > 1e-9 * (s.a12 + s.a13 + s.a23))) return false;
+  s.b12 = -dot3(y[0], y[1]);
+  s.b13 = -dot3(y[0], y[2]);
+  s.b23 = -dot3(y[1], y[2]);
+  const double ia23 = 1.0 / s.a23;
+  const double r12 = s.a12 * ia23, r13 = s.a13 * ia23;
+  const double D1[9] = {1.0, s.b12, 0.0, s.b12, 1.0 - r12, -r12 * s.b23, 0.0, -r12 * s.b23, -r12};
+  const double D2[9] = {1.0, 0.0, s.b13, 0.0, -r13, -r13 * s.b23, s.b13, -r13 * s.b23, 1.0 - r13};
   double A1[9], A2[9];
   adj3(D1, A1);
   adj3(D2, A2);
-  const double c0 = det3(D1), c1 = trace_prod(A1, D2), c2 = trace_prod(D1, A2), c3 = det3(D2);
+  s.c0 = det3(D1);
+  s.c1 = trace_prod(A1, D2);
+  s.c2 = trace_prod(D1, A2);
+  s.c3 = det3(D2);
+  for (int e = 0; e < 9; ++e) { s.D1[e] = D1[e]; s.D2[e] = D2[e]; }
+  return true;
+}
 
-  // degenerate pencil members: D1 + g D2 for |g| <= 1, e D1 + D2 for |e| < 1;
-  // keep the first one of best quality -S / (T^2 - 2 S)
-  double D0[9];
-  double best_q = 0.0, bestT = 0.0, bestS = 0.0;
-  bool have = false, best_f = true;
-  auto consider = [&](double root, bool from_f) {
-    double M[9], mx = 0.0;
-    for (int e = 0; e < 9; ++e) {
-      M[e] = from_f ? D1[e] + root * D2[e] : root * D1[e] + D2[e];
-      mx = fmax(mx, fabs(M[e]));
-    }
-    if (!(mx > 0.0)) return;
-    const double imx = 1.0 / mx;
-    for (int e = 0; e < 9; ++e) M[e] *= imx;
-    const double T = M[0] + M[4] + M[8];
-    const double S = (M[0] * M[4] - M[1] * M[3]) + (M[0] * M[8] - M[2] * M[6]) + (M[4] * M[8] - M[5] * M[7]);
-    const double den = T * T - 2.0 * S;
-    if (!(den > 0.0)) return;
-    const double q = -S / den;
-    if (q > best_q) {
-      best_q = q; have = true; best_f = from_f; bestT = T; bestS = S;
-      for (int e = 0; e < 9; ++e) D0[e] = M[e];
-    }
-  };
-  cubic_roots_in(c0, c1, c2, c3, -1.0, 1.0, [&](double r) { consider(r, true); });
-  cubic_roots_in(c3, c2, c1, c0, -1.0, 1.0, [&](double r) { if (fabs(r) < 1.0) consider(r, false); });
-  if (!have) return;
+// Degenerate pencil member D1 + g D2 (from_f, g = root) or e D1 + D2 (e =
+// root), scaled to unit largest entry, with its trace T and second invariant
+// S.  Returns its quality -S / (T^2 - 2 S), or 0 if it has none.
+__device__ inline double p3p_member(const P3PSetup& s, double root, bool from_f, double M[9], double& T, double& S) {
+  double mx = 0.0;
+  for (int e = 0; e < 9; ++e) {
+    M[e] = from_f ? s.D1[e] + root * s.D2[e] : root * s.D1[e] + s.D2[e];
+    mx = fmax(mx, fabs(M[e]));
+  }
+  if (!(mx > 0.0)) return 0.0;
+  const double imx = 1.0 / mx;
+  for (int e = 0; e < 9; ++e) M[e] *= imx;
+  T = M[0] + M[4] + M[8];
+  S = (M[0] * M[4] - M[1] * M[3]) + (M[0] * M[8] - M[2] * M[6]) + (M[4] * M[8] - M[5] * M[7]);
+  const double den = T * T - 2.0 * S;
+  if (!(den > 0.0)) return 0.0;
+  const double q = -S / den;
+  return q > 0.0 ? q : 0.0;
+}
+
+// One of the two searches for degenerate members: from_f, the roots g of
+// det(D1 + g D2) on [-1, 1]; otherwise the roots e of det(e D1 + D2) with
+// |e| < 1.  Returns the quality of the first member of best quality (0: none)
+// and its root.
+__device__ inline double p3p_best_member(const P3PSetup& s, bool from_f, double& best_root) {
+  double best_q = 0.0;
+  best_root = 0.0;
+  const double k0 = from_f ? s.c0 : s.c3, k1 = from_f ? s.c1 : s.c2;
+  const double k2 = from_f ? s.c2 : s.c1, k3 = from_f ? s.c3 : s.c0;
+  cubic_roots_in(k0, k1, k2, k3, -1.0, 1.0, [&](double r) {
+    if (!from_f && !(fabs(r) < 1.0)) return;
+    double M[9], T = 0.0, S = 0.0;
+    const double q = p3p_member(s, r, from_f, M, T, S);
+    if (q > best_q) { best_q = q; best_root = r; }
+  });
+  return best_q;
+}
+
+// Slot t = 2 line + intersection of the degenerate member D0 (trace T, second
+// invariant S; from_f says which conic to cut its lines with): the depths of
+// the solution on that slot, Newton-polished; false if the slot has none
+// (no intersection, a depth not positive, or a residual above 1e-6 of the
+// squared sides).
+__device__ inline bool p3p_slot(const P3PSetup& s, const double D0[9], double T, double S, bool from_f, int t,
+                                double l[3]) {
   // conic restricted to the lines: the pencil member farthest from D0
-  const double* Q = best_f ? D2 : D1;
-  const double half = 0.5 * bestT, disc = sqrt(half * half - bestS);
+  const double* Q = from_f ? s.D2 : s.D1;
+  const double half = 0.5 * T, disc = sqrt(half * half - S);
   const double s1 = half + disc, s2 = half - disc;  // s1 > 0 > s2
   double e1[3], e2[3], e3[3];
   sym_eigvec(D0, s1, e1);
   sym_eigvec(D0, s2, e2);
   cross3(e1, e2, e3);
   const double w1 = sqrt(s1), w2 = sqrt(-s2);
+  const double sgn = (t >> 1) == 0 ? -1.0 : 1.0;
+  double nrm[3], m[3];
+  for (int c = 0; c < 3; ++c) nrm[c] = w1 * e1[c] + sgn * w2 * e2[c];
+  cross3(nrm, e3, m);
+  const double mn = sqrt(dot3(m, m));
+  if (!(mn > 0.0)) return false;
+  const double imn = 1.0 / mn;
+  for (int c = 0; c < 3; ++c) m[c] *= imn;
+  double Qe[3], Qm[3];
+  for (int r = 0; r < 3; ++r) {
+    Qe[r] = Q[3 * r] * e3[0] + Q[3 * r + 1] * e3[1] + Q[3 * r + 2] * e3[2];
+    Qm[r] = Q[3 * r] * m[0] + Q[3 * r + 1] * m[1] + Q[3 * r + 2] * m[2];
+  }
+  const double A = dot3(e3, Qe), B = dot3(e3, Qm), C = dot3(m, Qm);
+  const double dq = B * B - A * C;
+  if (dq < 0.0) return false;
+  const double sq = sqrt(dq);
+  const double root_sign = (t & 1) == 0 ? 1.0 : -1.0;  // intersection 0: -B + sq, 1: -B - sq
+  double v[3];
+  if (fabs(A) >= fabs(C) && A != 0.0) {
+    const double ra = (-B + root_sign * sq) / A;  // alpha / beta
+    for (int c = 0; c < 3; ++c) v[c] = ra * e3[c] + m[c];
+  } else if (C != 0.0) {
+    const double ra = (-B + root_sign * sq) / C;  // beta / alpha
+    for (int c = 0; c < 3; ++c) v[c] = e3[c] + ra * m[c];
+  } else {
+    for (int c = 0; c < 3; ++c) v[c] = (t & 1) == 0 ? e3[c] : m[c];
+  }
+  const double s23 = v[1] * v[1] + v[2] * v[2] + 2.0 * s.b23 * v[1] * v[2];
+  if (!(s23 > 0.0)) return false;
+  const double sc = sqrt(s.a23 / s23) * ((v[0] + v[1] + v[2]) < 0.0 ? -1.0 : 1.0);
+  l[0] = sc * v[0];
+  l[1] = sc * v[1];
+  l[2] = sc * v[2];
+  if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) return false;
+  polish_depths(l, s.a12, s.a13, s.a23, s.b12, s.b13, s.b23);
+  if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) return false;
+  const double F0 = l[0] * l[0] + l[1] * l[1] + 2.0 * s.b12 * l[0] * l[1] - s.a12;
+  const double F1 = l[0] * l[0] + l[2] * l[2] + 2.0 * s.b13 * l[0] * l[2] - s.a13;
+  const double F2 = l[1] * l[1] + l[2] * l[2] + 2.0 * s.b23 * l[1] * l[2] - s.a23;
+  return fabs(F0) + fabs(F1) + fabs(F2) < 1e-6 * (s.a12 + s.a13 + s.a23);
+}
 
-  // slot 2 * line + intersection; key0/key1 = camera depths of points 0 and 1
-  double k0[4], k1[4];
-  int id[4];
-  bool ok[4];
+// Solutions of one sample from its four slots (ok[t], depths l0/l1/l2[t],
+// camera depths k0/k1[t] of points 0 and 1): a slot within 1e-9 (relative,
+// summed over the depths) of an earlier kept slot is a duplicate; the kept
+// ones are ordered by (k0, k1, slot).  Returns whether slot j is kept and its
+// rank among the kept ones.
+__device__ inline bool p3p_keep_rank(const int* ok, const double* l0, const double* l1, const double* l2,
+                                     const double* k0, const double* k1, int j, int& rank) {
+  bool keep[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    ok[t] = false;
-    id[t] = t;
-    k0[t] = __builtin_inf();
-    k1[t] = __builtin_inf();
-    out.l[t][0] = out.l[t][1] = out.l[t][2] = 0.0;
+    bool k = ok[t] != 0;
+    const double tol = 1e-9 * (l0[t] + l1[t] + l2[t]);
+#pragma unroll
+    for (int e = 0; e < t; ++e)
+      if (keep[e] && fabs(l0[e] - l0[t]) + fabs(l1[e] - l1[t]) + fabs(l2[e] - l2[t]) <= tol) k = false;
+    keep[t] = k;
   }
+  bool mine = false;
+  double m0 = 0.0, m1 = 0.0;
 #pragma unroll
-  for (int line = 0; line < 2; ++line) {
-    const double sgn = line == 0 ? -1.0 : 1.0;
-    double nrm[3], m[3];
-    for (int c = 0; c < 3; ++c) nrm[c] = w1 * e1[c] + sgn * w2 * e2[c];
-    cross3(nrm, e3, m);
-    const double mn = sqrt(dot3(m, m));
-    if (!(mn > 0.0)) continue;
-    const double imn = 1.0 / mn;
-    for (int c = 0; c < 3; ++c) m[c] *= imn;
-    double Qe[3], Qm[3];
-    for (int r = 0; r < 3; ++r) {
-      Qe[r] = Q[3 * r] * e3[0] + Q[3 * r + 1] * e3[1] + Q[3 * r + 2] * e3[2];
-      Qm[r] = Q[3 * r] * m[0] + Q[3 * r + 1] * m[1] + Q[3 * r + 2] * m[2];
-    }
-    const double A = dot3(e3, Qe), B = dot3(e3, Qm), C = dot3(m, Qm);
-    const double dq = B * B - A * C;
-    if (dq < 0.0) continue;
-    const double sq = sqrt(dq);
-    double dirs[2][3];
-    if (fabs(A) >= fabs(C) && A != 0.0) {
-      const double ra = (-B + sq) / A, rb = (-B - sq) / A;  // alpha / beta
-      for (int c = 0; c < 3; ++c) { dirs[0][c] = ra * e3[c] + m[c]; dirs[1][c] = rb * e3[c] + m[c]; }
-    } else if (C != 0.0) {
-      const double ra = (-B + sq) / C, rb = (-B - sq) / C;  // beta / alpha
-      for (int c = 0; c < 3; ++c) { dirs[0][c] = e3[c] + ra * m[c]; dirs[1][c] = e3[c] + rb * m[c]; }
-    } else {
-      for (int c = 0; c < 3; ++c) { dirs[0][c] = e3[c]; dirs[1][c] = m[c]; }
-    }
+  for (int t = 0; t < 4; ++t)
+    if (t == j) { mine = keep[t]; m0 = k0[t]; m1 = k1[t]; }
+  rank = 0;
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const int t = 2 * line + d;
-      const double* v = dirs[d];
-      const double s23 = v[1] * v[1] + v[2] * v[2] + 2.0 * b23 * v[1] * v[2];
-      if (!(s23 > 0.0)) continue;
-      const double sc = sqrt(a23 / s23) * ((v[0] + v[1] + v[2]) < 0.0 ? -1.0 : 1.0);
-      double l[3] = {sc * v[0], sc * v[1], sc * v[2]};
-      if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) continue;
-      polish_depths(l, a12, a13, a23, b12, b13, b23);
-      if (!(l[0] > 0.0 && l[1] > 0.0 && l[2] > 0.0)) continue;
-      const double F0 = l[0] * l[0] + l[1] * l[1] + 2.0 * b12 * l[0] * l[1] - a12;
-      const double F1 = l[0] * l[0] + l[2] * l[2] + 2.0 * b13 * l[0] * l[2] - a13;
-      const double F2 = l[1] * l[1] + l[2] * l[2] + 2.0 * b23 * l[1] * l[2] - a23;
-      if (!(fabs(F0) + fabs(F1) + fabs(F2) < 1e-6 * (a12 + a13 + a23))) continue;
-      // a duplicate of an earlier accepted slot is dropped
-      bool dup = false;
-#pragma unroll
-      for (int e = 0; e < t; ++e) {
-        const double dl = fabs(out.l[e][0] - l[0]) + fabs(out.l[e][1] - l[1]) + fabs(out.l[e][2] - l[2]);
-        if (ok[e] && dl <= 1e-9 * (l[0] + l[1] + l[2])) dup = true;
-      }
-      if (dup) continue;
-      ok[t] = true;
-      out.l[t][0] = l[0]; out.l[t][1] = l[1]; out.l[t][2] = l[2];
-      k0[t] = l[0] * y[0][2];
-      k1[t] = l[1] * y[1][2];
-    }
+  for (int e = 0; e < 4; ++e) {
+    const bool before = k0[e] < m0 || (k0[e] == m0 && (k1[e] < m1 || (k1[e] == m1 && e < j)));
+    if (keep[e] && e != j && before) ++rank;
   }
-  out.n = (int)ok[0] + (int)ok[1] + (int)ok[2] + (int)ok[3];
-  // four-input sorting network; ties (never between distinct solutions in
-  // practice) keep the slot order
-  p3p_order(out.l[0], k0[0], k1[0], id[0], out.l[1], k0[1], k1[1], id[1]);
-  p3p_order(out.l[2], k0[2], k1[2], id[2], out.l[3], k0[3], k1[3], id[3]);
-  p3p_order(out.l[0], k0[0], k1[0], id[0], out.l[2], k0[2], k1[2], id[2]);
-  p3p_order(out.l[1], k0[1], k1[1], id[1], out.l[3], k0[3], k1[3], id[3]);
-  p3p_order(out.l[1], k0[1], k1[1], id[1], out.l[2], k0[2], k1[2], id[2]);
+  return mine;
 }
 
 // Inverse of the world triangle frame X = [x1 - x2, x1 - x3, (x1 - x2) x

@@ -1,5 +1,5 @@
-// sample_p3p.hip -- minimal sampling (Philox4x64-10) and float64 P3P, one
-// lane per sample (generalised P3P of rig queries: eight lanes per sample),
+// sample_p3p.hip -- minimal sampling (Philox4x64-10) and float64 P3P, four
+// lanes per sample (generalised P3P of rig queries: eight lanes per sample),
 // candidates compacted per workgroup (ImLoc Sec. 3.3, "Pose Estimation":
 // batches of minimal sets, P3P hypotheses).
 #include "gp3p_device.h"
@@ -9,35 +9,48 @@
 
 namespace imloc {
 
-constexpr int kP3PBlock = 64;
 
-// grid (sample blocks, queries): lane s of block b of query q draws sample
-// drawn_q + 64 b + s.
-__global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* __restrict__ qd,
+// P3P: four lanes per sample (a workgroup of four waves holds 64 samples).
+// The four lanes of a sample draw the same minimal set and build the same
+// conics; lanes 0 and 2 search det(D1 + g D2) for degenerate members, lanes
+// 1 and 3 det(e D1 + D2), and the pair's better member (the first search's
+// on ties) is exchanged through LDS; lane j then cuts slot j (line j / 2,
+// intersection j % 2), and a scan over the four slots removes duplicates and
+// gives the canonical order.
+constexpr int kP3PLanes = 4;
+constexpr int kP3PThreads = 256;  // four waves, 64 samples: one slot reservation per 64 samples
+constexpr int kP3PSamples = kP3PThreads / kP3PLanes;
+
+// grid (sample blocks, queries): the lanes 4 g .. 4 g + 3 of block b of query
+// q work on sample drawn_q + 64 b + g.
+__global__ __launch_bounds__(kP3PThreads) void sample_p3p_kernel(const QueryDesc* __restrict__ qd,
                                                                const BestState* __restrict__ st, CandBuf cb,
                                                                int32_t* __restrict__ triples) {
   const int q = blockIdx.y;
   const QueryDesc& d = qd[q];
   if (d.ncam > 0) return;  // rig queries: sample_gp3p_kernel
   const int64_t count = d.B;
-  const int64_t s0 = (int64_t)blockIdx.x * kP3PBlock;
+  const int64_t s0 = (int64_t)blockIdx.x * kP3PSamples;
   if (s0 >= count) return;
-  const int64_t s = s0 + threadIdx.x;
+  const int grp = threadIdx.x / kP3PLanes, j = threadIdx.x % kP3PLanes;
+  const int64_t s = s0 + grp;
   const int64_t h0 = st[q].drawn;
   const Cam K{d.fx, d.fy, d.cx, d.cy};
-  P3PDepths sol;
-  sol.n = 0;
+  __shared__ double s_q[kP3PThreads], s_root[kP3PThreads];
+  __shared__ int s_ok[kP3PThreads];
+  __shared__ double s_l[5][kP3PThreads];
+  const int g0 = kP3PLanes * grp;
   double y[3][3], x[3][3];
-  if (s < count) {
+  double l[3] = {0.0, 0.0, 0.0};
+  bool keep = false;
+  int rank = 0;
+  if (s < count) {  // uniform over the four lanes of a sample from here on
     const uint64_t h = (uint64_t)(h0 + s);
     int idx[3] = {-1, -1, -1};
     const bool ok = d.exhaustive ? unrank_triple(h, (uint64_t)d.m, idx)
                                  : sample_triple(d.seed, d.qid, h, (uint64_t)d.m, idx);
-    if (triples) {
-      triples[3 * s] = ok ? idx[0] : -1;
-      triples[3 * s + 1] = ok ? idx[1] : -1;
-      triples[3 * s + 2] = ok ? idx[2] : -1;
-    }
+    if (triples && j < 3) triples[3 * s + j] = ok ? idx[j] : -1;
+    P3PSetup su;
     if (ok) {
       for (int k = 0; k < 3; ++k) {
         const int i = idx[k];
@@ -46,53 +59,83 @@ __global__ __launch_bounds__(kP3PBlock) void sample_p3p_kernel(const QueryDesc* 
         y[k][0] = bx * inv; y[k][1] = by * inv; y[k][2] = inv;
         x[k][0] = d.S.X[i]; x[k][1] = d.S.Y[i]; x[k][2] = d.S.Z[i];
       }
-      p3p_pencil(y, x, sol);
+    }
+    if (ok && p3p_setup(y, x, su)) {
+      // the best degenerate member of this lane's search, then of the pair
+      double root = 0.0;
+      const double mq = p3p_best_member(su, (j & 1) == 0, root);
+      s_q[threadIdx.x] = mq;
+      s_root[threadIdx.x] = root;
+      __syncwarp();
+      const double q1 = s_q[g0], q2 = s_q[g0 + 1];
+      const bool from_f = !(q2 > q1);
+      const double best_root = from_f ? s_root[g0] : s_root[g0 + 1];
+      __syncwarp();
+      int okj = 0;
+      double k0 = __builtin_inf(), k1 = __builtin_inf();
+      if (q1 > 0.0 || q2 > 0.0) {
+        double D0[9], T = 0.0, S = 0.0;
+        p3p_member(su, best_root, from_f, D0, T, S);
+        okj = p3p_slot(su, D0, T, S, from_f, j, l) ? 1 : 0;
+        if (okj) {
+          k0 = l[0] * y[0][2];
+          k1 = l[1] * y[1][2];
+        }
+      }
+      s_ok[threadIdx.x] = okj;
+      s_l[0][threadIdx.x] = l[0];
+      s_l[1][threadIdx.x] = l[1];
+      s_l[2][threadIdx.x] = l[2];
+      s_l[3][threadIdx.x] = k0;
+      s_l[4][threadIdx.x] = k1;
+      __syncwarp();
+      keep = p3p_keep_rank(s_ok + g0, s_l[0] + g0, s_l[1] + g0, s_l[2] + g0, s_l[3] + g0, s_l[4] + g0, j, rank);
     }
   }
-  const int ns = sol.n;
-  // workgroup-wide exclusive scan of the solution counts (sample order inside
-  // the workgroup; workgroups append in completion order -- the order of the
-  // candidates never enters a result)
-  __shared__ int s_scan[kP3PBlock];
-  __shared__ int s_base;
-  s_scan[threadIdx.x] = ns;
+  // candidate slots: one per kept solution of the workgroup, in lane order
+  // (workgroups append in completion order -- the order of the candidates
+  // never enters a result)
+  constexpr int kWaves = kP3PThreads / kWave;
+  __shared__ int s_wcnt[kWaves], s_base;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const uint64_t kept = __ballot(keep);
+  if (lane == 0) s_wcnt[wave] = __popcll(kept);
   __syncthreads();
-  for (int off = 1; off < kP3PBlock; off <<= 1) {
-    const int v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0;
-    __syncthreads();
-    s_scan[threadIdx.x] += v;
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    int total = 0;
+    for (int w = 0; w < kWaves; ++w) total += s_wcnt[w];
+    s_base = total > 0 ? atomicAdd(&cb.n[q], total) : 0;
   }
-  if (threadIdx.x == kP3PBlock - 1) s_base = s_scan[kP3PBlock - 1] > 0 ? atomicAdd(&cb.n[q], s_scan[kP3PBlock - 1]) : 0;
   __syncthreads();
-  const int base = s_base + s_scan[threadIdx.x] - ns;
+  if (!keep) return;
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += s_wcnt[w];
+  const int64_t local = s_base + before + __popcll(kept & ((1ull << lane) - 1ull));
+  const int64_t o = d.cand_off + local;
   double Xi[9];
-  if (ns > 0) p3p_frame_inverse(x, Xi);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (j >= ns) break;
-    const int64_t local = base + j;
-    const int64_t o = d.cand_off + local;
-    Pose P;
-    p3p_pose(sol.l[j], y, x, Xi, P);
-    for (int e = 0; e < 9; ++e) cb.pose[12 * o + e] = P.R[e];
-    for (int e = 0; e < 3; ++e) cb.pose[12 * o + 9 + e] = P.t[e];
-    write_candidate_rows(d, cb.proj, local, P);
-    cb.h[o] = h0 + s;
-    cb.j[o] = j;
-    cb.cnt[o] = 0;
-    cb.gain[o] = 0;
-  }
+  p3p_frame_inverse(x, Xi);
+  Pose P;
+  p3p_pose(l, y, x, Xi, P);
+  for (int e = 0; e < 9; ++e) cb.pose[12 * o + e] = P.R[e];
+  for (int e = 0; e < 3; ++e) cb.pose[12 * o + 9 + e] = P.t[e];
+  write_candidate_rows(d, cb.proj, local, P);
+  cb.h[o] = h0 + s;
+  cb.j[o] = rank;
+  cb.cnt[o] = 0;
+  cb.gain[o] = 0;
 }
 
-// Generalised P3P for rig queries: eight lanes per sample (a workgroup of one
-// wave holds eight samples).  The eight lanes of a sample draw the same
+// Generalised P3P for rig queries: eight lanes per sample (a one-wave
+// workgroup holds eight samples).  The eight lanes of a sample draw the same
 // minimal set and build the same resultant; lane j refines the root of piece j
 // at every level of the derivative splitting, lifts final root j to depths,
 // and writes solution j, the per-level results being exchanged through LDS
 // within the wave.
 constexpr int kGP3PLanes = 8;
-constexpr int kGP3PSamples = kP3PBlock / kGP3PLanes;
+// One wave (eight samples) per workgroup: a round of 2,048 samples is 256
+// waves, and one per CU runs faster than four per CU on a quarter of the CUs.
+constexpr int kGP3PThreads = 64;
+constexpr int kGP3PSamples = kGP3PThreads / kGP3PLanes;
 
 // Levels DEG..D of the derivative splitting of the degree-D resultant c on
 // lane j; kind/root: the sample's eight LDS slots.
@@ -123,7 +166,7 @@ __device__ inline bool gp3p_root(const double* c, int j, int* kind, double* root
 
 // grid (sample blocks, queries): the lanes 8 g .. 8 g + 7 of block b of query
 // q work on sample drawn_q + 8 b + g.
-__global__ __launch_bounds__(kP3PBlock) void sample_gp3p_kernel(const QueryDesc* __restrict__ qd,
+__global__ __launch_bounds__(kGP3PThreads) void sample_gp3p_kernel(const QueryDesc* __restrict__ qd,
                                                                 const BestState* __restrict__ st, CandBuf cb,
                                                                 int32_t* __restrict__ triples) {
   const int q = blockIdx.y;
@@ -135,9 +178,8 @@ __global__ __launch_bounds__(kP3PBlock) void sample_gp3p_kernel(const QueryDesc*
   const int grp = threadIdx.x / kGP3PLanes, j = threadIdx.x % kGP3PLanes;
   const int64_t s = s0 + grp;
   const int64_t h0 = st[q].drawn;
-  __shared__ int s_kind[kP3PBlock];
-  __shared__ double s_val[3][kP3PBlock];
-  __shared__ int s_base;
+  __shared__ int s_kind[kGP3PThreads];
+  __shared__ double s_val[3][kGP3PThreads];
   int* kind = s_kind + kGP3PLanes * grp;
   double* v0 = s_val[0] + kGP3PLanes * grp;
   double* v1 = s_val[1] + kGP3PLanes * grp;
@@ -200,12 +242,22 @@ __global__ __launch_bounds__(kP3PBlock) void sample_gp3p_kernel(const QueryDesc*
     }
   }
   // candidate slots: one per kept solution of the workgroup, in lane order
+  constexpr int kWaves = kGP3PThreads / kWave;
+  __shared__ int s_wcnt[kWaves], s_base;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const uint64_t kept = __ballot(keep);
-  const int total = __popcll(kept);
-  if (threadIdx.x == 0) s_base = total > 0 ? atomicAdd(&cb.n[q], total) : 0;
+  if (lane == 0) s_wcnt[wave] = __popcll(kept);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int total = 0;
+    for (int w = 0; w < kWaves; ++w) total += s_wcnt[w];
+    s_base = total > 0 ? atomicAdd(&cb.n[q], total) : 0;
+  }
   __syncthreads();
   if (!keep) return;
-  const int64_t local = s_base + __popcll(kept & ((1ull << threadIdx.x) - 1ull));
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += s_wcnt[w];
+  const int64_t local = s_base + before + __popcll(kept & ((1ull << lane) - 1ull));
   const int64_t o = d.cand_off + local;
   double P[3][3];
   for (int i = 0; i < 3; ++i)
@@ -228,8 +280,8 @@ __global__ __launch_bounds__(kP3PBlock) void sample_gp3p_kernel(const QueryDesc*
 hipError_t launch_sample_p3p(const QueryDesc* qd, const BestState* st, CandBuf cb, int nq, int64_t max_b,
                              int32_t* triples, hipStream_t s) {
   if (nq <= 0 || max_b <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((max_b + kP3PBlock - 1) / kP3PBlock);
-  hipLaunchKernelGGL(sample_p3p_kernel, dim3(blocks, nq), dim3(kP3PBlock), 0, s, qd, st, cb, triples);
+  const unsigned blocks = (unsigned)((max_b + kP3PSamples - 1) / kP3PSamples);
+  hipLaunchKernelGGL(sample_p3p_kernel, dim3(blocks, nq), dim3(kP3PThreads), 0, s, qd, st, cb, triples);
   return hipGetLastError();
 }
 
@@ -237,7 +289,7 @@ hipError_t launch_sample_gp3p(const QueryDesc* qd, const BestState* st, CandBuf 
                               int32_t* triples, hipStream_t s) {
   if (nq <= 0 || max_b <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((max_b + kGP3PSamples - 1) / kGP3PSamples);
-  hipLaunchKernelGGL(sample_gp3p_kernel, dim3(blocks, nq), dim3(kP3PBlock), 0, s, qd, st, cb, triples);
+  hipLaunchKernelGGL(sample_gp3p_kernel, dim3(blocks, nq), dim3(kGP3PThreads), 0, s, qd, st, cb, triples);
   return hipGetLastError();
 }
 
