@@ -130,7 +130,7 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
                                                uint32_t* __restrict__ ccnt, unsigned long long* __restrict__ cgain,
                                                BestState* st, int64_t tile, int64_t chunk, int ncand,
                                                uint32_t (*s_cnt)[kScoreWaves],
-                                               unsigned long long (*s_gain)[kScoreWaves]) {
+                                               unsigned long long (*s_gain)[kScoreWaves], uint32_t* s_item) {
   constexpr int PPL = kScorePPL32;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const float inv_tau = (float)(1.0 / d.tau);
@@ -198,6 +198,7 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
       s_gain[c][wave] = gfx;
     }
   }
+  if (lane == 0) s_item[wave] = item_cnt;
   __syncthreads();
   if ((int)threadIdx.x < cend) {
     const int c = threadIdx.x;
@@ -209,7 +210,12 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
     if (cnt) atomicAdd(&ccnt[slot], cnt);
     if (g) atomicAdd(&cgain[slot], g);
   }
-  if (lane == 0 && item_cnt) atomicAdd((unsigned long long*)&st->inlier_residuals, (unsigned long long)item_cnt);
+  if (threadIdx.x == 0) {  // one add per item to the query's counter (same-address atomics serialise)
+    unsigned long long tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScoreWaves; ++w) tot += s_item[w];
+    if (tot) atomicAdd((unsigned long long*)&st->inlier_residuals, tot);
+  }
   __syncthreads();
 }
 
@@ -220,7 +226,7 @@ __device__ __forceinline__ void score_item_f64(const QueryDesc& d, const double*
                                                uint32_t* __restrict__ ccnt, unsigned long long* __restrict__ cgain,
                                                BestState* st, int64_t tile, int64_t chunk, int ncand,
                                                uint32_t (*s_cnt)[kScoreWaves],
-                                               unsigned long long (*s_gain)[kScoreWaves]) {
+                                               unsigned long long (*s_gain)[kScoreWaves], uint32_t* s_item) {
   constexpr int PPL = kScorePPL64;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const ChunkRange rg = chunk_range(d, chunk);
@@ -278,6 +284,7 @@ __device__ __forceinline__ void score_item_f64(const QueryDesc& d, const double*
       s_gain[c][wave] = gfx;
     }
   }
+  if (lane == 0) s_item[wave] = item_cnt;
   __syncthreads();
   if ((int)threadIdx.x < cend) {
     const int c = threadIdx.x;
@@ -289,7 +296,12 @@ __device__ __forceinline__ void score_item_f64(const QueryDesc& d, const double*
     if (cnt) atomicAdd(&ccnt[slot], cnt);
     if (g) atomicAdd(&cgain[slot], g);
   }
-  if (lane == 0 && item_cnt) atomicAdd((unsigned long long*)&st->inlier_residuals, (unsigned long long)item_cnt);
+  if (threadIdx.x == 0) {  // one add per item to the query's counter (same-address atomics serialise)
+    unsigned long long tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScoreWaves; ++w) tot += s_item[w];
+    if (tot) atomicAdd((unsigned long long*)&st->inlier_residuals, tot);
+  }
   __syncthreads();
 }
 
@@ -306,6 +318,7 @@ __global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __r
                                                             const int64_t* __restrict__ item_off) {
   __shared__ uint32_t s_cnt[CT][kScoreWaves];
   __shared__ unsigned long long s_gain[CT][kScoreWaves];
+  __shared__ uint32_t s_item[kScoreWaves];
   const int64_t total = item_off[nq];
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     int lo = 0, hi = nq - 1;  // the query owning item w: last q with item_off[q] <= w
@@ -319,9 +332,9 @@ __global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __r
     const int64_t tile = local / chunks, chunk = local - tile * chunks;
     const int nc = ncand[lo];
     if (d.precision == 0)
-      score_item_f32<CT>(d, proj, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain);
+      score_item_f32<CT>(d, proj, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain, s_item);
     else
-      score_item_f64<CT>(d, pose, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain);
+      score_item_f64<CT>(d, pose, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain, s_item);
   }
 }
 
