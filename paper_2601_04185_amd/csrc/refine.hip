@@ -381,8 +381,14 @@ __device__ __forceinline__ bool gn_decide_wave(int j, int iters, const double* t
   if (lane < 12) {
     const int rr = lane < 9 ? lane / 3 : lane - 9, cc = lane < 9 ? lane % 3 : 3;
     const double* cur = s.eval;  // the accepted pose (s.cur holds the same values)
-    const double v = cc < 3 ? E[3 * rr] * cur[cc] + E[3 * rr + 1] * cur[3 + cc] + E[3 * rr + 2] * cur[6 + cc]
-                            : E[3 * rr] * cur[9] + E[3 * rr + 1] * cur[10] + E[3 * rr + 2] * cur[11] + d[3 + rr];
+    // row rr of E and entry rr of the translation step by selects (a lane-indexed
+    // register array would be placed in scratch memory)
+    const double er0 = rr == 0 ? E[0] : (rr == 1 ? E[3] : E[6]);
+    const double er1 = rr == 0 ? E[1] : (rr == 1 ? E[4] : E[7]);
+    const double er2 = rr == 0 ? E[2] : (rr == 1 ? E[5] : E[8]);
+    const double dt = rr == 0 ? d[3] : (rr == 1 ? d[4] : d[5]);
+    const double v = cc < 3 ? er0 * cur[cc] + er1 * cur[3 + cc] + er2 * cur[6 + cc]
+                            : er0 * cur[9] + er1 * cur[10] + er2 * cur[11] + dt;
     __builtin_amdgcn_wave_barrier();
     s.eval[lane] = v;
   }
