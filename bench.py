@@ -57,11 +57,12 @@ def _file_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(kernel_src, workload):
-    """HBM bytes per launch from the committed counter summary (key: value
-    lines), if it was taken on the current source of the kernel and this
-    workload."""
-    p = os.path.join(ROOT, "profiles", "score_single_large_traffic.txt")
+def _traffic(kernel_src, workload, shape):
+    """HBM bytes per launch from the committed counter summary of this launch
+    shape (key: value lines), if it was taken on the current source of the
+    kernel, this workload and this shape; else None."""
+    ct, wg = shape
+    p = os.path.join(ROOT, "profiles", f"score_single_large_traffic_{ct}x{wg}.txt")
     if not os.path.exists(p):
         return None
     d = {}
@@ -69,7 +70,8 @@ def _traffic(kernel_src, workload):
         if ":" in line and not line.startswith(("#", " ")):
             k, v = line.split(":", 1)
             d[k.strip()] = v.strip()
-    if d.get("workload") != workload or d.get("kernel_src_sha256_16") != _file_hash(kernel_src):
+    if (d.get("workload") != workload or d.get("kernel_src_sha256_16") != _file_hash(kernel_src)
+            or d.get("candidates_per_item") != str(ct) or d.get("workgroups") != str(wg)):
         return None
     try:
         return float(d["hbm_bytes_per_launch"])
@@ -445,7 +447,7 @@ def main():
     kernel_src = os.path.join(ROOT, "paper_2601_04185_amd", "csrc", "score.hip")
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=round(PEAK_F32_NONPACKED_TFLOPS, 2),
                     unit="TFLOP/s", frac=round(achieved / PEAK_F32_NONPACKED_TFLOPS, 4),
-                    traffic=_traffic(kernel_src, args.workload), kernel="score_f32_kernel",
+                    traffic=_traffic(kernel_src, args.workload, ctx.score_tuning()), kernel="score_f32_kernel",
                     launch_ms=round(launch_ms, 4), flop_per_launch=int(flops),
                     frac_of_packed_peak=round(achieved / PEAK_F32_PACKED_TFLOPS, 4),
                     residuals_per_s_kernel=round(res_per_launch / (launch_ms * 1e-3), 1),
