@@ -349,6 +349,19 @@ int imloc_sample_p3p(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const iml
 int imloc_score(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K, const double *poses,
                 int64_t np, double threshold_px, int32_t precision, int32_t *count, double *msac);
 
+/* The loop's choice of local-optimisation starts (Sec. 3.3 "Pose
+ * Estimation": hypotheses that beat the best so far are refined): score np
+ * poses (device double [np][12]) as imloc_score does, then take the k (1..32)
+ * with the smallest truncated cost below gate (+inf: every pose), ordered by
+ * that cost, then the larger inlier count, then the smaller pose index.  sel
+ * (device int32 [k]) receives their pose indices in that order, n_sel
+ * (device int32) how many there are (fewer than k when fewer poses pass the
+ * gate).  Workspace as imloc_score.  IMLOC_EINVAL for k outside [1, 32] or a
+ * NaN gate.  Returns once the results are written. */
+int imloc_select_top_k(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K, const double *poses,
+                       int64_t np, double threshold_px, int32_t precision, int32_t k, double gate, int32_t *sel,
+                       int32_t *n_sel);
+
 /* Local optimisation of np start poses (device double [np][12]) on n
  * correspondences; out_poses (device double [np][12]), cost (device double
  * [np]), count (device int64 [np]). */

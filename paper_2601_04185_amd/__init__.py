@@ -37,7 +37,7 @@ EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_err
             "imloc_lift", "imloc_lift_log8", "imloc_depth_encode_log8", "imloc_triangulate_workspace_bytes",
             "imloc_triangulate_depth", "imloc_rig_workspace_bytes", "imloc_rig_lo_ransac_pnp",
             "imloc_rig_stage_workspace_bytes", "imloc_rig_sample_gp3p", "imloc_rig_score",
-            "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score",
+            "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score", "imloc_select_top_k",
             "imloc_local_optimize", "imloc_refine", "imloc_paper_params",
             "imloc_set_gn_mode"]
 
@@ -143,6 +143,7 @@ def lib():
             "imloc_lo_ransac_pnp_batch": ([vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp], C.c_int),
             "imloc_sample_p3p": ([vp, vp, i64, vp, u64, u64, i32, i64, i64, vp, vp, vp, vp, vp], C.c_int),
             "imloc_score": ([vp, vp, i64, vp, vp, i64, dbl, i32, vp, vp], C.c_int),
+            "imloc_select_top_k": ([vp, vp, i64, vp, vp, i64, dbl, i32, i32, dbl, vp, vp], C.c_int),
             "imloc_local_optimize": ([vp, vp, i64, vp, vp, i32, dbl, i32, vp, vp, vp], C.c_int),
             "imloc_refine": ([vp, vp, i64, vp, vp, dbl, dbl, i32, vp, vp, vp], C.c_int),
         }
@@ -485,6 +486,24 @@ def imloc_score(ctx: Context, corr: dict, K, poses, threshold_px: float, precisi
     ctx.check(lib().imloc_score(ctx.h, C.byref(cs), n, C.byref(cam), _ptr(poses.contiguous()), npz, float(threshold_px),
                                 int(precision), _ptr(cnt), _ptr(ms)))
     return cnt[:npz], ms[:npz]
+
+
+def imloc_select_top_k(ctx: Context, corr: dict, K, poses, threshold_px: float, k: int, gate: float = float("inf"),
+                       precision=IMLOC_FP32_SCORE):
+    """poses: cuda float64 (np, 12).  Scores them as imloc_score does and
+    returns the indices (cuda int32) of the k with the smallest truncated
+    cost below gate, in order (ties: larger inlier count, then smaller index)."""
+    torch = ctx.torch
+    n = int(corr["u"].numel())
+    npz = int(poses.shape[0])
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    sel = torch.full((max(int(k), 1),), -1, dtype=torch.int32, device=poses.device)
+    nsel = torch.zeros(1, dtype=torch.int32, device=poses.device)
+    ctx.ensure_workspace(lib().imloc_score_workspace_bytes(n, npz, int(precision)))
+    cam = _cam(K)
+    ctx.check(lib().imloc_select_top_k(ctx.h, C.byref(cs), n, C.byref(cam), _ptr(poses.contiguous()), npz,
+                                       float(threshold_px), int(precision), int(k), float(gate), _ptr(sel), _ptr(nsel)))
+    return sel[:int(nsel.item())]
 
 
 def imloc_local_optimize(ctx: Context, corr: dict, K, start, threshold_px: float, iters: int = 10):

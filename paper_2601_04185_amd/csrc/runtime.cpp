@@ -1113,6 +1113,41 @@ int imloc_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_ca
   return IMLOC_OK;
 }
 
+int imloc_select_top_k(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K, const double* poses,
+                       int64_t np, double tau, int32_t precision, int32_t k, double gate, int32_t* sel,
+                       int32_t* n_sel) {
+  if (!ctx) return IMLOC_EINVAL;
+  if (n < 0 || n > INT32_MAX || np < 0 || np > INT32_MAX) return set_err(ctx, IMLOC_EINVAL, "bad sizes");
+  if (k < 1 || k > kMaxTopK) return set_err(ctx, IMLOC_EINVAL, "k must be in [1, %d]", kMaxTopK);
+  if (std::isnan(gate)) return set_err(ctx, IMLOC_EINVAL, "gate is NaN");
+  if (n > 0 && !corr_ok(pts)) return set_err(ctx, IMLOC_EINVAL, "null correspondence array");
+  if (!cam_ok(K)) return set_err(ctx, IMLOC_EINVAL, "bad intrinsics");
+  if (!(tau > 0.0)) return set_err(ctx, IMLOC_EINVAL, "threshold must be > 0");
+  if (precision != IMLOC_FP32_SCORE && precision != IMLOC_FP64_ALL) return set_err(ctx, IMLOC_EINVAL, "bad precision");
+  if (!sel || !n_sel || (np > 0 && !poses)) return set_err(ctx, IMLOC_EINVAL, "null pose / output array");
+  hipSetDevice(ctx->device);
+  StageQuery sq;
+  stage_setup(sq, n, np, tau, precision, 0, 0, 1.0, 1);
+  sq.pl.k = k;  // the query's k; the engine keeps one local optimisation slot (none runs here)
+  Arena a{ctx->ws, ctx->ws_bytes};
+  carve_engine(a, sq.e);
+  if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes", a.off);
+  int rc = stage_upload(ctx, sq, pts, n, K, 1, 0, nullptr);
+  if (rc) return rc;
+  hipStream_t s = ctx->stream;
+  if (!std::isinf(gate) || gate < 0.0) {  // the running best's cost (+inf after initialisation)
+    double* hg = reinterpret_cast<double*>(ctx->pinned + 256 * ((sizeof(QueryDesc) + 255) / 256) + sizeof(BestState));
+    *hg = gate;
+    HIP_TRY(ctx, hipMemcpyAsync(&sq.e.st[0].cost, hg, sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
+  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, ctx->tune.ct, sq.e.item_off, s));
+  HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, ctx->tune, precision, s));
+  HIP_TRY(ctx, launch_select(sq.e.qd, sq.e.st, sq.e.cb, 1, k, std::max<int64_t>(np, 1), sq.e.sel_part, sel, n_sel, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));  // the staging buffer held the gate
+  return IMLOC_OK;
+}
+
 int imloc_local_optimize(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K, const double* start,
                          int32_t np, double tau, int32_t iters, double* out_poses, double* cost, int64_t* count) {
   if (!ctx) return IMLOC_EINVAL;
