@@ -162,9 +162,11 @@ int imloc_set_graphs(imloc_ctx *ctx, int enable);
 int imloc_graph_counters(const imloc_ctx *ctx, int64_t *captures, int64_t *launches);
 
 /* Launch shape of the scoring kernel: candidates per work item (32, 64 or
- * 128) and persistent workgroups.  Neither changes any result (per-candidate
- * sums are integer-accumulated), only the speed; the autotuner in the Python
- * package picks them by timing. */
+ * 128, or 0, the default: picked per round, the largest tile that still
+ * gives about four work items per compute unit) and persistent workgroups.
+ * Neither changes any result (per-candidate sums are integer-accumulated),
+ * only the speed; the autotuner in the Python package picks them by timing.
+ * imloc_get_score_tuning reports 0 while the tile is picked per round. */
 int imloc_set_score_tuning(imloc_ctx *ctx, int32_t candidates_per_item, int32_t workgroups);
 int imloc_get_score_tuning(const imloc_ctx *ctx, int32_t *candidates_per_item, int32_t *workgroups);
 

@@ -36,7 +36,8 @@ struct imloc_ctx {
   size_t pinned_bytes = 0;
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
-  ScoreTune tune{64, 2048};
+  ScoreTune tune{0, 2048};  // ct == 0: the candidate tile is picked per round (round_tune)
+  int cus = 256;
   int gn_mode = 0;  // Gauss-Newton launch form: 0 by size, 1 fused, 2 split
   // hipGraph replay of the fixed-sample pipeline
   bool graphs = false;
@@ -119,6 +120,25 @@ struct QPlan {
   int k;
   int ncam = 0;  // 0: one camera; else the cameras of a rig
 };
+
+// Scoring launch shape: the context's fixed one, or (ct == 0) the largest
+// candidate tile of 128, 64 and 32 that still gives about four work items per
+// CU, so that small rounds keep every CU busy; est holds per query the
+// expected candidates (one per sample) and scoring chunks.  The tile never
+// changes a result (per-candidate sums are integer-accumulated).
+ScoreTune round_tune(const imloc_ctx* c, const std::vector<std::pair<int64_t, int64_t>>& est) {
+  if (c->tune.ct > 0) return c->tune;
+  for (int ct : {128, 64}) {
+    int64_t items = 0;
+    for (const auto& e : est) items += (e.first + ct - 1) / ct * e.second;
+    if (items >= 4 * (int64_t)c->cus) return ScoreTune{ct, c->tune.blocks};
+  }
+  return ScoreTune{32, c->tune.blocks};
+}
+
+// Scoring chunks of a query, estimated from its plan (2,048 points per chunk
+// in float32 scoring; a rig cuts its segments apart).
+int64_t est_chunks(const QPlan& pl) { return (pl.m + 2047) / 2048 + (pl.ncam > 1 ? pl.ncam - 1 : 0); }
 
 // Host view of a rig query (ncam == 0: a one-camera query).
 struct RigHost {
@@ -439,6 +459,9 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
 
   Timer tm(ctx);
   int rounds = 0;
+  std::vector<std::pair<int64_t, int64_t>> est(nq);
+  for (int q = 0; q < nq; ++q) est[q] = {std::min(pl[q].batch, pl[q].total), est_chunks(pl[q])};
+  const ScoreTune tune = round_tune(ctx, est);
   // The whole pipeline of a batch, enqueued on stream `st_`: table upload,
   // rounds, final refinement, mask, readback into pinned memory.  `sync`
   // lets adaptive batches read the active count after every round.
@@ -455,8 +478,8 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       if (e.any_rig) HIP_TRY(ctx, launch_sample_gp3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
       tm.end(kStSample, e0);
       hipEvent_t e1 = tm.begin();
-      HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, ctx->tune.ct, e.item_off, st_));
-      HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, ctx->tune, 0, st_));
+      HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, tune.ct, e.item_off, st_));
+      HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, tune, 0, st_));
       tm.end(kStScore, e1);
       hipEvent_t e2 = tm.begin();
       HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, e.kmax, e.max_cap, e.sel_part, e.sel, e.n_sel, st_));
@@ -489,8 +512,8 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
     // key of everything a captured graph bakes in: shapes, workspace, staging
     std::string key;
     char buf[160];
-    snprintf(buf, sizeof(buf), "%d|%p|%p|%d|%d|%d|%d|%d|", nq, (void*)ctx->ws, (void*)ctx->pinned, ctx->tune.ct,
-             ctx->tune.blocks, e.lo_iters, e.fin_iters, ctx->gn_mode);
+    snprintf(buf, sizeof(buf), "%d|%p|%p|%d|%d|%d|%d|%d|", nq, (void*)ctx->ws, (void*)ctx->pinned, tune.ct,
+             tune.blocks, e.lo_iters, e.fin_iters, ctx->gn_mode);
     key += buf;
     for (int q = 0; q < nq; ++q) {
       snprintf(buf, sizeof(buf), "%lld,%lld,%d,%lld,%lld,%d,%d;", (long long)pl[q].n, (long long)pl[q].m,
@@ -664,8 +687,9 @@ int imloc_create(imloc_ctx** out, int device, void* hip_stream) {
   }
   int cus = 256;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-  c->tune.ct = 128;
-  c->tune.blocks = 16 * (cus > 0 ? cus : 256);
+  c->cus = cus > 0 ? cus : 256;
+  c->tune.ct = 0;
+  c->tune.blocks = 16 * c->cus;
   *out = c;
   return IMLOC_OK;
 }
@@ -724,8 +748,8 @@ int imloc_graph_counters(const imloc_ctx* c, int64_t* captures, int64_t* launche
 
 int imloc_set_score_tuning(imloc_ctx* c, int32_t candidates_per_item, int32_t workgroups) {
   if (!c) return IMLOC_EINVAL;
-  if (candidates_per_item != 32 && candidates_per_item != 64 && candidates_per_item != 128)
-    return set_err(c, IMLOC_EINVAL, "candidates_per_item must be 32, 64 or 128");
+  if (candidates_per_item != 0 && candidates_per_item != 32 && candidates_per_item != 64 && candidates_per_item != 128)
+    return set_err(c, IMLOC_EINVAL, "candidates_per_item must be 0 (per round), 32, 64 or 128");
   if (workgroups < 1 || workgroups > (1 << 20)) return set_err(c, IMLOC_EINVAL, "workgroups out of range");
   c->tune.ct = candidates_per_item;
   c->tune.blocks = workgroups;
@@ -1066,8 +1090,9 @@ int imloc_rig_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imlo
   if (rc) return rc;
   hipStream_t s = ctx->stream;
   HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
-  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, ctx->tune.ct, sq.e.item_off, s));
-  HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, ctx->tune, precision, s));
+  const ScoreTune tune = round_tune(ctx, {{np, est_chunks(sq.pl)}});
+  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune.ct, sq.e.item_off, s));
+  HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, tune, precision, s));
   HIP_TRY(ctx, launch_candidate_costs(sq.e.qd, sq.e.st, sq.e.cb, np, count, msac, s));
   return IMLOC_OK;
 }
@@ -1107,8 +1132,9 @@ int imloc_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_ca
   if (rc) return rc;
   hipStream_t s = ctx->stream;
   HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
-  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, ctx->tune.ct, sq.e.item_off, s));
-  HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, ctx->tune, precision, s));
+  const ScoreTune tune = round_tune(ctx, {{np, est_chunks(sq.pl)}});
+  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune.ct, sq.e.item_off, s));
+  HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, tune, precision, s));
   HIP_TRY(ctx, launch_candidate_costs(sq.e.qd, sq.e.st, sq.e.cb, np, count, msac, s));
   return IMLOC_OK;
 }
@@ -1141,8 +1167,9 @@ int imloc_select_top_k(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const i
     HIP_TRY(ctx, hipMemcpyAsync(&sq.e.st[0].cost, hg, sizeof(double), hipMemcpyHostToDevice, s));
   }
   HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
-  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, ctx->tune.ct, sq.e.item_off, s));
-  HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, ctx->tune, precision, s));
+  const ScoreTune tune = round_tune(ctx, {{np, est_chunks(sq.pl)}});
+  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune.ct, sq.e.item_off, s));
+  HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, tune, precision, s));
   HIP_TRY(ctx, launch_select(sq.e.qd, sq.e.st, sq.e.cb, 1, k, std::max<int64_t>(np, 1), sq.e.sel_part, sel, n_sel, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));  // the staging buffer held the gate
   return IMLOC_OK;
@@ -1429,10 +1456,12 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
   }
   int nq = 0, kmax = 1, chunks_lo = 1, chunks_fin = 1, lo_iters = 0, fin_iters = 0, resident = 0;
   int64_t max_batch = 1, max_n = 0, max_m_sub = 0;
+  std::vector<std::pair<int64_t, int64_t>> est;
   for (int i = 0; i < S; ++i) {
     const ServerSlot& sl = srv->slots[i];
     if (!sl.used) continue;
     ++resident;
+    est.push_back({std::min(sl.pl.batch, sl.pl.total), est_chunks(sl.pl)});
     nq = i + 1;
     kmax = std::max(kmax, sl.pl.k);
     chunks_lo = std::max(chunks_lo, gn_chunks(sl.pl.m));
@@ -1479,8 +1508,9 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     HIP_TRY(ctx, launch_init_queries(e.qd, e.st, e.cb.n, nq, false, s));
     HIP_TRY(ctx, launch_begin_round(e.qd, e.st, e.cb, nq, s));
     HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, max_batch, nullptr, s));
-    HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, ctx->tune.ct, e.item_off, s));
-    HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, ctx->tune, 0, s));
+    const ScoreTune tune = round_tune(ctx, est);
+    HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, tune.ct, e.item_off, s));
+    HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, tune, 0, s));
     HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, 4 * max_batch, e.sel_part, e.sel, e.n_sel, s));
     HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * kmax, kmax, chunks_lo, lo_iters, e.gn_lo,
                            e.lo_pose, e.lo_cost, e.lo_count, false, ctx->gn_mode, s));

@@ -70,7 +70,7 @@ def test_tuning_does_not_change_results(pk):
     d = pk.to_device(q)
     prm = pk.make_params(threshold_px=4.0, fixed_samples=3000, batch=3000)
     ref = None
-    for ct, wg in [(32, 64), (64, 2048), (128, 517), (64, 1)]:
+    for ct, wg in [(32, 64), (64, 2048), (128, 517), (64, 1), (0, 4096)]:
         ctx = pk.Context(0)
         ctx.set_score_tuning(ct, wg)
         rc, R, t, st = pk.imloc_lo_ransac_pnp(ctx, d, q.K, prm)
