@@ -680,9 +680,17 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
         if (d.mask) d.mask[i] = in ? 1 : 0;
         cnt += in ? 1 : 0;
       }
+      // one add per workgroup to the query's counter (same-address atomics serialise)
+      __shared__ long long s_cnt[kGNWaves];
       cnt = wave_sum(cnt);
-      if ((threadIdx.x & (kWave - 1)) == 0 && cnt)
-        atomicAdd((unsigned long long*)&g.bst[q].full_count, (unsigned long long)cnt);
+      if ((threadIdx.x & (kWave - 1)) == 0) s_cnt[threadIdx.x / kWave] = cnt;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        long long tot = 0;
+#pragma unroll
+        for (int w = 0; w < kGNWaves; ++w) tot += s_cnt[w];
+        if (tot) atomicAdd((unsigned long long*)&g.bst[q].full_count, (unsigned long long)tot);
+      }
     }
   }
   if (s.done) return;
@@ -830,8 +838,8 @@ hipError_t launch_refine(const QueryDesc* qd, BestState* bst, const double* star
 
 // Inlier mask over all points of every query that just finished, at its final
 // pose (float64), and its count; a query without a pose gets a zero mask.
-__global__ void mask_kernel(const QueryDesc* __restrict__ qd, BestState* __restrict__ st,
-                            const double* __restrict__ fin_pose, int all) {
+__global__ __launch_bounds__(256) void mask_kernel(const QueryDesc* __restrict__ qd, BestState* __restrict__ st,
+                                                   const double* __restrict__ fin_pose, int all) {
   const int q = blockIdx.y;
   if (!all && st[q].finished != 1) return;
   const QueryDesc& d = qd[q];
@@ -843,9 +851,17 @@ __global__ void mask_kernel(const QueryDesc* __restrict__ qd, BestState* __restr
     in = mask_test(d, fin_pose + 12 * (int64_t)q, gmem(d.full.X)[i], gmem(d.full.Y)[i], gmem(d.full.Z)[i],
                    gmem(d.full.u)[i], gmem(d.full.v)[i], i) ? 1 : 0;
   if (i < d.n && d.mask) d.mask[i] = (uint8_t)in;
+  // one add per workgroup to the query's counter (same-address atomics serialise)
+  __shared__ long long s_cnt[256 / kWave];
   const long long tot = wave_sum(in);
-  if ((threadIdx.x & (kWave - 1)) == 0 && tot)
-    atomicAdd((unsigned long long*)&st[q].full_count, (unsigned long long)tot);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_cnt[threadIdx.x / kWave] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long sum = 0;
+#pragma unroll
+    for (int w = 0; w < 256 / kWave; ++w) sum += s_cnt[w];
+    if (sum) atomicAdd((unsigned long long*)&st[q].full_count, (unsigned long long)sum);
+  }
 }
 
 hipError_t launch_mask(const QueryDesc* qd, BestState* st, const double* fin_pose, int nq, int64_t max_n, int all,
