@@ -186,6 +186,7 @@ struct Engine {
   int64_t max_batch = 1, max_n = 0, slots = 0, max_rounds = 0;
   bool all_fixed = true;
   bool any_rig = false;
+  bool any_single = false;  // some query has one camera (the P3P sampler has work)
   int64_t max_cap = 4, proj_floats = 16, rig_doubles = 0;
   QueryDesc* qd;
   double* rig;
@@ -225,6 +226,7 @@ void plan_engine(Engine& e, int nq, const QPlan* pl, const imloc_ransac_params* 
     rigd += 16 * pl[q].ncam;
     e.max_cap = std::max(e.max_cap, pl[q].cap);
     if (pl[q].ncam > 0) e.any_rig = true;
+    else e.any_single = true;
     e.in_set_off[q] = in_bytes;
     in_bytes += (pl[q].n + 255) & ~int64_t(255);
     e.subset_off[q] = sub;
@@ -474,7 +476,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
     rounds = 0;
     for (int64_t r = 0; r < e.max_rounds; ++r) {
       hipEvent_t e0 = tm.begin();
-      HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
+      if (e.any_single) HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
       if (e.any_rig) HIP_TRY(ctx, launch_sample_gp3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
       tm.end(kStSample, e0);
       hipEvent_t e1 = tm.begin();
