@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "scored residuals/s and queries/s at 1 GPU; p50/p99 query latency at fixed accuracy"
 # Non-packed float32 FMA peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
-# (Packed float32 instructions are disabled in this build; the 157.3 TFLOP/s
+# (The library is compiled with packed float32 instructions disabled; the 157.3 TFLOP/s
 # packed figure is reported beside it.)
 PEAK_F32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_F32_PACKED_TFLOPS = 157.3
