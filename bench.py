@@ -98,7 +98,9 @@ def batch_leg(pk, ctx_plain, steps, n_queries=256):
     prms = [pk.make_params(threshold_px=4.0, fixed_samples=4096, batch=4096, lo_top_k=8, query_id=i)
             for i in range(len(qs))]
     ctx = pk.Context(0, graphs=True)  # the fixed-sample batch replays as one captured hipGraph
-    ctx.set_score_tuning(*ctx_plain.score_tuning())
+    # the batch's own scoring launch shape (its rounds are far larger than one query's)
+    from paper_2601_04185_amd.autotune import tune_scoring
+    tuned = tune_scoring(ctx, lambda c: pk.imloc_lo_ransac_pnp_batch(c, ds, Ks, prms)[2], reps=1)
     pk.imloc_lo_ransac_pnp_batch(ctx, ds, Ks, prms)  # warm-up (workspace, capture)
     torch.cuda.synchronize()
     t_f = []
@@ -107,7 +109,7 @@ def batch_leg(pk, ctx_plain, steps, n_queries=256):
         status, poses, stats = pk.imloc_lo_ransac_pnp_batch(ctx, ds, Ks, prms)
         t_f.append(time.perf_counter() - t0)
     eager = pk.Context(0)
-    eager.set_score_tuning(*ctx_plain.score_tuning())
+    eager.set_score_tuning(*ctx.score_tuning())
     pk.imloc_lo_ransac_pnp_batch(eager, ds, Ks, prms)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -136,6 +138,7 @@ def batch_leg(pk, ctx_plain, steps, n_queries=256):
                 fused_ms=round(tf * 1e3, 3), fused_queries_per_s=round(len(qs) / tf, 2),
                 fused_residuals_per_s=round(res / tf, 1), fused_eager_ms=round(t_eager * 1e3, 3),
                 graph_captures_replays=list(ctx.graph_counters()),
+                score_launch_shape=dict(zip(("candidates_per_item", "workgroups"), ctx.score_tuning())),
                 plain_ms=round(t_plain * 1e3, 3), plain_queries_per_s=round(len(qs) / t_plain, 2),
                 speedup_fused_vs_plain=round(t_plain / tf, 3), residuals=res,
                 score_ms=round(score_ms, 3), score_tflops=round(flops / (score_ms * 1e-3) / 1e12, 3),
@@ -328,7 +331,7 @@ def rig_leg(pk, steps=10):
     q = synth.make_rig_query(1007, 20000, 0.35, 1.0)
     d = pk.to_device(q)
     prm = pk.make_params(threshold_px=4.0, fixed_samples=2048, batch=2048, lo_top_k=8)
-    ctx = pk.Context(0)
+    ctx = pk.Context(0, graphs=True)  # fixed samples: replayed as one captured hipGraph
     for _ in range(2):
         pk.imloc_rig_lo_ransac_pnp(ctx, d, q.rig, q.cam_start(), prm)
     lat = []
@@ -345,7 +348,8 @@ def rig_leg(pk, steps=10):
                 residuals_per_s=round(st["residuals"] / float(np.median(lat)), 1),
                 rot_err_vs_oracle_deg=_rot_deg(R, ref["R"]),
                 t_rel_err_vs_oracle=float(np.linalg.norm(t - ref["t"]) / max(1.0, np.linalg.norm(ref["t"]))),
-                rot_err_vs_truth_deg=_rot_deg(R, q.R), t_err_vs_truth_m=float(np.linalg.norm(t - q.t)))
+                rot_err_vs_truth_deg=_rot_deg(R, q.R), t_err_vs_truth_m=float(np.linalg.norm(t - q.t)),
+                graph_captures_replays=list(ctx.graph_counters()))
 
 
 def cpu_baseline(q, params, reps):
