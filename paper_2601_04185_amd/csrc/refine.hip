@@ -310,23 +310,65 @@ __device__ void gn_part_sum(const double* part, int C, const GNPart& r, double (
 // start); unless the iteration budget is spent, the normal equations at the
 // accepted pose give the pose of evaluation j + 1.  A cost-raising step, or a
 // system that is not positive definite, ends the run with the accepted pose.
-// Run by the 64 lanes of wave 0 (every lane takes the same branches): the
-// 6 x 7 system [H | -g] is reduced by Gauss-Jordan elimination with one row
-// per lane (lanes 0..5) and the pivot row broadcast by readlane -- a positive
-// definite matrix needs no pivoting and has positive pivots -- and lane e < 12
-// forms element e of the next pose.  Returns true when this decision ends the
-// run.
+// Run by the 64 lanes of wave 0 (every lane takes the same branches): every
+// lane solves the 6 x 6 system itself (solve6_schur), and lane e < 12 forms
+// element e of the next pose.  Returns true when this decision ends the run.
 struct GNShared {
   double cur[12], eval[12];
   double cost, count;
   int done, accepted;
 };
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+// H d = -g for the 6x6 normal equations given by tot (upper triangle of H,
+// packed by rows, then g), through the Schur complement of the rotation
+// block: H = [A B; B^T C], d_t = S^-1 (b_t - B^T A^-1 b_r) with S = C - B^T
+// A^-1 B, d_r = A^-1 b_r - A^-1 B d_t; the 3x3 inverses by adjugates.  H is
+// positive definite exactly when A and S are (leading minors checked); false
+// otherwise.  Every lane solves it in its own registers: no lane exchanges,
+// two divisions on the dependency chain.
+__device__ __forceinline__ bool solve6_schur(const double* t, double x[6]) {
+  const double h00 = t[0], h01 = t[1], h02 = t[2], h03 = t[3], h04 = t[4], h05 = t[5];
+  const double h11 = t[6], h12 = t[7], h13 = t[8], h14 = t[9], h15 = t[10];
+  const double h22 = t[11], h23 = t[12], h24 = t[13], h25 = t[14];
+  const double h33 = t[15], h34 = t[16], h35 = t[17], h44 = t[18], h45 = t[19], h55 = t[20];
+  const double br[3] = {-t[21], -t[22], -t[23]}, bt[3] = {-t[24], -t[25], -t[26]};
+  // A^-1 by its adjugate
+  const double c00 = fma(h11, h22, -h12 * h12), c01 = fma(h02, h12, -h01 * h22), c02 = fma(h01, h12, -h02 * h11);
+  const double c11 = fma(h00, h22, -h02 * h02), c12 = fma(h01, h02, -h00 * h12), c22 = fma(h00, h11, -h01 * h01);
+  const double detA = fma(h00, c00, fma(h01, c01, h02 * c02));
+  const bool okA = h00 > 0.0 && c22 > 0.0 && detA > 0.0;
+  const double ia = 1.0 / detA;
+  const double I[3][3] = {{c00 * ia, c01 * ia, c02 * ia}, {c01 * ia, c11 * ia, c12 * ia}, {c02 * ia, c12 * ia, c22 * ia}};
+  const double B[3][3] = {{h03, h04, h05}, {h13, h14, h15}, {h23, h24, h25}};
+  const double C[3][3] = {{h33, h34, h35}, {h34, h44, h45}, {h35, h45, h55}};
+  // T = A^-1 B, u = A^-1 b_r
+  double T[3][3], u[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T[r][c] = fma(I[r][0], B[0][c], fma(I[r][1], B[1][c], I[r][2] * B[2][c]));
+    u[r] = fma(I[r][0], br[0], fma(I[r][1], br[1], I[r][2] * br[2]));
+  }
+  // S = C - B^T T, r = b_t - B^T u
+  double S[3][3], rt[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S[r][c] = C[r][c] - fma(B[0][r], T[0][c], fma(B[1][r], T[1][c], B[2][r] * T[2][c]));
+    rt[r] = bt[r] - fma(B[0][r], u[0], fma(B[1][r], u[1], B[2][r] * u[2]));
+  }
+  const double d00 = fma(S[1][1], S[2][2], -S[1][2] * S[1][2]), d01 = fma(S[0][2], S[1][2], -S[0][1] * S[2][2]);
+  const double d02 = fma(S[0][1], S[1][2], -S[0][2] * S[1][1]), d11 = fma(S[0][0], S[2][2], -S[0][2] * S[0][2]);
+  const double d12 = fma(S[0][1], S[0][2], -S[0][0] * S[1][2]), d22 = fma(S[0][0], S[1][1], -S[0][1] * S[0][1]);
+  const double detS = fma(S[0][0], d00, fma(S[0][1], d01, S[0][2] * d02));
+  const bool okS = S[0][0] > 0.0 && d22 > 0.0 && detS > 0.0;
+  const double is = 1.0 / detS;
+  const double J[3][3] = {{d00 * is, d01 * is, d02 * is}, {d01 * is, d11 * is, d12 * is}, {d02 * is, d12 * is, d22 * is}};
+#pragma unroll
+  for (int r = 0; r < 3; ++r) x[3 + r] = fma(J[r][0], rt[0], fma(J[r][1], rt[1], J[r][2] * rt[2]));
+#pragma unroll
+  for (int r = 0; r < 3; ++r) x[r] = u[r] - fma(T[r][0], x[3], fma(T[r][1], x[4], T[r][2] * x[5]));
+  return okA && okS;
 }
 
 __device__ __forceinline__ bool gn_decide_wave(int j, int iters, const double* tot, GNShared& s) {
@@ -349,32 +391,11 @@ __device__ __forceinline__ bool gn_decide_wave(int j, int iters, const double* t
     if (lane == 0) s.done = 1;
     return true;
   }
-  // Gauss-Jordan on [H | -g]: lane r < 6 holds row r
-  const int r = lane < 6 ? lane : 0;
-  double a[7];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) a[c] = tot[r <= c ? upk(r, c) : upk(c, r)];
-  a[6] = -tot[21 + r];
-  bool ok = true;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const double piv = readlane_f64(a[i], i);
-    ok = ok && piv > 0.0;
-    const double ip = 1.0 / piv;
-    double prow[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) prow[c] = readlane_f64(a[c], i);
-    const double f = a[i] * ip;
-#pragma unroll
-    for (int c = 0; c < 7; ++c) a[c] = lane == i ? a[c] * ip : fma(-f, prow[c], a[c]);
-  }
-  if (!ok) {
+  double d[6];
+  if (!solve6_schur(tot, d)) {
     if (lane == 0) s.done = 1;
     return true;
   }
-  double d[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) d[k] = readlane_f64(a[6], k);
   // left update: R' = Exp(dw) R, t' = Exp(dw) t + dt, element `lane` (< 12)
   double E[9];
   so3_exp(d, E);
