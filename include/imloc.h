@@ -290,10 +290,10 @@ typedef struct {
  *   (device [H][W], each may be NULL): depth (float32 z-depth in metres, 0 =
  *   none), inliers (int32, the winning set's size), codes (uint8 8-bit
  *   log-depth codes of depth, as imloc_depth_encode_log8).  Asynchronous on
- *   the context's stream; needs imloc_triangulate_workspace_bytes(n_views) of
- *   workspace.  IMLOC_EINVAL for n_views outside 1..32, H or W < 1, null
+ *   the context's stream; needs imloc_triangulate_workspace_bytes(H, W,
+ *   n_views) of workspace (16 B per pixel: the queue of pixels to refine).  IMLOC_EINVAL for n_views outside 1..32, H or W < 1, null
  *   inputs or bad intrinsics. */
-size_t imloc_triangulate_workspace_bytes(int32_t n_views);
+size_t imloc_triangulate_workspace_bytes(int32_t H, int32_t W, int32_t n_views);
 int imloc_triangulate_depth(imloc_ctx *ctx, int32_t H, int32_t W, const imloc_camera *K_map,
                             const imloc_pose *T_map, int32_t n_views, const imloc_camera *K_views,
                             const imloc_pose *T_views, const imloc_dense_matches *m,

@@ -124,7 +124,10 @@ static double tri_grad(const tri_pixel *px, double l, int n, const double (*Ck)[
 /* Newton's method on the cost's derivative (its own derivative by a central
  * difference, the Gauss-Newton curvature where that is not positive), a step
  * that raises the cost halved up to 30 times, until the step is below 1e-12 l
- * or max_iters steps. */
+ * or max_iters steps.  A step below 1e-12 l counts as convergence also while
+ * it is being halved: it is not tried (near the minimum the cost's rounding
+ * noise exceeds the decrease of such a step, and trying it would only halve
+ * it on towards one ulp). */
 static double tri_refine_full(const double C0[3], const double r0[3], double l0, int n, const double (*Ck)[3],
                               const double (*rk)[3], const double *w, int max_iters, double *cost_out,
                               double *curv_out);
@@ -153,6 +156,7 @@ static double tri_refine_full(const double C0[3], const double r0[3], double l0,
     double step = -g / curv;
     int moved = 0;
     for (int half = 0; half < 30; ++half) {
+      if (fabs(step) <= 1e-12 * l) break;
       const double ln = l + step;
       if (ln > 0.0) {
         const double en = tri_cost(&px, ln, n, Ck, rk, w);

@@ -132,7 +132,7 @@ def lib():
             "imloc_lift": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_lift_log8": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_depth_encode_log8": ([vp, vp, i64, vp], C.c_int),
-            "imloc_triangulate_workspace_bytes": ([i32], C.c_size_t),
+            "imloc_triangulate_workspace_bytes": ([i32, i32, i32], C.c_size_t),
             "imloc_rig_workspace_bytes": ([i64, i32, vp], C.c_size_t),
             "imloc_rig_lo_ransac_pnp": ([vp, vp, i64, vp, i32, vp, vp, vp, vp, vp], C.c_int),
             "imloc_rig_stage_workspace_bytes": ([i64, i32, i64], C.c_size_t),
@@ -438,7 +438,7 @@ def imloc_triangulate_depth(ctx: Context, K_map, T_map, K_views, T_views, mu, mv
     poses = (Pose * V)(*[_pose12(t) for t in Tv])
     m = DenseMatches(mu.contiguous().data_ptr(), mv.contiguous().data_ptr(), conf.contiguous().data_ptr())
     prm = TriangulationParams(float(min_conf), float(angle_deg), int(min_inliers), int(max_refine_iters))
-    ctx.ensure_workspace(lib().imloc_triangulate_workspace_bytes(V))
+    ctx.ensure_workspace(lib().imloc_triangulate_workspace_bytes(H, W, V))
     k0 = _cam(K_map)
     t0 = _pose12(T_map)
     ctx.check(lib().imloc_triangulate_depth(ctx.h, H, W, C.byref(k0), C.byref(t0), V, cams, poses, C.byref(m),

@@ -123,6 +123,12 @@ hipError_t launch_lift(const LiftArgs& a, hipStream_t s);
 hipError_t launch_log8_encode(const float* depth, int64_t n, uint8_t* codes, hipStream_t s);
 
 // --- mapping-time depth by 1-DoF triangulation ------------------------------
+// a pixel whose depth is refined: its winning hypothesis and inlier set
+struct TriTask {
+  double l;
+  int32_t p;
+  uint32_t set;
+};
 struct TriArgs {
   int32_t H, W, V;               // mapping image size, covisible views (<= 32)
   const double* views;           // device [V + 1][16]: fx, fy, cx, cy, R^T (9), C0 - Ck (3); entry 0 = mapping camera
@@ -133,6 +139,8 @@ struct TriArgs {
   float* depth;                  // device [H][W] or null
   int32_t* inliers;              // device [H][W] or null
   uint8_t* codes;                // device [H][W] 8-bit log-depth codes, or null
+  int32_t* n_tasks;              // device scratch: length of the refinement queue
+  TriTask* tasks;                // device scratch [H * W]: the pixels to refine
 };
 hipError_t launch_triangulate(const TriArgs& a, hipStream_t s);
 

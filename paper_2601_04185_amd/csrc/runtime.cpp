@@ -926,9 +926,11 @@ int imloc_depth_encode_log8(imloc_ctx* ctx, const float* depth, int64_t count, u
   return IMLOC_OK;
 }
 
-size_t imloc_triangulate_workspace_bytes(int32_t n_views) {
+size_t imloc_triangulate_workspace_bytes(int32_t H, int32_t W, int32_t n_views) {
   const int v = n_views < 0 ? 0 : n_views;
-  return ((size_t)(v + 1) * 16 * sizeof(double) + 255) & ~size_t(255);
+  const size_t hw = H > 0 && W > 0 ? (size_t)H * W : 0;
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return up((size_t)(v + 1) * 16 * sizeof(double)) + up(sizeof(int32_t)) + up(hw * sizeof(TriTask));
 }
 
 int imloc_triangulate_depth(imloc_ctx* ctx, int32_t H, int32_t W, const imloc_camera* K_map, const imloc_pose* T_map,
@@ -948,6 +950,8 @@ int imloc_triangulate_depth(imloc_ctx* ctx, int32_t H, int32_t W, const imloc_ca
   hipSetDevice(ctx->device);
   Arena a{ctx->ws, ctx->ws_bytes};
   double* dviews = a.take<double>((size_t)(n_views + 1) * 16);
+  int32_t* n_tasks = a.take<int32_t>(1);
+  TriTask* tasks = a.take<TriTask>((size_t)H * W);
   if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small for triangulation: need %zu bytes", a.off);
   const size_t hb = (size_t)(n_views + 1) * 16 * sizeof(double);
   if (!ensure_pinned(ctx, hb + 512)) return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
@@ -979,6 +983,7 @@ int imloc_triangulate_depth(imloc_ctx* ctx, int32_t H, int32_t W, const imloc_ca
   ta.min_inliers = p->min_inliers;
   ta.max_iters = p->max_refine_iters;
   ta.depth = depth; ta.inliers = inliers; ta.codes = codes;
+  ta.n_tasks = n_tasks; ta.tasks = tasks;
   HIP_TRY(ctx, launch_triangulate(ta, ctx->stream));
   return IMLOC_OK;
 }

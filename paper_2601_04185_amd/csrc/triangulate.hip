@@ -18,12 +18,22 @@
 //      while the cost rises, to a step below 1e-12 l);
 //   4. it is kept if the inlier set has at least min_inliers (4) members.
 //
-// One thread per pixel, one wave per workgroup, float64 throughout (on MI355X
-// the float64 vector rate equals the non-packed float32 rate).  The per-view
-// constants sit in LDS (broadcast reads), and so do the pixel's unit match
-// rays and weights ([view][lane], sized by the template bound on the view
-// count), which keeps the loops over views compact.  Match arrays are
-// [view][H][W], so the loads of a wave are coalesced.
+// Two launches, one thread per pixel, one wave per workgroup, float64
+// throughout (on MI355X the float64 vector rate equals the non-packed float32
+// rate):
+//   - triangulate_kernel: steps 1, 2 and 4 for every pixel; a pixel whose
+//     depth needs refinement is appended to a queue (one atomic per wave);
+//   - tri_refine_kernel: step 3, a quad of lanes per queued pixel.
+// Refinement is most of the arithmetic, but only the pixels with enough
+// inliers (about half of a mapping image) need it, and each runs its own
+// number of Newton steps; run in place, every wave would pay for its slowest
+// lane while its other lanes idle.  Compacted, the waves of the second launch
+// are full.  The per-view constants sit in LDS (broadcast reads), and so do
+// the pixel's unit match rays and weights ([view][lane]), which keeps the
+// loops over views compact.  The LDS is sized by the actual view count at
+// launch (28 B per view and lane).  Match arrays are [view][H][W], so the
+// loads of the first launch are coalesced; the second recomputes the rays of
+// its pixel's inliers with the same arithmetic.
 #include "imloc_device.h"
 #include "imloc_kernels.h"
 
@@ -41,7 +51,25 @@ __device__ inline void tri_ray(const TriViewDev& v, double u, double w, double r
   for (int c = 0; c < 3; ++c) r[c] = v.Rt[3 * c] * dx + v.Rt[3 * c + 1] * dy + v.Rt[3 * c + 2];
 }
 
-// angle between a = b + l r0 and the unit ray r, and, on request, d(angle)/dl
+// unit ray of a match (u, w) in a view
+__device__ inline void tri_unit_ray(const TriViewDev& v, float u, float w, double r[3]) {
+  tri_ray(v, u, w, r);
+  const double inv = 1.0 / sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  r[0] *= inv;
+  r[1] *= inv;
+  r[2] *= inv;
+}
+
+// angle between a = b + l r0 and the unit ray r
+__device__ inline double tri_angle(const double b[3], const double r0[3], double l, const double r[3]) {
+  const double a0 = b[0] + l * r0[0], a1 = b[1] + l * r0[1], a2 = b[2] + l * r0[2];
+  const double x0 = a1 * r[2] - a2 * r[1], x1 = a2 * r[0] - a0 * r[2], x2 = a0 * r[1] - a1 * r[0];
+  const double S = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+  const double s = a0 * r[0] + a1 * r[1] + a2 * r[2];
+  return atan2(S, s);
+}
+
+// the same angle and, on request, d(angle)/dl
 __device__ inline double tri_angle_d(const double b[3], const double r0[3], double l, const double r[3],
                                      double* dth) {
   const double a0 = b[0] + l * r0[0], a1 = b[1] + l * r0[1], a2 = b[2] + l * r0[2];
@@ -63,72 +91,147 @@ __device__ inline double tri_angle_d(const double b[3], const double r0[3], doub
   return th;
 }
 
-// Cost terms at up to three depths l[0..np): g = sum w th dth/dl, e = sum w
-// th^2 and the Gauss-Newton curvature hgn = sum w (dth/dl)^2 (at l[0]) over
-// the views in `set`, rays read from LDS.
-struct TriEval {
-  double g[3], e[3], hgn;
-};
-
-template <int VMAX>
-__device__ inline TriEval tri_eval(const TriViewDev* views, const double (*rx)[kWave], const double (*ry)[kWave],
-                                   const double (*rz)[kWave], const float (*wk)[kWave], int lane, uint32_t set,
-                                   const double r0[3], const double* l, int np) {
-  TriEval out{};
-  for (uint32_t m = set; m != 0; m &= m - 1) {
-    const int k = __ffs(m) - 1;
-    const double r[3] = {rx[k][lane], ry[k][lane], rz[k][lane]};
-    const double w = wk[k][lane];
-    for (int t = 0; t < np; ++t) {
-      double J;
-      const double th = tri_angle_d(views[k + 1].b, r0, l[t], r, &J);
-      out.g[t] += w * th * J;
-      out.e[t] += w * th * th;
-      if (t == 0) out.hgn += w * J * J;
-    }
-  }
-  return out;
+// Dynamic LDS of one workgroup: per-view constants [V + 1] (entry 0: the
+// mapping camera), then the unit match rays x, y, z and the weights, each
+// [rows][kWave] (rows = V for the hypotheses; for the refinement, where a
+// lane holds every fourth view, rows = ceil(V / 4)).
+size_t tri_lds_bytes(int V, int rows) {
+  return (size_t)(V + 1) * sizeof(TriViewDev) + (size_t)rows * kWave * (3 * sizeof(double) + sizeof(float));
 }
 
-// One wave per workgroup; each lane's match rays and weights live in LDS
-// ([view][lane], so the lanes of a wave hit distinct banks).
-template <int VMAX>
-__global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
-  __shared__ TriViewDev s_view[VMAX + 1];  // [0]: the mapping camera (b unused)
-  __shared__ double s_rx[VMAX][kWave], s_ry[VMAX][kWave], s_rz[VMAX][kWave];
-  __shared__ float s_w[VMAX][kWave];
-  const int lane = threadIdx.x;
-  for (int e = lane; e <= a.V; e += kWave) {
+struct TriLds {
+  TriViewDev* view;
+  double *rx, *ry, *rz;
+  float* w;
+};
+
+// carve the dynamic LDS and load the per-view constants (every lane of the
+// workgroup takes part)
+__device__ inline TriLds tri_lds_setup(const TriArgs& a, int rows) {
+  extern __shared__ double s_dyn[];
+  TriLds L;
+  L.view = reinterpret_cast<TriViewDev*>(s_dyn);
+  L.rx = s_dyn + (size_t)(a.V + 1) * (sizeof(TriViewDev) / sizeof(double));
+  L.ry = L.rx + rows * kWave;
+  L.rz = L.ry + rows * kWave;
+  L.w = reinterpret_cast<float*>(L.rz + rows * kWave);
+  for (int e = threadIdx.x; e <= a.V; e += kWave) {
     const double* src = a.views + 16 * e;
     TriViewDev v;
     v.fx = src[0]; v.fy = src[1]; v.cx = src[2]; v.cy = src[3];
     for (int c = 0; c < 9; ++c) v.Rt[c] = src[4 + c];
     for (int c = 0; c < 3; ++c) v.b[c] = src[13 + c];
     v.pad = 0.0;
-    s_view[e] = v;
+    L.view[e] = v;
   }
   __syncthreads();
+  return L;
+}
+
+// The refinement runs on a quad of lanes per pixel: lane j of the quad takes
+// the views k = j, j + 4, ... of the inlier set, and the sums are added over
+// the quad by DPP.  The butterfly gives every lane of the quad the same bits
+// ((x0 + x1) + (x2 + x3) up to commutation), so the four lanes take the same
+// decisions.  A pixel's Newton chain is a quarter as long, and four times as
+// many waves hide each other's latency.
+constexpr int kTriQuad = 4;
+
+__host__ __device__ inline int tri_quad_rows(int V) { return (V + kTriQuad - 1) / kTriQuad; }
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long v = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double quad_sum(double x) {
+  x += dpp_f64<0xb1>(x);  // quad_perm [1, 0, 3, 2]
+  x += dpp_f64<0x4e>(x);  // quad_perm [2, 3, 0, 1]
+  return x;
+}
+
+// Cost e = sum w th^2 at depth l over the quad's share of the inlier set
+// (rays read from LDS), summed over the quad.
+__device__ inline double tri_cost(const TriLds& L, int V, int lane, uint32_t set, const double r0[3], double l) {
+  double e = 0.0;
+  for (int k = lane & (kTriQuad - 1); k < V; k += kTriQuad) {
+    if (!((set >> k) & 1u)) continue;
+    const int o = (k / kTriQuad) * kWave + lane;
+    const double r[3] = {L.rx[o], L.ry[o], L.rz[o]};
+    const double w = L.w[o];
+    const double th = tri_angle(L.view[k + 1].b, r0, l, r);
+    e += w * th * th;
+  }
+  return quad_sum(e);
+}
+
+// g = sum w th dth/dl at the depths l[0..3) (three independent chains) and
+// the Gauss-Newton curvature hgn = sum w (dth/dl)^2 at l[0], summed over the
+// quad.
+struct TriGrad {
+  double g[3], hgn;
+};
+
+__device__ inline TriGrad tri_grad3(const TriLds& L, int V, int lane, uint32_t set, const double r0[3],
+                                    const double l[3]) {
+  TriGrad out{};
+  for (int k = lane & (kTriQuad - 1); k < V; k += kTriQuad) {
+    if (!((set >> k) & 1u)) continue;
+    const int o = (k / kTriQuad) * kWave + lane;
+    const double r[3] = {L.rx[o], L.ry[o], L.rz[o]};
+    const double w = L.w[o];
+    const double* b = L.view[k + 1].b;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      double J;
+      const double th = tri_angle_d(b, r0, l[t], r, &J);
+      out.g[t] += w * th * J;
+      if (t == 0) out.hgn += w * J * J;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 3; ++t) out.g[t] = quad_sum(out.g[t]);
+  out.hgn = quad_sum(out.hgn);
+  return out;
+}
+
+// the ray of pixel p of the mapping image (unnormalised: its z-component in
+// the camera is 1, so that l is the z-depth)
+__device__ inline void tri_pixel_ray(const TriArgs& a, const TriViewDev& v0, int64_t p, double r0[3]) {
+  const int i = (int)(p / a.W), j = (int)(p - (int64_t)i * a.W);
+  tri_ray(v0, (double)j + 0.5, (double)i + 0.5, r0);
+}
+
+// Steps 1, 2 and 4: one wave per workgroup; each lane's match rays and
+// weights live in LDS ([view][lane], so the lanes of a wave hit distinct
+// banks).  A pixel to refine is queued with its hypothesis and inlier set.
+__global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
+  const TriLds L = tri_lds_setup(a, a.V);
+  TriViewDev* s_view = L.view;
+  double *s_rx = L.rx, *s_ry = L.ry, *s_rz = L.rz;
+  float* s_w = L.w;
+  const int lane = threadIdx.x;
   const int64_t HW = (int64_t)a.H * a.W;
   const int64_t p = (int64_t)blockIdx.x * kWave + lane;
-  if (p >= HW) return;
-  const int i = (int)(p / a.W), j = (int)(p - (int64_t)i * a.W);
+  const bool pix = p < HW;  // the lanes past the image take part in the queue's ballot only
   double r0[3];
-  tri_ray(s_view[0], (double)j + 0.5, (double)i + 0.5, r0);
+  tri_pixel_ray(a, s_view[0], pix ? p : 0, r0);
   const double ep = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
 
   // the pixel's matches: unit rays and weights
   uint32_t ok = 0;
-  for (int k = 0; k < a.V; ++k) {
+  for (int k = 0; pix && k < a.V; ++k) {
     const int64_t o = (int64_t)k * HW + p;
     const float mu = a.mu[o], mv = a.mv[o], cf = a.conf[o];
     if (cf >= a.min_conf && isfinite(mu) && isfinite(mv)) {
       double r[3];
-      tri_ray(s_view[k + 1], mu, mv, r);
-      const double inv = 1.0 / sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-      s_rx[k][lane] = r[0] * inv;
-      s_ry[k][lane] = r[1] * inv;
-      s_rz[k][lane] = r[2] * inv;
-      s_w[k][lane] = cf;
+      tri_unit_ray(s_view[k + 1], mu, mv, r);
+      s_rx[k * kWave + lane] = r[0];
+      s_ry[k * kWave + lane] = r[1];
+      s_rz[k * kWave + lane] = r[2];
+      s_w[k * kWave + lane] = cf;
       ok |= 1u << k;
     }
   }
@@ -140,7 +243,8 @@ __global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
   for (uint32_t mh = ok; mh != 0; mh &= mh - 1) {
     const int h = __ffs(mh) - 1;
     const double* b = s_view[h + 1].b;
-    const double rh[3] = {s_rx[h][lane], s_ry[h][lane], s_rz[h][lane]};
+    const int oh = h * kWave + lane;
+    const double rh[3] = {s_rx[oh], s_ry[oh], s_rz[oh]};
     const double al = b[0] * rh[0] + b[1] * rh[1] + b[2] * rh[2];
     const double be = r0[0] * rh[0] + r0[1] * rh[1] + r0[2] * rh[2];
     const double ga = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
@@ -157,7 +261,8 @@ __global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
       const int k = __ffs(mk) - 1;
       const double* bk = s_view[k + 1].b;
       const double a0 = bk[0] + l * r0[0], a1 = bk[1] + l * r0[1], a2 = bk[2] + l * r0[2];
-      const double s = a0 * s_rx[k][lane] + a1 * s_ry[k][lane] + a2 * s_rz[k][lane];
+      const int ok_ = k * kWave + lane;
+      const double s = a0 * s_rx[ok_] + a1 * s_ry[ok_] + a2 * s_rz[ok_];
       const double q = a0 * a0 + a1 * a1 + a2 * a2;
       if (s > 0.0 && s * s > a.cos2_thr * q) set |= 1u << k;
     }
@@ -169,57 +274,106 @@ __global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
     }
   }
 
-  double depth = 0.0;
-  if (best_n > 0 && best_n >= a.min_inliers) {
-    double l = best_l;
-    double pts[3] = {l, 0.0, 0.0};
-    double e = tri_eval<VMAX>(s_view, s_rx, s_ry, s_rz, s_w, lane, best_set, r0, pts, 1).e[0];
-    for (int it = 0; it < a.max_iters; ++it) {
-      const double dl = 1e-6 * l;
-      pts[0] = l; pts[1] = l + dl; pts[2] = l - dl;
-      const TriEval ev = tri_eval<VMAX>(s_view, s_rx, s_ry, s_rz, s_w, lane, best_set, r0, pts, 3);
-      const double g = ev.g[0];
-      if (g == 0.0) break;
-      const double gp = (ev.g[1] - ev.g[2]) / (2.0 * dl);
-      const double curv = gp > 0.0 ? gp : ev.hgn;
-      if (!(curv > 0.0)) break;
-      double step = -g / curv;
-      bool moved = false;
-      for (int half = 0; half < 30; ++half) {
-        const double ln = l + step;
-        if (ln > 0.0) {
-          pts[0] = ln;
-          const double en = tri_eval<VMAX>(s_view, s_rx, s_ry, s_rz, s_w, lane, best_set, r0, pts, 1).e[0];
-          if (en <= e) {
-            moved = ln != l;
-            l = ln;
-            e = en;
-            break;
-          }
-        }
-        step *= 0.5;
-      }
-      if (!moved || fabs(step) <= 1e-12 * l) break;
+  const bool refine = pix && best_n > 0 && best_n >= a.min_inliers;
+  // queue the pixels to refine: one counter add per wave, slots in lane order
+  const uint64_t bal = __ballot(refine);
+  if (bal) {
+    int base = 0;
+    if (lane == __ffsll((unsigned long long)bal) - 1) base = atomicAdd(a.n_tasks, __popcll(bal));
+    base = __shfl(base, __ffsll((unsigned long long)bal) - 1);
+    if (refine) {
+      const int slot = base + __popcll(bal & ((1ull << lane) - 1));
+      a.tasks[slot] = TriTask{best_l, (int32_t)p, best_set};
     }
-    depth = l > 0.0 ? l : 0.0;
   }
-  const float d32 = (float)depth;
-  if (a.depth) a.depth[p] = d32;
+  if (!pix) return;
   if (a.inliers) a.inliers[p] = best_n;
-  if (a.codes) a.codes[p] = depth > 0.0 ? log8_code(d32) : (uint8_t)0;
+  if (!refine) {
+    if (a.depth) a.depth[p] = 0.0f;
+    if (a.codes) a.codes[p] = 0;
+  }
 }
 
-int tri_vmax(int V) { return V <= 8 ? 8 : (V <= 16 ? 16 : 32); }
+// Step 3 for the queued pixels, a quad of lanes each: Newton's method on the
+// derivative of the confidence-weighted sum of squared angular errors over
+// the inlier set (its own derivative by a central difference, the
+// Gauss-Newton curvature where that is not positive), a step that raises the
+// cost halved up to 30 times, until the step is below 1e-12 l or max_iters
+// steps.  A step below 1e-12 l is not tried while being halved either: near
+// the minimum the cost's rounding noise exceeds such a step's decrease, and a
+// wave would otherwise halve on towards one ulp for its unluckiest lane.  Launched over the largest possible queue; waves past its length
+// return at once.
+__global__ __launch_bounds__(kWave) void tri_refine_kernel(TriArgs a) {
+  constexpr int kPerWave = kWave / kTriQuad;  // pixels per wave
+  const int n = *a.n_tasks;
+  if ((int64_t)blockIdx.x * kPerWave >= n) return;
+  const TriLds L = tri_lds_setup(a, tri_quad_rows(a.V));
+  const int lane = threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * kPerWave + lane / kTriQuad;
+  if (t >= n) return;  // the whole quad
+  const TriTask task = a.tasks[t];
+  const int64_t HW = (int64_t)a.H * a.W;
+  const int64_t p = task.p;
+  const uint32_t set = task.set;
+  double r0[3];
+  tri_pixel_ray(a, L.view[0], p, r0);
+  for (int k = lane & (kTriQuad - 1); k < a.V; k += kTriQuad) {  // this lane's share of the rays
+    if (!((set >> k) & 1u)) continue;
+    const int64_t o = (int64_t)k * HW + p;
+    double r[3];
+    tri_unit_ray(L.view[k + 1], a.mu[o], a.mv[o], r);
+    const int row = (k / kTriQuad) * kWave + lane;
+    L.rx[row] = r[0];
+    L.ry[row] = r[1];
+    L.rz[row] = r[2];
+    L.w[row] = a.conf[o];
+  }
+  double l = task.l;
+  double e = tri_cost(L, a.V, lane, set, r0, l);
+  for (int it = 0; it < a.max_iters; ++it) {
+    const double dl = 1e-6 * l;
+    const double pts[3] = {l, l + dl, l - dl};
+    const TriGrad ev = tri_grad3(L, a.V, lane, set, r0, pts);
+    const double g = ev.g[0];
+    if (g == 0.0) break;
+    const double gp = (ev.g[1] - ev.g[2]) / (2.0 * dl);
+    const double curv = gp > 0.0 ? gp : ev.hgn;
+    if (!(curv > 0.0)) break;
+    double step = -g / curv;
+    bool moved = false;
+    for (int half = 0; half < 30; ++half) {
+      if (fabs(step) <= 1e-12 * l) break;  // converged: not tried
+      const double ln = l + step;
+      if (ln > 0.0) {
+        const double en = tri_cost(L, a.V, lane, set, r0, ln);
+        if (en <= e) {
+          moved = ln != l;
+          l = ln;
+          e = en;
+          break;
+        }
+      }
+      step *= 0.5;
+    }
+    if (!moved || fabs(step) <= 1e-12 * l) break;
+  }
+  const double depth = l > 0.0 ? l : 0.0;
+  const float d32 = (float)depth;
+  if ((lane & (kTriQuad - 1)) == 0) {
+    if (a.depth) a.depth[p] = d32;
+    if (a.codes) a.codes[p] = depth > 0.0 ? log8_code(d32) : (uint8_t)0;
+  }
+}
 
 hipError_t launch_triangulate(const TriArgs& a, hipStream_t s) {
   const int64_t HW = (int64_t)a.H * a.W;
   if (HW <= 0) return hipSuccess;
   const dim3 grid((unsigned)((HW + kWave - 1) / kWave));
-  switch (tri_vmax(a.V)) {
-    case 8: hipLaunchKernelGGL(triangulate_kernel<8>, grid, dim3(kWave), 0, s, a); break;
-    case 16: hipLaunchKernelGGL(triangulate_kernel<16>, grid, dim3(kWave), 0, s, a); break;
-    default: hipLaunchKernelGGL(triangulate_kernel<32>, grid, dim3(kWave), 0, s, a); break;
-  }
+  const hipError_t e = launch_fill_i32(a.n_tasks, 1, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(triangulate_kernel, grid, dim3(kWave), tri_lds_bytes(a.V, a.V), s, a);
+  const dim3 grid_refine((unsigned)((HW * kTriQuad + kWave - 1) / kWave));
+  hipLaunchKernelGGL(tri_refine_kernel, grid_refine, dim3(kWave), tri_lds_bytes(a.V, tri_quad_rows(a.V)), s, a);
   return hipGetLastError();
 }
 
