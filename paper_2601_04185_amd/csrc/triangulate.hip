@@ -92,11 +92,12 @@ __device__ inline double tri_angle_d(const double b[3], const double r0[3], doub
 }
 
 // Dynamic LDS of one workgroup: per-view constants [V + 1] (entry 0: the
-// mapping camera), then the unit match rays x, y, z and the weights, each
-// [rows][kWave] (rows = V for the hypotheses; for the refinement, where a
-// lane holds every fourth view, rows = ceil(V / 4)).
-size_t tri_lds_bytes(int V, int rows) {
-  return (size_t)(V + 1) * sizeof(TriViewDev) + (size_t)rows * kWave * (3 * sizeof(double) + sizeof(float));
+// mapping camera), then the unit match rays x, y, z, each [rows][kWave], and
+// for the refinement the weights [rows][kWave] (rows = V for the hypotheses;
+// for the refinement, where a lane holds every fourth view, rows = ceil(V / 4)).
+size_t tri_lds_bytes(int V, int rows, bool weights) {
+  return (size_t)(V + 1) * sizeof(TriViewDev) +
+         (size_t)rows * kWave * (3 * sizeof(double) + (weights ? sizeof(float) : 0));
 }
 
 struct TriLds {
@@ -107,14 +108,14 @@ struct TriLds {
 
 // carve the dynamic LDS and load the per-view constants (every lane of the
 // workgroup takes part)
-__device__ inline TriLds tri_lds_setup(const TriArgs& a, int rows) {
+__device__ inline TriLds tri_lds_setup(const TriArgs& a, int rows, bool weights) {
   extern __shared__ double s_dyn[];
   TriLds L;
   L.view = reinterpret_cast<TriViewDev*>(s_dyn);
   L.rx = s_dyn + (size_t)(a.V + 1) * (sizeof(TriViewDev) / sizeof(double));
   L.ry = L.rx + rows * kWave;
   L.rz = L.ry + rows * kWave;
-  L.w = reinterpret_cast<float*>(L.rz + rows * kWave);
+  L.w = weights ? reinterpret_cast<float*>(L.rz + rows * kWave) : nullptr;
   for (int e = threadIdx.x; e <= a.V; e += kWave) {
     const double* src = a.views + 16 * e;
     TriViewDev v;
@@ -135,6 +136,7 @@ __device__ inline TriLds tri_lds_setup(const TriArgs& a, int rows) {
 // decisions.  A pixel's Newton chain is a quarter as long, and four times as
 // many waves hide each other's latency.
 constexpr int kTriQuad = 4;
+constexpr int kTriLoadGroup = 8;  // match loads issued together
 
 __host__ __device__ inline int tri_quad_rows(int V) { return (V + kTriQuad - 1) / kTriQuad; }
 
@@ -204,14 +206,16 @@ __device__ inline void tri_pixel_ray(const TriArgs& a, const TriViewDev& v0, int
   tri_ray(v0, (double)j + 0.5, (double)i + 0.5, r0);
 }
 
-// Steps 1, 2 and 4: one wave per workgroup; each lane's match rays and
-// weights live in LDS ([view][lane], so the lanes of a wave hit distinct
-// banks).  A pixel to refine is queued with its hypothesis and inlier set.
+// Steps 1, 2 and 4: one wave per workgroup; each lane's match rays live in
+// LDS ([view][lane], so the lanes of a wave hit distinct banks).  The loops
+// over hypotheses and views run over all views with the same view in every
+// lane (a lane skips the views it has no match in), so the view constants are
+// uniform and come from scalar loads.  A pixel to refine is queued with its
+// hypothesis and inlier set.
 __global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
-  const TriLds L = tri_lds_setup(a, a.V);
+  const TriLds L = tri_lds_setup(a, a.V, false);
   TriViewDev* s_view = L.view;
   double *s_rx = L.rx, *s_ry = L.ry, *s_rz = L.rz;
-  float* s_w = L.w;
   const int lane = threadIdx.x;
   const int64_t HW = (int64_t)a.H * a.W;
   const int64_t p = (int64_t)blockIdx.x * kWave + lane;
@@ -220,19 +224,27 @@ __global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
   tri_pixel_ray(a, s_view[0], pix ? p : 0, r0);
   const double ep = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
 
-  // the pixel's matches: unit rays and weights
+  // the pixel's matches: unit rays.  The loads of a group of views are issued
+  // together, so that the group waits for one memory latency, not one per view.
   uint32_t ok = 0;
-  for (int k = 0; pix && k < a.V; ++k) {
-    const int64_t o = (int64_t)k * HW + p;
-    const float mu = a.mu[o], mv = a.mv[o], cf = a.conf[o];
-    if (cf >= a.min_conf && isfinite(mu) && isfinite(mv)) {
-      double r[3];
-      tri_unit_ray(s_view[k + 1], mu, mv, r);
-      s_rx[k * kWave + lane] = r[0];
-      s_ry[k * kWave + lane] = r[1];
-      s_rz[k * kWave + lane] = r[2];
-      s_w[k * kWave + lane] = cf;
-      ok |= 1u << k;
+  for (int k0 = 0; pix && k0 < a.V; k0 += kTriLoadGroup) {
+    float mu[kTriLoadGroup], mv[kTriLoadGroup], cf[kTriLoadGroup];
+#pragma unroll
+    for (int j = 0; j < kTriLoadGroup; ++j) {
+      const int64_t o = (int64_t)min(k0 + j, a.V - 1) * HW + p;
+      mu[j] = a.mu[o]; mv[j] = a.mv[o]; cf[j] = a.conf[o];
+    }
+#pragma unroll
+    for (int j = 0; j < kTriLoadGroup; ++j) {
+      const int k = k0 + j;
+      if (k < a.V && cf[j] >= a.min_conf && isfinite(mu[j]) && isfinite(mv[j])) {
+        double r[3];
+        tri_unit_ray(s_view[k + 1], mu[j], mv[j], r);
+        s_rx[k * kWave + lane] = r[0];
+        s_ry[k * kWave + lane] = r[1];
+        s_rz[k * kWave + lane] = r[2];
+        ok |= 1u << k;
+      }
     }
   }
 
@@ -240,9 +252,9 @@ __global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
   int best_n = 0;
   double best_l = 0.0;
   uint32_t best_set = 0;
-  for (uint32_t mh = ok; mh != 0; mh &= mh - 1) {
-    const int h = __ffs(mh) - 1;
-    const double* b = s_view[h + 1].b;
+  for (int h = 0; h < a.V; ++h) {
+    if (!((ok >> h) & 1u)) continue;
+    const double* b = a.views + 16 * (h + 1) + 13;  // C0 - C_h
     const int oh = h * kWave + lane;
     const double rh[3] = {s_rx[oh], s_ry[oh], s_rz[oh]};
     const double al = b[0] * rh[0] + b[1] * rh[1] + b[2] * rh[2];
@@ -257,9 +269,9 @@ __global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
     if (!(cosl > fabs(be) / sqrt(ep))) continue;
     // inliers: angle < thr  <=>  a.r > 0 and (a.r)^2 > cos^2(thr) |a|^2
     uint32_t set = 0;
-    for (uint32_t mk = ok; mk != 0; mk &= mk - 1) {
-      const int k = __ffs(mk) - 1;
-      const double* bk = s_view[k + 1].b;
+    for (int k = 0; k < a.V; ++k) {
+      if (!((ok >> k) & 1u)) continue;
+      const double* bk = a.views + 16 * (k + 1) + 13;
       const double a0 = bk[0] + l * r0[0], a1 = bk[1] + l * r0[1], a2 = bk[2] + l * r0[2];
       const int ok_ = k * kWave + lane;
       const double s = a0 * s_rx[ok_] + a1 * s_ry[ok_] + a2 * s_rz[ok_];
@@ -307,7 +319,7 @@ __global__ __launch_bounds__(kWave) void tri_refine_kernel(TriArgs a) {
   constexpr int kPerWave = kWave / kTriQuad;  // pixels per wave
   const int n = *a.n_tasks;
   if ((int64_t)blockIdx.x * kPerWave >= n) return;
-  const TriLds L = tri_lds_setup(a, tri_quad_rows(a.V));
+  const TriLds L = tri_lds_setup(a, tri_quad_rows(a.V), true);
   const int lane = threadIdx.x;
   const int64_t t = (int64_t)blockIdx.x * kPerWave + lane / kTriQuad;
   if (t >= n) return;  // the whole quad
@@ -317,16 +329,28 @@ __global__ __launch_bounds__(kWave) void tri_refine_kernel(TriArgs a) {
   const uint32_t set = task.set;
   double r0[3];
   tri_pixel_ray(a, L.view[0], p, r0);
-  for (int k = lane & (kTriQuad - 1); k < a.V; k += kTriQuad) {  // this lane's share of the rays
-    if (!((set >> k) & 1u)) continue;
-    const int64_t o = (int64_t)k * HW + p;
-    double r[3];
-    tri_unit_ray(L.view[k + 1], a.mu[o], a.mv[o], r);
-    const int row = (k / kTriQuad) * kWave + lane;
-    L.rx[row] = r[0];
-    L.ry[row] = r[1];
-    L.rz[row] = r[2];
-    L.w[row] = a.conf[o];
+  // this lane's share of the rays, the loads of a group issued together
+  const int sub = lane & (kTriQuad - 1);
+  for (int k0 = sub; k0 < a.V; k0 += kTriQuad * kTriLoadGroup) {
+    float mu[kTriLoadGroup], mv[kTriLoadGroup], cf[kTriLoadGroup];
+#pragma unroll
+    for (int j = 0; j < kTriLoadGroup; ++j) {
+      const int k = k0 + kTriQuad * j;
+      const int64_t o = (int64_t)(k < a.V ? k : 0) * HW + p;  // view 0 always exists
+      mu[j] = a.mu[o]; mv[j] = a.mv[o]; cf[j] = a.conf[o];
+    }
+#pragma unroll
+    for (int j = 0; j < kTriLoadGroup; ++j) {
+      const int k = k0 + kTriQuad * j;
+      if (k >= a.V || !((set >> k) & 1u)) continue;
+      double r[3];
+      tri_unit_ray(L.view[k + 1], mu[j], mv[j], r);
+      const int row = (k / kTriQuad) * kWave + lane;
+      L.rx[row] = r[0];
+      L.ry[row] = r[1];
+      L.rz[row] = r[2];
+      L.w[row] = cf[j];
+    }
   }
   double l = task.l;
   double e = tri_cost(L, a.V, lane, set, r0, l);
@@ -371,9 +395,9 @@ hipError_t launch_triangulate(const TriArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)((HW + kWave - 1) / kWave));
   const hipError_t e = launch_fill_i32(a.n_tasks, 1, 0, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(triangulate_kernel, grid, dim3(kWave), tri_lds_bytes(a.V, a.V), s, a);
+  hipLaunchKernelGGL(triangulate_kernel, grid, dim3(kWave), tri_lds_bytes(a.V, a.V, false), s, a);
   const dim3 grid_refine((unsigned)((HW * kTriQuad + kWave - 1) / kWave));
-  hipLaunchKernelGGL(tri_refine_kernel, grid_refine, dim3(kWave), tri_lds_bytes(a.V, tri_quad_rows(a.V)), s, a);
+  hipLaunchKernelGGL(tri_refine_kernel, grid_refine, dim3(kWave), tri_lds_bytes(a.V, tri_quad_rows(a.V), true), s, a);
   return hipGetLastError();
 }
 
