@@ -154,18 +154,29 @@ __device__ __forceinline__ double quad_sum(double x) {
   return x;
 }
 
+// Lane j of a quad holds the views k = j + 4 s in slots s < KQ (KQ =
+// ceil(V / 4), a template bound, so the slot loops unroll); a slot without an
+// inlier holds the ray (0, 0, 1) with weight 0 and contributes an exact 0.
+
 // Cost e = sum w th^2 at depth l over the quad's share of the inlier set
-// (rays read from LDS), summed over the quad.
+// (rays read from LDS), summed over the quad.  Branch-free over the slots, so
+// that their angle computations interleave.
+template <int KQ>
 __device__ inline double tri_cost(const TriLds& L, int V, int lane, uint32_t set, const double r0[3], double l) {
-  double e = 0.0;
-  for (int k = lane & (kTriQuad - 1); k < V; k += kTriQuad) {
-    if (!((set >> k) & 1u)) continue;
-    const int o = (k / kTriQuad) * kWave + lane;
+  const int sub = lane & (kTriQuad - 1);
+  double c[KQ];
+#pragma unroll
+  for (int j = 0; j < KQ; ++j) {
+    const int k = sub + kTriQuad * j;
+    const bool in = k < V && ((set >> k) & 1u);
+    const int o = j * kWave + lane;
     const double r[3] = {L.rx[o], L.ry[o], L.rz[o]};
-    const double w = L.w[o];
-    const double th = tri_angle(L.view[k + 1].b, r0, l, r);
-    e += w * th * th;
+    const double th = tri_angle(L.view[in ? k + 1 : 1].b, r0, l, r);
+    c[j] = in ? (double)L.w[o] * th * th : 0.0;
   }
+  double e = 0.0;
+#pragma unroll
+  for (int j = 0; j < KQ; ++j) e += c[j];
   return quad_sum(e);
 }
 
@@ -176,12 +187,16 @@ struct TriGrad {
   double g[3], hgn;
 };
 
+template <int KQ>
 __device__ inline TriGrad tri_grad3(const TriLds& L, int V, int lane, uint32_t set, const double r0[3],
                                     const double l[3]) {
+  const int sub = lane & (kTriQuad - 1);
   TriGrad out{};
-  for (int k = lane & (kTriQuad - 1); k < V; k += kTriQuad) {
-    if (!((set >> k) & 1u)) continue;
-    const int o = (k / kTriQuad) * kWave + lane;
+#pragma unroll
+  for (int j = 0; j < KQ; ++j) {
+    const int k = sub + kTriQuad * j;
+    if (!(k < V && ((set >> k) & 1u))) continue;
+    const int o = j * kWave + lane;
     const double r[3] = {L.rx[o], L.ry[o], L.rz[o]};
     const double w = L.w[o];
     const double* b = L.view[k + 1].b;
@@ -315,6 +330,7 @@ __global__ __launch_bounds__(kWave) void triangulate_kernel(TriArgs a) {
 // the minimum the cost's rounding noise exceeds such a step's decrease, and a
 // wave would otherwise halve on towards one ulp for its unluckiest lane.  Launched over the largest possible queue; waves past its length
 // return at once.
+template <int KQ>
 __global__ __launch_bounds__(kWave) void tri_refine_kernel(TriArgs a) {
   constexpr int kPerWave = kWave / kTriQuad;  // pixels per wave
   const int n = *a.n_tasks;
@@ -329,35 +345,36 @@ __global__ __launch_bounds__(kWave) void tri_refine_kernel(TriArgs a) {
   const uint32_t set = task.set;
   double r0[3];
   tri_pixel_ray(a, L.view[0], p, r0);
-  // this lane's share of the rays, the loads of a group issued together
+  // this lane's share of the rays (slot j: view sub + 4 j), loads issued together
   const int sub = lane & (kTriQuad - 1);
-  for (int k0 = sub; k0 < a.V; k0 += kTriQuad * kTriLoadGroup) {
-    float mu[kTriLoadGroup], mv[kTriLoadGroup], cf[kTriLoadGroup];
+  float mu[KQ], mv[KQ], cf[KQ];
 #pragma unroll
-    for (int j = 0; j < kTriLoadGroup; ++j) {
-      const int k = k0 + kTriQuad * j;
-      const int64_t o = (int64_t)(k < a.V ? k : 0) * HW + p;  // view 0 always exists
-      mu[j] = a.mu[o]; mv[j] = a.mv[o]; cf[j] = a.conf[o];
-    }
+  for (int j = 0; j < KQ; ++j) {
+    const int k = sub + kTriQuad * j;
+    const int64_t o = (int64_t)(k < a.V ? k : 0) * HW + p;  // view 0 always exists
+    mu[j] = a.mu[o]; mv[j] = a.mv[o]; cf[j] = a.conf[o];
+  }
 #pragma unroll
-    for (int j = 0; j < kTriLoadGroup; ++j) {
-      const int k = k0 + kTriQuad * j;
-      if (k >= a.V || !((set >> k) & 1u)) continue;
-      double r[3];
+  for (int j = 0; j < KQ; ++j) {
+    const int k = sub + kTriQuad * j;
+    double r[3] = {0.0, 0.0, 1.0};
+    float w = 0.0f;
+    if (k < a.V && ((set >> k) & 1u)) {
       tri_unit_ray(L.view[k + 1], mu[j], mv[j], r);
-      const int row = (k / kTriQuad) * kWave + lane;
-      L.rx[row] = r[0];
-      L.ry[row] = r[1];
-      L.rz[row] = r[2];
-      L.w[row] = cf[j];
+      w = cf[j];
     }
+    const int row = j * kWave + lane;
+    L.rx[row] = r[0];
+    L.ry[row] = r[1];
+    L.rz[row] = r[2];
+    L.w[row] = w;
   }
   double l = task.l;
-  double e = tri_cost(L, a.V, lane, set, r0, l);
+  double e = tri_cost<KQ>(L, a.V, lane, set, r0, l);
   for (int it = 0; it < a.max_iters; ++it) {
     const double dl = 1e-6 * l;
     const double pts[3] = {l, l + dl, l - dl};
-    const TriGrad ev = tri_grad3(L, a.V, lane, set, r0, pts);
+    const TriGrad ev = tri_grad3<KQ>(L, a.V, lane, set, r0, pts);
     const double g = ev.g[0];
     if (g == 0.0) break;
     const double gp = (ev.g[1] - ev.g[2]) / (2.0 * dl);
@@ -369,7 +386,7 @@ __global__ __launch_bounds__(kWave) void tri_refine_kernel(TriArgs a) {
       if (fabs(step) <= 1e-12 * l) break;  // converged: not tried
       const double ln = l + step;
       if (ln > 0.0) {
-        const double en = tri_cost(L, a.V, lane, set, r0, ln);
+        const double en = tri_cost<KQ>(L, a.V, lane, set, r0, ln);
         if (en <= e) {
           moved = ln != l;
           l = ln;
@@ -397,7 +414,17 @@ hipError_t launch_triangulate(const TriArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(triangulate_kernel, grid, dim3(kWave), tri_lds_bytes(a.V, a.V, false), s, a);
   const dim3 grid_refine((unsigned)((HW * kTriQuad + kWave - 1) / kWave));
-  hipLaunchKernelGGL(tri_refine_kernel, grid_refine, dim3(kWave), tri_lds_bytes(a.V, tri_quad_rows(a.V), true), s, a);
+  const size_t lds = tri_lds_bytes(a.V, tri_quad_rows(a.V), true);
+  switch (tri_quad_rows(a.V)) {  // slots per lane, 1..8 for 1..32 views
+    case 1: hipLaunchKernelGGL(tri_refine_kernel<1>, grid_refine, dim3(kWave), lds, s, a); break;
+    case 2: hipLaunchKernelGGL(tri_refine_kernel<2>, grid_refine, dim3(kWave), lds, s, a); break;
+    case 3: hipLaunchKernelGGL(tri_refine_kernel<3>, grid_refine, dim3(kWave), lds, s, a); break;
+    case 4: hipLaunchKernelGGL(tri_refine_kernel<4>, grid_refine, dim3(kWave), lds, s, a); break;
+    case 5: hipLaunchKernelGGL(tri_refine_kernel<5>, grid_refine, dim3(kWave), lds, s, a); break;
+    case 6: hipLaunchKernelGGL(tri_refine_kernel<6>, grid_refine, dim3(kWave), lds, s, a); break;
+    case 7: hipLaunchKernelGGL(tri_refine_kernel<7>, grid_refine, dim3(kWave), lds, s, a); break;
+    default: hipLaunchKernelGGL(tri_refine_kernel<8>, grid_refine, dim3(kWave), lds, s, a); break;
+  }
   return hipGetLastError();
 }
 
