@@ -68,7 +68,7 @@ def test_parity_noisy_scene(pk, ctx, orc):
 
 
 @pytest.mark.parametrize("V,H,W", [(1, 23, 37), (3, 23, 37), (8, 31, 17), (9, 31, 17), (16, 19, 41), (17, 19, 41),
-                                   (32, 11, 13)])
+                                   (21, 13, 17), (24, 13, 17), (27, 9, 11), (32, 11, 13)])
 def test_parity_view_counts_and_ragged_sizes(pk, ctx, orc, V, H, W):
     w = synth.dense_match_scene(n_views=V, width=W, height=H, correct_frac=0.8, noise_px=0.3, seed=40 + V,
                                 f=0.8 * 96)
