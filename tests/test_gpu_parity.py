@@ -157,6 +157,39 @@ def test_score_ragged_candidate_counts(pk, ctx, orc):
         assert len(c) == npz and np.all(c >= lo) and np.all(c <= hi)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_score_non_finite_and_behind_camera(pk, ctx, orc, precision):
+    """Correspondences with NaN or infinite coordinates never count as
+    inliers, and points behind a candidate's camera cost tau^2 (Sec. 3.3,
+    truncated reprojection cost): both sides on the same inputs."""
+    import dataclasses
+    q = synth.make_query(95, 4100, 0.4, 1.0)
+    rng = np.random.default_rng(95)
+    u, v, X, Y, Z = (a.copy() for a in (q.u, q.v, q.X, q.Y, q.Z))
+    bad = rng.choice(q.n, 120, replace=False)
+    u[bad[:30]] = np.nan
+    v[bad[30:60]] = np.inf
+    X[bad[60:90]] = np.nan
+    Z[bad[90:]] = -np.inf
+    # 300 inliers moved behind the true camera (reflected through its centre)
+    C = -q.R.T @ q.t
+    back = rng.choice(np.flatnonzero(q.is_inlier), 300, replace=False)
+    P = np.stack([X[back], Y[back], Z[back]], 1).astype(np.float64)
+    P = C + (C - P)
+    X[back], Y[back], Z[back] = (P[:, c].astype(np.float32) for c in range(3))
+    q2 = dataclasses.replace(q, u=u, v=v, X=X, Y=Y, Z=Z)
+    poses = _oracle_pose_set(orc, q, count=100)
+    tau = 4.0
+    cnt, ms = pk.imloc_score(ctx, _dev(q2), q2.K, _poses_tensor(poses), tau, precision)
+    cnt, ms = cnt.cpu().numpy(), ms.cpu().numpy()
+    lo, hi, eb = orc.score_band(poses, q2.corr(), q2.K, tau, band_abs=1e-5, with_f32=(precision == 0))
+    ocnt, oms = orc.score(poses, q2.corr(), q2.K, tau)
+    assert np.all(cnt >= lo) and np.all(cnt <= hi)
+    assert np.all(np.isfinite(ms))
+    tol = eb + (1e-11 * oms if precision == 1 else tau * tau * 2e-5 * hi + 1e-6 * oms)
+    assert np.all(np.abs(ms - oms) <= tol + 1e-9)
+
+
 # ---------------------------------------------------- LO and refinement ----
 def test_local_optimize_parity(pk, ctx, orc):
     import torch
