@@ -481,6 +481,20 @@ __device__ __forceinline__ void gn_store_state(const GNShared& s, GNState* st) {
   }
 }
 
+// the same from the registers of gn_state_issue
+__device__ __forceinline__ void gn_store_state_regs(const GNStateRegs& r, GNState* st) {
+  if (threadIdx.x < 12) {
+    st->cur[threadIdx.x] = r.cur;
+    st->eval[threadIdx.x] = r.eval;
+  }
+  if (threadIdx.x == 0) {
+    st->cur_cost = r.cost;
+    st->cur_count = r.count;
+    st->done = r.done;
+    st->accepted = r.accepted;
+  }
+}
+
 __device__ __forceinline__ void gn_outputs(const GNArgs& g, const GNShared& s, int p) {
   if (threadIdx.x < 12 && g.out_pose) g.out_pose[12 * (int64_t)p + threadIdx.x] = s.cur[threadIdx.x];
   if (threadIdx.x == 0) {
@@ -634,6 +648,9 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
   // loads whose addresses need only the launch: partial sums, descriptor
   // fields, state -- issued together, so that one round trip covers them (the
   // compiler would otherwise fetch each field in the branch that first uses it)
+  // the state first: a run that has ended waits for it alone (below)
+  GNStateRegs sr;
+  gn_state_issue(k >= 2 ? g.gst + (int64_t)(k & 1) * g.nprob + p : nullptr, sr);
   GNPart pr;
   if (k > 0) gn_part_issue(gn_part(g, (k - 1) & 1, p), g.cmax, pr);
   const int q = gn_query<MODE>(g, p);
@@ -641,8 +658,6 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
   const CorrF32 c = MODE == 0 ? d.S : d.full;
   const int64_t n = MODE == 0 ? d.m : d.n;
   uint8_t* in_set = MODE == 1 ? g.in_set_all + d.in_set_off : nullptr;
-  GNStateRegs sr;
-  gn_state_issue(k >= 2 ? g.gst + (int64_t)(k & 1) * g.nprob + p : nullptr, sr);
   asm volatile("" ::"s"(c.X), "s"(c.Y), "s"(c.Z), "s"(c.u), "s"(c.v), "s"(c.w), "s"(n), "s"(in_set));
   const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
   // the points are loaded before any test (indices are clamped), so that the
@@ -650,6 +665,13 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
   // reduction and the decision
   GNPoints pt;
   gn_load_points<MODE>(c, n, base, in_set, k > 0, g.part, pt);
+  // A run that ended at an earlier launch: decision k - 1 would leave its
+  // state as it is, so carry the state to the slot the next launch reads and
+  // stop, without waiting for the partial sums and points in flight.
+  if (k >= 2 && sr.done) {
+    if (chunk == 0) gn_store_state_regs(sr, g.gst + (int64_t)((k - 1) & 1) * g.nprob + p);
+    return;
+  }
   const int C = chunks_for(n);
   if (chunk >= C) return;
   const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
