@@ -29,11 +29,12 @@
 // number of Newton steps; run in place, every wave would pay for its slowest
 // lane while its other lanes idle.  Compacted, the waves of the second launch
 // are full.  The per-view constants sit in LDS (broadcast reads), and so do
-// the pixel's unit match rays and weights ([view][lane]), which keeps the
-// loops over views compact.  The LDS is sized by the actual view count at
-// launch (28 B per view and lane).  Match arrays are [view][H][W], so the
-// loads of the first launch are coalesced; the second recomputes the rays of
-// its pixel's inliers with the same arithmetic.
+// the pixels' unit match rays (first launch: [view][lane], 24 B per view and
+// lane; second: [slot][lane] with the weights, 28 B per slot and lane), which
+// keeps the loops over views compact; the LDS is sized by the actual view
+// count at launch.  Match arrays are [view][H][W], so the loads of the first
+// launch are coalesced; the second recomputes the rays of its pixel's inliers
+// with the same arithmetic.
 #include "imloc_device.h"
 #include "imloc_kernels.h"
 
