@@ -83,6 +83,12 @@ def test_host_side_checks_without_device():
     assert L.imloc_server_workspace_bytes(C.byref(cfg)) > 0
     bad = pk.ServerConfig(0, 8, 200000, 64 * 4096, 64 * 200256)
     assert L.imloc_server_workspace_bytes(C.byref(bad)) == 0
+    # mapping depth: the view table plus a 16-byte refinement-queue entry per pixel
+    t1 = L.imloc_triangulate_workspace_bytes(480, 640, 10)
+    assert t1 >= 16 * 480 * 640 + 11 * 16 * 8
+    assert L.imloc_triangulate_workspace_bytes(480, 640, 32) > t1
+    assert L.imloc_triangulate_workspace_bytes(960, 640, 10) > t1
+    assert L.imloc_triangulate_workspace_bytes(0, 640, 10) < t1
 
 
 def test_paper_params():
