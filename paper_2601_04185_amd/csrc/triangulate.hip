@@ -75,16 +75,17 @@ __device__ inline double tri_angle_d(const double b[3], const double r0[3], doub
                                      double* dth) {
   const double a0 = b[0] + l * r0[0], a1 = b[1] + l * r0[1], a2 = b[2] + l * r0[2];
   const double x0 = a1 * r[2] - a2 * r[1], x1 = a2 * r[0] - a0 * r[2], x2 = a0 * r[1] - a1 * r[0];
-  const double S = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+  const double S2 = x0 * x0 + x1 * x1 + x2 * x2;
+  const double S = sqrt(S2);
   const double s = a0 * r[0] + a1 * r[1] + a2 * r[2];
   const double th = atan2(S, s);
   if (dth) {
     const double q = a0 * a0 + a1 * a1 + a2 * a2;
     const double y0 = r0[1] * r[2] - r0[2] * r[1], y1 = r0[2] * r[0] - r0[0] * r[2], y2 = r0[0] * r[1] - r0[1] * r[0];
     const double be = r0[0] * r[0] + r0[1] * r[1] + r0[2] * r[2];
-    if (S > 1e-12 * sqrt(q)) {
-      const double dS = (x0 * y0 + x1 * y1 + x2 * y2) / S;
-      *dth = (s * dS - S * be) / q;
+    if (S2 > 1e-24 * q) {
+      // (s dS/dl - S be) / q with dS/dl = (x . y) / S, over one division
+      *dth = (s * (x0 * y0 + x1 * y1 + x2 * y2) - S2 * be) / (S * q);
     } else {
       *dth = s * sqrt(y0 * y0 + y1 * y1 + y2 * y2) / q;  // the limit where the angle vanishes
     }
