@@ -79,6 +79,7 @@ def lib():
         L.orc_p3p.restype = C.c_int
         L.orc_score.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
         L.orc_score_band.argtypes = [vp, i64, vp, vp, dbl, dbl, i32, vp, vp, vp]
+        L.orc_residual_band.argtypes = [vp, vp, vp, dbl, dbl, i32, vp, vp]
         L.orc_lo.argtypes = [vp, vp, vp, dbl, i32, vp, vp, vp]
         L.orc_lo.restype = C.c_int
         L.orc_refine.argtypes = [vp, vp, vp, dbl, dbl, i32, vp, vp, vp]
@@ -210,6 +211,21 @@ def score_band(poses, corr, K, tau, band_abs=1e-5, with_f32=True):
     lib().orc_score_band(_p(P), P.shape[0], C.byref(h.c), C.byref(cam), float(tau), float(band_abs),
                          1 if with_f32 else 0, _p(lo), _p(hi), _p(eb))
     return lo, hi, eb
+
+
+def residual_band(pose, corr, K, tau, band_abs=1e-5, with_f32=True):
+    """-> (r, beta) per residual at one pose: exact pixel distance (NaN behind
+    the camera or on its plane within float32 resolution) and the ambiguity
+    band that score_band applies (inf where unbounded)."""
+    P = _poses([pose])
+    h = _CorrHold(corr)
+    n = h.c.n
+    r = np.zeros(max(n, 1), np.float64)
+    beta = np.zeros(max(n, 1), np.float64)
+    cam = _cam(K)
+    lib().orc_residual_band(_p(P), C.byref(h.c), C.byref(cam), float(tau), float(band_abs), 1 if with_f32 else 0,
+                            _p(r), _p(beta))
+    return r[:n], beta[:n]
 
 
 def lo(start, corr, K, tau, iters=10):

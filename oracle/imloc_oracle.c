@@ -466,44 +466,108 @@ void orc_score(const orc_pose *poses, int64_t np, const orc_corr *c, const orc_c
   }
 }
 
+/* Ambiguity band of one residual (reading of the float32/float64 question of
+ * the scoring step, Sec. 3.3): a bound on how far the pixel distance that a
+ * float32 evaluation of the test acts on can sit from the exact one.  The
+ * float32 evaluation it bounds: the rows p0 = P0/tau, p1 = P1/tau, p2 = P2 of
+ * P = K [R | t] rounded to float32; a' = p0.X~, b' = p1.X~, w = p2.X~ by three
+ * fused multiply-adds each (X~ = (X, Y, Z, 1) from the float32 inputs);
+ * u' = u * fl(1/tau); du' = a' - u' w and dv' = b' - v' w by one fused
+ * multiply-add each; e' = du'^2 + dv'^2 (a product and a fused multiply-add);
+ * inlier iff e' < w |w|, i.e. iff rho' = sqrt(e' / (w |w|)) < 1.  With unit
+ * roundoff u = 2^-24, g_k = k u / (1 - k u), A = sum_j |P0j X~j|,
+ * B = sum_j |P1j X~j|, W = sum_j |P2j X~j|, the exact depth z = P2.X~ and the
+ * exact distance r = tau rho (standard model of each rounding, no underflow):
+ *   |da'| <= g4 A / tau, |db'| <= g4 B / tau, |dw| <= g4 W = k |z|
+ *   |u' - u/tau| <= g3 |u| / tau                (1/tau, product, double)
+ *   |du' - du| <= (1 + u) Pa / tau + u |du|, Pa = g4 A + g3 |u| (|z| + g4 W) + g4 |u| W
+ * (likewise dv' with B, v, Pb).  The vector (du', dv') then moves
+ * sqrt(du^2 + dv^2) by at most (1 + u) hypot(Pa, Pb) / tau + u rho |z|; 1/|w|
+ * moves by at most k / (1 - k) relative; the roundings of e' and w |w| scale
+ * rho' by a factor within 1.5 u' of 1 (u' = 1.001 u).  Collecting,
+ *   |rho' tau - r| <= beta = (1.5 u' r + ((1 + u) hypot(Pa, Pb) / |z| + u r
+ *                             + k r) / (1 - k)) / (1 - 1.5 u'),
+ * taken at the residual's own r, so the float32 decision equals the exact one
+ * whenever |r - tau| >= beta.  The sign of w is right when |z| > g4 W; a point
+ * with |z| <= 8 u W is ambiguous (it may be either). */
+static void residual_band(const double P[3][4], const orc_pose *pose, const orc_camera *K, const double Xt[4],
+                          double u, double v, double tau, double band_abs, int32_t with_f32, double *r,
+                          double *beta, int *behind) {
+  const double uq = ldexp(1.0, -24), uq1 = 1.001 * uq;
+  const double g3 = 3.0 * uq / (1.0 - 3.0 * uq), g4 = 4.0 * uq / (1.0 - 4.0 * uq);
+  double xc[3];
+  transform(pose, Xt, xc);
+  double A = 0, B = 0, W = 0;
+  for (int k = 0; k < 4; ++k) { A += fabs(P[0][k] * Xt[k]); B += fabs(P[1][k] * Xt[k]); W += fabs(P[2][k] * Xt[k]); }
+  const double z = xc[2];
+  const double wsign_err = with_f32 ? 8.0 * uq * W : 0.0;
+  *r = NAN;
+  *beta = INFINITY;
+  if (!(z > wsign_err)) {
+    /* behind the camera (1), or (float32) possibly on either side of its
+     * plane (2); a NaN depth is behind */
+    *behind = z > -wsign_err ? 2 : 1;
+    return;
+  }
+  *behind = 0;
+  const double px = K->fx * xc[0] / z + K->cx, py = K->fy * xc[1] / z + K->cy;
+  const double d = sqrt((px - u) * (px - u) + (py - v) * (py - v));
+  double b = band_abs;
+  if (with_f32) {
+    const double k = g4 * W / z;
+    const double Pa = g4 * A + g3 * fabs(u) * (z + g4 * W) + g4 * fabs(u) * W;
+    const double Pb = g4 * B + g3 * fabs(v) * (z + g4 * W) + g4 * fabs(v) * W;
+    const double b32 = (1.5 * uq1 * d + ((1.0 + uq) * hypot(Pa, Pb) / z + uq * d + k * d) / (1.0 - k)) /
+                       (1.0 - 1.5 * uq1);
+    if (b32 > b) b = b32;
+  }
+  *r = d;
+  *beta = b;
+}
+
+/* rows of K [R | t] */
+static void proj_rows(const orc_pose *pose, const orc_camera *K, double P[3][4]) {
+  const double *R = pose->R, *t = pose->t;
+  for (int k = 0; k < 3; ++k) {
+    P[0][k] = K->fx * R[k] + K->cx * R[6 + k];
+    P[1][k] = K->fy * R[3 + k] + K->cy * R[6 + k];
+    P[2][k] = R[6 + k];
+  }
+  P[0][3] = K->fx * t[0] + K->cx * t[2];
+  P[1][3] = K->fy * t[1] + K->cy * t[2];
+  P[2][3] = t[2];
+}
+
+void orc_residual_band(const orc_pose *pose, const orc_corr *c, const orc_camera *K, double tau, double band_abs,
+                       int32_t with_f32, double *r, double *beta) {
+  double P[3][4];
+  proj_rows(pose, K, P);
+  for (int64_t i = 0; i < c->n; ++i) {
+    const double Xt[4] = {c->X[i], c->Y[i], c->Z[i], 1.0};
+    int behind;
+    residual_band(P, pose, K, Xt, c->u[i], c->v[i], tau, band_abs, with_f32, &r[i], &beta[i], &behind);
+  }
+}
+
 void orc_score_band(const orc_pose *poses, int64_t np, const orc_corr *c, const orc_camera *K,
                     double tau, double band_abs, int32_t with_f32,
                     int32_t *count_lo, int32_t *count_hi, double *msac_err_bound) {
-  const double u32 = ldexp(1.0, -24);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t p = 0; p < np; ++p) {
-    const double *R = poses[p].R, *t = poses[p].t;
-    /* rows of K [R | t] */
     double P[3][4];
-    for (int k = 0; k < 3; ++k) {
-      P[0][k] = K->fx * R[k] + K->cx * R[6 + k];
-      P[1][k] = K->fy * R[3 + k] + K->cy * R[6 + k];
-      P[2][k] = R[6 + k];
-    }
-    P[0][3] = K->fx * t[0] + K->cx * t[2];
-    P[1][3] = K->fy * t[1] + K->cy * t[2];
-    P[2][3] = t[2];
+    proj_rows(&poses[p], K, P);
     int32_t lo = 0, hi = 0;
     double errb = 0.0;
     for (int64_t i = 0; i < c->n; ++i) {
-      double Xt[4] = {c->X[i], c->Y[i], c->Z[i], 1.0}, xc[3];
-      transform(&poses[p], Xt, xc);
-      double A = 0, B = 0, W = 0;
-      for (int k = 0; k < 4; ++k) { A += fabs(P[0][k] * Xt[k]); B += fabs(P[1][k] * Xt[k]); W += fabs(P[2][k] * Xt[k]); }
-      double u = c->u[i], v = c->v[i], z = xc[2], w = corr_w(c, i);
-      double wsign_err = with_f32 ? 8.0 * u32 * W : 0.0;
-      if (!(z > wsign_err)) {
-        /* behind (or, in float32, possibly on either side of) the camera plane */
-        if (z > -wsign_err) { ++hi; errb += w * tau * tau; }
+      const double Xt[4] = {c->X[i], c->Y[i], c->Z[i], 1.0};
+      const double w = corr_w(c, i);
+      double r, beta;
+      int behind;
+      residual_band(P, &poses[p], K, Xt, c->u[i], c->v[i], tau, band_abs, with_f32, &r, &beta, &behind);
+      if (behind) {
+        if (behind == 2) { ++hi; errb += w * tau * tau; }
         continue;
       }
-      double beta = band_abs;
-      if (with_f32) {
-        double b32 = 16.0 * u32 * ((A + B + (fabs(u) + fabs(v) + tau) * W) / fabs(z) + tau);
-        if (b32 > beta) beta = b32;
-      }
-      double px = K->fx * xc[0] / z + K->cx, py = K->fy * xc[1] / z + K->cy;
-      double r = sqrt((px - u) * (px - u) + (py - v) * (py - v));
       if (r < tau - beta) ++lo;
       if (r < tau + beta) ++hi;
       if (r < tau + beta) errb += w * (2.0 * fmin(r + beta, tau + beta) * beta + beta * beta);

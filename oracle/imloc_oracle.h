@@ -97,10 +97,18 @@ void orc_score(const orc_pose *poses, int64_t np, const orc_corr *c,
  * inside tau - b_i, count_hi those inside tau + b_i, where
  * b_i = max(band_abs, f32_bound_i) and f32_bound_i (used when with_f32 != 0)
  * bounds the error of evaluating the residual in float32 from a float32-rounded
- * projection matrix. */
+ * projection matrix (derivation at residual_band in imloc_oracle.c; a point
+ * too close to the camera plane to sign its depth in float32 counts in
+ * count_hi only). */
 void orc_score_band(const orc_pose *poses, int64_t np, const orc_corr *c,
                     const orc_camera *K, double tau, double band_abs, int32_t with_f32,
                     int32_t *count_lo, int32_t *count_hi, double *msac_err_bound);
+
+/* Per residual of one pose: the exact pixel distance r_i (NaN when the point is
+ * behind the camera or, with with_f32, too close to its plane to sign the depth
+ * in float32) and its band b_i as used by orc_score_band. */
+void orc_residual_band(const orc_pose *pose, const orc_corr *c, const orc_camera *K, double tau, double band_abs,
+                       int32_t with_f32, double *r, double *beta);
 
 /* Truncated cost at a pose and the Gauss-Newton normal equations over its
  * inliers: H = sum_i w_i J_i^T J_i, g = sum_i w_i J_i^T r_i, with J_i the
