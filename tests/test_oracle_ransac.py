@@ -116,3 +116,69 @@ def test_too_few_points(orc, n):
     corr["w"] = None
     res = orc.lo_ransac_pnp(corr, (500, 500, 320, 240), fixed_samples=16)
     assert res["status"] == 1 and np.array_equal(res["R"], np.eye(3)) and not res["t"].any()
+
+
+def _stagewise_lo_ransac(orc, corr, K, tau, total, batch, k, lo_iters):
+    """LO-RANSAC in exhaustive mode written from the oracle's stage functions
+    only (unranked triples, P3P, scoring, LO), with the batched trigger of the
+    local optimisation read from Sec. 3.3 "Pose Estimation" (refine when a
+    hypothesis beats the best so far): per batch, the k candidates of lowest
+    (MSAC, -count, h, j) among those whose pre-LO MSAC is below the running
+    best post-LO cost; a refined cost strictly below the running best replaces
+    it.  Returns the driver's statistics and the per-batch chosen keys."""
+    n = len(corr["u"])
+    best_cost, best_count, best_hj, lo_runs, gated_out, chosen_all = math.inf, 0, (-1, -1), 0, 0, []
+    for b0 in range(0, total, batch):
+        cands = []
+        for h in range(b0, min(total, b0 + batch)):
+            ok, idx = orc.unrank_triple(h, n)
+            assert ok
+            uv = np.stack([corr["u"][idx], corr["v"][idx]], 1).astype(np.float64)
+            Xw = np.stack([corr["X"][idx], corr["Y"][idx], corr["Z"][idx]], 1).astype(np.float64)
+            sols, _ = orc.p3p(uv, Xw, K)
+            cands += [(h, j, R, t) for j, (R, t) in enumerate(sols)]
+        if not cands:
+            continue
+        cnt, ms = orc.score([(c[2], c[3]) for c in cands], corr, K, tau)
+        keys = sorted(range(len(cands)), key=lambda a: (ms[a], -cnt[a], cands[a][0], cands[a][1]))
+        eligible = [a for a in keys if ms[a] < best_cost]
+        gated_out += len(keys) - len(eligible)
+        chosen = eligible[:k]
+        chosen_all.append([(cands[a][0], cands[a][1], float(ms[a]), int(cnt[a])) for a in chosen])
+        for a in chosen:
+            _, _, cost, count, _ = orc.lo((cands[a][2], cands[a][3]), corr, K, tau, iters=lo_iters)
+            lo_runs += 1
+            if cost < best_cost:
+                best_cost, best_count, best_hj = cost, count, (cands[a][0], cands[a][1])
+    return dict(best_msac=best_cost, best_count=best_count, best_hj=best_hj, lo_runs=lo_runs,
+                gated_out=gated_out, chosen=chosen_all)
+
+
+def test_multibatch_topk_gate_matches_stagewise_loop(orc):
+    """The driver's per-batch top-k gate (k = 3, ten Gauss-Newton iterations,
+    five batches over every triple of 18 points) equals the stage-wise loop
+    above.  Points 1 and 3 are exact copies of points 0 and 2, so distinct
+    triples give bitwise-equal candidates and the (h, j) tie order is
+    exercised."""
+    q = synth.make_query(77, 16, 0.5, 1.0)
+    a, b = (int(i) for i in np.flatnonzero(q.is_inlier)[:2])
+    rest = [i for i in range(16) if i not in (a, b)]
+    order = [a, a, b, b] + rest  # points 1 and 3 copy points 0 and 2
+    corr = {c: getattr(q, c)[order].astype(np.float32) for c in ("u", "v", "X", "Y", "Z")}
+    corr["w"] = None
+    n = 18
+    total, batch, k, tau = math.comb(n, 3), 200, 3, 4.0
+    ref = _stagewise_lo_ransac(orc, corr, q.K, tau, total, batch, k, 10)
+    res = orc.lo_ransac_pnp(corr, q.K, threshold_px=tau, fixed_samples=total, batch=batch, exhaustive=1,
+                            lo_top_k=k, lo_iters=10, final_iters=0)
+    assert res["status"] == 0 and res["batches"] == 5
+    assert (res["best_h"], res["best_j"]) == ref["best_hj"]
+    assert res["lo_runs"] == ref["lo_runs"]
+    assert res["best_msac"] == ref["best_msac"] and res["best_count"] == ref["best_count"]
+    # the pin is sensitive to the gate and to k: later batches lose candidates to
+    # the gate, the first one refines k of them, and an ungated driver would
+    # refine k per batch
+    assert ref["gated_out"] > 0 and len(ref["chosen"][0]) == k and ref["lo_runs"] < 5 * k
+    # some chosen keys tie in (MSAC, count) and are ordered by (h, j)
+    ties = [(a, b) for ch in ref["chosen"] for a in ch for b in ch if a < b and a[2:] == b[2:]]
+    assert ties
