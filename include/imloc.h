@@ -21,8 +21,12 @@
  * memory.  The library never frees or keeps a caller pointer beyond the call.
  * Scratch memory comes from a caller-provided workspace
  * (imloc_set_workspace); the library itself allocates no device memory after
- * imloc_create.  Work is enqueued on the context's stream; calls that return
- * host results synchronise that stream before returning.
+ * imloc_create.  Host staging (pinned memory for query tables and results)
+ * is allocated by imloc_create and imloc_set_staging only: a call that needs
+ * more staging returns IMLOC_ENOMEM instead of growing it, and timing events
+ * are created by imloc_set_timing, so the query calls allocate nothing.
+ * Work is enqueued on the context's stream; calls that return host results
+ * synchronise that stream before returning.
  *
  * Errors: functions return IMLOC_OK (0), IMLOC_NO_POSE (1, the call ran but
  * no pose candidate exists), or a negative code; imloc_last_error() gives a
@@ -42,7 +46,7 @@ extern "C" {
 #define IMLOC_NO_POSE 1
 #define IMLOC_PENDING 2     /* imloc_server_poll: the query has not finished yet */
 #define IMLOC_EINVAL (-1)   /* bad argument (null pointer, size, threshold, intrinsics) */
-#define IMLOC_ENOMEM (-2)   /* workspace too small: see imloc_workspace_bytes */
+#define IMLOC_ENOMEM (-2)   /* workspace or host staging too small: see imloc_workspace_bytes, imloc_staging_bytes */
 #define IMLOC_EHIP (-3)     /* HIP runtime error */
 
 #define IMLOC_FP32_SCORE 0  /* scoring in float32; P3P, local optimisation, refinement in float64 */
@@ -106,7 +110,10 @@ typedef struct {
   int64_t best_h;            /* sample the best model grew from */
   int32_t best_j;            /* its P3P solution index */
   int32_t score_launches;    /* scoring kernel launches (for per-launch timing) */
-  float ms_sample, ms_score, ms_select, ms_lo, ms_refine, ms_total;  /* device time, if timing is on */
+  /* device time in ms, if timing is on: sampling + P3P + the scoring work
+   * list, the scoring kernel alone, selection, local optimisation with the
+   * round's end, final refinement with the mask, and the whole call */
+  float ms_sample, ms_score, ms_select, ms_lo, ms_refine, ms_total;
 } imloc_stats;
 
 /* Fill *p with the LO-RANSAC settings of Sec. 3.3 "Pose Estimation": batches
@@ -133,6 +140,20 @@ const char *imloc_last_error(const imloc_ctx *ctx);
  * must stay valid while calls that use it are in flight). */
 int imloc_set_workspace(imloc_ctx *ctx, void *device_ptr, size_t bytes);
 
+/* Host staging.  imloc_create gives every context 1 MiB of pinned staging,
+ * enough for a batch of about 1,400 queries; imloc_staging_bytes(nq, c) is
+ * what a batch of nq queries with c rig cameras in total (0 without rigs)
+ * needs (never less than the default), and imloc_set_staging replaces the
+ * context's staging by `bytes` of pinned host memory (it waits for the
+ * context's stream first and drops a captured graph that used the old
+ * buffer; a server created on the context must not be stepping).
+ * imloc_get_staging reports the current size.  A call whose tables do not
+ * fit returns IMLOC_ENOMEM and names the size needed.  imloc_set_staging
+ * returns IMLOC_EINVAL above 4 GiB and IMLOC_EHIP if the allocation fails. */
+size_t imloc_staging_bytes(int32_t n_queries, int32_t n_rig_cameras);
+int imloc_set_staging(imloc_ctx *ctx, size_t bytes);
+size_t imloc_get_staging(const imloc_ctx *ctx);
+
 /* Workspace bytes imloc_lo_ransac_pnp needs for up to n correspondences. */
 size_t imloc_workspace_bytes(int64_t n, const imloc_ransac_params *p);
 
@@ -151,7 +172,10 @@ size_t imloc_lo_workspace_bytes(int64_t n, int32_t np);
 size_t imloc_refine_workspace_bytes(int64_t n);
 size_t imloc_lift_workspace_bytes(int64_t n_matches, int32_t n_views);
 
-/* 1: record per-stage device time with HIP events into imloc_stats. */
+/* 1: record per-stage device time with HIP events into imloc_stats (the
+ * first call with 1 creates the context's pool of 256 events; when a call
+ * needs more spans than the pool holds, the stream is synchronised and the
+ * pool reused, so timing perturbs long adaptive runs slightly). */
 int imloc_set_timing(imloc_ctx *ctx, int enable);
 
 /* 1: run batches with a fixed sample count as one captured hipGraph, replayed

@@ -117,6 +117,8 @@ def lib():
         L.orc_normal_equations.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
         L.orc_normal_equations.restype = dbl
         L.orc_pose_update.argtypes = [vp, vp, vp]
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_max_threads.restype = i32
         _lib = L
     return _lib
 
@@ -291,6 +293,15 @@ def make_params(**kw) -> Params:
                   int(d["max_iters"]), float(d["confidence"]), int(d["lo_top_k"]), int(d["lo_iters"]),
                   int(d["max_score_points"]), int(d["final_iters"]), float(d["cauchy_scale_px"]),
                   int(d["exhaustive"]), int(d["seed"]), int(d["query_id"]))
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def lo_ransac_pnp(corr, K, **params):

@@ -27,6 +27,7 @@
 
 #include <float.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -1002,3 +1003,7 @@ int64_t orc_lift_log8(const float *q_u, const float *q_v, const float *db_u, con
   return lift_maps(q_u, q_v, db_u, db_v, conf, view, n_matches, subpixel, NULL, codes, n_views, H, W, cams, poses,
                    min_conf, out_u, out_v, out_X, out_Y, out_Z, out_w, out_src);
 }
+
+void orc_set_threads(int32_t n) { omp_set_num_threads(n >= 1 ? n : 1); }
+
+int32_t orc_max_threads(void) { return (int32_t)omp_get_max_threads(); }

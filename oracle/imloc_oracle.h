@@ -226,6 +226,12 @@ int orc_rig_refine(const orc_pose *start, const orc_rig_corr *c, const orc_rig_c
 int orc_rig_lo_ransac(const orc_rig_corr *c, const orc_rig_camera *cams, int32_t n_cams, const orc_params *p,
                       orc_pose *pose, uint8_t *mask, orc_stats *st);
 
+/* Host threads of the OpenMP loops (independent candidates only, so the
+ * results do not depend on it): orc_set_threads(n) for n >= 1, and the
+ * number the next parallel loop will use. */
+void orc_set_threads(int32_t n);
+int32_t orc_max_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,7 +39,7 @@ EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_err
             "imloc_rig_stage_workspace_bytes", "imloc_rig_sample_gp3p", "imloc_rig_score",
             "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score", "imloc_select_top_k",
             "imloc_local_optimize", "imloc_refine", "imloc_paper_params",
-            "imloc_set_gn_mode"]
+            "imloc_set_gn_mode", "imloc_staging_bytes", "imloc_set_staging", "imloc_get_staging"]
 
 
 class ImlocError(RuntimeError):
@@ -129,6 +129,9 @@ def lib():
             "imloc_set_timing": ([vp, C.c_int], C.c_int),
             "imloc_paper_params": ([dbl, vp], C.c_int),
             "imloc_set_gn_mode": ([vp, i32], C.c_int),
+            "imloc_staging_bytes": ([i32, i32], C.c_size_t),
+            "imloc_set_staging": ([vp, C.c_size_t], C.c_int),
+            "imloc_get_staging": ([vp], C.c_size_t),
             "imloc_lift": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_lift_log8": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_depth_encode_log8": ([vp, vp, i64, vp], C.c_int),
@@ -243,6 +246,13 @@ class Context:
         self.check(lib().imloc_get_score_tuning(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def ensure_staging(self, n_queries: int, n_rig_cameras: int = 0):
+        """Grow the context's pinned host staging (a setup call, outside the
+        query calls) so that a batch of n_queries fits."""
+        need = lib().imloc_staging_bytes(int(n_queries), int(n_rig_cameras))
+        if lib().imloc_get_staging(self.h) < need:
+            self.check(lib().imloc_set_staging(self.h, need))
+
     def ensure_workspace(self, nbytes: int):
         if self.ws is None or self.ws.numel() < nbytes:
             self.ws = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=f"cuda:{self.device}")
@@ -281,6 +291,7 @@ def imloc_lo_ransac_pnp_batch(ctx: Context, corrs: list, Ks: list, params, masks
     plist = params if isinstance(params, (list, tuple)) else [params]
     pa = (RansacParams * len(plist))(*plist)
     ctx.ensure_workspace(lib().imloc_batch_workspace_bytes(nq, ns, pa, len(plist)))
+    ctx.ensure_staging(nq)
     poses = (Pose * nq)()
     stats = (Stats * nq)()
     status = (C.c_int32 * nq)()
@@ -567,6 +578,7 @@ class Server:
         if nbytes == 0:
             raise ImlocError("bad server configuration")
         self.ctx.ensure_workspace(nbytes)
+        self.ctx.ensure_staging(max_slots)
         h = C.c_void_p()
         self.ctx.check(lib().imloc_server_create(self.ctx.h, C.byref(self.cfg), C.byref(h)))
         self.h = h

@@ -32,8 +32,16 @@ struct imloc_ctx {
   size_t ws_bytes = 0;
   bool timing = false;
   std::string err;
-  char* pinned = nullptr;  // host staging: query table in, states and poses out
+  // Host staging (pinned): query tables and view tables in, states and poses
+  // out.  Allocated by imloc_create / imloc_set_staging only; a call that
+  // needs more returns IMLOC_ENOMEM.  `staging_ev` is recorded after the last
+  // asynchronous copy that uses it, so the host waits for that copy (and only
+  // that) before writing the buffer again.
+  char* pinned = nullptr;
   size_t pinned_bytes = 0;
+  hipEvent_t staging_ev = nullptr;
+  bool staging_pending = false;
+  // timing events, created when timing is switched on (imloc_set_timing)
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
   ScoreTune tune{0, 2048};  // ct == 0: the candidate tile is picked per round (round_tune)
@@ -42,7 +50,6 @@ struct imloc_ctx {
   // hipGraph replay of the fixed-sample pipeline
   bool graphs = false;
   hipStream_t gstream = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::string gkey;
@@ -283,9 +290,35 @@ void carve_engine(Arena& a, Engine& e) {
   e.subset = a.take<float>((size_t)std::max<int64_t>(e.subset_off.back(), 1));
 }
 
-bool ensure_pinned(imloc_ctx* c, size_t bytes) {
-  if (bytes <= c->pinned_bytes) return true;
-  if (c->gexec) {  // a captured graph copies from / to the old staging buffer
+// Host staging of the context: at least `bytes` of it, else an error naming
+// the size to pass to imloc_set_staging.  Nothing is allocated here.
+int staging_check(imloc_ctx* c, size_t bytes) {
+  if (bytes <= c->pinned_bytes) return IMLOC_OK;
+  return set_err(c, IMLOC_ENOMEM, "host staging too small: need %zu bytes, have %zu (imloc_set_staging)", bytes,
+                 c->pinned_bytes);
+}
+
+// Wait until no queued copy reads or writes the staging buffer.
+int staging_wait(imloc_ctx* c) {
+  if (!c->staging_pending) return IMLOC_OK;
+  HIP_TRY(c, hipEventSynchronize(c->staging_ev));
+  c->staging_pending = false;
+  return IMLOC_OK;
+}
+
+// After enqueueing copies that use the staging buffer on the context stream.
+int staging_mark(imloc_ctx* c) {
+  HIP_TRY(c, hipEventRecord(c->staging_ev, c->stream));
+  c->staging_pending = true;
+  return IMLOC_OK;
+}
+
+// Replace the staging buffer (setup calls only): waits for the stream, drops
+// a captured graph that copies from or to the old buffer.
+int staging_alloc(imloc_ctx* c, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 4096);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->gexec) {
     if (c->gstream) hipStreamSynchronize(c->gstream);
     hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
@@ -296,47 +329,68 @@ bool ensure_pinned(imloc_ctx* c, size_t bytes) {
   if (c->pinned) hipHostFree(c->pinned);
   c->pinned = nullptr;
   c->pinned_bytes = 0;
-  size_t sz = std::max<size_t>(bytes, 4096);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), sz, hipHostMallocDefault) != hipSuccess) return false;
-  c->pinned_bytes = sz;
-  return true;
+  c->staging_pending = false;
+  HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->pinned), bytes, hipHostMallocDefault));
+  c->pinned_bytes = bytes;
+  return IMLOC_OK;
 }
 
-hipEvent_t take_event(imloc_ctx* c) {
-  if (c->next_event == c->events.size()) {
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    c->events.push_back(e);
-  }
-  return c->events[c->next_event++];
-}
+constexpr size_t kDefaultStaging = size_t(1) << 20;
+constexpr size_t kTimingEvents = 256;  // events of the timing pool (reused within a call)
 
-// Per-stage timing with HIP events on the context stream.
+// Per-stage timing with HIP events on the context stream.  The events come
+// from the pool created by imloc_set_timing; event 0 opens the whole call,
+// the stage spans use the rest, and when the pool runs out the stream is
+// synchronised, the closed spans are added up and the pool is reused.
 struct Timer {
   imloc_ctx* c;
   struct Span { int stage; hipEvent_t a, b; };
   std::vector<Span> spans;
-  explicit Timer(imloc_ctx* cc) : c(cc) { c->next_event = 0; }
-  hipEvent_t begin() {
-    if (!c->timing) return nullptr;
-    hipEvent_t e = take_event(c);
-    if (e) hipEventRecord(e, c->stream);
-    return e;
+  float acc[6] = {0, 0, 0, 0, 0, 0};
+  bool on;
+  explicit Timer(imloc_ctx* cc) : c(cc), on(cc->timing && cc->events.size() == kTimingEvents) {
+    c->next_event = 1;
   }
-  void end(int stage, hipEvent_t a) {
-    if (!c->timing || !a) return;
-    hipEvent_t e = take_event(c);
-    if (!e) return;
-    hipEventRecord(e, c->stream);
-    spans.push_back({stage, a, e});
-  }
-  void fill(imloc_stats* st) {
-    if (!c->timing || !st) return;
-    float acc[6] = {0, 0, 0, 0, 0, 0};
+  void fold() {
+    hipStreamSynchronize(c->stream);
     for (auto& s : spans) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, s.a, s.b) == hipSuccess) acc[s.stage] += ms;
     }
+    spans.clear();
+    c->next_event = 1;
+  }
+  hipEvent_t total_begin() {
+    if (!on) return nullptr;
+    hipEventRecord(c->events[0], c->stream);
+    return c->events[0];
+  }
+  void total_end(hipEvent_t a) {  // the last event of the pool closes the whole call
+    if (!on || !a) return;
+    hipEvent_t e = c->events[kTimingEvents - 1];
+    hipEventRecord(e, c->stream);
+    spans.push_back({5, a, e});
+  }
+  hipEvent_t begin() {
+    if (!on) return nullptr;
+    if (c->next_event + 2 > kTimingEvents - 1) fold();
+    hipEvent_t e = c->events[c->next_event++];
+    hipEventRecord(e, c->stream);
+    return e;
+  }
+  void end(int stage, hipEvent_t a) {
+    if (!on || !a) return;
+    hipEvent_t e = c->events[c->next_event++];
+    hipEventRecord(e, c->stream);
+    spans.push_back({stage, a, e});
+  }
+  void fill(imloc_stats* st) {
+    if (!on || !st) return;
+    for (auto& s : spans) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, s.a, s.b) == hipSuccess) acc[s.stage] += ms;
+    }
+    spans.clear();
     st->ms_sample = acc[0]; st->ms_score = acc[1]; st->ms_select = acc[2];
     st->ms_lo = acc[3]; st->ms_refine = acc[4]; st->ms_total = acc[5];
   }
@@ -413,10 +467,18 @@ void fill_rig_tables(double* h, int nq, const RigHost* rigs, const Engine& e) {
   }
 }
 
+// Device scratch of a call: the context's workspace, or the library's
+// fixed array for the allocation-free entry point.
+struct Scratch {
+  char* base;
+  size_t bytes;
+};
+
 // Validate, plan, carve and run a batch.  Outputs are host arrays of nq.
+// `ws` is the device scratch; `may_capture` allows the captured-graph form.
 int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, const imloc_camera* K,
               const imloc_ransac_params* params, int n_params, imloc_pose* poses, uint8_t* const* masks,
-              imloc_stats* stats, int32_t* status, const RigHost* rigs = nullptr) {
+              imloc_stats* stats, int32_t* status, const RigHost* rigs, Scratch ws, bool may_capture) {
   std::vector<const imloc_ransac_params*> pp(nq);
   std::vector<QPlan> pl(nq);
   for (int q = 0; q < nq; ++q) {
@@ -438,13 +500,16 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
   hipStream_t s = ctx->stream;
   Engine e;
   plan_engine(e, nq, pl.data(), pp.data());
-  Arena a{ctx->ws, ctx->ws_bytes};
+  Arena a{ws.base, ws.bytes};
   carve_engine(a, e);
-  if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes, have %zu", a.off, ctx->ws_bytes);
+  if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small: need %zu bytes, have %zu", a.off, ws.bytes);
   const size_t tab = (size_t)nq * sizeof(QueryDesc);
   const size_t outb = (size_t)nq * sizeof(BestState) + (size_t)nq * 13 * sizeof(double) + 64;
   const size_t rigb = (size_t)e.rig_doubles * sizeof(double);
-  if (!ensure_pinned(ctx, tab + outb + 512 + rigb)) return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
+  int rc0 = staging_check(ctx, tab + outb + 512 + rigb);
+  if (rc0) return rc0;
+  rc0 = staging_wait(ctx);  // an earlier asynchronous call may still copy from the staging buffer
+  if (rc0) return rc0;
   QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
   for (int q = 0; q < nq; ++q)
     htab[q] = make_desc(&pts[q], n[q], rigs && rigs[q].ncam > 0 ? nullptr : &K[q], pp[q], pl[q], e, q,
@@ -468,7 +533,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
   // rounds, final refinement, mask, readback into pinned memory.  `sync`
   // lets adaptive batches read the active count after every round.
   auto enqueue = [&](hipStream_t st_, bool sync) -> int {
-    hipEvent_t ev_total = tm.begin();
+    hipEvent_t ev_total = tm.total_begin();
     HIP_TRY(ctx, hipMemcpyAsync(e.qd, htab, tab, hipMemcpyHostToDevice, st_));
     if (rigb) HIP_TRY(ctx, hipMemcpyAsync(e.rig, hrig, rigb, hipMemcpyHostToDevice, st_));
     HIP_TRY(ctx, launch_gather_subsets(e.qd, nq, max_m_sub, st_));
@@ -478,9 +543,9 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       hipEvent_t e0 = tm.begin();
       if (e.any_single) HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
       if (e.any_rig) HIP_TRY(ctx, launch_sample_gp3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
-      tm.end(kStSample, e0);
-      hipEvent_t e1 = tm.begin();
       HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, tune.ct, e.item_off, st_));
+      tm.end(kStSample, e0);
+      hipEvent_t e1 = tm.begin();  // the scoring span holds the scoring kernel alone
       HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, tune, 0, st_));
       tm.end(kStScore, e1);
       hipEvent_t e2 = tm.begin();
@@ -505,27 +570,22 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
                                e.fin_cost, e.any_rig, ctx->gn_mode, true, &mask_done, st_));
     if (!mask_done) HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, e.max_n, 0, st_));
     tm.end(kStRefine, e4);
-    tm.end(kStTotal, ev_total);
+    tm.total_end(ev_total);
     HIP_TRY(ctx, hipMemcpyAsync(hst, e.st, result_bytes(nq), hipMemcpyDeviceToHost, st_));
     return IMLOC_OK;
   };
 
-  if (ctx->graphs && e.all_fixed && !ctx->timing) {
+  if (may_capture && ctx->graphs && ctx->gstream && e.all_fixed && !ctx->timing) {
     // key of everything a captured graph bakes in: shapes, workspace, staging
     std::string key;
     char buf[160];
-    snprintf(buf, sizeof(buf), "%d|%p|%p|%d|%d|%d|%d|%d|", nq, (void*)ctx->ws, (void*)ctx->pinned, tune.ct,
+    snprintf(buf, sizeof(buf), "%d|%p|%p|%d|%d|%d|%d|%d|", nq, (void*)ws.base, (void*)ctx->pinned, tune.ct,
              tune.blocks, e.lo_iters, e.fin_iters, ctx->gn_mode);
     key += buf;
     for (int q = 0; q < nq; ++q) {
       snprintf(buf, sizeof(buf), "%lld,%lld,%d,%lld,%lld,%d,%d;", (long long)pl[q].n, (long long)pl[q].m,
                (int)pl[q].subset, (long long)pl[q].total, (long long)pl[q].batch, pl[q].k, pl[q].ncam);
       key += buf;
-    }
-    if (!ctx->gstream) {
-      HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
-      HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
-      HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
     }
     if (key != ctx->gkey || !ctx->gexec) {
       if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
@@ -644,9 +704,10 @@ size_t stage_bytes(StageQuery& sq, int nprob_lo) {
 int stage_upload(imloc_ctx* ctx, StageQuery& sq, const imloc_corr* pts, int64_t n, const imloc_camera* K,
                  int64_t B, int64_t drawn, uint8_t* mask, const RigHost* rig = nullptr) {
   const size_t rig_at = 256 * ((sizeof(QueryDesc) + sizeof(BestState) + 512 + 255) / 256);
-  if (!ensure_pinned(ctx, rig_at + (size_t)sq.e.rig_doubles * sizeof(double)))
-    return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the staging buffer may still feed an earlier copy
+  int rc = staging_check(ctx, rig_at + (size_t)sq.e.rig_doubles * sizeof(double));
+  if (rc) return rc;
+  rc = staging_wait(ctx);  // the staging buffer may still feed an earlier copy
+  if (rc) return rc;
   QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
   htab[0] = make_desc(pts, n, K, &sq.p, sq.pl, sq.e, 0, mask, rig);
   htab[0].B = B;
@@ -665,9 +726,8 @@ int stage_upload(imloc_ctx* ctx, StageQuery& sq, const imloc_corr* pts, int64_t 
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     hb->drawn = drawn;
     HIP_TRY(ctx, hipMemcpyAsync(sq.e.st, hb, sizeof(BestState), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   }
-  return IMLOC_OK;
+  return staging_mark(ctx);
 }
 
 }  // namespace
@@ -683,8 +743,9 @@ int imloc_create(imloc_ctx** out, int device, void* hip_stream) {
   imloc_ctx* c = new imloc_ctx();
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  if (!ensure_pinned(c, 64 * 1024)) {
-    delete c;
+  if (hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess ||
+      staging_alloc(c, kDefaultStaging) != IMLOC_OK) {
+    imloc_destroy(c);
     return IMLOC_EHIP;
   }
   int cus = 256;
@@ -703,8 +764,7 @@ void imloc_destroy(imloc_ctx* c) {
   for (auto e : c->events) hipEventDestroy(e);
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->graph) hipGraphDestroy(c->graph);
-  if (c->ev_in) hipEventDestroy(c->ev_in);
-  if (c->ev_out) hipEventDestroy(c->ev_out);
+  if (c->staging_ev) hipEventDestroy(c->staging_ev);
   if (c->gstream) {
     hipStreamSynchronize(c->gstream);
     hipStreamDestroy(c->gstream);
@@ -731,15 +791,44 @@ int imloc_set_workspace(imloc_ctx* c, void* p, size_t bytes) {
 
 int imloc_set_timing(imloc_ctx* c, int enable) {
   if (!c) return IMLOC_EINVAL;
+  if (enable && c->events.size() < kTimingEvents) {
+    hipSetDevice(c->device);
+    while (c->events.size() < kTimingEvents) {
+      hipEvent_t e;
+      HIP_TRY(c, hipEventCreate(&e));
+      c->events.push_back(e);
+    }
+  }
   c->timing = enable != 0;
   return IMLOC_OK;
 }
 
 int imloc_set_graphs(imloc_ctx* c, int enable) {
   if (!c) return IMLOC_EINVAL;
+  if (enable && !c->gstream) {  // the capture stream
+    hipSetDevice(c->device);
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+  }
   c->graphs = enable != 0;
   return IMLOC_OK;
 }
+
+size_t imloc_staging_bytes(int32_t n_queries, int32_t n_rig_cameras) {
+  const size_t nq = n_queries > 0 ? (size_t)n_queries : 0;
+  const size_t nc = n_rig_cameras > 0 ? (size_t)n_rig_cameras : 0;
+  const size_t batch = nq * (sizeof(QueryDesc) + sizeof(BestState) + 13 * sizeof(double)) + 64 + 512 +
+                       nc * 16 * sizeof(double);
+  return std::max(batch, kDefaultStaging);
+}
+
+int imloc_set_staging(imloc_ctx* c, size_t bytes) {
+  if (!c) return IMLOC_EINVAL;
+  if (bytes > (size_t(1) << 32)) return set_err(c, IMLOC_EINVAL, "staging above 4 GiB");
+  hipSetDevice(c->device);
+  return staging_alloc(c, bytes);
+}
+
+size_t imloc_get_staging(const imloc_ctx* c) { return c ? c->pinned_bytes : 0; }
 
 int imloc_graph_counters(const imloc_ctx* c, int64_t* captures, int64_t* launches) {
   if (!c || !captures || !launches) return IMLOC_EINVAL;
@@ -880,8 +969,10 @@ static int lift_impl(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, 
   if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small for lift: need %zu bytes", a.off);
   if (n_matches > 0) {
     const size_t hb = (size_t)n_views * 16 * sizeof(double);
-    if (!ensure_pinned(ctx, hb + 512)) return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the staging buffer may still feed an earlier copy
+    int rc = staging_check(ctx, hb + 512);
+    if (rc) return rc;
+    rc = staging_wait(ctx);  // the staging buffer may still feed an earlier copy
+    if (rc) return rc;
     double* hc = reinterpret_cast<double*>(ctx->pinned);
     double* hp = hc + 4 * (size_t)n_views;
     for (int k = 0; k < n_views; ++k) {
@@ -891,6 +982,8 @@ static int lift_impl(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, 
     }
     HIP_TRY(ctx, hipMemcpyAsync(dcams, hc, 4 * (size_t)n_views * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(dposes, hp, 12 * (size_t)n_views * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    rc = staging_mark(ctx);
+    if (rc) return rc;
   }
   LiftArgs la;
   la.q_u = m ? m->q_u : nullptr; la.q_v = m ? m->q_v : nullptr; la.db_u = m ? m->db_u : nullptr;
@@ -954,8 +1047,10 @@ int imloc_triangulate_depth(imloc_ctx* ctx, int32_t H, int32_t W, const imloc_ca
   TriTask* tasks = a.take<TriTask>((size_t)H * W);
   if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small for triangulation: need %zu bytes", a.off);
   const size_t hb = (size_t)(n_views + 1) * 16 * sizeof(double);
-  if (!ensure_pinned(ctx, hb + 512)) return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the staging buffer may still feed an earlier copy
+  int rc = staging_check(ctx, hb + 512);
+  if (rc) return rc;
+  rc = staging_wait(ctx);  // the staging buffer may still feed an earlier copy
+  if (rc) return rc;
   double* h = reinterpret_cast<double*>(ctx->pinned);
   auto centre = [](const imloc_pose& T, double C[3]) {
     for (int r = 0; r < 3; ++r) C[r] = -(T.R[r] * T.t[0] + T.R[3 + r] * T.t[1] + T.R[6 + r] * T.t[2]);
@@ -974,6 +1069,8 @@ int imloc_triangulate_depth(imloc_ctx* ctx, int32_t H, int32_t W, const imloc_ca
     for (int c = 0; c < 3; ++c) o[13 + c] = e == 0 ? 0.0 : C0[c] - C[c];
   }
   HIP_TRY(ctx, hipMemcpyAsync(dviews, h, hb, hipMemcpyHostToDevice, ctx->stream));
+  rc = staging_mark(ctx);
+  if (rc) return rc;
   TriArgs ta;
   ta.H = H; ta.W = W; ta.V = n_views; ta.views = dviews;
   ta.mu = m->u; ta.mv = m->v; ta.conf = m->conf;
@@ -996,7 +1093,8 @@ int imloc_lo_ransac_pnp(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const 
   imloc_corr none{};
   int32_t status = 0;
   uint8_t* masks[1] = {mask};
-  int rc = run_batch(ctx, 1, pts ? pts : &none, &n, K, p, 1, pose_out, masks, stats, &status);
+  int rc = run_batch(ctx, 1, pts ? pts : &none, &n, K, p, 1, pose_out, masks, stats, &status, nullptr,
+                     Scratch{ctx->ws, ctx->ws_bytes}, true);
   return rc < 0 ? rc : status;
 }
 
@@ -1009,7 +1107,8 @@ int imloc_lo_ransac_pnp_batch(imloc_ctx* ctx, const imloc_corr* pts, const int64
   if (nq > 65535) return set_err(ctx, IMLOC_EINVAL, "at most 65535 queries per batch");
   if (n_params != 1 && n_params != nq) return set_err(ctx, IMLOC_EINVAL, "n_params must be 1 or nq");
   if (nq == 0) return IMLOC_OK;
-  return run_batch(ctx, nq, pts, n, K, params, n_params, poses, masks, stats, status);
+  return run_batch(ctx, nq, pts, n, K, params, n_params, poses, masks, stats, status, nullptr,
+                   Scratch{ctx->ws, ctx->ws_bytes}, true);
 }
 
 int imloc_sample_p3p(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K, uint64_t seed,
@@ -1115,7 +1214,8 @@ int imloc_rig_lo_ransac_pnp(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, co
   uint8_t* masks[1] = {mask};
   const RigHost rig{n_cams, cams, cam_start};
   imloc_camera unused{1.0, 1.0, 0.0, 0.0};
-  int rc = run_batch(ctx, 1, pts ? pts : &none, &n, &unused, p, 1, pose_out, masks, stats, &status, &rig);
+  int rc = run_batch(ctx, 1, pts ? pts : &none, &n, &unused, p, 1, pose_out, masks, stats, &status, &rig,
+                     Scratch{ctx->ws, ctx->ws_bytes}, true);
   return rc < 0 ? rc : status;
 }
 
@@ -1378,9 +1478,11 @@ int imloc_server_create(imloc_ctx* ctx, const imloc_server_config* cfg, imloc_se
   srv->bytes_pool.reset(cfg->byte_pool);
   // every slot starts retired
   const size_t tab = (size_t)cfg->max_slots * sizeof(QueryDesc);
-  if (!ensure_pinned(ctx, tab + (size_t)cfg->max_slots * (sizeof(BestState) + 13 * sizeof(double)) + 512)) {
+  int rc = staging_check(ctx, tab + (size_t)cfg->max_slots * (sizeof(BestState) + 13 * sizeof(double)) + 512);
+  if (!rc) rc = staging_wait(ctx);
+  if (rc) {
     delete srv;
-    return set_err(ctx, IMLOC_EHIP, "pinned host allocation failed");
+    return rc;
   }
   hipSetDevice(ctx->device);
   QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
@@ -1483,6 +1585,10 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
   if (nq > 0) {
     kmax = srv->cfg.max_top_k;  // problem index layout of the LO buffers
     const size_t tab = (size_t)nq * sizeof(QueryDesc);
+    // the table and the results of all slots must fit (imloc_set_staging, between steps)
+    int rc = staging_check(ctx, (size_t)S * (sizeof(QueryDesc) + sizeof(BestState) + 13 * sizeof(double)) + 512);
+    if (!rc) rc = staging_wait(ctx);  // an earlier asynchronous call may still copy from the staging buffer
+    if (rc) return rc;
     QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
     for (int i = 0; i < nq; ++i) {
       ServerSlot& sl = srv->slots[i];
@@ -1509,7 +1615,6 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     }
     hipSetDevice(ctx->device);
     hipStream_t s = ctx->stream;
-    Timer tm(ctx);
     HIP_TRY(ctx, hipMemcpyAsync(e.qd, htab, tab, hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, launch_gather_subsets(e.qd, nq, max_m_sub, s));
     HIP_TRY(ctx, launch_init_queries(e.qd, e.st, e.cb.n, nq, false, s));

@@ -1,0 +1,101 @@
+"""Runtime behaviour of the C ABI on the device.
+
+- The pinned host staging buffer of a context is never rewritten while an
+  earlier asynchronous call still copies from it: an asynchronous call queued
+  behind a GPU spin, followed at once by a pose query on the same context,
+  gives the results each call gives alone.
+- The query calls allocate no staging: an undersized buffer is an error
+  (IMLOC_ENOMEM naming the size needed), and after imloc_set_staging the same
+  call runs and gives the same results.
+- Per-stage timing reuses its event pool within a long adaptive call and does
+  not change the result.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2601_04185_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    import paper_2601_04185_amd as pk
+    assert torch.cuda.is_available()
+    return pk
+
+
+def _tri(pk, ctx, w, dev):
+    return pk.imloc_triangulate_depth(ctx, w.K0, w.T0, w.Ks, w.Ts, dev["mu"], dev["mv"], dev["conf"])
+
+
+def test_async_call_then_query_same_context(pk):
+    import torch
+    w = synth.dense_match_scene(n_views=6, width=128, height=96, seed=71)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(getattr(w, k))).cuda() for k in ("mu", "mv", "conf")}
+    q = synth.make_query(72, 3000, 0.4, 1.0)
+    d = pk.to_device(q)
+    prm = pk.make_params(threshold_px=4.0, fixed_samples=512, batch=512, lo_top_k=4)
+    # each call alone
+    ctx = pk.Context(0)
+    ref_tri = {k: v.cpu().numpy() for k, v in _tri(pk, ctx, w, dev).items()}
+    ref = pk.imloc_lo_ransac_pnp(ctx, d, q.K, prm)
+    # the workspace already fits both, so no reallocation separates the calls
+    for _ in range(3):
+        torch.cuda._sleep(5_000_000)  # the view-table copy waits behind this spin
+        g = _tri(pk, ctx, w, dev)       # asynchronous: returns with its copy queued
+        got = pk.imloc_lo_ransac_pnp(ctx, d, q.K, prm)  # writes the staging buffer at once
+        np.testing.assert_array_equal(g["depth"].cpu().numpy(), ref_tri["depth"])
+        np.testing.assert_array_equal(g["inliers"].cpu().numpy(), ref_tri["inliers"])
+        assert got[0] == ref[0]
+        np.testing.assert_array_equal(got[1], ref[1])
+        np.testing.assert_array_equal(got[2], ref[2])
+
+
+def test_undersized_staging_is_an_error(pk):
+    L = pk.lib()
+    qs = synth.config3_batch(40, n_lo=3000, n_hi=6000, seed=73)
+    ds = [pk.to_device(q) for q in qs]
+    prm = pk.make_params(threshold_px=4.0, fixed_samples=256, batch=256, lo_top_k=2)
+    ctx = pk.Context(0)
+    want = pk.imloc_lo_ransac_pnp_batch(ctx, ds, [q.K for q in qs], prm)
+    need = L.imloc_staging_bytes(len(qs), 0)
+    assert need >= L.imloc_get_staging(ctx.h) > 0
+    ctx.check(L.imloc_set_staging(ctx.h, 8192))
+    assert L.imloc_get_staging(ctx.h) == 8192
+    nq = len(qs)
+    ns = (C.c_int64 * nq)(*[q.n for q in qs])
+    cs = (pk.Corr * nq)(*[pk.corr_struct(x["u"], x["v"], x["X"], x["Y"], x["Z"], x.get("w")) for x in ds])
+    cams = (pk.Camera * nq)(*[pk.Camera(*q.K) for q in qs])
+    poses, stats, status = (pk.Pose * nq)(), (pk.Stats * nq)(), (C.c_int32 * nq)()
+    rc = L.imloc_lo_ransac_pnp_batch(ctx.h, cs, ns, cams, nq, C.byref(prm), 1, poses, None, stats, status)
+    assert rc == pk.IMLOC_ENOMEM
+    assert "staging" in ctx.error() and str(40 * 744 + 576) in ctx.error()
+    # the binding grows it in a setup call; the results are the same
+    got = pk.imloc_lo_ransac_pnp_batch(ctx, ds, [q.K for q in qs], prm)
+    assert L.imloc_get_staging(ctx.h) >= 40 * 744 + 576
+    assert got[0] == want[0]
+    for a, b in zip(got[1], want[1]):
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_timing_pool_reused_in_long_adaptive_call(pk):
+    # a low inlier ratio keeps the adaptive loop going for dozens of rounds,
+    # more stage spans than the 256-event pool holds
+    q = synth.make_query(74, 4000, 0.12, 1.0)
+    d = pk.to_device(q)
+    prm = pk.make_params(threshold_px=4.0, batch=64, min_iters=64, max_iters=40000, confidence=0.999, lo_top_k=2)
+    plain = pk.imloc_lo_ransac_pnp(pk.Context(0), d, q.K, prm)
+    tctx = pk.Context(0, timing=True)
+    timed = pk.imloc_lo_ransac_pnp(tctx, d, q.K, prm)
+    st = timed[3]
+    assert st["batches"] > 40, st["batches"]
+    assert timed[0] == plain[0]
+    np.testing.assert_array_equal(timed[1], plain[1])
+    np.testing.assert_array_equal(timed[2], plain[2])
+    assert st["ms_total"] > 0 and st["ms_score"] > 0 and st["ms_lo"] > 0
+    assert st["ms_sample"] + st["ms_score"] + st["ms_select"] + st["ms_lo"] + st["ms_refine"] <= st["ms_total"] * 1.01
