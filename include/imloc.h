@@ -344,6 +344,24 @@ int imloc_lo_ransac_pnp(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const 
                         const imloc_ransac_params *p, imloc_pose *pose_out, uint8_t *inlier_mask,
                         imloc_stats *stats);
 
+/* imloc_lo_ransac_pnp for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, rules and results, but the device scratch is a fixed
+ * array of imloc_noalloc_max_bytes() bytes (32 MiB) inside the library,
+ * which every GPU the library runs on holds until the process ends, and the
+ * call never captures a graph.  It allocates nothing: no device or host
+ * memory, no events, no streams (the context's pinned staging from
+ * imloc_create serves the tables).  A query whose scratch would exceed the
+ * array returns IMLOC_ENOMEM (imloc_workspace_bytes(n, p) is the size it
+ * needs; a 50,000-point query with 10,000 samples per batch needs about
+ * 8 MB).  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind, so calls that overlap on one GPU (two host threads, or
+ * two contexts on different streams) race: serialise them. */
+int imloc_lo_ransac_pnp_noalloc(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K_query,
+                                const imloc_ransac_params *p, imloc_pose *pose_out, uint8_t *inlier_mask,
+                                imloc_stats *stats);
+size_t imloc_noalloc_max_bytes(void);
+
 /* The same for nq independent queries in one batched pipeline: the samples,
  * P3P solves, scoring, selection and local optimisation of all queries run in
  * shared launches.  Each query's result equals what imloc_lo_ransac_pnp gives

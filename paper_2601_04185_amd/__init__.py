@@ -39,7 +39,8 @@ EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_err
             "imloc_rig_stage_workspace_bytes", "imloc_rig_sample_gp3p", "imloc_rig_score",
             "imloc_lo_ransac_pnp", "imloc_lo_ransac_pnp_batch", "imloc_sample_p3p", "imloc_score", "imloc_select_top_k",
             "imloc_local_optimize", "imloc_refine", "imloc_paper_params",
-            "imloc_set_gn_mode", "imloc_staging_bytes", "imloc_set_staging", "imloc_get_staging"]
+            "imloc_set_gn_mode", "imloc_staging_bytes", "imloc_set_staging", "imloc_get_staging",
+            "imloc_lo_ransac_pnp_noalloc", "imloc_noalloc_max_bytes"]
 
 
 class ImlocError(RuntimeError):
@@ -132,6 +133,8 @@ def lib():
             "imloc_staging_bytes": ([i32, i32], C.c_size_t),
             "imloc_set_staging": ([vp, C.c_size_t], C.c_int),
             "imloc_get_staging": ([vp], C.c_size_t),
+            "imloc_lo_ransac_pnp_noalloc": ([vp, vp, i64, vp, vp, vp, vp, vp], C.c_int),
+            "imloc_noalloc_max_bytes": ([], C.c_size_t),
             "imloc_lift": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_lift_log8": ([vp, vp, i64, vp, i32, i32, i32, vp, vp, i32, C.c_float, vp, i64, vp], C.c_int),
             "imloc_depth_encode_log8": ([vp, vp, i64, vp], C.c_int),
@@ -276,6 +279,21 @@ def imloc_lo_ransac_pnp(ctx: Context, corr: dict, K, params: RansacParams, mask=
     cam = _cam(K)
     rc = ctx.check(lib().imloc_lo_ransac_pnp(ctx.h, C.byref(cs), n, C.byref(cam), C.byref(params), C.byref(pose),
                                              _ptr(mask), C.byref(st)))
+    R = np.array(pose.R[:], dtype=np.float64).reshape(3, 3)
+    t = np.array(pose.t[:], dtype=np.float64)
+    return rc, R, t, st.as_dict()
+
+
+def imloc_lo_ransac_pnp_noalloc(ctx: Context, corr: dict, K, params: RansacParams, mask=None):
+    """imloc_lo_ransac_pnp on the library's fixed device scratch (no workspace
+    is set up: the call allocates nothing).  Same arguments and results."""
+    n = int(corr["u"].numel())
+    cs = corr_struct(corr["u"], corr["v"], corr["X"], corr["Y"], corr["Z"], corr.get("w"))
+    pose = Pose()
+    st = Stats()
+    cam = _cam(K)
+    rc = ctx.check(lib().imloc_lo_ransac_pnp_noalloc(ctx.h, C.byref(cs), n, C.byref(cam), C.byref(params),
+                                                     C.byref(pose), _ptr(mask), C.byref(st)))
     R = np.array(pose.R[:], dtype=np.float64).reshape(3, 3)
     t = np.array(pose.t[:], dtype=np.float64)
     return rc, R, t, st.as_dict()

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -25,13 +26,87 @@
 
 using namespace imloc;
 
+// Device scratch of the allocation-free entry point
+// (imloc_lo_ransac_pnp_noalloc): a fixed array that every GPU the library
+// runs on holds until the process ends.  Host code never passes `scratch`
+// itself to a kernel (on the host it is only a stand-in symbol): its device
+// address is looked up once per device, with that device current, and kept.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Called by imloc_create with `device` current.
+hipError_t noalloc_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+}  // namespace
+
+// Vector with room for N elements inside the object: a call on up to N
+// queries builds its host-side plan without touching the heap (the
+// allocation-free entry point relies on this for its one query).
+template <class T, int N>
+class SmallVec {
+ public:
+  SmallVec() = default;
+  explicit SmallVec(size_t n) { resize(n); }
+  SmallVec(const SmallVec&) = delete;
+  SmallVec& operator=(const SmallVec&) = delete;
+  void resize(size_t n) {
+    if (p_ == inl_ && n <= (size_t)N) {
+      for (size_t i = n_; i < n; ++i) inl_[i] = T();
+      n_ = n;
+      return;
+    }
+    if (p_ == inl_) heap_.assign(inl_, inl_ + n_);
+    heap_.resize(n);
+    p_ = heap_.data();
+    n_ = n;
+  }
+  void assign(size_t n, const T& v) {
+    resize(n);
+    for (size_t i = 0; i < n; ++i) p_[i] = v;
+  }
+  void push_back(const T& v) {
+    resize(n_ + 1);
+    p_[n_ - 1] = v;
+  }
+  T& operator[](size_t i) { return p_[i]; }
+  const T& operator[](size_t i) const { return p_[i]; }
+  T& back() { return p_[n_ - 1]; }
+  const T& back() const { return p_[n_ - 1]; }
+  const T* data() const { return p_; }
+  size_t size() const { return n_; }
+
+ private:
+  T inl_[N] = {};
+  std::vector<T> heap_;
+  T* p_ = inl_;
+  size_t n_ = 0;
+};
+
 struct imloc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool timing = false;
-  std::string err;
+  char err[512] = "";
   // Host staging (pinned): query tables and view tables in, states and poses
   // out.  Allocated by imloc_create / imloc_set_staging only; a call that
   // needs more returns IMLOC_ENOMEM.  `staging_ev` is recorded after the last
@@ -65,7 +140,7 @@ int set_err(imloc_ctx* c, int code, const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
-    c->err = buf;
+    snprintf(c->err, sizeof(c->err), "%s", buf);
   }
   return code;
 }
@@ -133,11 +208,12 @@ struct QPlan {
 // CU, so that small rounds keep every CU busy; est holds per query the
 // expected candidates (one per sample) and scoring chunks.  The tile never
 // changes a result (per-candidate sums are integer-accumulated).
-ScoreTune round_tune(const imloc_ctx* c, const std::vector<std::pair<int64_t, int64_t>>& est) {
+using EstList = SmallVec<std::pair<int64_t, int64_t>, 4>;
+ScoreTune round_tune(const imloc_ctx* c, const std::pair<int64_t, int64_t>* est, size_t n_est) {
   if (c->tune.ct > 0) return c->tune;
   for (int ct : {128, 64}) {
     int64_t items = 0;
-    for (const auto& e : est) items += (e.first + ct - 1) / ct * e.second;
+    for (size_t q = 0; q < n_est; ++q) items += (est[q].first + ct - 1) / ct * est[q].second;
     if (items >= 4 * (int64_t)c->cus) return ScoreTune{ct, c->tune.blocks};
   }
   return ScoreTune{32, c->tune.blocks};
@@ -213,7 +289,7 @@ struct Engine {
   void* gn_lo;
   void* gn_fin;
   float* subset;
-  std::vector<int64_t> cand_off, in_set_off, subset_off, proj_off, rig_off;
+  SmallVec<int64_t, 4> cand_off, in_set_off, subset_off, proj_off, rig_off;
 };
 
 void plan_engine(Engine& e, int nq, const QPlan* pl, const imloc_ransac_params* const* pp) {
@@ -345,52 +421,52 @@ constexpr size_t kTimingEvents = 256;  // events of the timing pool (reused with
 struct Timer {
   imloc_ctx* c;
   struct Span { int stage; hipEvent_t a, b; };
-  std::vector<Span> spans;
+  Span spans[kTimingEvents];  // closed spans not yet added up (fewer than events in the pool)
+  size_t n_spans = 0;
   float acc[6] = {0, 0, 0, 0, 0, 0};
   bool on;
   explicit Timer(imloc_ctx* cc) : c(cc), on(cc->timing && cc->events.size() == kTimingEvents) {
     c->next_event = 1;
   }
-  void fold() {
-    hipStreamSynchronize(c->stream);
-    for (auto& s : spans) {
+  void add_up() {
+    for (size_t k = 0; k < n_spans; ++k) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, s.a, s.b) == hipSuccess) acc[s.stage] += ms;
+      if (hipEventElapsedTime(&ms, spans[k].a, spans[k].b) == hipSuccess) acc[spans[k].stage] += ms;
     }
-    spans.clear();
+    n_spans = 0;
+  }
+  void fold() {
+    (void)hipStreamSynchronize(c->stream);
+    add_up();
     c->next_event = 1;
   }
   hipEvent_t total_begin() {
     if (!on) return nullptr;
-    hipEventRecord(c->events[0], c->stream);
+    (void)hipEventRecord(c->events[0], c->stream);
     return c->events[0];
   }
   void total_end(hipEvent_t a) {  // the last event of the pool closes the whole call
     if (!on || !a) return;
     hipEvent_t e = c->events[kTimingEvents - 1];
-    hipEventRecord(e, c->stream);
-    spans.push_back({5, a, e});
+    (void)hipEventRecord(e, c->stream);
+    spans[n_spans++] = Span{5, a, e};
   }
   hipEvent_t begin() {
     if (!on) return nullptr;
     if (c->next_event + 2 > kTimingEvents - 1) fold();
     hipEvent_t e = c->events[c->next_event++];
-    hipEventRecord(e, c->stream);
+    (void)hipEventRecord(e, c->stream);
     return e;
   }
   void end(int stage, hipEvent_t a) {
     if (!on || !a) return;
     hipEvent_t e = c->events[c->next_event++];
-    hipEventRecord(e, c->stream);
-    spans.push_back({stage, a, e});
+    (void)hipEventRecord(e, c->stream);
+    spans[n_spans++] = Span{stage, a, e};
   }
   void fill(imloc_stats* st) {
     if (!on || !st) return;
-    for (auto& s : spans) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, s.a, s.b) == hipSuccess) acc[s.stage] += ms;
-    }
-    spans.clear();
+    add_up();
     st->ms_sample = acc[0]; st->ms_score = acc[1]; st->ms_select = acc[2];
     st->ms_lo = acc[3]; st->ms_refine = acc[4]; st->ms_total = acc[5];
   }
@@ -479,8 +555,8 @@ struct Scratch {
 int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, const imloc_camera* K,
               const imloc_ransac_params* params, int n_params, imloc_pose* poses, uint8_t* const* masks,
               imloc_stats* stats, int32_t* status, const RigHost* rigs, Scratch ws, bool may_capture) {
-  std::vector<const imloc_ransac_params*> pp(nq);
-  std::vector<QPlan> pl(nq);
+  SmallVec<const imloc_ransac_params*, 4> pp(nq);
+  SmallVec<QPlan, 4> pl(nq);
   for (int q = 0; q < nq; ++q) {
     pp[q] = &params[n_params == 1 ? 0 : q];
     int rc = check_params(ctx, pp[q]);
@@ -526,9 +602,9 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
 
   Timer tm(ctx);
   int rounds = 0;
-  std::vector<std::pair<int64_t, int64_t>> est(nq);
+  EstList est(nq);
   for (int q = 0; q < nq; ++q) est[q] = {std::min(pl[q].batch, pl[q].total), est_chunks(pl[q])};
-  const ScoreTune tune = round_tune(ctx, est);
+  const ScoreTune tune = round_tune(ctx, est.data(), est.size());
   // The whole pipeline of a batch, enqueued on stream `st_`: table upload,
   // rounds, final refinement, mask, readback into pinned memory.  `sync`
   // lets adaptive batches read the active count after every round.
@@ -740,6 +816,7 @@ int imloc_create(imloc_ctx** out, int device, void* hip_stream) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return IMLOC_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return IMLOC_EHIP;
+  if (noalloc_setup(device) != hipSuccess) return IMLOC_EHIP;
   imloc_ctx* c = new imloc_ctx();
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -779,7 +856,7 @@ int imloc_set_stream(imloc_ctx* c, void* s) {
   return IMLOC_OK;
 }
 
-const char* imloc_last_error(const imloc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* imloc_last_error(const imloc_ctx* c) { return c ? c->err : "null context"; }
 
 int imloc_set_workspace(imloc_ctx* c, void* p, size_t bytes) {
   if (!c) return IMLOC_EINVAL;
@@ -1098,6 +1175,25 @@ int imloc_lo_ransac_pnp(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const 
   return rc < 0 ? rc : status;
 }
 
+size_t imloc_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int imloc_lo_ransac_pnp_noalloc(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_camera* K,
+                                const imloc_ransac_params* p, imloc_pose* pose_out, uint8_t* mask,
+                                imloc_stats* stats) {
+  if (!ctx) return IMLOC_EINVAL;
+  if (!pose_out) return set_err(ctx, IMLOC_EINVAL, "pose_out is null");
+  if (!p) return set_err(ctx, IMLOC_EINVAL, "params is null");
+  void* base = noalloc_scratch(ctx->device);
+  if (!base) return set_err(ctx, IMLOC_EHIP, "device %d has no fixed scratch address", ctx->device);
+  imloc_corr none{};
+  int32_t status = 0;
+  uint8_t* masks[1] = {mask};
+  // the size check of run_batch (workspace too small -> IMLOC_ENOMEM) bounds the call by the array's size
+  int rc = run_batch(ctx, 1, pts ? pts : &none, &n, K, p, 1, pose_out, masks, stats, &status, nullptr,
+                     Scratch{reinterpret_cast<char*>(base), kNoAllocScratchBytes}, false);
+  return rc < 0 ? rc : status;
+}
+
 int imloc_lo_ransac_pnp_batch(imloc_ctx* ctx, const imloc_corr* pts, const int64_t* n, const imloc_camera* K,
                               int32_t nq, const imloc_ransac_params* params, int32_t n_params, imloc_pose* poses,
                               uint8_t* const* masks, imloc_stats* stats, int32_t* status) {
@@ -1196,7 +1292,8 @@ int imloc_rig_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imlo
   if (rc) return rc;
   hipStream_t s = ctx->stream;
   HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
-  const ScoreTune tune = round_tune(ctx, {{np, est_chunks(sq.pl)}});
+  const std::pair<int64_t, int64_t> est1{np, est_chunks(sq.pl)};
+  const ScoreTune tune = round_tune(ctx, &est1, 1);
   HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune.ct, sq.e.item_off, s));
   HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, tune, precision, s));
   HIP_TRY(ctx, launch_candidate_costs(sq.e.qd, sq.e.st, sq.e.cb, np, count, msac, s));
@@ -1239,7 +1336,8 @@ int imloc_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_ca
   if (rc) return rc;
   hipStream_t s = ctx->stream;
   HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
-  const ScoreTune tune = round_tune(ctx, {{np, est_chunks(sq.pl)}});
+  const std::pair<int64_t, int64_t> est1{np, est_chunks(sq.pl)};
+  const ScoreTune tune = round_tune(ctx, &est1, 1);
   HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune.ct, sq.e.item_off, s));
   HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, tune, precision, s));
   HIP_TRY(ctx, launch_candidate_costs(sq.e.qd, sq.e.st, sq.e.cb, np, count, msac, s));
@@ -1274,7 +1372,8 @@ int imloc_select_top_k(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const i
     HIP_TRY(ctx, hipMemcpyAsync(&sq.e.st[0].cost, hg, sizeof(double), hipMemcpyHostToDevice, s));
   }
   HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
-  const ScoreTune tune = round_tune(ctx, {{np, est_chunks(sq.pl)}});
+  const std::pair<int64_t, int64_t> est1{np, est_chunks(sq.pl)};
+  const ScoreTune tune = round_tune(ctx, &est1, 1);
   HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune.ct, sq.e.item_off, s));
   HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, tune, precision, s));
   HIP_TRY(ctx, launch_select(sq.e.qd, sq.e.st, sq.e.cb, 1, k, std::max<int64_t>(np, 1), sq.e.sel_part, sel, n_sel, s));
@@ -1565,7 +1664,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
   }
   int nq = 0, kmax = 1, chunks_lo = 1, chunks_fin = 1, lo_iters = 0, fin_iters = 0, resident = 0;
   int64_t max_batch = 1, max_n = 0, max_m_sub = 0;
-  std::vector<std::pair<int64_t, int64_t>> est;
+  EstList est;
   for (int i = 0; i < S; ++i) {
     const ServerSlot& sl = srv->slots[i];
     if (!sl.used) continue;
@@ -1620,7 +1719,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     HIP_TRY(ctx, launch_init_queries(e.qd, e.st, e.cb.n, nq, false, s));
     HIP_TRY(ctx, launch_begin_round(e.qd, e.st, e.cb, nq, s));
     HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, max_batch, nullptr, s));
-    const ScoreTune tune = round_tune(ctx, est);
+    const ScoreTune tune = round_tune(ctx, est.data(), est.size());
     HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, tune.ct, e.item_off, s));
     HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, tune, 0, s));
     HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, 4 * max_batch, e.sel_part, e.sel, e.n_sel, s));
