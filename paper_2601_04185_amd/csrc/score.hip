@@ -8,17 +8,22 @@
 // list, so one launch covers any mix of queries.
 //
 // Layout: one lane per correspondence (PPL correspondences per lane kept in
-// registers, coalesced structure-of-arrays loads), candidates wave-uniform so
-// their projection rows live in scalar registers.  The rows are K [R | t] with
-// the first two divided by tau, and the observations enter divided by tau, so
+// registers, coalesced structure-of-arrays loads).  A work item first stages
+// its tile's projection rows in LDS; each wave then reads a candidate's rows
+// with broadcast LDS loads into vector registers, so that every multiply-add
+// of the loop has vector operands only (on gfx950 a multiply-add with a
+// scalar-register operand issues about 1.7 times slower, one with a neg or
+// abs modifier about 1.5 times).  The rows are K [R | t] with the first two
+// divided by tau, and the observations enter divided by tau and negated, so
 // per residual:
 //   (a', b', w) = P' [X, 1]              9 FMA
-//   du' = a' - u' w, dv' = b' - v' w     2 FMA
+//   du' = a' + (-u') w, dv' likewise     2 FMA
 //   e' = du'^2 + dv'^2                   MUL + FMA    (= e / tau^2)
-//   inlier iff e' < w |w|                MUL + CMP    (division-free; rejects w <= 0)
+//   inlier iff e' - w |w| < 0            FMA + CMP    (one rounding; rejects w <= 0 and NaN)
 // The inlier count is a wave ballot + popcount (scalar unit).  The truncated
-// cost is MSAC = tau^2 (sum_i w_i - G), G = sum_in w_i (1 - e'/(w |w|)), so
-// only inlier lanes of a wave with at least one inlier pay a reciprocal.
+// cost is MSAC = tau^2 (sum_i w_i - G), G = sum_in w_i (w |w| - e')/(w |w|),
+// computed only in point slots whose ballot is not empty (a wave-uniform
+// branch), so most candidates pay no reciprocal at all.
 //
 // Accumulation: each wave's partial G (a float sum over its fixed set of
 // 64 * PPL correspondences) is converted once to fixed point (2^-32) and all
@@ -33,14 +38,6 @@ namespace imloc {
 
 constexpr int kScoreBlock = 256;
 constexpr int kScoreWaves = kScoreBlock / kWave;
-
-// Copy a wave-uniform value into a vector register once, so that FMAs taking
-// two uniform operands do not re-materialise it for every residual.
-__device__ inline float to_vgpr(float x) {
-  float r;
-  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
-  return r;
-}
 
 // Sum over the 64 lanes of a full wave with DPP lane moves (pairs, quads,
 // rows of 16 by shifts, then the row broadcasts 15 and 31), total read from
@@ -130,12 +127,28 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
                                                uint32_t* __restrict__ ccnt, unsigned long long* __restrict__ cgain,
                                                BestState* st, int64_t tile, int64_t chunk, int ncand,
                                                uint32_t (*s_cnt)[kScoreWaves],
-                                               unsigned long long (*s_gain)[kScoreWaves], uint32_t* s_item) {
+                                               unsigned long long (*s_gain)[kScoreWaves], uint32_t* s_item,
+                                               float4 (*s_rows)[3]) {
   constexpr int PPL = kScorePPL32;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const float inv_tau = (float)(1.0 / d.tau);
   const ChunkRange rg = chunk_range(d, chunk);
   const int64_t base = rg.begin + wave * (kWave * PPL) + lane;
+  const int c0 = (int)(tile * CT);
+  const int cend = min(CT, ncand - c0);
+  // the tile's projection rows into LDS: every wave then reads a candidate's
+  // 12 values as three broadcast 16-byte LDS loads into vector registers
+  // (a multiply-add with a scalar-register operand issues about 1.7 times
+  // slower than one with vector operands only on this chip)
+  {
+    const int rows = rows_per_slot(d);
+    const float4* __restrict__ pc =
+        reinterpret_cast<const float4*>(proj + d.proj_off + 16 * ((int64_t)rows * c0 + rg.cam));
+    for (int e = threadIdx.x; e < 3 * cend; e += kScoreBlock) {
+      const int c = e / 3, r = e - 3 * c;
+      s_rows[c][r] = pc[(int64_t)4 * rows * c + r];
+    }
+  }
   const auto U = gmem(d.S.u);
   const auto V = gmem(d.S.v);
   const auto X = gmem(d.S.X);
@@ -147,48 +160,47 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
   for (int k = 0; k < PPL; ++k) {
     const int64_t i = base + (int64_t)k * kWave;
     if (i < rg.end) {
-      pu[k] = U[i] * inv_tau; pv[k] = V[i] * inv_tau; px[k] = X[i]; py[k] = Y[i]; pz[k] = Z[i];
+      // observations negated, so that du' = a' + pu w is a multiply-add without modifiers
+      pu[k] = -(U[i] * inv_tau); pv[k] = -(V[i] * inv_tau); px[k] = X[i]; py[k] = Y[i]; pz[k] = Z[i];
       pw[k] = W ? W[i] : 1.0f;
     } else {  // a NaN residual is never an inlier
       pu[k] = __builtin_nanf(""); pv[k] = 0.f; px[k] = 0.f; py[k] = 0.f; pz[k] = 0.f; pw[k] = 0.f;
     }
   }
-  const int c0 = (int)(tile * CT);
-  const int cend = min(CT, ncand - c0);
-  const int rows = rows_per_slot(d);
-  const float4* __restrict__ pc =
-      reinterpret_cast<const float4*>(proj + d.proj_off + 16 * ((int64_t)rows * c0 + rg.cam));
-  const int stride = 4 * rows;  // float4s from one candidate's rows to the next one's
-  float4 n0 = pc[0], n1 = pc[1], n2 = pc[2];
+  __syncthreads();
   uint32_t item_cnt = 0;
-#pragma unroll 2
   for (int c = 0; c < cend; ++c) {
-    const float4 r0 = n0, r1 = n1, r2 = n2;
-    if (c + 1 < cend) {  // prefetch the next candidate's rows
-      n0 = pc[stride * (c + 1)]; n1 = pc[stride * (c + 1) + 1]; n2 = pc[stride * (c + 1) + 2];
-    }
-    const float o0 = to_vgpr(r0.w), o1 = to_vgpr(r1.w), o2 = to_vgpr(r2.w);
+    // (the other waves of the SIMD cover the LDS latency)
+    const float4 r0 = s_rows[c][0], r1 = s_rows[c][1], r2 = s_rows[c][2];
     uint32_t cnt = 0;
-    uint64_t any = 0;
-    float e[PPL], t[PPL];
+    uint64_t bal[PPL];
+    float dd[PPL], ww[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
-      const float a = fmaf(r0.z, pz[k], fmaf(r0.y, py[k], fmaf(r0.x, px[k], o0)));
-      const float b = fmaf(r1.z, pz[k], fmaf(r1.y, py[k], fmaf(r1.x, px[k], o1)));
-      const float w = fmaf(r2.z, pz[k], fmaf(r2.y, py[k], fmaf(r2.x, px[k], o2)));
-      const float du = fmaf(-pu[k], w, a), dv = fmaf(-pv[k], w, b);
-      e[k] = fmaf(dv, dv, du * du);
-      t[k] = w * fabsf(w);
-      const uint64_t bal = __ballot(e[k] < t[k]);
-      cnt += (uint32_t)__popcll(bal);
-      any |= bal;
+      const float a = fmaf(r0.z, pz[k], fmaf(r0.y, py[k], fmaf(r0.x, px[k], r0.w)));
+      const float b = fmaf(r1.z, pz[k], fmaf(r1.y, py[k], fmaf(r1.x, px[k], r1.w)));
+      const float w = fmaf(r2.z, pz[k], fmaf(r2.y, py[k], fmaf(r2.x, px[k], r2.w)));
+      const float du = fmaf(pu[k], w, a), dv = fmaf(pv[k], w, b);
+      // inlier iff e' < w |w|: the sign of e' - w |w| rounded once (rejects w <= 0 and NaN)
+      dd[k] = fmaf(-w, fabsf(w), fmaf(dv, dv, du * du));
+      ww[k] = w;
+      bal[k] = __ballot(dd[k] < 0.f);
+      cnt += (uint32_t)__popcll(bal[k]);
     }
     unsigned long long gfx = 0;
-    if (any) {
+    if (cnt) {  // G += w_i (w|w| - e') / (w|w|) over the inliers, point slots with no inlier skipped
+      // (the empty volatile statements keep these wave-uniform branches as
+      // branches: most candidates have no inlier in most slots)
+      asm volatile("");
       float gain = 0.f;
 #pragma unroll
-      for (int k = 0; k < PPL; ++k)
-        if (e[k] < t[k]) gain = fmaf(pw[k], fmaf(-e[k], __builtin_amdgcn_rcpf(t[k]), 1.0f), gain);
+      for (int k = 0; k < PPL; ++k) {
+        if (bal[k]) {
+          asm volatile("");
+          const float t = ww[k] * fabsf(ww[k]);
+          if (dd[k] < 0.f) gain = fmaf(-pw[k] * dd[k], __builtin_amdgcn_rcpf(t), gain);
+        }
+      }
       gain = wave_total_dpp(gain);
       gfx = (unsigned long long)((double)gain * kGainScale);
     }
@@ -319,6 +331,7 @@ __global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __r
   __shared__ uint32_t s_cnt[CT][kScoreWaves];
   __shared__ unsigned long long s_gain[CT][kScoreWaves];
   __shared__ uint32_t s_item[kScoreWaves];
+  __shared__ float4 s_rows[CT][3];
   const int64_t total = item_off[nq];
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     int lo = 0, hi = nq - 1;  // the query owning item w: last q with item_off[q] <= w
@@ -332,7 +345,7 @@ __global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __r
     const int64_t tile = local / chunks, chunk = local - tile * chunks;
     const int nc = ncand[lo];
     if (d.precision == 0)
-      score_item_f32<CT>(d, proj, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain, s_item);
+      score_item_f32<CT>(d, proj, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain, s_item, s_rows);
     else
       score_item_f64<CT>(d, pose, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain, s_item);
   }
