@@ -772,6 +772,44 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
                            const_cast<double*>(gn_part(g, j & 1, p)) + (int64_t)chunk * kAcc);
 }
 
+// Split form of the local optimisation, evaluation j, for problems that
+// start from selected candidates: one workgroup per (chunk, query) loads the
+// chunk's points once and evaluates every live problem of the query in slot
+// order (up to lo_top_k poses on the same points).  Each problem's
+// accumulation is gn_accumulate with the same thread-to-point map, so the
+// partial sums are those of gn_eval_kernel bit for bit.
+template <bool RIG>
+__global__ __launch_bounds__(kGNThreads) void gn_eval_lo_multi_kernel(GNArgs g, int j) {
+  const int q = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const int ns = g.n_sel[q];
+  if (ns <= 0) return;
+  const QueryDesc& d = g.qd[q];
+  const int64_t n = d.m;
+  const int C = chunks_for(n);
+  if (chunk >= C) return;
+  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
+  GNPoints pt;
+  gn_load_points<0>(d.S, n, base, nullptr, false, g.part, pt);
+  __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
+  if (RIG && d.ncam > 0)
+    for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
+  __shared__ double s_eval[12];
+  __shared__ double s_rows[kGNWaves][kAcc];
+  for (int slot = 0; slot < ns; ++slot) {
+    const int p = q * g.kmax + slot;
+    const GNState* st = j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr;
+    if (st && st->done) continue;
+    const double* start = st ? nullptr : gn_start<0>(g, p, q);
+    // every thread has left the previous problem's accumulation (its last
+    // barrier) before s_eval is rewritten
+    if (threadIdx.x < 12) s_eval[threadIdx.x] = st ? st->eval[threadIdx.x] : start[threadIdx.x];
+    __syncthreads();
+    gn_accumulate<0, RIG>(d, s_rig, s_eval, j, base, pt, nullptr, s_rows,
+                          const_cast<double*>(gn_part(g, j & 1, p)) + (int64_t)chunk * kAcc);
+  }
+}
+
 // ... then decision j (one workgroup per problem), with the same reduction
 // order and decision as the fused form, so both give identical results.
 template <int MODE>
@@ -824,8 +862,15 @@ static void launch_gn(const GNArgs& g, int iters_max, bool fused, hipStream_t s)
     for (int k = 0; k <= iters_max + 1; ++k)
       hipLaunchKernelGGL((gn_fused_kernel<MODE, RIG>), grid, dim3(kGNThreads), 0, s, g, k);
   } else {
+    // local optimisation from selected candidates: one workgroup per chunk and
+    // query evaluates all of the query's problems (points loaded once)
+    const bool multi = MODE == 0 && !g.start_direct && g.kmax > 1;
+    const dim3 grid_multi(g.cmax, g.nprob / (g.kmax > 0 ? g.kmax : 1));
     for (int j = 0; j <= iters_max; ++j) {
-      hipLaunchKernelGGL((gn_eval_kernel<MODE, RIG>), grid, dim3(kGNThreads), 0, s, g, j);
+      if (multi)
+        hipLaunchKernelGGL((gn_eval_lo_multi_kernel<RIG>), grid_multi, dim3(kGNThreads), 0, s, g, j);
+      else
+        hipLaunchKernelGGL((gn_eval_kernel<MODE, RIG>), grid, dim3(kGNThreads), 0, s, g, j);
       hipLaunchKernelGGL((gn_decide_kernel<MODE>), dim3(g.nprob), dim3(kGNThreads), 0, s, g, j);
     }
   }
