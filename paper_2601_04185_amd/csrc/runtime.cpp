@@ -341,8 +341,9 @@ void carve_engine(Arena& a, Engine& e) {
   // staging buffer, so that one copy returns all results
   char* res = a.take<char>(result_bytes(nq));
   e.st = reinterpret_cast<BestState*>(res);
-  e.fin_pose = reinterpret_cast<double*>(res + (size_t)nq * sizeof(BestState));
-  e.fin_cost = e.fin_pose + (size_t)nq * 12;
+  // (sizing passes carve from a null base: no pointer arithmetic on it)
+  e.fin_pose = res ? reinterpret_cast<double*>(res + (size_t)nq * sizeof(BestState)) : nullptr;
+  e.fin_cost = res ? e.fin_pose + (size_t)nq * 12 : nullptr;
   e.cb.pose = a.take<double>(12 * S);
   e.cb.proj = a.take<float>((size_t)e.proj_floats);
   e.rig = a.take<double>((size_t)std::max<int64_t>(e.rig_doubles, 16));

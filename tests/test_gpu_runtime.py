@@ -99,3 +99,60 @@ def test_timing_pool_reused_in_long_adaptive_call(pk):
     np.testing.assert_array_equal(timed[2], plain[2])
     assert st["ms_total"] > 0 and st["ms_score"] > 0 and st["ms_lo"] > 0
     assert st["ms_sample"] + st["ms_score"] + st["ms_select"] + st["ms_lo"] + st["ms_refine"] <= st["ms_total"] * 1.01
+
+
+def test_allocation_failure_fails_alone(pk):
+    """Injected allocation failures: a batch call whose workspace is too small
+    fails with IMLOC_ENOMEM before any device work and leaves the context
+    usable; a server refuses, at submission, a query larger than its pools,
+    while the queries around it are served with the results they give alone."""
+    import torch
+    L = pk.lib()
+    qs = [synth.make_query(90 + i, 4000 + 1000 * i, 0.4, 1.0) for i in range(3)]
+    ds = [pk.to_device(q) for q in qs]
+    prm = pk.make_params(threshold_px=4.0, fixed_samples=512, batch=512, lo_top_k=4)
+    ctx = pk.Context(0)
+    want = pk.imloc_lo_ransac_pnp_batch(ctx, ds, [q.K for q in qs], prm)
+    small = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    ctx.check(L.imloc_set_workspace(ctx.h, C.c_void_p(small.data_ptr()), 4096))
+    ctx.ws = small
+    with pytest.raises(pk.ImlocError, match="workspace too small"):
+        _batch_no_grow(pk, ctx, ds, qs, prm)
+    got = pk.imloc_lo_ransac_pnp_batch(ctx, ds, [q.K for q in qs], prm)  # the binding grows it again
+    for a, b in zip(got[1], want[1]):
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+    # a server whose byte pool fits queries of up to 10,000 points
+    srv = pk.Server(0, max_slots=4, max_top_k=4, max_n=60000, byte_pool=4 * (10000 + 256))
+    big = synth.make_query(99, 50000, 0.4, 1.0)
+    tick = {srv.submit(ds[0], qs[0].K, prm): 0}
+    with pytest.raises(pk.ImlocError, match="larger than the server's pools"):
+        srv.submit(pk.to_device(big), big.K, prm)
+    tick[srv.submit(ds[1], qs[1].K, prm)] = 1
+    tick[srv.submit(ds[2], qs[2].K, prm)] = 2
+    out = {}
+    for _ in range(100):
+        done, _, _ = srv.step()
+        for t in done:
+            out[tick[t]] = srv.poll(t)
+        if len(out) == 3:
+            break
+    assert len(out) == 3
+    for i in range(3):
+        assert out[i][0] == 0
+        np.testing.assert_array_equal(out[i][1], want[1][i][0])
+        np.testing.assert_array_equal(out[i][2], want[1][i][1])
+    srv.close()
+
+
+def _batch_no_grow(pk, ctx, ds, qs, prm):
+    """imloc_lo_ransac_pnp_batch through the C ABI without the binding's
+    workspace growth."""
+    L = pk.lib()
+    nq = len(qs)
+    ns = (C.c_int64 * nq)(*[q.n for q in qs])
+    cs = (pk.Corr * nq)(*[pk.corr_struct(x["u"], x["v"], x["X"], x["Y"], x["Z"], x.get("w")) for x in ds])
+    cams = (pk.Camera * nq)(*[pk.Camera(*q.K) for q in qs])
+    poses, stats, status = (pk.Pose * nq)(), (pk.Stats * nq)(), (C.c_int32 * nq)()
+    return ctx.check(L.imloc_lo_ransac_pnp_batch(ctx.h, cs, ns, cams, nq, C.byref(prm), 1, poses, None, stats,
+                                                 status))
