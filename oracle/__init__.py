@@ -10,7 +10,7 @@ stated in ``imloc_oracle.h``:
   lift              -- Sec. 3.3 "Query Time Matching and 2D-3D Lifting"
   sample / p3p      -- Sec. 3.3 "Pose Estimation" (minimal sets, P3P solver)
   score             -- Sec. 3.3 (truncated, confidence-weighted reprojection error)
-  lo                -- Sec. 3.3 (non-linear refinement of the truncated cost)
+  lo                -- Sec. 3.3 (Gauss-Newton on the truncated cost)
   required_samples  -- Sec. 3.3 (stop when P(missing the best model) is small)
   refine            -- Sec. 3.3 (final robust Cauchy refinement on all inliers)
 """

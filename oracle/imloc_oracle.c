@@ -440,8 +440,8 @@ int orc_p3p(const double uv[6], const double Xw[9], const orc_camera *K, orc_pos
 }
 
 /* ------------------------------------------------------------------------- */
-/* Scoring (Sec. 3.3: truncated squared reprojection error weighted by the   */
-/* matching confidence, every hypothesis against every scored point).        */
+/* Scoring (Sec. 3.3 "Pose Estimation"): MSAC sum of clipped squared pixel  */
+/* errors, confidence-weighted, every hypothesis against every scored point. */
 /* ------------------------------------------------------------------------- */
 static double corr_w(const orc_corr *c, int64_t i) { return c->w ? (double)c->w[i] : 1.0; }
 

@@ -11,11 +11,12 @@
  *     2D-3D through the stored depth maps (bilinear at sub-pixel database
  *     coordinates, plain lookup otherwise), keep matches with valid depth and
  *     confidence above 0.05.
- *   - Sec. 3.3 "Pose Estimation": LO-RANSAC over P3P minimal sets, scoring by a
- *     confidence-weighted truncated squared reprojection error, non-linear
- *     refinement of that truncated cost on each new best, stop at an
- *     iteration cap or when the probability of missing the best model falls
- *     below a bound, final robust Cauchy refinement on all inliers.
+ *   - Sec. 3.3 "Pose Estimation": LO-RANSAC over P3P minimal sets; each
+ *     hypothesis is scored by the MSAC sum of squared pixel errors clipped at
+ *     the threshold, weighted by the matching confidences; a hypothesis that
+ *     beats the running best is refined by Gauss-Newton on that clipped sum;
+ *     sampling ends at a cap or once the standard RANSAC confidence bound is
+ *     met; the best pose is then refined over every inlier with a Cauchy loss.
  *   - Sec. 1 cites the Haralick et al. (1994) review for PnP; the P3P here is
  *     Grunert's law-of-cosines elimination described in that review.
  * The paper prints no formulas; the readings taken where it is silent are the

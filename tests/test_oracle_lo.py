@@ -1,7 +1,7 @@
-"""Pins of the oracle's local optimisation and final refinement (Sec. 3.3:
-non-linear refinement of the truncated squared reprojection error on each new
-best; final refinement of all inliers with a robust Cauchy loss weighted by the
-matching confidence).
+"""Pins of the oracle's local optimisation (Gauss-Newton on the truncated
+cost, started from each new best; Sec. 3.3 "Pose Estimation") and of its final
+refinement (Cauchy-loss IRLS over every inlier, confidence-weighted; same
+section).
 
 Pins: the gradient and Gauss-Newton matrix against central finite differences
 of the cost under the same left update; convergence to the ground truth on

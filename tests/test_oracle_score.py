@@ -1,5 +1,5 @@
-"""Pins of the oracle's hypothesis scoring (Sec. 3.3: truncated squared
-reprojection error weighted by the matching confidence, every hypothesis
+"""Pins of the oracle's hypothesis scoring (Sec. 3.3: each match adds its
+confidence times its squared reprojection error capped at the threshold, every hypothesis
 against every scored correspondence).  Constructed points with exactly known
 pixel residuals fix the threshold's strictness, cheirality and weighting."""
 import numpy as np

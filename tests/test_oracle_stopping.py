@@ -1,5 +1,5 @@
-"""Pins of the stopping rule (Sec. 3.3: stop at 100K iterations or when the
-probability of missing the best model falls below a bound; minimal size 3).
+"""Pins of the stopping rule (Sec. 3.3 "Pose Estimation": a 100K-sample cap
+and the standard RANSAC confidence bound, read for minimal sets of 3).
 
 The defining property: k is the smallest sample count with
 (1 - eps^3)^k <= 1 - confidence, i.e. the chance that none of k samples is
