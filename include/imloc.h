@@ -5,10 +5,10 @@
  * arXiv 2601.04185, Sec. 3.3): dense query-to-database matches are lifted to
  * 2D-3D correspondences through the stored depth maps, intrinsics and poses
  * ("Query Time Matching and 2D-3D Lifting"), then the query pose is estimated
- * by LO-RANSAC over P3P minimal sets with confidence-weighted truncated
- * reprojection scoring, non-linear refinement of each new best, an adaptive
- * stopping rule and a final robust Cauchy refinement on all inliers ("Pose
- * Estimation").  Every step runs in HIP kernels on the GPU.
+ * by LO-RANSAC over P3P minimal sets: MSAC scoring of clipped squared pixel
+ * errors weighted by confidence, Gauss-Newton refinement of a hypothesis that
+ * beats the running best, an adaptive stopping rule, and a last Cauchy-loss
+ * refinement over every inlier ("Pose Estimation").  Every step runs in HIP kernels on the GPU.
  *
  * Conventions (the paper fixes none of them):
  *   - pinhole cameras without distortion; pixel (row i, col j) has its centre
@@ -454,10 +454,20 @@ void imloc_server_destroy(imloc_server *srv);
 int imloc_server_submit(imloc_server *srv, const imloc_corr *pts, int64_t n, const imloc_camera *K,
                         const imloc_ransac_params *p, uint8_t *inlier_mask, int64_t *ticket);
 
-/* Admit what fits, run one round, finish the queries whose stopping rule
- * fired.  done_tickets (host, capacity entries, may be NULL) receives the
- * tickets finished in this step; *n_done their number, *n_resident the
- * queries still on the device, *n_queued those waiting. */
+/* One step: admit what fits, enqueue one round for every resident query (the
+ * queries whose stopping rule fires get their final refinement and mask in
+ * that round), then read back the round enqueued by the previous step, if it
+ * is still in flight, and retire its finished queries.  While queries wait
+ * in the queue the new round is left in flight, to be read back by the next
+ * step (a two-deep pipeline: the host's admission and bookkeeping overlap the
+ * device's rounds, and a query finished in it is reported one step later);
+ * otherwise the step reads the new round back before it returns.  Keep
+ * stepping until every ticket is done; a step with nothing resident and
+ * nothing in flight does nothing.  done_tickets (host, capacity entries, may
+ * be NULL) receives the tickets finished in this step; *n_done their number,
+ * *n_resident the queries holding a slot, *n_queued those waiting.  The
+ * server's context needs imloc_staging_bytes(2 * max_slots + 2, 0) of
+ * staging (two halves); IMLOC_ENOMEM otherwise. */
 int imloc_server_step(imloc_server *srv, int64_t *done_tickets, int32_t capacity, int32_t *n_done,
                       int32_t *n_resident, int32_t *n_queued);
 

@@ -596,7 +596,7 @@ class Server:
         if nbytes == 0:
             raise ImlocError("bad server configuration")
         self.ctx.ensure_workspace(nbytes)
-        self.ctx.ensure_staging(max_slots)
+        self.ctx.ensure_staging(2 * max_slots + 2)  # two halves: one round in flight, one being built
         h = C.c_void_p()
         self.ctx.check(lib().imloc_server_create(self.ctx.h, C.byref(self.cfg), C.byref(h)))
         self.h = h

@@ -1,9 +1,11 @@
-// refine.hip -- float64 Gauss-Newton of LO-RANSAC (ImLoc Sec. 3.3):
-//   local optimisation: non-linear refinement of the truncated squared
-//     reprojection error of a new best hypothesis on the scoring set, the
-//     inlier set re-evaluated at every iterate;
-//   final refinement: robust Cauchy loss, weighted by the confidences, over
-//     all inliers of the full set at the best pose (held fixed).
+// refine.hip -- float64 Gauss-Newton of LO-RANSAC (ImLoc Sec. 3.3, "Pose
+// Estimation"):
+//   local optimisation: Gauss-Newton on the truncated cost over the scoring
+//     set, started from a candidate that beats the running best; the inlier
+//     set is taken again at every iterate;
+//   final refinement: IRLS on the Cauchy loss, each point weighted by its
+//     confidence, over the inliers of the full set at the best pose (that set
+//     stays fixed).
 // Each Gauss-Newton iteration is one launch over (point chunk x problem)
 // workgroups for every problem of a batch of queries (or, for large batches,
 // an evaluation launch and a decision launch).  A workgroup accumulates the

@@ -1488,6 +1488,7 @@ struct ServerQuery {
 struct ServerSlot {
   bool used = false;
   bool fresh = false;
+  int64_t first_round = 0;  // the first round the query is part of
   ServerQuery q;
   QPlan pl;
   int64_t cand_off = 0, cand_len = 0, byte_off = 0, byte_len = 0;
@@ -1514,8 +1515,22 @@ struct imloc_server {
   std::unordered_map<int64_t, Finished> done;
   RangePool cand_pool, bytes_pool;
   int64_t next_ticket = 0;
-  int64_t rounds = 0;
+  int64_t rounds = 0;      // rounds enqueued so far
+  // The round enqueued by the last step, still to be read back: its staging
+  // half is (round & 1), its completion event ev[round & 1].
+  bool inflight = false;
+  int64_t inflight_round = 0;
+  int inflight_nq = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
 };
+
+namespace {
+// One half of a server's double-buffered staging: the slot table of a round,
+// then the states, final poses and costs of every slot.
+size_t server_half_bytes(int S) {
+  return ((size_t)S * (sizeof(QueryDesc) + sizeof(BestState) + 13 * sizeof(double)) + 512 + 255) & ~size_t(255);
+}
+}  // namespace
 
 namespace {
 
@@ -1578,13 +1593,18 @@ int imloc_server_create(imloc_ctx* ctx, const imloc_server_config* cfg, imloc_se
   srv->bytes_pool.reset(cfg->byte_pool);
   // every slot starts retired
   const size_t tab = (size_t)cfg->max_slots * sizeof(QueryDesc);
-  int rc = staging_check(ctx, tab + (size_t)cfg->max_slots * (sizeof(BestState) + 13 * sizeof(double)) + 512);
+  int rc = staging_check(ctx, 2 * server_half_bytes(cfg->max_slots));
   if (!rc) rc = staging_wait(ctx);
   if (rc) {
     delete srv;
     return rc;
   }
   hipSetDevice(ctx->device);
+  if (hipEventCreateWithFlags(&srv->ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&srv->ev[1], hipEventDisableTiming) != hipSuccess) {
+    imloc_server_destroy(srv);
+    return set_err(ctx, IMLOC_EHIP, "server event creation failed");
+  }
   QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
   std::memset(htab, 0, tab);
   for (int q = 0; q < cfg->max_slots; ++q) htab[q].fresh = 1;
@@ -1592,7 +1612,7 @@ int imloc_server_create(imloc_ctx* ctx, const imloc_server_config* cfg, imloc_se
   if (hipMemcpyAsync(srv->e.qd, htab, tab, hipMemcpyHostToDevice, s) != hipSuccess ||
       launch_init_queries(srv->e.qd, srv->e.st, srv->e.cb.n, cfg->max_slots, false, s) != hipSuccess ||
       launch_retire(srv->e.st, cfg->max_slots, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-    delete srv;
+    imloc_server_destroy(srv);
     return set_err(ctx, IMLOC_EHIP, "server initialisation failed");
   }
   *out = srv;
@@ -1601,7 +1621,9 @@ int imloc_server_create(imloc_ctx* ctx, const imloc_server_config* cfg, imloc_se
 
 void imloc_server_destroy(imloc_server* srv) {
   if (!srv) return;
-  hipStreamSynchronize(srv->ctx->stream);
+  (void)hipStreamSynchronize(srv->ctx->stream);
+  for (hipEvent_t e : srv->ev)
+    if (e) (void)hipEventDestroy(e);
   delete srv;
 }
 
@@ -1630,12 +1652,80 @@ int imloc_server_submit(imloc_server* srv, const imloc_corr* pts, int64_t n, con
   return IMLOC_OK;
 }
 
+// Read back round r of a server (its staging half and event) and retire the
+// queries that finished in it: slots admitted for a later round are left
+// alone (their state in this read-back is the previous occupant's).
+static int server_collect(imloc_server* srv, int64_t r, int nq, int64_t* done_tickets, int32_t capacity,
+                          int32_t* ndone) {
+  imloc_ctx* ctx = srv->ctx;
+  const Engine& e = srv->e;
+  const int S = srv->cfg.max_slots;
+  HIP_TRY(ctx, hipEventSynchronize(srv->ev[r & 1]));
+  char* half = ctx->pinned + (size_t)(r & 1) * server_half_bytes(S);
+  const size_t tab = (size_t)S * sizeof(QueryDesc);
+  const BestState* hst = reinterpret_cast<const BestState*>(half + tab);
+  const double* hfin = reinterpret_cast<const double*>(half + tab + (size_t)e.nq * sizeof(BestState));
+  for (int i = 0; i < nq; ++i) {
+    ServerSlot& sl = srv->slots[i];
+    if (!sl.used || sl.first_round > r) continue;
+    const BestState& b = hst[i];
+    if (b.finished != 2) continue;
+    Finished f;
+    const bool have = b.have != 0;
+    f.status = have ? IMLOC_OK : IMLOC_NO_POSE;
+    identity_pose(&f.pose);
+    if (have) {
+      for (int x = 0; x < 9; ++x) f.pose.R[x] = hfin[12 * i + x];
+      for (int x = 0; x < 3; ++x) f.pose.t[x] = hfin[12 * i + 9 + x];
+    }
+    std::memset(&f.stats, 0, sizeof(f.stats));
+    f.stats.samples = b.drawn;
+    f.stats.candidates = b.candidates;
+    f.stats.residuals = b.candidates * sl.pl.m;
+    f.stats.inlier_residuals = b.inlier_residuals;
+    f.stats.best_count = have ? b.count : 0;
+    f.stats.full_count = have ? b.full_count : 0;
+    f.stats.batches = b.batches;
+    f.stats.lo_runs = (int32_t)b.lo_runs;
+    f.stats.status = f.status;
+    f.stats.best_msac = have ? b.cost : 0.0;
+    f.stats.final_cost = have ? hfin[12 * e.nq + i] : 0.0;
+    f.stats.best_h = have ? b.h : -1;
+    f.stats.best_j = have ? b.j : -1;
+    f.stats.score_launches = (int32_t)b.batches;
+    srv->done[sl.q.ticket] = f;
+    if (done_tickets && *ndone < capacity) done_tickets[*ndone] = sl.q.ticket;
+    ++*ndone;
+    srv->cand_pool.release(sl.cand_off, sl.cand_len);
+    srv->bytes_pool.release(sl.byte_off, sl.byte_len);
+    sl.used = false;
+  }
+  return IMLOC_OK;
+}
+
+// One step: admit, enqueue round r for every resident query, then read back
+// round r - 1 (enqueued by the previous step) while round r runs, so the
+// host's work overlaps the device's.  A query that finished in round r - 1 is
+// still in round r's table (retired on the device, so every kernel skips it)
+// and its slot and pool ranges are freed here, for the next step's
+// admission.  Round r stays in flight only while queries wait in the queue
+// (then the next step's admission overlaps it); otherwise it is read back
+// before the step returns.
 int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity, int32_t* n_done,
                       int32_t* n_resident, int32_t* n_queued) {
   if (!srv) return IMLOC_EINVAL;
   imloc_ctx* ctx = srv->ctx;
   Engine& e = srv->e;
   const int S = srv->cfg.max_slots;
+  const int64_t r = srv->rounds;  // the round this step enqueues
+  int32_t ndone = 0;
+  // a previous round that has already completed is read back first, so that
+  // its finished queries free their slots for this step's admission
+  if (srv->inflight && hipEventQuery(srv->ev[srv->inflight_round & 1]) == hipSuccess) {
+    const int rc = server_collect(srv, srv->inflight_round, srv->inflight_nq, done_tickets, capacity, &ndone);
+    if (rc) return rc;
+    srv->inflight = false;
+  }
   // admission, first come first served: a slot and room in both pools
   while (!srv->queue.empty()) {
     const ServerQuery& q = srv->queue.front();
@@ -1655,6 +1745,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     ServerSlot& sl = srv->slots[slot];
     sl.used = true;
     sl.fresh = true;
+    sl.first_round = r;
     sl.q = q;
     sl.pl = pl;
     sl.cand_off = co;
@@ -1663,13 +1754,12 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     sl.byte_len = bl;
     srv->queue.pop_front();
   }
-  int nq = 0, kmax = 1, chunks_lo = 1, chunks_fin = 1, lo_iters = 0, fin_iters = 0, resident = 0;
+  int nq = 0, kmax = 1, chunks_lo = 1, chunks_fin = 1, lo_iters = 0, fin_iters = 0;
   int64_t max_batch = 1, max_n = 0, max_m_sub = 0;
   EstList est;
   for (int i = 0; i < S; ++i) {
     const ServerSlot& sl = srv->slots[i];
     if (!sl.used) continue;
-    ++resident;
     est.push_back({std::min(sl.pl.batch, sl.pl.total), est_chunks(sl.pl)});
     nq = i + 1;
     kmax = std::max(kmax, sl.pl.k);
@@ -1681,15 +1771,14 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     max_n = std::max(max_n, sl.pl.n);
     if (sl.pl.subset && sl.fresh) max_m_sub = std::max(max_m_sub, sl.pl.m);
   }
-  int32_t ndone = 0;
   if (nq > 0) {
     kmax = srv->cfg.max_top_k;  // problem index layout of the LO buffers
     const size_t tab = (size_t)nq * sizeof(QueryDesc);
-    // the table and the results of all slots must fit (imloc_set_staging, between steps)
-    int rc = staging_check(ctx, (size_t)S * (sizeof(QueryDesc) + sizeof(BestState) + 13 * sizeof(double)) + 512);
-    if (!rc) rc = staging_wait(ctx);  // an earlier asynchronous call may still copy from the staging buffer
+    int rc = staging_check(ctx, 2 * server_half_bytes(S));
     if (rc) return rc;
-    QueryDesc* htab = reinterpret_cast<QueryDesc*>(ctx->pinned);
+    // the half of round r was last used by round r - 2, read back by the previous step
+    char* half = ctx->pinned + (size_t)(r & 1) * server_half_bytes(S);
+    QueryDesc* htab = reinterpret_cast<QueryDesc*>(half);
     for (int i = 0; i < nq; ++i) {
       ServerSlot& sl = srv->slots[i];
       if (!sl.used) {
@@ -1712,6 +1801,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
       }
       d.fresh = sl.fresh ? 1 : 0;
       htab[i] = d;
+      sl.fresh = false;
     }
     hipSetDevice(ctx->device);
     hipStream_t s = ctx->stream;
@@ -1734,49 +1824,31 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     if (!mask_done) HIP_TRY(ctx, launch_mask(e.qd, e.st, e.fin_pose, nq, max_n, 0, s));
     HIP_TRY(ctx, launch_retire(e.st, nq, s));
     // the results block is laid out for all e.nq slots (the table may be shorter)
-    BestState* hst = reinterpret_cast<BestState*>(ctx->pinned + tab);
-    double* hfin = reinterpret_cast<double*>(ctx->pinned + tab + (size_t)e.nq * sizeof(BestState));
-    HIP_TRY(ctx, hipMemcpyAsync(hst, e.st, result_bytes(e.nq), hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    srv->rounds++;
-    for (int i = 0; i < nq; ++i) {
-      ServerSlot& sl = srv->slots[i];
-      if (!sl.used) continue;
-      sl.fresh = false;
-      const BestState& b = hst[i];
-      if (b.finished != 2) continue;
-      Finished f;
-      const bool have = b.have != 0;
-      f.status = have ? IMLOC_OK : IMLOC_NO_POSE;
-      identity_pose(&f.pose);
-      if (have) {
-        for (int x = 0; x < 9; ++x) f.pose.R[x] = hfin[12 * i + x];
-        for (int x = 0; x < 3; ++x) f.pose.t[x] = hfin[12 * i + 9 + x];
-      }
-      std::memset(&f.stats, 0, sizeof(f.stats));
-      f.stats.samples = b.drawn;
-      f.stats.candidates = b.candidates;
-      f.stats.residuals = b.candidates * sl.pl.m;
-      f.stats.inlier_residuals = b.inlier_residuals;
-      f.stats.best_count = have ? b.count : 0;
-      f.stats.full_count = have ? b.full_count : 0;
-      f.stats.batches = b.batches;
-      f.stats.lo_runs = (int32_t)b.lo_runs;
-      f.stats.status = f.status;
-      f.stats.best_msac = have ? b.cost : 0.0;
-      f.stats.final_cost = have ? hfin[12 * e.nq + i] : 0.0;
-      f.stats.best_h = have ? b.h : -1;
-      f.stats.best_j = have ? b.j : -1;
-      f.stats.score_launches = (int32_t)b.batches;
-      srv->done[sl.q.ticket] = f;
-      if (done_tickets && ndone < capacity) done_tickets[ndone] = sl.q.ticket;
-      ++ndone;
-      srv->cand_pool.release(sl.cand_off, sl.cand_len);
-      srv->bytes_pool.release(sl.byte_off, sl.byte_len);
-      sl.used = false;
-      --resident;
+    HIP_TRY(ctx, hipMemcpyAsync(half + (size_t)S * sizeof(QueryDesc), e.st, result_bytes(e.nq),
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipEventRecord(srv->ev[r & 1], s));
+  }
+  if (srv->inflight) {  // round r - 1 runs (or ran) ahead of round r: read it back now
+    const int rc = server_collect(srv, srv->inflight_round, srv->inflight_nq, done_tickets, capacity, &ndone);
+    if (rc) return rc;
+    srv->inflight = false;
+  }
+  if (nq > 0) {
+    srv->rounds = r + 1;
+    if (srv->queue.empty()) {
+      // nothing waits for admission, so there is no host work to overlap:
+      // read round r back now (a query that finishes is reported at once
+      // and no round is spent on it after it finished)
+      const int rc = server_collect(srv, r, nq, done_tickets, capacity, &ndone);
+      if (rc) return rc;
+    } else {
+      srv->inflight = true;
+      srv->inflight_round = r;
+      srv->inflight_nq = nq;
     }
   }
+  int32_t resident = 0;
+  for (int i = 0; i < S; ++i) resident += srv->slots[i].used ? 1 : 0;
   if (n_done) *n_done = ndone;
   if (n_resident) *n_resident = resident;
   if (n_queued) *n_queued = (int32_t)srv->queue.size();

@@ -6,7 +6,7 @@ is shared by the GPU-path tests, the oracle tests and the benchmark so that both
 sides see the same float32 arrays.
 
 The paper evaluates on Oxford Day & Night, LaMAR, Cambridge Landmarks and
-Aachen with RoMa dense matches from the top-K retrieved database images
+Aachen, matching each query densely (RoMa) against its K best database views
 (K = 10 or 50 at 560 x 560, Sec. 3.3 / Sec. 4).  Those datasets and the matcher
 weights are not available, so every generator below stands in for them with
 the same shapes: thousands of dense matches per retrieved view, inlier ratios

@@ -289,8 +289,8 @@ def test_ransac_subsample_and_weights(pk, ctx, orc):
 def test_ransac_paper_mode(pk, ctx, orc):
     """The paper's own settings (Sec. 3.3 "Pose Estimation"): stride subsample
     to at most 10,000 scoring points, batches of 1,000 minimal sets, local
-    optimisation of a new best, stop at 100,000 samples or when the chance of
-    missing the best model is below 1e-4, confidence-weighted costs, final
+    optimisation of a new best, stop at 100,000 samples or once the
+    probability that an all-inlier sample was never drawn falls under 1e-4, confidence-weighted costs, final
     Cauchy refinement over the full set."""
     q = synth.make_query(120, 50000, 0.25, 1.5, weights="conf", n_views=10)
     rc, R, t, st, mask, ref = _run_both(pk, ctx, orc, q, threshold_px=6.0, batch=1000, min_iters=1000,

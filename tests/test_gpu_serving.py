@@ -1,5 +1,6 @@
 """Serving by continuous batching: queries admitted by memory footprint into a
-resident slot table, one round per step for every resident query.  Each
+resident slot table, one round per step for every resident query (a two-deep
+pipeline: a step enqueues a round and reads back the previous one).  Each
 result equals what the query gives alone; admission respects the pools; a
 failing query fails alone."""
 import numpy as np
@@ -88,4 +89,20 @@ def test_server_interleaved_arrivals(pk):
     srv = pk.Server(0, max_slots=4, max_top_k=8, max_n=40000)
     out, steps = _run_server(pk, srv, qs, P, arrive_every=2)
     _check_alone(pk, qs, P, out)
+    srv.close()
+
+
+def test_server_one_slot_pipeline(pk):
+    """One slot: every query reuses it right after the previous one leaves,
+    while the pipeline has a round in flight; results equal alone, and once
+    everything is reported further steps do nothing."""
+    qs, ps = _queries()
+    P = [pk.make_params(**p) for p in ps]
+    srv = pk.Server(0, max_slots=1, max_top_k=8, max_n=40000, candidate_pool=4 * 3000 + 4 * 1024,
+                    byte_pool=300000)
+    out, steps = _run_server(pk, srv, qs, P)
+    _check_alone(pk, qs, P, out)
+    for _ in range(3):
+        done, resident, queued = srv.step()
+        assert done == [] and resident == 0 and queued == 0
     srv.close()
