@@ -608,6 +608,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-query-per-call form")
     ap.add_argument("--serving-queries", type=int, default=2000)
     ap.add_argument("--headline-only", action="store_true", help="skip every sub-leg")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="skip the headline batch (for profiling a sub-leg alone; the line then has no headline)")
     ap.add_argument("--legs", default="single_large,single_small,serving,lift_ransac,paper_mode,mapping_depth,rig",
                     help="comma-separated sub-legs to run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
@@ -629,7 +631,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    out = headline(pk, args)
+    out = dict(headline="skipped (--legs-only)") if args.legs_only else headline(pk, args)
     legs = [] if args.headline_only else [x for x in args.legs.split(",") if x]
     table = dict(single_large=lambda: single_large_leg(pk, args), single_small=lambda: single_small_leg(pk),
                  serving=lambda: serving_leg(pk, args), lift_ransac=lambda: e2e_leg(pk),
