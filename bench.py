@@ -68,6 +68,11 @@ def _traffic(kernel_src, workload, shape):
         return None
 
 
+def _score_kernel_name(ct):
+    """The scoring kernel's name for a candidate tile (0: the tile is picked per round)."""
+    return f"score_kernel<{ct}>" if ct > 0 else "score_kernel<CT picked per round>"
+
+
 def _rot_deg(Ra, Rb):
     import numpy as np
     M = Ra @ Rb.T
@@ -199,7 +204,7 @@ def headline(pk, args):
     kernel_src = os.path.join(ROOT, "paper_2601_04185_amd", "csrc", "score.hip")
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_F32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_F32_TFLOPS, 4), traffic=_traffic(kernel_src, "batch256", (ct, wg)),
-                    kernel=f"score_kernel<{ct}>", launch_ms=round(launch_ms, 4), flop_per_launch=int(flops),
+                    kernel=_score_kernel_name(ct), launch_ms=round(launch_ms, 4), flop_per_launch=int(flops),
                     residuals_per_launch=res, residuals_per_s_kernel=round(res / (launch_ms * 1e-3), 1),
                     launch_shape=dict(candidates_per_item=ct, workgroups=wg))
 
@@ -315,7 +320,7 @@ def single_large_leg(pk, args):
                residuals_per_s=round(st["residuals"] / float(np.median(lat)), 1),
                stage_ms={k: round(stage[k], 4) for k in ("ms_sample", "ms_score", "ms_select", "ms_lo", "ms_refine",
                                                          "ms_total")},
-               score_launch=dict(kernel=f"score_kernel<{ctx.score_tuning()[0]}>", launch_ms=round(launch_ms, 4),
+               score_launch=dict(kernel=_score_kernel_name(ctx.score_tuning()[0]), launch_ms=round(launch_ms, 4),
                                  achieved_tflops=round(flops / (launch_ms * 1e-3) / 1e12, 3),
                                  frac_of_peak=round(flops / (launch_ms * 1e-3) / 1e12 / PEAK_F32_TFLOPS, 4),
                                  launch_shape=dict(zip(("candidates_per_item", "workgroups"), ctx.score_tuning()))),
