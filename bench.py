@@ -50,8 +50,8 @@ def _traffic(kernel_src, workload, shape):
     """HBM bytes per launch from the committed counter summary of this
     workload and launch shape, if it was taken on the current source of the
     kernel; else None."""
-    ct, wg = shape
-    p = os.path.join(ROOT, "profiles", f"score_{workload}_traffic_{ct}x{wg}.txt")
+    ct, pts, wg = shape
+    p = os.path.join(ROOT, "profiles", f"score_{workload}_traffic_{ct}x{pts}x{wg}.txt")
     if not os.path.exists(p):
         return None
     d = {}
@@ -60,12 +60,26 @@ def _traffic(kernel_src, workload, shape):
             k, v = line.split(":", 1)
             d[k.strip()] = v.strip()
     if (d.get("workload") != workload or d.get("kernel_src_sha256_16") != _file_hash(kernel_src)
-            or d.get("candidates_per_item") != str(ct) or d.get("workgroups") != str(wg)):
+            or d.get("candidates_per_item") != str(ct) or d.get("points_per_item") != str(pts)
+            or d.get("workgroups") != str(wg)):
         return None
     try:
         return float(d["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def set_shape(ctx, spec):
+    """--score-shape CT,WG[,PTS]: candidates per item, workgroups, correspondences per item."""
+    v = [int(x) for x in spec.split(",")]
+    ctx.set_score_tuning(v[0], v[1])
+    if len(v) > 2:
+        ctx.set_score_points(v[2])
+
+
+def copy_shape(src, dst):
+    dst.set_score_tuning(*src.score_tuning())
+    dst.set_score_points(src.score_points())
 
 
 def _score_kernel_name(ct):
@@ -169,7 +183,7 @@ def headline(pk, args):
     ctx = pk.Context(0, graphs=True)  # fixed samples: one captured hipGraph per batch shape, replayed
     tuned = None
     if args.score_shape:
-        ctx.set_score_tuning(*(int(x) for x in args.score_shape.split(",")))
+        set_shape(ctx, args.score_shape)
     elif not args.no_tune:
         from paper_2601_04185_amd.autotune import tune_scoring
         tuned = tune_scoring(ctx, lambda c: run(c)[2], reps=args.tune_reps)
@@ -191,7 +205,7 @@ def headline(pk, args):
 
     # the scoring kernel's launch, HIP events on the library's stream (one round: one launch per call)
     tctx = pk.Context(0, timing=True)
-    tctx.set_score_tuning(*ctx.score_tuning())
+    copy_shape(ctx, tctx)
     launch, stage = [], None
     for _ in range(max(5, min(args.steps, 20))):
         _, _, st_t = run(tctx)
@@ -201,12 +215,13 @@ def headline(pk, args):
     flops = FLOP_PER_RESIDUAL * res + FLOP_PER_INLIER * inl
     achieved = flops / (launch_ms * 1e-3) / 1e12
     ct, wg = ctx.score_tuning()
+    pts = ctx.score_points()
     kernel_src = os.path.join(ROOT, "paper_2601_04185_amd", "csrc", "score.hip")
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_F32_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_F32_TFLOPS, 4), traffic=_traffic(kernel_src, "batch256", (ct, wg)),
+                    frac=round(achieved / PEAK_F32_TFLOPS, 4), traffic=_traffic(kernel_src, "batch256", (ct, pts, wg)),
                     kernel=_score_kernel_name(ct), launch_ms=round(launch_ms, 4), flop_per_launch=int(flops),
                     residuals_per_launch=res, residuals_per_s_kernel=round(res / (launch_ms * 1e-3), 1),
-                    launch_shape=dict(candidates_per_item=ct, workgroups=wg))
+                    launch_shape=dict(candidates_per_item=ct, points_per_item=pts, workgroups=wg))
 
     out = dict(metric=METRIC, value=round(res * args.steps / total, 1), unit="residuals/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(total / args.steps * 1e3, 4),
@@ -234,7 +249,7 @@ def headline(pk, args):
     # the plain form: one query per call, same seeds and parameters
     if not args.no_plain:
         pctx = pk.Context(0, graphs=True)
-        pctx.set_score_tuning(*ctx.score_tuning())
+        copy_shape(ctx, pctx)
         for i in range(4):
             pk.imloc_lo_ransac_pnp(pctx, ds[i], Ks[i], prms[i])
         torch.cuda.synchronize()
@@ -302,7 +317,7 @@ def single_large_leg(pk, args):
         rc, R, t, st = pk.imloc_lo_ransac_pnp(ctx, d, q.K, prm)
         lat.append(time.perf_counter() - s)
     tctx = pk.Context(0, timing=True)
-    tctx.set_score_tuning(*ctx.score_tuning())
+    copy_shape(ctx, tctx)
     per, inl, stage = [], [], None
     for _ in range(20):
         _, _, _, s2 = pk.imloc_lo_ransac_pnp(tctx, d, q.K, prm)
@@ -323,7 +338,9 @@ def single_large_leg(pk, args):
                score_launch=dict(kernel=_score_kernel_name(ctx.score_tuning()[0]), launch_ms=round(launch_ms, 4),
                                  achieved_tflops=round(flops / (launch_ms * 1e-3) / 1e12, 3),
                                  frac_of_peak=round(flops / (launch_ms * 1e-3) / 1e12 / PEAK_F32_TFLOPS, 4),
-                                 launch_shape=dict(zip(("candidates_per_item", "workgroups"), ctx.score_tuning()))),
+                                 launch_shape=dict(candidates_per_item=ctx.score_tuning()[0],
+                                                   points_per_item=ctx.score_points(),
+                                                   workgroups=ctx.score_tuning()[1])),
                accuracy=dict(vs_oracle=vs_oracle([(R, t, ref)]), vs_truth=recall([(R, t, q.R, q.t)])),
                graph_captures_replays=list(ctx.graph_counters()))
     if tuned is not None:
@@ -607,7 +624,8 @@ def main():
     ap.add_argument("--tune-reps", type=int, default=3, help="timed runs per candidate scoring shape")
     ap.add_argument("--no-tune", action="store_true", help="keep the default scoring launch shape")
     ap.add_argument("--score-shape", default=None,
-                    help="CT,WG: scoring launch shape (candidates per item, workgroups) instead of autotuning")
+                    help="CT,WG[,PTS]: scoring launch shape (candidates per item, workgroups, correspondences per "
+                         "item) instead of autotuning")
     ap.add_argument("--cpu-queries", type=int, default=8, help="queries of the batch the all-core oracle runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-query-per-call form")

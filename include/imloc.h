@@ -194,6 +194,17 @@ int imloc_graph_counters(const imloc_ctx *ctx, int64_t *captures, int64_t *launc
 int imloc_set_score_tuning(imloc_ctx *ctx, int32_t candidates_per_item, int32_t workgroups);
 int imloc_get_score_tuning(const imloc_ctx *ctx, int32_t *candidates_per_item, int32_t *workgroups);
 
+/* Correspondence tile of the float32 scoring kernel: correspondences per work
+ * item, 512, 1024, 2048 (default) or 4096.  A wave always scores a block of
+ * 512 consecutive correspondences against a candidate, and the per-block
+ * partial sums are added as integers, so the tile changes no result, only
+ * the speed (longer items stage each candidate tile once for more
+ * correspondences; shorter ones give more items to small rounds).  Float64
+ * scoring keeps its own 512-correspondence items.  IMLOC_EINVAL for other
+ * values. */
+int imloc_set_score_points(imloc_ctx *ctx, int32_t points_per_item);
+int imloc_get_score_points(const imloc_ctx *ctx, int32_t *points_per_item);
+
 /* Launch form of the Gauss-Newton runs (local optimisation and final
  * refinement): 0 (default) picks by size, 1 = one launch per iteration in
  * which every workgroup of a problem re-reduces the previous partial sums,

@@ -31,6 +31,7 @@ EXPORTED = ["imloc_create", "imloc_destroy", "imloc_set_stream", "imloc_last_err
             "imloc_workspace_bytes", "imloc_batch_workspace_bytes", "imloc_score_workspace_bytes",
             "imloc_lift_workspace_bytes", "imloc_lo_workspace_bytes", "imloc_refine_workspace_bytes",
             "imloc_sample_workspace_bytes", "imloc_set_timing", "imloc_set_score_tuning", "imloc_get_score_tuning",
+            "imloc_set_score_points", "imloc_get_score_points",
             "imloc_set_graphs", "imloc_graph_counters", "imloc_server_workspace_bytes", "imloc_server_create",
             "imloc_server_destroy", "imloc_server_submit", "imloc_server_step", "imloc_server_poll",
             "imloc_server_usage",
@@ -123,6 +124,8 @@ def lib():
             "imloc_server_poll": ([vp, i64, vp, vp], C.c_int),
             "imloc_server_usage": ([vp, vp, vp], C.c_int),
             "imloc_get_score_tuning": ([vp, vp, vp], C.c_int),
+            "imloc_set_score_points": ([vp, i32], C.c_int),
+            "imloc_get_score_points": ([vp, vp], C.c_int),
             "imloc_score_workspace_bytes": ([i64, i64, i32], C.c_size_t),
             "imloc_lift_workspace_bytes": ([i64, i32], C.c_size_t),
             "imloc_lo_workspace_bytes": ([i64, i32], C.c_size_t),
@@ -248,6 +251,15 @@ class Context:
         a, b = C.c_int32(), C.c_int32()
         self.check(lib().imloc_get_score_tuning(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def set_score_points(self, points_per_item: int):
+        """Correspondences per float32 scoring work item (512, 1024, 2048, 4096; no result changes)."""
+        self.check(lib().imloc_set_score_points(self.h, int(points_per_item)))
+
+    def score_points(self) -> int:
+        a = C.c_int32()
+        self.check(lib().imloc_get_score_points(self.h, C.byref(a)))
+        return a.value
 
     def ensure_staging(self, n_queries: int, n_rig_cameras: int = 0):
         """Grow the context's pinned host staging (a setup call, outside the

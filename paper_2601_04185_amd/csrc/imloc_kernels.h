@@ -22,6 +22,7 @@ struct CamH { double fx, fy, cx, cy; };
 constexpr int kMaxTopK = 32;       // local optimisations per query and batch, at most
 constexpr int kMaxCams = 8;        // cameras of a rig query, at most
 constexpr int kScorePPL32 = 8;     // correspondences per lane, float32 scoring (fixes the summation order)
+constexpr int kScoreWaveBlock = 64 * kScorePPL32;  // a wave's 512 consecutive correspondences, float32 scoring
 constexpr int kScorePPL64 = 2;     // correspondences per lane, float64 scoring
 constexpr double kGainScale = 4294967296.0;  // fixed-point scale of the accumulated truncated-cost gain
 
@@ -182,8 +183,10 @@ hipError_t launch_set_candidates(const QueryDesc* qd, const double* poses, int64
 struct ScoreTune {
   int ct;       // candidates per work item (32, 64 or 128)
   int blocks;   // persistent workgroups
+  int pts;      // correspondences per float32 work item (512, 1024, 2048 or 4096)
 };
-hipError_t launch_worklist(const QueryDesc* qd, CandBuf cb, int nq, int ct, int64_t* item_off, hipStream_t s);
+hipError_t launch_worklist(const QueryDesc* qd, CandBuf cb, int nq, ScoreTune tune, int64_t* item_off,
+                           hipStream_t s);
 hipError_t launch_score(const QueryDesc* qd, CandBuf cb, BestState* st, int nq, const int64_t* item_off,
                         ScoreTune tune, int precision, hipStream_t s);
 // truncated cost of the candidates of query 0: count and msac outputs

@@ -119,7 +119,7 @@ struct imloc_ctx {
   // timing events, created when timing is switched on (imloc_set_timing)
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
-  ScoreTune tune{0, 2048};  // ct == 0: the candidate tile is picked per round (round_tune)
+  ScoreTune tune{0, 2048, 2048};  // ct == 0: the candidate tile is picked per round (round_tune)
   int cus = 256;
   int gn_mode = 0;  // Gauss-Newton launch form: 0 by size, 1 fused, 2 split
   // hipGraph replay of the fixed-sample pipeline
@@ -206,22 +206,24 @@ struct QPlan {
 // Scoring launch shape: the context's fixed one, or (ct == 0) the largest
 // candidate tile of 128, 64 and 32 that still gives about four work items per
 // CU, so that small rounds keep every CU busy; est holds per query the
-// expected candidates (one per sample) and scoring chunks.  The tile never
-// changes a result (per-candidate sums are integer-accumulated).
+// expected candidates (one per sample) and scoring points.  Neither the tile
+// nor the correspondences per item change a result (per-candidate sums are
+// integer-accumulated over fixed wave blocks).
 using EstList = SmallVec<std::pair<int64_t, int64_t>, 4>;
 ScoreTune round_tune(const imloc_ctx* c, const std::pair<int64_t, int64_t>* est, size_t n_est) {
   if (c->tune.ct > 0) return c->tune;
+  const int64_t pts = c->tune.pts;
   for (int ct : {128, 64}) {
     int64_t items = 0;
-    for (size_t q = 0; q < n_est; ++q) items += (est[q].first + ct - 1) / ct * est[q].second;
-    if (items >= 4 * (int64_t)c->cus) return ScoreTune{ct, c->tune.blocks};
+    for (size_t q = 0; q < n_est; ++q) items += (est[q].first + ct - 1) / ct * ((est[q].second + pts - 1) / pts);
+    if (items >= 4 * (int64_t)c->cus) return ScoreTune{ct, c->tune.blocks, c->tune.pts};
   }
-  return ScoreTune{32, c->tune.blocks};
+  return ScoreTune{32, c->tune.blocks, c->tune.pts};
 }
 
-// Scoring chunks of a query, estimated from its plan (2,048 points per chunk
-// in float32 scoring; a rig cuts its segments apart).
-int64_t est_chunks(const QPlan& pl) { return (pl.m + 2047) / 2048 + (pl.ncam > 1 ? pl.ncam - 1 : 0); }
+// Scoring points of a query for the estimate above (a rig cuts its segments
+// apart: about one more partial item per further camera).
+int64_t est_points(const QPlan& pl) { return pl.m + (pl.ncam > 1 ? (int64_t)(pl.ncam - 1) * 2048 : 0); }
 
 // Host view of a rig query (ncam == 0: a one-camera query).
 struct RigHost {
@@ -604,7 +606,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
   Timer tm(ctx);
   int rounds = 0;
   EstList est(nq);
-  for (int q = 0; q < nq; ++q) est[q] = {std::min(pl[q].batch, pl[q].total), est_chunks(pl[q])};
+  for (int q = 0; q < nq; ++q) est[q] = {std::min(pl[q].batch, pl[q].total), est_points(pl[q])};
   const ScoreTune tune = round_tune(ctx, est.data(), est.size());
   // The whole pipeline of a batch, enqueued on stream `st_`: table upload,
   // rounds, final refinement, mask, readback into pinned memory.  `sync`
@@ -620,7 +622,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       hipEvent_t e0 = tm.begin();
       if (e.any_single) HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
       if (e.any_rig) HIP_TRY(ctx, launch_sample_gp3p(e.qd, e.st, e.cb, nq, e.max_batch, nullptr, st_));
-      HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, tune.ct, e.item_off, st_));
+      HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, tune, e.item_off, st_));
       tm.end(kStSample, e0);
       hipEvent_t e1 = tm.begin();  // the scoring span holds the scoring kernel alone
       HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, tune, 0, st_));
@@ -656,8 +658,8 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
     // key of everything a captured graph bakes in: shapes, workspace, staging
     std::string key;
     char buf[160];
-    snprintf(buf, sizeof(buf), "%d|%p|%p|%d|%d|%d|%d|%d|", nq, (void*)ws.base, (void*)ctx->pinned, tune.ct,
-             tune.blocks, e.lo_iters, e.fin_iters, ctx->gn_mode);
+    snprintf(buf, sizeof(buf), "%d|%p|%p|%d|%d|%d|%d|%d|%d|", nq, (void*)ws.base, (void*)ctx->pinned, tune.ct,
+             tune.blocks, tune.pts, e.lo_iters, e.fin_iters, ctx->gn_mode);
     key += buf;
     for (int q = 0; q < nq; ++q) {
       snprintf(buf, sizeof(buf), "%lld,%lld,%d,%lld,%lld,%d,%d;", (long long)pl[q].n, (long long)pl[q].m,
@@ -936,6 +938,20 @@ int imloc_get_score_tuning(const imloc_ctx* c, int32_t* candidates_per_item, int
   if (!c || !candidates_per_item || !workgroups) return IMLOC_EINVAL;
   *candidates_per_item = c->tune.ct;
   *workgroups = c->tune.blocks;
+  return IMLOC_OK;
+}
+
+int imloc_set_score_points(imloc_ctx* c, int32_t points_per_item) {
+  if (!c) return IMLOC_EINVAL;
+  if (points_per_item != 512 && points_per_item != 1024 && points_per_item != 2048 && points_per_item != 4096)
+    return set_err(c, IMLOC_EINVAL, "points_per_item must be 512, 1024, 2048 or 4096");
+  c->tune.pts = points_per_item;
+  return IMLOC_OK;
+}
+
+int imloc_get_score_points(const imloc_ctx* c, int32_t* points_per_item) {
+  if (!c || !points_per_item) return IMLOC_EINVAL;
+  *points_per_item = c->tune.pts;
   return IMLOC_OK;
 }
 
@@ -1293,9 +1309,9 @@ int imloc_rig_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imlo
   if (rc) return rc;
   hipStream_t s = ctx->stream;
   HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
-  const std::pair<int64_t, int64_t> est1{np, est_chunks(sq.pl)};
+  const std::pair<int64_t, int64_t> est1{np, est_points(sq.pl)};
   const ScoreTune tune = round_tune(ctx, &est1, 1);
-  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune.ct, sq.e.item_off, s));
+  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune, sq.e.item_off, s));
   HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, tune, precision, s));
   HIP_TRY(ctx, launch_candidate_costs(sq.e.qd, sq.e.st, sq.e.cb, np, count, msac, s));
   return IMLOC_OK;
@@ -1337,9 +1353,9 @@ int imloc_score(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const imloc_ca
   if (rc) return rc;
   hipStream_t s = ctx->stream;
   HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
-  const std::pair<int64_t, int64_t> est1{np, est_chunks(sq.pl)};
+  const std::pair<int64_t, int64_t> est1{np, est_points(sq.pl)};
   const ScoreTune tune = round_tune(ctx, &est1, 1);
-  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune.ct, sq.e.item_off, s));
+  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune, sq.e.item_off, s));
   HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, tune, precision, s));
   HIP_TRY(ctx, launch_candidate_costs(sq.e.qd, sq.e.st, sq.e.cb, np, count, msac, s));
   return IMLOC_OK;
@@ -1373,9 +1389,9 @@ int imloc_select_top_k(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const i
     HIP_TRY(ctx, hipMemcpyAsync(&sq.e.st[0].cost, hg, sizeof(double), hipMemcpyHostToDevice, s));
   }
   HIP_TRY(ctx, launch_set_candidates(sq.e.qd, poses, np, sq.e.cb, s));
-  const std::pair<int64_t, int64_t> est1{np, est_chunks(sq.pl)};
+  const std::pair<int64_t, int64_t> est1{np, est_points(sq.pl)};
   const ScoreTune tune = round_tune(ctx, &est1, 1);
-  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune.ct, sq.e.item_off, s));
+  HIP_TRY(ctx, launch_worklist(sq.e.qd, sq.e.cb, 1, tune, sq.e.item_off, s));
   HIP_TRY(ctx, launch_score(sq.e.qd, sq.e.cb, sq.e.st, 1, sq.e.item_off, tune, precision, s));
   HIP_TRY(ctx, launch_select(sq.e.qd, sq.e.st, sq.e.cb, 1, k, std::max<int64_t>(np, 1), sq.e.sel_part, sel, n_sel, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));  // the staging buffer held the gate
@@ -1760,7 +1776,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
   for (int i = 0; i < S; ++i) {
     const ServerSlot& sl = srv->slots[i];
     if (!sl.used) continue;
-    est.push_back({std::min(sl.pl.batch, sl.pl.total), est_chunks(sl.pl)});
+    est.push_back({std::min(sl.pl.batch, sl.pl.total), est_points(sl.pl)});
     nq = i + 1;
     kmax = std::max(kmax, sl.pl.k);
     chunks_lo = std::max(chunks_lo, gn_chunks(sl.pl.m));
@@ -1811,7 +1827,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     HIP_TRY(ctx, launch_begin_round(e.qd, e.st, e.cb, nq, s));
     HIP_TRY(ctx, launch_sample_p3p(e.qd, e.st, e.cb, nq, max_batch, nullptr, s));
     const ScoreTune tune = round_tune(ctx, est.data(), est.size());
-    HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, tune.ct, e.item_off, s));
+    HIP_TRY(ctx, launch_worklist(e.qd, e.cb, nq, tune, e.item_off, s));
     HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, tune, 0, s));
     HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, 4 * max_batch, e.sel_part, e.sel, e.n_sel, s));
     HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * kmax, kmax, chunks_lo, lo_iters, e.gn_lo,

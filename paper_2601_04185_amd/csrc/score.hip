@@ -56,9 +56,13 @@ __device__ inline float wave_total_dpp(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
-__device__ inline int ppl_of(const QueryDesc& d) { return d.precision ? kScorePPL64 : kScorePPL32; }
-__device__ inline int64_t chunks_of(const QueryDesc& d) {
-  const int64_t per = (int64_t)kScoreBlock * ppl_of(d);
+// Correspondences per work item: `pts` in float32 scoring (a multiple of the
+// 512-correspondence wave block), 256 * kScorePPL64 in float64 scoring.
+__device__ inline int64_t chunk_pts(const QueryDesc& d, int pts) {
+  return d.precision ? (int64_t)kScoreBlock * kScorePPL64 : (int64_t)pts;
+}
+__device__ inline int64_t chunks_of(const QueryDesc& d, int pts) {
+  const int64_t per = chunk_pts(d, pts);
   int64_t c = 0;
   if (d.ncam == 0) {
     c = (d.m + per - 1) / per;
@@ -73,8 +77,8 @@ struct ChunkRange {
   int64_t begin, end;
   int cam;
 };
-__device__ inline ChunkRange chunk_range(const QueryDesc& d, int64_t chunk) {
-  const int64_t per = (int64_t)kScoreBlock * ppl_of(d);
+__device__ inline ChunkRange chunk_range(const QueryDesc& d, int64_t chunk, int pts) {
+  const int64_t per = chunk_pts(d, pts);
   if (d.ncam == 0) return ChunkRange{chunk * per, d.m, 0};
   for (int k = 0; k < d.ncam; ++k) {
     const int64_t nch = (d.segS[k + 1] - d.segS[k] + per - 1) / per;
@@ -89,7 +93,7 @@ __device__ inline ChunkRange chunk_range(const QueryDesc& d, int64_t chunk) {
 // item_off = exclusive prefix, item_off[nq] = total (one workgroup).  Also
 // zeroes the round's selection counters (the selection follows the scoring).
 __global__ __launch_bounds__(1024) void worklist_kernel(const QueryDesc* __restrict__ qd,
-                                                        const int32_t* __restrict__ n_cand, int nq, int ct,
+                                                        const int32_t* __restrict__ n_cand, int nq, int ct, int pts,
                                                         int64_t* __restrict__ item_off, int32_t* __restrict__ sel_done) {
   __shared__ long long s[1024];
   const int seg = (nq + 1023) / 1024;
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(1024) void worklist_kernel(const QueryDesc* __restr
   long long sum = 0;
   for (int q = q0; q < q1; ++q) {
     const QueryDesc& d = qd[q];
-    if (d.B > 0) sum += (long long)((n_cand[q] + ct - 1) / ct) * chunks_of(d);
+    if (d.B > 0) sum += (long long)((n_cand[q] + ct - 1) / ct) * chunks_of(d, pts);
   }
   s[threadIdx.x] = sum;
   __syncthreads();
@@ -112,30 +116,49 @@ __global__ __launch_bounds__(1024) void worklist_kernel(const QueryDesc* __restr
     item_off[q] = run;
     sel_done[q] = 0;
     const QueryDesc& d = qd[q];
-    if (d.B > 0) run += (long long)((n_cand[q] + ct - 1) / ct) * chunks_of(d);
+    if (d.B > 0) run += (long long)((n_cand[q] + ct - 1) / ct) * chunks_of(d, pts);
   }
   if (threadIdx.x == 1023) item_off[nq] = s[1023];
 }
 
-hipError_t launch_worklist(const QueryDesc* qd, CandBuf cb, int nq, int ct, int64_t* item_off, hipStream_t s) {
-  hipLaunchKernelGGL(worklist_kernel, dim3(1), dim3(1024), 0, s, qd, cb.n, nq, ct, item_off, cb.sel_done);
+hipError_t launch_worklist(const QueryDesc* qd, CandBuf cb, int nq, ScoreTune tune, int64_t* item_off,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(worklist_kernel, dim3(1), dim3(1024), 0, s, qd, cb.n, nq, tune.ct, tune.pts, item_off,
+                     cb.sel_done);
   return hipGetLastError();
 }
 
-template <int CT>
+// One float32 work item: CT candidates against pts correspondences.  The
+// correspondences come in wave blocks of 512 (lane l, slot k: block start +
+// 64 k + l); every (candidate, wave block) pair is scored by exactly one wave,
+// whose count and gain partial (a float sum over that block, converted once
+// to fixed point) are then added as integers, so the results do not depend on
+// pts.  pts >= 2048: each wave takes blocks w, w + 4, ... for every
+// candidate; pts < 2048: the waves split into 2048 / pts candidate groups,
+// each of pts / 512 waves (one block each).  MULTI: pts > 2048, compiled
+// apart (the loop over a wave's blocks costs registers the one-block form
+// does not need).
+template <int CT, bool MULTI>
 __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* __restrict__ proj,
                                                uint32_t* __restrict__ ccnt, unsigned long long* __restrict__ cgain,
-                                               BestState* st, int64_t tile, int64_t chunk, int ncand,
+                                               BestState* st, int64_t tile, int64_t chunk, int ncand, int pts,
                                                uint32_t (*s_cnt)[kScoreWaves],
                                                unsigned long long (*s_gain)[kScoreWaves], uint32_t* s_item,
                                                float4 (*s_rows)[3]) {
   constexpr int PPL = kScorePPL32;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  // the wave index in a scalar register: the candidate range and the block
+  // derived from it are wave-uniform, so the candidate loop stays scalar
+  const int lane = threadIdx.x & (kWave - 1), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const float inv_tau = (float)(1.0 / d.tau);
-  const ChunkRange rg = chunk_range(d, chunk);
-  const int64_t base = rg.begin + wave * (kWave * PPL) + lane;
+  const ChunkRange rg = chunk_range(d, chunk, pts);
   const int c0 = (int)(tile * CT);
   const int cend = min(CT, ncand - c0);
+  const int nblk = pts / kScoreWaveBlock;  // wave blocks of the item
+  const int groups = nblk >= kScoreWaves ? 1 : kScoreWaves / nblk;
+  const int wpg = kScoreWaves / groups;    // waves per candidate group
+  const int grp = wave / wpg, gsz = CT / groups;
+  const int cg0 = grp * gsz, cg1 = min(cend, cg0 + gsz);
+  const int rounds = MULTI ? nblk / kScoreWaves : 1;
   // the tile's projection rows into LDS: every wave then reads a candidate's
   // 12 values as three broadcast 16-byte LDS loads into vector registers
   // (a multiply-add with a scalar-register operand issues about 1.7 times
@@ -155,69 +178,72 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
   const auto Y = gmem(d.S.Y);
   const auto Z = gmem(d.S.Z);
   const auto W = gmem(d.S.w);
-  float pu[PPL], pv[PPL], px[PPL], py[PPL], pz[PPL], pw[PPL];
-#pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    const int64_t i = base + (int64_t)k * kWave;
-    if (i < rg.end) {
-      // observations negated, so that du' = a' + pu w is a multiply-add without modifiers
-      pu[k] = -(U[i] * inv_tau); pv[k] = -(V[i] * inv_tau); px[k] = X[i]; py[k] = Y[i]; pz[k] = Z[i];
-      pw[k] = W ? W[i] : 1.0f;
-    } else {  // a NaN residual is never an inlier
-      pu[k] = __builtin_nanf(""); pv[k] = 0.f; px[k] = 0.f; py[k] = 0.f; pz[k] = 0.f; pw[k] = 0.f;
-    }
-  }
-  __syncthreads();
   uint32_t item_cnt = 0;
-  for (int c = 0; c < cend; ++c) {
-    // (the other waves of the SIMD cover the LDS latency)
-    const float4 r0 = s_rows[c][0], r1 = s_rows[c][1], r2 = s_rows[c][2];
-    uint32_t cnt = 0;
-    uint64_t bal[PPL];
-    float dd[PPL], ww[PPL];
+  for (int r = 0; r < rounds; ++r) {
+    const int blk = nblk >= kScoreWaves ? wave + r * kScoreWaves : wave % wpg;
+    const int64_t base = rg.begin + (int64_t)blk * kScoreWaveBlock + lane;
+    float pu[PPL], pv[PPL], px[PPL], py[PPL], pz[PPL], pw[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
-      const float a = fmaf(r0.z, pz[k], fmaf(r0.y, py[k], fmaf(r0.x, px[k], r0.w)));
-      const float b = fmaf(r1.z, pz[k], fmaf(r1.y, py[k], fmaf(r1.x, px[k], r1.w)));
-      const float w = fmaf(r2.z, pz[k], fmaf(r2.y, py[k], fmaf(r2.x, px[k], r2.w)));
-      const float du = fmaf(pu[k], w, a), dv = fmaf(pv[k], w, b);
-      // inlier iff e' < w |w|: the sign of e' - w |w| rounded once (rejects w <= 0 and NaN)
-      dd[k] = fmaf(-w, fabsf(w), fmaf(dv, dv, du * du));
-      ww[k] = w;
-      bal[k] = __ballot(dd[k] < 0.f);
-      cnt += (uint32_t)__popcll(bal[k]);
+      const int64_t i = base + (int64_t)k * kWave;
+      if (i < rg.end) {
+        // observations negated, so that du' = a' + pu w is a multiply-add without modifiers
+        pu[k] = -(U[i] * inv_tau); pv[k] = -(V[i] * inv_tau); px[k] = X[i]; py[k] = Y[i]; pz[k] = Z[i];
+        pw[k] = W ? W[i] : 1.0f;
+      } else {  // a NaN residual is never an inlier
+        pu[k] = __builtin_nanf(""); pv[k] = 0.f; px[k] = 0.f; py[k] = 0.f; pz[k] = 0.f; pw[k] = 0.f;
+      }
     }
-    unsigned long long gfx = 0;
-    if (cnt) {  // G += w_i (w|w| - e') / (w|w|) over the inliers, point slots with no inlier skipped
-      // (the empty volatile statements keep these wave-uniform branches as
-      // branches: most candidates have no inlier in most slots)
-      asm volatile("");
-      float gain = 0.f;
+    if (r == 0) __syncthreads();  // the rows are staged
+    for (int c = cg0; c < cg1; ++c) {
+      // (the other waves of the SIMD cover the LDS latency)
+      const float4 r0 = s_rows[c][0], r1 = s_rows[c][1], r2 = s_rows[c][2];
+      uint32_t cnt = 0;
+      uint64_t bal[PPL];
+      float dd[PPL], ww[PPL];
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        if (bal[k]) {
-          asm volatile("");
-          const float t = ww[k] * fabsf(ww[k]);
-          if (dd[k] < 0.f) gain = fmaf(-pw[k] * dd[k], __builtin_amdgcn_rcpf(t), gain);
-        }
+        const float a = fmaf(r0.z, pz[k], fmaf(r0.y, py[k], fmaf(r0.x, px[k], r0.w)));
+        const float b = fmaf(r1.z, pz[k], fmaf(r1.y, py[k], fmaf(r1.x, px[k], r1.w)));
+        const float w = fmaf(r2.z, pz[k], fmaf(r2.y, py[k], fmaf(r2.x, px[k], r2.w)));
+        const float du = fmaf(pu[k], w, a), dv = fmaf(pv[k], w, b);
+        // inlier iff e' < w |w|: the sign of e' - w |w| rounded once (rejects w <= 0 and NaN)
+        dd[k] = fmaf(-w, fabsf(w), fmaf(dv, dv, du * du));
+        ww[k] = w;
+        bal[k] = __ballot(dd[k] < 0.f);
+        cnt += (uint32_t)__popcll(bal[k]);
       }
-      gain = wave_total_dpp(gain);
-      gfx = (unsigned long long)((double)gain * kGainScale);
-    }
-    item_cnt += cnt;
-    if (lane == 0) {
-      s_cnt[c][wave] = cnt;
-      s_gain[c][wave] = gfx;
+      unsigned long long gfx = 0;
+      if (cnt) {  // G += w_i (w|w| - e') / (w|w|) over the inliers, point slots with no inlier skipped
+        // (the empty volatile statements keep these wave-uniform branches as
+        // branches: most candidates have no inlier in most slots)
+        asm volatile("");
+        float gain = 0.f;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+          if (bal[k]) {
+            asm volatile("");
+            const float t = ww[k] * fabsf(ww[k]);
+            if (dd[k] < 0.f) gain = fmaf(-pw[k] * dd[k], __builtin_amdgcn_rcpf(t), gain);
+          }
+        }
+        gain = wave_total_dpp(gain);
+        gfx = (unsigned long long)((double)gain * kGainScale);
+      }
+      item_cnt += cnt;
+      if (lane == 0) {
+        s_cnt[c][wave] = r == 0 ? cnt : s_cnt[c][wave] + cnt;
+        s_gain[c][wave] = r == 0 ? gfx : s_gain[c][wave] + gfx;
+      }
     }
   }
   if (lane == 0) s_item[wave] = item_cnt;
   __syncthreads();
-  if ((int)threadIdx.x < cend) {
-    const int c = threadIdx.x;
+  if ((int)threadIdx.x < cend) {  // the waves of the candidate's group
+    const int c = threadIdx.x, w0 = (c / gsz) * wpg;
     uint32_t cnt = 0;
     unsigned long long g = 0;
-#pragma unroll
-    for (int w = 0; w < kScoreWaves; ++w) { cnt += s_cnt[c][w]; g += s_gain[c][w]; }
+    for (int w = w0; w < w0 + wpg; ++w) { cnt += s_cnt[c][w]; g += s_gain[c][w]; }
     const int64_t slot = d.cand_off + c0 + c;
     if (cnt) atomicAdd(&ccnt[slot], cnt);
     if (g) atomicAdd(&cgain[slot], g);
@@ -241,7 +267,7 @@ __device__ __forceinline__ void score_item_f64(const QueryDesc& d, const double*
                                                unsigned long long (*s_gain)[kScoreWaves], uint32_t* s_item) {
   constexpr int PPL = kScorePPL64;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const ChunkRange rg = chunk_range(d, chunk);
+  const ChunkRange rg = chunk_range(d, chunk, 0);
   const int64_t base = rg.begin + wave * (kWave * PPL) + lane;
   const double tau2 = d.tau * d.tau;
   double pu[PPL], pv[PPL], px[PPL], py[PPL], pz[PPL], pw[PPL];
@@ -319,14 +345,14 @@ __device__ __forceinline__ void score_item_f64(const QueryDesc& d, const double*
 
 // Persistent workgroups over the work list; every workgroup exits once the
 // item index passes the device-side total.
-template <int CT>
+template <int CT, bool MULTI>
 __global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __restrict__ qd,
                                                             const float* __restrict__ proj,
                                                             const double* __restrict__ pose,
                                                             const int32_t* __restrict__ ncand,
                                                             uint32_t* __restrict__ ccnt,
                                                             unsigned long long* __restrict__ cgain,
-                                                            BestState* __restrict__ st, int nq,
+                                                            BestState* __restrict__ st, int nq, int pts,
                                                             const int64_t* __restrict__ item_off) {
   __shared__ uint32_t s_cnt[CT][kScoreWaves];
   __shared__ unsigned long long s_gain[CT][kScoreWaves];
@@ -340,12 +366,13 @@ __global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __r
       if (item_off[mid] <= w) lo = mid; else hi = mid - 1;
     }
     const QueryDesc& d = qd[lo];
-    const int64_t chunks = chunks_of(d);
+    const int64_t chunks = chunks_of(d, pts);
     const int64_t local = w - item_off[lo];
     const int64_t tile = local / chunks, chunk = local - tile * chunks;
     const int nc = ncand[lo];
     if (d.precision == 0)
-      score_item_f32<CT>(d, proj, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain, s_item, s_rows);
+      score_item_f32<CT, MULTI>(d, proj, ccnt, cgain, st + lo, tile, chunk, nc, pts, s_cnt, s_gain, s_item,
+                                s_rows);
     else
       score_item_f64<CT>(d, pose, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain, s_item);
   }
@@ -356,17 +383,27 @@ hipError_t launch_score(const QueryDesc* qd, CandBuf cb, BestState* st, int nq, 
   (void)precision;
   const dim3 grid(tune.blocks > 0 ? tune.blocks : 2048), block(kScoreBlock);
   unsigned long long* g = reinterpret_cast<unsigned long long*>(cb.gain);
+  const int pts = tune.pts;
+  const bool multi = pts > kScoreBlock * kScorePPL32;
+#define IMLOC_SCORE_LAUNCH(CT)                                                                                 \
+  if (multi)                                                                                                   \
+    hipLaunchKernelGGL((score_kernel<CT, true>), grid, block, 0, s, qd, cb.proj, cb.pose, cb.n, cb.cnt, g, st, nq, \
+                       pts, item_off);                                                                         \
+  else                                                                                                         \
+    hipLaunchKernelGGL((score_kernel<CT, false>), grid, block, 0, s, qd, cb.proj, cb.pose, cb.n, cb.cnt, g, st,    \
+                       nq, pts, item_off);
   switch (tune.ct) {
     case 128:
-      hipLaunchKernelGGL(score_kernel<128>, grid, block, 0, s, qd, cb.proj, cb.pose, cb.n, cb.cnt, g, st, nq, item_off);
+      IMLOC_SCORE_LAUNCH(128)
       break;
     case 64:
-      hipLaunchKernelGGL(score_kernel<64>, grid, block, 0, s, qd, cb.proj, cb.pose, cb.n, cb.cnt, g, st, nq, item_off);
+      IMLOC_SCORE_LAUNCH(64)
       break;
     default:
-      hipLaunchKernelGGL(score_kernel<32>, grid, block, 0, s, qd, cb.proj, cb.pose, cb.n, cb.cnt, g, st, nq, item_off);
+      IMLOC_SCORE_LAUNCH(32)
       break;
   }
+#undef IMLOC_SCORE_LAUNCH
   return hipGetLastError();
 }
 

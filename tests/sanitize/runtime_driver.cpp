@@ -62,6 +62,9 @@ int main() {
   check(imloc_set_workspace(nullptr, nullptr, 0) == IMLOC_EINVAL, "null ctx workspace");
   check(imloc_set_staging(nullptr, 4096) == IMLOC_EINVAL, "null ctx staging");
   check(imloc_get_staging(nullptr) == 0, "null ctx get staging");
+  int32_t pts = 0;
+  check(imloc_set_score_points(nullptr, 2048) == IMLOC_EINVAL, "null ctx score points");
+  check(imloc_get_score_points(nullptr, &pts) == IMLOC_EINVAL, "null ctx get score points");
   check(std::strcmp(imloc_last_error(nullptr), "null context") == 0, "null ctx error");
   // no GPU here: creating a context fails cleanly
   imloc_ctx* ctx = nullptr;

@@ -70,14 +70,16 @@ def test_tuning_does_not_change_results(pk):
     d = pk.to_device(q)
     prm = pk.make_params(threshold_px=4.0, fixed_samples=3000, batch=3000)
     ref = None
-    for ct, wg in [(32, 64), (64, 2048), (128, 517), (64, 1), (0, 4096)]:
+    for ct, wg, pts in [(32, 64, 2048), (64, 2048, 512), (128, 517, 4096), (64, 1, 1024), (0, 4096, 2048),
+                        (0, 4096, 512)]:
         ctx = pk.Context(0)
         ctx.set_score_tuning(ct, wg)
+        ctx.set_score_points(pts)
         rc, R, t, st = pk.imloc_lo_ransac_pnp(ctx, d, q.K, prm)
         cur = (R.tobytes(), t.tobytes(), st["best_msac"], st["inlier_residuals"], st["candidates"])
         if ref is None:
             ref = cur
-        assert cur == ref, (ct, wg)
+        assert cur == ref, (ct, wg, pts)
 
 
 def test_graph_replays_match_eager(pk):

@@ -146,6 +146,39 @@ def test_score_parity(pk, ctx, orc, precision, n, weights):
     assert np.all(np.abs(ms - oms) <= tol + 1e-9)
 
 
+@pytest.mark.parametrize("n", [700, 4097, 70001])
+def test_score_tiles_give_identical_scores(pk, orc, n):
+    """The scoring kernel's tiling (candidates and correspondences per work
+    item, workgroups) changes no score: every per-candidate count and
+    truncated cost is bitwise the same for every shape, and inside the
+    oracle's band."""
+    q = synth.make_query(170 + n, n, 0.4, 1.0, weights="conf")
+    poses = _oracle_pose_set(orc, q, count=130)
+    lo, hi, _ = orc.score_band(poses, q.corr(), q.K, 4.0, band_abs=1e-5, with_f32=True)
+    ref = None
+    for ct, wg, pts in [(128, 2048, 2048), (32, 300, 512), (64, 1024, 1024), (128, 4096, 4096), (32, 7, 4096),
+                        (64, 513, 512)]:
+        c = pk.Context(0)
+        c.set_score_tuning(ct, wg)
+        c.set_score_points(pts)
+        assert c.score_points() == pts
+        cnt, ms = pk.imloc_score(c, _dev(q), q.K, _poses_tensor(poses), 4.0, 0)
+        cur = (cnt.cpu().numpy(), ms.cpu().numpy())
+        assert np.all(cur[0] >= lo) and np.all(cur[0] <= hi), (ct, wg, pts)
+        if ref is None:
+            ref = cur
+        np.testing.assert_array_equal(cur[0], ref[0])
+        np.testing.assert_array_equal(cur[1], ref[1])
+
+
+def test_score_points_rejects_other_values(pk):
+    c = pk.Context(0)
+    for bad in (0, 256, 768, 3000, 8192, -1):
+        with pytest.raises(pk.ImlocError):
+            c.set_score_points(bad)
+    assert c.score_points() == 2048
+
+
 def test_score_ragged_candidate_counts(pk, ctx, orc):
     q = synth.make_query(80, 3000, 0.3, 1.0)
     allp = _oracle_pose_set(orc, q, count=60)

@@ -121,6 +121,29 @@ def test_rig_score_parity(pk, ctx, orc, precision, band, n):
     np.testing.assert_allclose(ms[exact], om[exact], rtol=rtol)
 
 
+def test_rig_scores_identical_across_tiles(pk, orc):
+    """Rig queries chunk every camera's segment on its own; the scores are
+    still independent of the correspondences per work item."""
+    import torch
+    q = synth.make_rig_query(59, 5000, 0.5, 1.0, weights="conf")
+    d = _dev(q)
+    rng = np.random.default_rng(59)
+    from scipy.spatial.transform import Rotation
+    P = np.stack([np.concatenate([(Rotation.from_rotvec(rng.normal(0, 0.01, 3)).as_matrix() @ q.R).reshape(9),
+                                  q.t + rng.normal(0, 0.05, 3)]) for _ in range(90)])
+    ref = None
+    for ct, pts in [(64, 2048), (32, 512), (128, 4096), (64, 1024)]:
+        c = pk.Context(0)
+        c.set_score_tuning(ct, 1024)
+        c.set_score_points(pts)
+        cnt, ms = pk.imloc_rig_score(c, d, q.rig, q.cam_start(), torch.from_numpy(P).cuda(), 4.0, 0)
+        cur = (cnt.cpu().numpy(), ms.cpu().numpy())
+        if ref is None:
+            ref = cur
+        np.testing.assert_array_equal(cur[0], ref[0])
+        np.testing.assert_array_equal(cur[1], ref[1])
+
+
 def _run_both(pk, ctx, orc, q, **kw):
     import torch
     prm = pk.make_params(**kw)
