@@ -416,20 +416,25 @@ def imloc_lift(ctx: Context, matches: dict, depth, cams, poses, subpixel=True, m
     cap = n if capacity is None else int(capacity)
     nv, H, W = depth.shape
     dev = depth.device
-    out = {k: torch.empty(max(cap, 1), dtype=torch.float32, device=dev) for k in ("u", "v", "X", "Y", "Z", "w")}
-    out["src"] = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-    n_out = torch.zeros(1, dtype=torch.int32, device=dev)
-    m = Matches(*[matches[k].data_ptr() for k in ("q_u", "q_v", "db_u", "db_v", "conf", "view")])
-    co = CorrOut(*[out[k].data_ptr() for k in ("u", "v", "X", "Y", "Z", "w", "src")])
-    cams_a = (Camera * nv)(*[_cam(c) for c in np.asarray(cams).reshape(nv, 4)])
-    P = np.asarray(poses, np.float64).reshape(nv, 12)
-    poses_a = (Pose * nv)(*[Pose((C.c_double * 9)(*P[k, :9]), (C.c_double * 3)(*P[k, 9:])) for k in range(nv)])
-    ctx.ensure_workspace(lib().imloc_lift_workspace_bytes(n, nv))
-    fn = lib().imloc_lift_log8 if depth.dtype == torch.uint8 else lib().imloc_lift
     if depth.dtype not in (torch.uint8, torch.float32) or not depth.is_contiguous():
         raise ValueError("depth must be contiguous float32 maps or uint8 code maps")
-    ctx.check(fn(ctx.h, C.byref(m), n, C.c_void_p(depth.data_ptr()), nv, H, W, cams_a, poses_a,
-                 1 if subpixel else 0, C.c_float(min_conf), C.byref(co), cap, C.c_void_p(n_out.data_ptr())))
+    # one allocation for the seven output arrays and the count (the library
+    # always writes the count)
+    c1 = (max(cap, 1) + 63) // 64 * 64  # each array 256-byte aligned
+    buf = torch.empty(7 * c1 + 1, dtype=torch.float32, device=dev)
+    out = {k: buf[i * c1:(i + 1) * c1] for i, k in enumerate(("u", "v", "X", "Y", "Z", "w"))}
+    out["src"] = buf[6 * c1:7 * c1].view(torch.int32)
+    n_out = buf[7 * c1:].view(torch.int32)
+    m = Matches(*[matches[k].data_ptr() for k in ("q_u", "q_v", "db_u", "db_v", "conf", "view")])
+    co = CorrOut(*[out[k].data_ptr() for k in ("u", "v", "X", "Y", "Z", "w", "src")])
+    # Camera and Pose are rows of 4 and 12 doubles
+    cams_a = np.ascontiguousarray(np.asarray(cams, np.float64).reshape(nv, 4))
+    poses_a = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(nv, 12))
+    ctx.ensure_workspace(lib().imloc_lift_workspace_bytes(n, nv))
+    fn = lib().imloc_lift_log8 if depth.dtype == torch.uint8 else lib().imloc_lift
+    ctx.check(fn(ctx.h, C.byref(m), n, C.c_void_p(depth.data_ptr()), nv, H, W, cams_a.ctypes.data_as(C.c_void_p),
+                 poses_a.ctypes.data_as(C.c_void_p), 1 if subpixel else 0, C.c_float(min_conf), C.byref(co), cap,
+                 C.c_void_p(n_out.data_ptr())))
     k = int(n_out.item())
     res = {key: v[:min(k, cap)] for key, v in out.items()}
     res["n"] = k

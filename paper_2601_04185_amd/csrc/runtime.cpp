@@ -1030,8 +1030,7 @@ size_t imloc_lift_workspace_bytes(int64_t n_matches, int32_t n_views) {
   if (n_matches < 0 || n_views < 0) return 0;
   Arena a{nullptr, (size_t)-1};
   const int nb = lift_blocks(n_matches);
-  a.take<double>(4 * (size_t)(n_views > 0 ? n_views : 1));
-  a.take<double>(12 * (size_t)(n_views > 0 ? n_views : 1));
+  a.take<double>(16 * (size_t)(n_views > 0 ? n_views : 1));
   a.take<int32_t>((size_t)(nb > 0 ? nb : 1));
   return a.off + 256;
 }
@@ -1057,8 +1056,9 @@ static int lift_impl(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, 
   hipSetDevice(ctx->device);
   Arena a{ctx->ws, ctx->ws_bytes};
   const int nb = lift_blocks(n_matches);
-  double* dcams = a.take<double>(4 * (size_t)(n_views > 0 ? n_views : 1));
-  double* dposes = a.take<double>(12 * (size_t)(n_views > 0 ? n_views : 1));
+  // the view table: intrinsics of every view, then the poses (one upload)
+  double* dcams = a.take<double>(16 * (size_t)(n_views > 0 ? n_views : 1));
+  double* dposes = dcams + 4 * (size_t)(n_views > 0 ? n_views : 1);
   int32_t* blk = a.take<int32_t>((size_t)(nb > 0 ? nb : 1));
   if (!a.ok) return set_err(ctx, IMLOC_ENOMEM, "workspace too small for lift: need %zu bytes", a.off);
   if (n_matches > 0) {
@@ -1074,8 +1074,7 @@ static int lift_impl(imloc_ctx* ctx, const imloc_matches* m, int64_t n_matches, 
       for (int e = 0; e < 9; ++e) hp[12 * k + e] = poses[k].R[e];
       for (int e = 0; e < 3; ++e) hp[12 * k + 9 + e] = poses[k].t[e];
     }
-    HIP_TRY(ctx, hipMemcpyAsync(dcams, hc, 4 * (size_t)n_views * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(dposes, hp, 12 * (size_t)n_views * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(dcams, hc, 16 * (size_t)n_views * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     rc = staging_mark(ctx);
     if (rc) return rc;
   }
