@@ -311,16 +311,39 @@ def imloc_lo_ransac_pnp_noalloc(ctx: Context, corr: dict, K, params: RansacParam
     return rc, R, t, st.as_dict()
 
 
-def imloc_lo_ransac_pnp_batch(ctx: Context, corrs: list, Ks: list, params, masks=None):
-    """corrs: list of dicts of float32 cuda tensors; params: one RansacParams or a
-    list.  Returns (status list, list of (R, t), list of stats dicts)."""
-    nq = len(corrs)
-    ns = (C.c_int64 * nq)(*[int(c["u"].numel()) for c in corrs])
-    cs = (Corr * nq)(*[corr_struct(c["u"], c["v"], c["X"], c["Y"], c["Z"], c.get("w")) for c in corrs])
-    cams = (Camera * nq)(*[_cam(K) for K in Ks])
-    plist = params if isinstance(params, (list, tuple)) else [params]
-    pa = (RansacParams * len(plist))(*plist)
-    ctx.ensure_workspace(lib().imloc_batch_workspace_bytes(nq, ns, pa, len(plist)))
+class BatchQueries:
+    """The host-side descriptors of a batch of queries -- device pointers of
+    every query's arrays, sizes, intrinsics and parameters -- validated and
+    packed once, for callers that run the same device buffers repeatedly
+    (their contents may change between calls).  imloc_lo_ransac_pnp_batch
+    accepts it in place of the three lists; the library still builds, uploads
+    and runs everything per call."""
+
+    def __init__(self, corrs: list, Ks: list, params):
+        self.nq = nq = len(corrs)
+        self.corrs = corrs  # keeps the tensors alive
+        self.ns = (C.c_int64 * nq)(*[int(c["u"].numel()) for c in corrs])
+        self.cs = (Corr * nq)(*[corr_struct(c["u"], c["v"], c["X"], c["Y"], c["Z"], c.get("w")) for c in corrs])
+        self.cams = (Camera * nq)(*[_cam(K) for K in Ks])
+        plist = params if isinstance(params, (list, tuple)) else [params]
+        self.np = len(plist)
+        self.pa = (RansacParams * self.np)(*plist)
+        self.ws_bytes = lib().imloc_batch_workspace_bytes(nq, self.ns, self.pa, self.np)
+
+
+_STATS_DTYPE = None
+
+
+def imloc_lo_ransac_pnp_batch(ctx: Context, corrs, Ks: list = None, params=None, masks=None, arrays=False):
+    """corrs: list of dicts of float32 cuda tensors (with Ks and params: one
+    RansacParams or a list), or a BatchQueries.  Returns (status list, list
+    of (R, t), list of stats dicts); with arrays=True, (status (nq,) int32,
+    poses (nq, 12) float64 -- R row-major, then t --, stats as a structured
+    array with the fields of the stats dicts)."""
+    global _STATS_DTYPE
+    b = corrs if isinstance(corrs, BatchQueries) else BatchQueries(corrs, Ks, params)
+    nq = b.nq
+    ctx.ensure_workspace(b.ws_bytes)
     ctx.ensure_staging(nq)
     poses = (Pose * nq)()
     stats = (Stats * nq)()
@@ -328,7 +351,13 @@ def imloc_lo_ransac_pnp_batch(ctx: Context, corrs: list, Ks: list, params, masks
     mk = None
     if masks is not None:
         mk = (C.c_void_p * nq)(*[None if m is None else m.data_ptr() for m in masks])
-    ctx.check(lib().imloc_lo_ransac_pnp_batch(ctx.h, cs, ns, cams, nq, pa, len(plist), poses, mk, stats, status))
+    ctx.check(lib().imloc_lo_ransac_pnp_batch(ctx.h, b.cs, b.ns, b.cams, nq, b.pa, b.np, poses, mk, stats, status))
+    if arrays:
+        if _STATS_DTYPE is None:
+            _STATS_DTYPE = np.ctypeslib.as_array((Stats * 1)()).dtype
+        return (np.frombuffer(status, dtype=np.int32).copy(),
+                np.frombuffer(poses, dtype=np.float64).reshape(nq, 12).copy(),
+                np.frombuffer(stats, dtype=_STATS_DTYPE).copy())
     out = [(np.array(p.R[:]).reshape(3, 3), np.array(p.t[:])) for p in poses]
     return list(status), out, [s.as_dict() for s in stats]
 

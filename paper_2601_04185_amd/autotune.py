@@ -24,7 +24,7 @@ def candidate_shapes(cus: int):
 
 def tune_scoring(ctx: Context, run, reps: int = 2, cus: int | None = None) -> dict:
     """run(ctx) must execute the workload once and return imloc stats (a dict,
-    or a list of dicts for a batch).  Returns the timing table and leaves the
+    or a list of dicts or a stats array for a batch).  Returns the timing table and leaves the
     fastest shape set on ctx."""
     if cus is None:
         import torch
@@ -38,8 +38,8 @@ def tune_scoring(ctx: Context, run, reps: int = 2, cus: int | None = None) -> di
             best = None
             for _ in range(reps):
                 st = run(ctx)
-                st0 = st[0] if isinstance(st, (list, tuple)) else st
-                ms = st0["ms_score"]
+                st0 = st if isinstance(st, dict) else st[0]  # one query's stats, or a batch's (list or array)
+                ms = float(st0["ms_score"])
                 best = ms if best is None else min(best, ms)
             table.append(dict(candidates_per_item=ct, points_per_item=pts, workgroups=wg, score_ms=best))
     finally:

@@ -65,6 +65,25 @@ def test_mix_matches_oracle(pk, orc):
             assert stats[i]["samples"] == ref["samples"]
 
 
+def test_packed_batch_and_array_results_equal_lists(pk):
+    """BatchQueries (descriptors packed once) with array results gives the
+    list form's results, call after call."""
+    ctx = pk.Context(0)
+    qs, prms = _mix()
+    P = [pk.make_params(**p) for p in prms]
+    ds = [pk.to_device(q) for q in qs]
+    status, poses, stats = pk.imloc_lo_ransac_pnp_batch(ctx, ds, [q.K for q in qs], P)
+    b = pk.BatchQueries(ds, [q.K for q in qs], P)
+    for _ in range(2):
+        st_a, po_a, sa = pk.imloc_lo_ransac_pnp_batch(ctx, b, arrays=True)
+        assert st_a.tolist() == list(status)
+        for i in range(len(qs)):
+            assert np.array_equal(po_a[i, :9].reshape(3, 3), poses[i][0])
+            assert np.array_equal(po_a[i, 9:], poses[i][1])
+            for k, v in stats[i].items():
+                assert sa[i][k] == v, (i, k)
+
+
 def test_tuning_does_not_change_results(pk):
     q = synth.make_query(400, 30000, 0.3, 1.0)
     d = pk.to_device(q)
