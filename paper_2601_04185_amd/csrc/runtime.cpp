@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -116,6 +117,8 @@ struct imloc_ctx {
   size_t pinned_bytes = 0;
   hipEvent_t staging_ev = nullptr;
   bool staging_pending = false;
+  // recorded behind a synchronous call's work and polled (wait_stream)
+  hipEvent_t done_ev = nullptr;
   // timing events, created when timing is switched on (imloc_set_timing)
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
@@ -385,6 +388,27 @@ int staging_wait(imloc_ctx* c) {
   return IMLOC_OK;
 }
 
+// Wait for the work enqueued on s so far: an event recorded behind it is
+// polled for up to kSpinWait (a blocking wait wakes about 13 us after the
+// work ends on this system, a sizeable part of a single query's latency),
+// then waited on.
+constexpr auto kSpinWait = std::chrono::microseconds(2000);
+int wait_event(imloc_ctx* c, hipEvent_t ev) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t q = hipEventQuery(ev);
+    if (q == hipSuccess) return IMLOC_OK;
+    if (q != hipErrorNotReady) HIP_TRY(c, q);
+    if (std::chrono::steady_clock::now() - t0 > kSpinWait) break;
+  }
+  HIP_TRY(c, hipEventSynchronize(ev));
+  return IMLOC_OK;
+}
+int wait_stream(imloc_ctx* c, hipStream_t s) {
+  HIP_TRY(c, hipEventRecord(c->done_ev, s));
+  return wait_event(c, c->done_ev);
+}
+
 // After enqueueing copies that use the staging buffer on the context stream.
 int staging_mark(imloc_ctx* c) {
   HIP_TRY(c, hipEventRecord(c->staging_ev, c->stream));
@@ -639,7 +663,8 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       ++rounds;
       if (sync) {
         HIP_TRY(ctx, hipMemcpyAsync(hact, e.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
-        HIP_TRY(ctx, hipStreamSynchronize(st_));
+        int rcw = wait_stream(ctx, st_);
+        if (rcw) return rcw;
         if (*hact == 0) break;
       }
     }
@@ -685,13 +710,15 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
     }
     // captured on the internal stream, replayed on the caller's stream
     HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
+    int rcw = wait_stream(ctx, s);
+    if (rcw) return rcw;
     ctx->graph_launches++;
     rounds = (int)e.max_rounds;
   } else {
     int rc = enqueue(s, !e.all_fixed);
     if (rc) return rc;
-    HIP_TRY(ctx, hipStreamSynchronize(s));
+    rc = wait_stream(ctx, s);
+    if (rc) return rc;
   }
 
   imloc_stats shared_t;
@@ -824,6 +851,7 @@ int imloc_create(imloc_ctx** out, int device, void* hip_stream) {
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess ||
       staging_alloc(c, kDefaultStaging) != IMLOC_OK) {
     imloc_destroy(c);
     return IMLOC_EHIP;
@@ -845,6 +873,7 @@ void imloc_destroy(imloc_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->graph) hipGraphDestroy(c->graph);
   if (c->staging_ev) hipEventDestroy(c->staging_ev);
+  if (c->done_ev) hipEventDestroy(c->done_ev);
   if (c->gstream) {
     hipStreamSynchronize(c->gstream);
     hipStreamDestroy(c->gstream);
@@ -1675,7 +1704,8 @@ static int server_collect(imloc_server* srv, int64_t r, int nq, int64_t* done_ti
   imloc_ctx* ctx = srv->ctx;
   const Engine& e = srv->e;
   const int S = srv->cfg.max_slots;
-  HIP_TRY(ctx, hipEventSynchronize(srv->ev[r & 1]));
+  int rcw = wait_event(ctx, srv->ev[r & 1]);
+  if (rcw) return rcw;
   char* half = ctx->pinned + (size_t)(r & 1) * server_half_bytes(S);
   const size_t tab = (size_t)S * sizeof(QueryDesc);
   const BestState* hst = reinterpret_cast<const BestState*>(half + tab);
