@@ -216,7 +216,7 @@ int imloc_set_gn_mode(imloc_ctx *ctx, int32_t mode);
 
 /* ---- the hot path -------------------------------------------------------- */
 
-/* Lift 2D-2D matches to 2D-3D correspondences (Sec. 3.3 "Query Time Matching
+/* Give each query-to-database match a world point (Sec. 3.3 "Query Time Matching
  * and 2D-3D Lifting").  A match is kept iff conf > min_conf (float32
  * comparison; the paper uses 0.05), its view index is in [0, n_views), its
  * coordinates are finite, and its depth is valid: subpixel != 0 interpolates

@@ -7,10 +7,10 @@
  * shares no source with the GPU library and includes none of its headers.
  *
  * What it follows (ImLoc, Jiang et al., arXiv 2601.04185):
- *   - Sec. 3.3 "Query Time Matching and 2D-3D Lifting": lift 2D-2D matches to
- *     2D-3D through the stored depth maps (bilinear at sub-pixel database
- *     coordinates, plain lookup otherwise), keep matches with valid depth and
- *     confidence above 0.05.
+ *   - Sec. 3.3 "Query Time Matching and 2D-3D Lifting": give every
+ *     query-to-database match a world point through the stored depth maps
+ *     (bilinear at sub-pixel database coordinates, plain lookup otherwise),
+ *     keep matches with valid depth and confidence above 0.05.
  *   - Sec. 3.3 "Pose Estimation": LO-RANSAC over P3P minimal sets; each
  *     hypothesis is scored by the MSAC sum of squared pixel errors clipped at
  *     the threshold, weighted by the matching confidences; a hypothesis that
@@ -141,7 +141,7 @@ int64_t orc_required_samples(double eps, double confidence, int64_t max_iters);
 int orc_lo_ransac_pnp(const orc_corr *c, const orc_camera *K, const orc_params *p,
                       orc_pose *pose, uint8_t *mask, orc_stats *stats);
 
-/* Lifting of 2D-2D matches to 2D-3D.  Views: depth[k*H*W + row*W + col].
+/* Lifting: a world point for every image-to-image match.  Views: depth[k*H*W + row*W + col].
  * cams[k], poses[k] per view (cam_from_world).  subpixel != 0: bilinear depth at
  * (db_u - 0.5, db_v - 0.5); else lookup at (floor(db_v), floor(db_u)).
  * Keeps a match iff conf > min_conf (compared in float32), view in range and

@@ -1,5 +1,5 @@
-// lift.hip -- 2D-2D matches to 2D-3D correspondences through the stored depth
-// maps (ImLoc Sec. 3.3 "Query Time Matching and 2D-3D Lifting": bilinear depth
+// lift.hip -- a world point for every query-to-database match, through the
+// stored depth maps (ImLoc Sec. 3.3 "Query Time Matching and 2D-3D Lifting": bilinear depth
 // at sub-pixel database coordinates, plain lookup otherwise; keep matches with
 // valid depth and confidence above the threshold).
 //
