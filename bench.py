@@ -504,7 +504,7 @@ def e2e_leg(pk, steps=10):
                 status=int(rc), ms_per_query=round(tt * 1e3, 3), queries_per_s=round(1.0 / tt, 2),
                 lift_device_ms=round(td, 4), lift_matches_per_s_device=round(n_match / (td * 1e-3), 1),
                 lift_gb_per_s_device=round(lift_bytes / (td * 1e-3) / 1e9, 2),
-                lift_device_note="events on the stream around the whole call: two view-table uploads, three "
+                lift_device_note="events on the stream around the whole call: the view-table upload, three "
                                  "kernels and the 4-byte count the binding reads back (the kernels alone: "
                                  "profiles/lift_kernel_trace.md)",
                 lift_ms_incl_host=round(tl * 1e3, 4), lift_bytes_algorithmic=int(lift_bytes),
