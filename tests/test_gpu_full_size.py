@@ -13,6 +13,9 @@ benchmark times, on sampled outputs the oracle computes one by one.
   may differ from the oracle's; the float64 configuration checks it).
 - Lifting of 20 views x 8,000 matches: the kept set and source indices equal
   the oracle's, the lifted points within 1.01 float32 ulp.
+- Beyond the workloads: a query of 2,000,000 correspondences against the
+  oracle, and one fused call of 1,500 small queries against the same queries
+  run alone.
 """
 import numpy as np
 import pytest
@@ -75,3 +78,46 @@ def test_lift_full_size_against_oracle(pk, orc):
         a = g[k].cpu().numpy().astype(np.float64)
         b = ref[k]
         assert np.all(np.abs(a - b) <= 1.01 * np.spacing(np.abs(b).astype(np.float32)).astype(np.float64) + 1e-12)
+
+
+def test_query_ten_times_the_largest_workload_against_oracle(pk, orc):
+    """One query of 2,000,000 correspondences (ten times the largest query of
+    the serving workload), 1,024 samples, LO on the top 8: the whole pipeline
+    against the float64 oracle."""
+    import torch
+    q = synth.make_query(77, 2_000_000, 0.3, 1.0)
+    d = pk.to_device(q)
+    kw = dict(threshold_px=4.0, fixed_samples=1024, batch=1024, lo_top_k=8)
+    ctx = pk.Context(0)
+    mask = torch.empty(q.n, dtype=torch.uint8, device="cuda")
+    rc, R, t, st = pk.imloc_lo_ransac_pnp(ctx, d, q.K, pk.make_params(**kw), mask=mask)
+    ref = orc.lo_ransac_pnp(q.corr(), q.K, **kw)
+    assert rc == 0 and ref["status"] == 0
+    ok, ang, dt = pose_close(R, t, ref["R"], ref["t"])
+    assert ok, (ang, dt)
+    assert st["candidates"] == ref["candidates"]
+    assert st["residuals"] == ref["candidates"] * q.n
+    assert abs(st["full_count"] - ref["full_count"]) <= 4
+    assert int((mask.cpu().numpy() != ref["mask"]).sum()) <= 4
+
+
+def test_batch_of_many_small_queries_equals_alone(pk):
+    """1,500 queries of 6 to 400 correspondences in one fused call (the work
+    list's per-thread query segments, ragged candidate tiles, tiny chunks): every
+    result equals the query run alone, bit for bit, on a sample."""
+    rng = np.random.default_rng(5)
+    nq = 1500
+    ns = rng.integers(6, 401, nq)
+    qs = [synth.make_query(9000 + i, int(ns[i]), float(rng.uniform(0.3, 0.8)), 1.0) for i in range(nq)]
+    ds = [pk.to_device(q) for q in qs]
+    P = [pk.make_params(threshold_px=4.0, fixed_samples=64, batch=64, lo_top_k=2, query_id=i) for i in range(nq)]
+    ctx = pk.Context(0)
+    status, poses, stats = pk.imloc_lo_ransac_pnp_batch(ctx, pk.BatchQueries(ds, [q.K for q in qs], P), arrays=True)
+    assert np.all((status == 0) | (status == pk.IMLOC_NO_POSE))
+    assert np.mean(status == 0) > 0.9
+    alone = pk.Context(0)
+    for i in list(range(0, nq, 97)) + [nq - 1]:
+        rc, R, t, st = pk.imloc_lo_ransac_pnp(alone, ds[i], qs[i].K, P[i])
+        assert rc == status[i], i
+        assert np.array_equal(R.reshape(9), poses[i, :9]) and np.array_equal(t, poses[i, 9:]), i
+        assert st["candidates"] == stats[i]["candidates"] and st["best_count"] == stats[i]["best_count"], i
