@@ -212,8 +212,8 @@ size_t gn_scratch_bytes(int nprob, int chunks_max);
 // and decision launches); every form gives identical results.
 hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
                      const double* start_direct, int nprob, int kmax, int chunks_max, int iters_max, void* scratch,
-                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, int gn_mode,
-                     hipStream_t s);
+                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, bool any_weighted,
+                     int gn_mode, hipStream_t s);
 hipError_t launch_refine(const QueryDesc* qd, BestState* st, const double* start_direct, int nq, int chunks_max,
                          int iters_max, uint8_t* in_set, void* scratch, double* out_pose, double* out_cost,
                          bool any_rig, int gn_mode, bool fuse_mask, bool* mask_done, hipStream_t s);

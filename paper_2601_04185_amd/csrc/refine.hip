@@ -28,7 +28,11 @@ constexpr int kGNChunk = kGNThreads * kGNPPT;   // points per chunk (fixed: the 
 // Normal equations of one point, given iz = 1 / z of its camera coordinates.
 // The rows of d(pixel)/d(dw, dt) are J0 = (a02 y, a00 z - a02 x, -a00 y, a00,
 // 0, a02) and J1 = (a12 y - a11 z, -a12 x, a11 x, 0, a11, a12); the products
-// with their structural zeros are left out (H[3][4] gets nothing).
+// with their structural zeros are left out (H[3][4] gets nothing).  W false:
+// every weight is 1 (the local optimisation of queries without confidences),
+// whose weighted rows are the rows themselves -- the same bits without the
+// ten multiplications.
+template <bool W>
 __device__ inline void acc_point(double* a, const Cam& K, double x, double y, double z, double iz, double du,
                                  double dv, double wt) {
   const double a00 = K.fx * iz, a02 = -K.fx * x * iz * iz;
@@ -38,8 +42,8 @@ __device__ inline void acc_point(double* a, const Cam& K, double x, double y, do
   double W0[6], W1[6];
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
-    W0[r] = wt * J0[r];
-    W1[r] = wt * J1[r];
+    W0[r] = W ? wt * J0[r] : J0[r];
+    W1[r] = W ? wt * J1[r] : J1[r];
   }
   int k = 0;
 #pragma unroll
@@ -551,7 +555,7 @@ __device__ __forceinline__ void gn_load_points(const CorrF32& c, int64_t n, int6
 // Accumulate one chunk at pose P and store its partial sums: per thread in
 // point order, then across the wave by recursive halving, then the waves in
 // wave order.
-template <int MODE, bool RIG>
+template <int MODE, bool RIG, bool W>
 __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* s_rig, const double* P, int j,
                                               int64_t base, const GNPoints& pt, uint8_t* in_set,
                                               double (*s_rows)[kAcc], double* part_out) {
@@ -603,7 +607,7 @@ __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* 
         a[27] += w * r2;
         a[28] += 1.0;
         if (rig) acc_point_rig(a, Kp, xr, x, y, iz, Rc, du, dv, w);
-        else acc_point(a, K, x, y, z, iz, du, dv, w);
+        else acc_point<W>(a, K, x, y, z, iz, du, dv, w);
       } else {
         a[27] += w * tau2;
       }
@@ -621,7 +625,7 @@ __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* 
       const double q = r2 * inv_s2;
       a[27] += w * s2 * log1p(q);
       if (rig) acc_point_rig(a, Kp, xr, x, y, iz, Rc, du, dv, w / (1.0 + q));
-      else acc_point(a, K, x, y, z, iz, du, dv, w / (1.0 + q));
+      else acc_point<true>(a, K, x, y, z, iz, du, dv, w / (1.0 + q));
     }
   }
   const double tot = wave_sum29(a);
@@ -642,7 +646,7 @@ __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* 
 // only evaluates the start pose; the last launch only decides.  Workgroup
 // (0, p) records the state for the next launch and, when the run ends, the
 // outputs.
-template <int MODE, bool RIG>
+template <int MODE, bool RIG, bool W>
 __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
   const int p = blockIdx.y;
   const int chunk = blockIdx.x;
@@ -739,13 +743,13 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
     }
   }
   if (s.done) return;
-  gn_accumulate<MODE, RIG>(d, s_rig, s.eval, k, base, pt, in_set, s_rows,
+  gn_accumulate<MODE, RIG, W>(d, s_rig, s.eval, k, base, pt, in_set, s_rows,
                            const_cast<double*>(gn_part(g, k & 1, p)) + (int64_t)chunk * kAcc);
 }
 
 // Split form, for batches where the redundant reduction of the fused form
 // would read too much: evaluation j (one workgroup per chunk) ...
-template <int MODE, bool RIG>
+template <int MODE, bool RIG, bool W>
 __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
   const int p = blockIdx.y;
   const int chunk = blockIdx.x;
@@ -770,7 +774,7 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
   const double* start = st ? nullptr : gn_start<MODE>(g, p, q);
   if (threadIdx.x < 12) s_eval[threadIdx.x] = st ? st->eval[threadIdx.x] : start[threadIdx.x];
   __syncthreads();
-  gn_accumulate<MODE, RIG>(d, s_rig, s_eval, j, base, pt, in_set, s_rows,
+  gn_accumulate<MODE, RIG, W>(d, s_rig, s_eval, j, base, pt, in_set, s_rows,
                            const_cast<double*>(gn_part(g, j & 1, p)) + (int64_t)chunk * kAcc);
 }
 
@@ -780,7 +784,7 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
 // order (up to lo_top_k poses on the same points).  Each problem's
 // accumulation is gn_accumulate with the same thread-to-point map, so the
 // partial sums are those of gn_eval_kernel bit for bit.
-template <bool RIG>
+template <bool RIG, bool W>
 __global__ __launch_bounds__(kGNThreads) void gn_eval_lo_multi_kernel(GNArgs g, int j) {
   const int q = blockIdx.y;
   const int chunk = blockIdx.x;
@@ -807,7 +811,7 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_lo_multi_kernel(GNArgs g, 
     // barrier) before s_eval is rewritten
     if (threadIdx.x < 12) s_eval[threadIdx.x] = st ? st->eval[threadIdx.x] : start[threadIdx.x];
     __syncthreads();
-    gn_accumulate<0, RIG>(d, s_rig, s_eval, j, base, pt, nullptr, s_rows,
+    gn_accumulate<0, RIG, W>(d, s_rig, s_eval, j, base, pt, nullptr, s_rows,
                           const_cast<double*>(gn_part(g, j & 1, p)) + (int64_t)chunk * kAcc);
   }
 }
@@ -857,12 +861,12 @@ static bool use_fused(int gn_mode, int nprob, int chunks_max) {
   return (double)nprob * chunks_max * chunks_max * kAcc * sizeof(double) <= 32.0 * 1024 * 1024;
 }
 
-template <int MODE, bool RIG>
+template <int MODE, bool RIG, bool W>
 static void launch_gn(const GNArgs& g, int iters_max, bool fused, hipStream_t s) {
   const dim3 grid(g.cmax, g.nprob);
   if (fused) {
     for (int k = 0; k <= iters_max + 1; ++k)
-      hipLaunchKernelGGL((gn_fused_kernel<MODE, RIG>), grid, dim3(kGNThreads), 0, s, g, k);
+      hipLaunchKernelGGL((gn_fused_kernel<MODE, RIG, W>), grid, dim3(kGNThreads), 0, s, g, k);
   } else {
     // local optimisation from selected candidates: one workgroup per chunk and
     // query evaluates all of the query's problems (points loaded once)
@@ -870,9 +874,9 @@ static void launch_gn(const GNArgs& g, int iters_max, bool fused, hipStream_t s)
     const dim3 grid_multi(g.cmax, g.nprob / (g.kmax > 0 ? g.kmax : 1));
     for (int j = 0; j <= iters_max; ++j) {
       if (multi)
-        hipLaunchKernelGGL((gn_eval_lo_multi_kernel<RIG>), grid_multi, dim3(kGNThreads), 0, s, g, j);
+        hipLaunchKernelGGL((gn_eval_lo_multi_kernel<RIG, W>), grid_multi, dim3(kGNThreads), 0, s, g, j);
       else
-        hipLaunchKernelGGL((gn_eval_kernel<MODE, RIG>), grid, dim3(kGNThreads), 0, s, g, j);
+        hipLaunchKernelGGL((gn_eval_kernel<MODE, RIG, W>), grid, dim3(kGNThreads), 0, s, g, j);
       hipLaunchKernelGGL((gn_decide_kernel<MODE>), dim3(g.nprob), dim3(kGNThreads), 0, s, g, j);
     }
   }
@@ -880,8 +884,8 @@ static void launch_gn(const GNArgs& g, int iters_max, bool fused, hipStream_t s)
 
 hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const int32_t* n_sel,
                      const double* start_direct, int nprob, int kmax, int chunks_max, int iters_max, void* scratch,
-                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, int gn_mode,
-                     hipStream_t s) {
+                     double* out_pose, double* out_cost, int64_t* out_count, bool any_rig, bool any_weighted,
+                     int gn_mode, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   GNArgs g{};
   split_scratch(scratch, nprob, &g.gst, &g.part);
@@ -897,8 +901,14 @@ hipError_t launch_lo(const QueryDesc* qd, CandBuf cb, const int32_t* sel, const 
   g.cmax = chunks_max;
   g.nprob = nprob;
   const bool fused = use_fused(gn_mode, nprob, chunks_max);
-  if (any_rig) launch_gn<0, true>(g, iters_max, fused, s);
-  else launch_gn<0, false>(g, iters_max, fused, s);
+  // queries without confidences take the unweighted accumulation (same bits)
+  if (any_rig) {
+    if (any_weighted) launch_gn<0, true, true>(g, iters_max, fused, s);
+    else launch_gn<0, true, false>(g, iters_max, fused, s);
+  } else {
+    if (any_weighted) launch_gn<0, false, true>(g, iters_max, fused, s);
+    else launch_gn<0, false, false>(g, iters_max, fused, s);
+  }
   return hipGetLastError();
 }
 
@@ -921,8 +931,8 @@ hipError_t launch_refine(const QueryDesc* qd, BestState* bst, const double* star
   const bool fused = use_fused(gn_mode, nq, chunks_max);
   g.fuse_mask = fused && fuse_mask && !start_direct ? 1 : 0;
   if (mask_done) *mask_done = g.fuse_mask != 0;
-  if (any_rig) launch_gn<1, true>(g, iters_max, fused, s);
-  else launch_gn<1, false>(g, iters_max, fused, s);
+  if (any_rig) launch_gn<1, true, true>(g, iters_max, fused, s);
+  else launch_gn<1, false, true>(g, iters_max, fused, s);
   return hipGetLastError();
 }
 

@@ -627,6 +627,10 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
   for (int q = 0; q < nq; ++q)
     if (pl[q].subset) max_m_sub = std::max(max_m_sub, pl[q].m);
 
+  // a query with confidences needs the weighted local optimisation (the
+  // unweighted one gives the same bits when every weight is 1)
+  bool any_w = false;
+  for (int q = 0; q < nq; ++q) any_w = any_w || (n[q] > 0 && pts[q].w != nullptr);
   Timer tm(ctx);
   int rounds = 0;
   EstList est(nq);
@@ -656,7 +660,7 @@ int run_batch(imloc_ctx* ctx, int nq, const imloc_corr* pts, const int64_t* n, c
       tm.end(kStSelect, e2);
       hipEvent_t e3 = tm.begin();
       HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * e.kmax, e.kmax, e.chunks_lo, e.lo_iters,
-                             e.gn_lo, e.lo_pose, e.lo_cost, e.lo_count, e.any_rig, ctx->gn_mode, st_));
+                             e.gn_lo, e.lo_pose, e.lo_cost, e.lo_count, e.any_rig, any_w, ctx->gn_mode, st_));
       HIP_TRY(ctx, launch_round_end(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, e.kmax, e.st,
                                     e.active_count, true, st_));
       tm.end(kStLO, e3);
@@ -1446,7 +1450,7 @@ int imloc_local_optimize(imloc_ctx* ctx, const imloc_corr* pts, int64_t n, const
   int rc = stage_upload(ctx, sq, pts, n, K, 0, 0, nullptr);
   if (rc) return rc;
   HIP_TRY(ctx, launch_lo(sq.e.qd, sq.e.cb, nullptr, nullptr, start, np, 1, sq.e.chunks_lo, iters, scratch, out_poses,
-                         cost, count, false, ctx->gn_mode, ctx->stream));
+                         cost, count, false, n > 0 && pts->w != nullptr, ctx->gn_mode, ctx->stream));
   return IMLOC_OK;
 }
 
@@ -1801,10 +1805,12 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
   }
   int nq = 0, kmax = 1, chunks_lo = 1, chunks_fin = 1, lo_iters = 0, fin_iters = 0;
   int64_t max_batch = 1, max_n = 0, max_m_sub = 0;
+  bool any_w = false;  // a resident query with confidences: the weighted local optimisation
   EstList est;
   for (int i = 0; i < S; ++i) {
     const ServerSlot& sl = srv->slots[i];
     if (!sl.used) continue;
+    any_w = any_w || (sl.q.n > 0 && sl.q.pts.w != nullptr);
     est.push_back({std::min(sl.pl.batch, sl.pl.total), est_points(sl.pl)});
     nq = i + 1;
     kmax = std::max(kmax, sl.pl.k);
@@ -1860,7 +1866,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
     HIP_TRY(ctx, launch_score(e.qd, e.cb, e.st, nq, e.item_off, tune, 0, s));
     HIP_TRY(ctx, launch_select(e.qd, e.st, e.cb, nq, kmax, 4 * max_batch, e.sel_part, e.sel, e.n_sel, s));
     HIP_TRY(ctx, launch_lo(e.qd, e.cb, e.sel, e.n_sel, nullptr, nq * kmax, kmax, chunks_lo, lo_iters, e.gn_lo,
-                           e.lo_pose, e.lo_cost, e.lo_count, false, ctx->gn_mode, s));
+                           e.lo_pose, e.lo_cost, e.lo_count, false, any_w, ctx->gn_mode, s));
     HIP_TRY(ctx, launch_round_end(e.qd, e.cb, e.sel, e.n_sel, e.lo_pose, e.lo_cost, e.lo_count, nq, kmax, e.st,
                                   e.active_count, false, s));
     bool mask_done = false;  // the fused final refinement writes the masks itself
