@@ -450,7 +450,11 @@ typedef struct {
   int32_t max_top_k;        /* largest lo_top_k accepted (<= 32) */
   int64_t max_n;            /* largest query accepted (correspondences) */
   int64_t candidate_pool;   /* candidate slots shared by the resident queries */
-  int64_t byte_pool;        /* bytes shared by the resident queries */
+  int64_t byte_pool;        /* bytes shared by the resident queries: a query of n
+                             * correspondences takes 1,024 ceil(n / 512) bytes
+                             * plus a 256-byte-aligned count table for its
+                             * refinement's in-set, and 24 m more for a
+                             * gathered scoring subset of m points */
 } imloc_server_config;
 
 /* Workspace bytes a server needs; the server uses the context's workspace

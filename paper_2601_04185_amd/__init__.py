@@ -635,8 +635,8 @@ class Server:
         self.ctx = Context(device, stream=stream)
         if candidate_pool is None:
             candidate_pool = max_slots * 4 * 1024
-        if byte_pool is None:
-            byte_pool = max_slots * (max_n + 256)
+        if byte_pool is None:  # each query's refinement in-set: 1 KiB per 512 points and its count table
+            byte_pool = max_slots * (1024 * ((max_n + 511) // 512) + 2 * ((max_n + 511) // 512) + 512)
         self.cfg = ServerConfig(int(max_slots), int(max_top_k), int(max_n), int(candidate_pool), int(byte_pool))
         nbytes = lib().imloc_server_workspace_bytes(C.byref(self.cfg))
         if nbytes == 0:

@@ -205,6 +205,8 @@ hipError_t launch_select(const QueryDesc* qd, const BestState* st, CandBuf cb, i
 // starts from the best pose of query q (or start_direct[q]) and runs on its
 // full set, if the query has just finished sampling.
 int gn_chunks(int64_t n);
+// bytes of the final refinement's compacted in-set of a query of n points
+int64_t gn_inset_bytes(int64_t n);
 size_t gn_scratch_bytes(int nprob, int chunks_max);
 // any_rig: some problem belongs to a rig query (selects the kernel variant
 // that takes residuals through rig cameras).  gn_mode: 0 = pick the launch

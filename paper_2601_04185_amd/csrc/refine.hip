@@ -13,7 +13,10 @@
 // inlier count of a 512-point chunk in float64 with a fixed thread-to-point
 // map and reduction tree; partial sums are combined in chunk order, so the
 // result depends on the problem alone, not on the batch around it or the
-// launch form.  Residual r = pi(R X + t) - x; left update on SO(3).
+// launch form.  The final refinement's first evaluation also compacts each
+// chunk's in-set; its later evaluations take only those points (thread t:
+// the chunk's t-th and (t + 256)-th in-set points).  Residual
+// r = pi(R X + t) - x; left update on SO(3).
 #include "imloc_device.h"
 #include "imloc_kernels.h"
 
@@ -108,6 +111,17 @@ __host__ __device__ inline int chunks_for(int64_t n) {
 }
 
 int gn_chunks(int64_t n) { return chunks_for(n); }
+
+// The final refinement's in-set, compacted per chunk by its first evaluation
+// (the set stays fixed): a count per chunk (uint16, padded to 256 bytes), then
+// per chunk the offsets in the chunk of its in-set points, in point order
+// (uint16 x kGNChunk).  Later evaluations read only those points.
+__host__ __device__ inline int64_t inset_head_bytes(int64_t C) { return (2 * C + 255) & ~int64_t(255); }
+__host__ __device__ inline int64_t inset_bytes_for(int64_t n) {
+  const int64_t C = chunks_for(n);
+  return inset_head_bytes(C) + (int64_t)2 * kGNChunk * C;
+}
+int64_t gn_inset_bytes(int64_t n) { return inset_bytes_for(n); }
 
 size_t gn_scratch_bytes(int nprob, int chunks_max) {
   if (nprob < 1) nprob = 1;
@@ -509,23 +523,22 @@ __device__ __forceinline__ void gn_outputs(const GNArgs& g, const GNShared& s, i
   }
 }
 
-// A chunk's points, loaded into registers.
+// A chunk's points, loaded into registers: point t of the thread is point
+// chunk * kGNChunk + loc[t] of the set.
 struct GNPoints {
   float X[kGNPPT], Y[kGNPPT], Z[kGNPPT], u[kGNPPT], v[kGNPPT], w[kGNPPT];
   bool use[kGNPPT];
-  int in[kGNPPT];  // in-set byte (refinement), tested only when accumulating
-  bool has_w;      // confidence weights present (else every weight is 1)
-  bool read_in;    // the in-set bytes are valid (refinement from evaluation 1 on)
+  int loc[kGNPPT];
+  bool has_w;  // confidence weights present (else every weight is 1)
 };
 
-// MODE 1 reads the in-set flags from evaluation 1 on (evaluation 0 writes
-// them).  Branch-free: lanes past the end load the last point (and do not use
-// it), a query without points or weights reads from `safe` (any valid device
-// address), and every select happens where the value is used -- so the loads
-// issue back to back and nothing waits for them before the accumulation.
-template <int MODE>
-__device__ __forceinline__ void gn_load_points(const CorrF32& c, int64_t n, int64_t base, const uint8_t* in_set,
-                                               bool read_in_set, const void* safe, GNPoints& pt) {
+// Every point of the chunk (thread t: offsets t, t + 256).  Branch-free:
+// lanes past the end load the last point (and do not use it), a query without
+// points or weights reads from `safe` (any valid device address), and every
+// select happens where the value is used -- so the loads issue back to back
+// and nothing waits for them before the accumulation.
+__device__ __forceinline__ void gn_load_points(const CorrF32& c, int64_t n, int chunk, const void* safe,
+                                               GNPoints& pt) {
   const bool any = n > 0;
   const float* sf = reinterpret_cast<const float*>(safe);
   const float* X = any ? c.X : sf;
@@ -534,12 +547,11 @@ __device__ __forceinline__ void gn_load_points(const CorrF32& c, int64_t n, int6
   const float* U = any ? c.u : sf;
   const float* V = any ? c.v : sf;
   const float* W = any && c.w ? c.w : X;
-  const uint8_t* IS = MODE == 1 && any ? in_set : reinterpret_cast<const uint8_t*>(safe);
   pt.has_w = any && c.w != nullptr;
-  pt.read_in = MODE == 1 && read_in_set;
 #pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
-    const int64_t i = base + (int64_t)t * kGNThreads;
+    pt.loc[t] = (int)threadIdx.x + t * kGNThreads;
+    const int64_t i = (int64_t)chunk * kGNChunk + pt.loc[t];
     pt.use[t] = i < n;
     const int64_t ic = i < n ? i : (any ? n - 1 : 0);
     pt.X[t] = gmem(X)[ic];
@@ -548,16 +560,57 @@ __device__ __forceinline__ void gn_load_points(const CorrF32& c, int64_t n, int6
     pt.u[t] = gmem(U)[ic];
     pt.v[t] = gmem(V)[ic];
     pt.w[t] = gmem(W)[ic];
-    pt.in[t] = MODE == 1 ? (int)gmem(IS)[ic] : 1;
+  }
+}
+
+// The in-set points of the chunk (final refinement after its first
+// evaluation): thread t takes the compacted positions t and t + 256.  The
+// count and the offsets are loaded together (offsets past the count are read
+// but not used), then the points.
+__device__ __forceinline__ void gn_load_points_inset(const CorrF32& c, int64_t n, int chunk, const uint8_t* inset,
+                                                     const void* safe, GNPoints& pt) {
+  const bool any = n > 0;
+  const int64_t C = chunks_for(n);
+  // workgroups past the query's chunks read its last chunk (and exit later)
+  const int cc = chunk < C ? chunk : (int)C - 1;
+  const uint16_t* cnts = reinterpret_cast<const uint16_t*>(any ? inset : reinterpret_cast<const uint8_t*>(safe));
+  const uint16_t* offs = any ? reinterpret_cast<const uint16_t*>(inset + inset_head_bytes(C)) + (int64_t)cc * kGNChunk
+                             : reinterpret_cast<const uint16_t*>(safe);
+  // (a query without points reads element 0 of `safe`)
+  const int cnt = any ? (int)gmem(cnts)[any ? cc : 0] : 0;
+  int off[kGNPPT];
+#pragma unroll
+  for (int t = 0; t < kGNPPT; ++t) off[t] = any ? (int)gmem(offs)[any ? (int)threadIdx.x + t * kGNThreads : 0] : 0;
+  const float* sf = reinterpret_cast<const float*>(safe);
+  const float* X = any ? c.X : sf;
+  const float* Y = any ? c.Y : sf;
+  const float* Z = any ? c.Z : sf;
+  const float* U = any ? c.u : sf;
+  const float* V = any ? c.v : sf;
+  const float* W = any && c.w ? c.w : X;
+  pt.has_w = any && c.w != nullptr;
+#pragma unroll
+  for (int t = 0; t < kGNPPT; ++t) {
+    pt.use[t] = (int)threadIdx.x + t * kGNThreads < cnt;
+    pt.loc[t] = pt.use[t] ? off[t] : 0;
+    const int64_t i = (int64_t)cc * kGNChunk + pt.loc[t];
+    const int64_t ic = i < n ? i : (any ? n - 1 : 0);
+    pt.X[t] = gmem(X)[ic];
+    pt.Y[t] = gmem(Y)[ic];
+    pt.Z[t] = gmem(Z)[ic];
+    pt.u[t] = gmem(U)[ic];
+    pt.v[t] = gmem(V)[ic];
+    pt.w[t] = gmem(W)[ic];
   }
 }
 
 // Accumulate one chunk at pose P and store its partial sums: per thread in
 // point order, then across the wave by recursive halving, then the waves in
-// wave order.
+// wave order.  The final refinement's first evaluation (MODE 1, j = 0) also
+// writes the chunk's compacted in-set (its count and offsets).
 template <int MODE, bool RIG, bool W>
 __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* s_rig, const double* P, int j,
-                                              int64_t base, const GNPoints& pt, uint8_t* in_set,
+                                              int chunk, const GNPoints& pt, uint8_t* inset,
                                               double (*s_rows)[kAcc], double* part_out) {
   const double tau2 = d.tau * d.tau, s2 = d.cauchy_s * d.cauchy_s;
   const double inv_s2 = 1.0 / s2;
@@ -567,17 +620,12 @@ __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* 
   double a[kAcc];
 #pragma unroll
   for (int e = 0; e < kAcc; ++e) a[e] = 0.0;
-  int in[kGNPPT];
+  bool keep[kGNPPT];  // MODE 1, j = 0: the point is in the set
 #pragma unroll
   for (int t = 0; t < kGNPPT; ++t) {
-    // keeps the test of the in-set byte (and the wait for its load) here
-    in[t] = pt.in[t];
-    asm volatile("" : "+v"(in[t]));
-  }
-#pragma unroll
-  for (int t = 0; t < kGNPPT; ++t) {
-    if (!pt.use[t] || (pt.read_in && in[t] == 0)) continue;
-    const int64_t i = base + (int64_t)t * kGNThreads;
+    keep[t] = false;
+    if (!pt.use[t]) continue;
+    const int64_t i = (int64_t)chunk * kGNChunk + pt.loc[t];
     const double X = pt.X[t], Y = pt.Y[t], Z = pt.Z[t];
     const double w = pt.has_w ? (double)pt.w[t] : 1.0;
     double x = P[0] * X + P[1] * Y + P[2] * Z + P[9];
@@ -613,9 +661,8 @@ __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* 
       }
     } else {
       if (j == 0) {
-        const bool in = front && r2 < tau2;
-        in_set[i] = in ? 1 : 0;
-        if (!in) continue;
+        keep[t] = front && r2 < tau2;
+        if (!keep[t]) continue;
       }
       a[28] += 1.0;
       if (!front) {
@@ -627,6 +674,29 @@ __device__ __forceinline__ void gn_accumulate(const QueryDesc& d, const double* 
       if (rig) acc_point_rig(a, Kp, xr, x, y, iz, Rc, du, dv, w / (1.0 + q));
       else acc_point<true>(a, K, x, y, z, iz, du, dv, w / (1.0 + q));
     }
+  }
+  if (MODE == 1 && j == 0) {  // the chunk's in-set: points of slot 0 in lane order, then slot 1
+    __shared__ int s_cnt[kGNPPT][kGNWaves];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint64_t m[kGNPPT];
+#pragma unroll
+    for (int t = 0; t < kGNPPT; ++t) {
+      m[t] = __ballot(keep[t]);
+      if (lane == 0) s_cnt[t][wave] = __popcll(m[t]);
+    }
+    __syncthreads();
+    const int64_t C = chunks_for(d.n);
+    uint16_t* offs = reinterpret_cast<uint16_t*>(inset + inset_head_bytes(C)) + (int64_t)chunk * kGNChunk;
+    int before = 0;
+#pragma unroll
+    for (int t = 0; t < kGNPPT; ++t) {
+      int pos = before;
+      for (int w = 0; w < wave; ++w) pos += s_cnt[t][w];
+      pos += __popcll(m[t] & ((1ull << lane) - 1ull));
+      if (keep[t]) offs[pos] = (uint16_t)pt.loc[t];
+      for (int w = 0; w < kGNWaves; ++w) before += s_cnt[t][w];
+    }
+    if (threadIdx.x == 0) reinterpret_cast<uint16_t*>(inset)[chunk] = (uint16_t)before;
   }
   const double tot = wave_sum29(a);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -665,12 +735,13 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
   const int64_t n = MODE == 0 ? d.m : d.n;
   uint8_t* in_set = MODE == 1 ? g.in_set_all + d.in_set_off : nullptr;
   asm volatile("" ::"s"(c.X), "s"(c.Y), "s"(c.Z), "s"(c.u), "s"(c.v), "s"(c.w), "s"(n), "s"(in_set));
-  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
   // the points are loaded before any test (indices are clamped), so that the
   // descriptor fields are read together and the point latency overlaps the
-  // reduction and the decision
+  // reduction and the decision; the final refinement reads its compacted
+  // in-set from the second launch on
   GNPoints pt;
-  gn_load_points<MODE>(c, n, base, in_set, k > 0, g.part, pt);
+  if (MODE == 1 && k > 0) gn_load_points_inset(c, n, chunk, in_set, g.part, pt);
+  else gn_load_points(c, n, chunk, g.part, pt);
   // A run that ended at an earlier launch: decision k - 1 would leave its
   // state as it is, so carry the state to the slot the next launch reads and
   // stop, without waiting for the partial sums and points in flight.
@@ -699,7 +770,7 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
       if (MODE == 1 && g.fuse_mask && d.mask && g.bst[q].finished == 1) {
 #pragma unroll
         for (int t = 0; t < kGNPPT; ++t)
-          if (pt.use[t]) d.mask[base + (int64_t)t * kGNThreads] = 0;
+          if (pt.use[t]) d.mask[(int64_t)chunk * kGNChunk + pt.loc[t]] = 0;
       }
       return;
     }
@@ -720,12 +791,14 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
       if (s_end) gn_outputs(g, s, p);
     }
     if (MODE == 1 && g.fuse_mask && s_end) {  // the run ended: mask of this chunk at the final pose
+      GNPoints fp;  // every point of the chunk
+      gn_load_points(c, n, chunk, g.part, fp);
       long long cnt = 0;
 #pragma unroll
       for (int t = 0; t < kGNPPT; ++t) {
-        const int64_t i = base + (int64_t)t * kGNThreads;
-        if (!pt.use[t]) continue;
-        const bool in = mask_test(d, s.cur, pt.X[t], pt.Y[t], pt.Z[t], pt.u[t], pt.v[t], i);
+        const int64_t i = (int64_t)chunk * kGNChunk + fp.loc[t];
+        if (!fp.use[t]) continue;
+        const bool in = mask_test(d, s.cur, fp.X[t], fp.Y[t], fp.Z[t], fp.u[t], fp.v[t], i);
         if (d.mask) d.mask[i] = in ? 1 : 0;
         cnt += in ? 1 : 0;
       }
@@ -743,7 +816,7 @@ __global__ __launch_bounds__(kGNThreads) void gn_fused_kernel(GNArgs g, int k) {
     }
   }
   if (s.done) return;
-  gn_accumulate<MODE, RIG, W>(d, s_rig, s.eval, k, base, pt, in_set, s_rows,
+  gn_accumulate<MODE, RIG, W>(d, s_rig, s.eval, k, chunk, pt, in_set, s_rows,
                            const_cast<double*>(gn_part(g, k & 1, p)) + (int64_t)chunk * kAcc);
 }
 
@@ -763,9 +836,9 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
   const GNState* st = j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr;
   if (st && st->done) return;
   uint8_t* in_set = MODE == 1 ? g.in_set_all + d.in_set_off : nullptr;
-  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
   GNPoints pt;
-  gn_load_points<MODE>(c, n, base, in_set, j > 0, g.part, pt);
+  if (MODE == 1 && j > 0) gn_load_points_inset(c, n, chunk, in_set, g.part, pt);
+  else gn_load_points(c, n, chunk, g.part, pt);
   __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
   if (RIG && d.ncam > 0)
     for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
@@ -774,7 +847,7 @@ __global__ __launch_bounds__(kGNThreads) void gn_eval_kernel(GNArgs g, int j) {
   const double* start = st ? nullptr : gn_start<MODE>(g, p, q);
   if (threadIdx.x < 12) s_eval[threadIdx.x] = st ? st->eval[threadIdx.x] : start[threadIdx.x];
   __syncthreads();
-  gn_accumulate<MODE, RIG, W>(d, s_rig, s_eval, j, base, pt, in_set, s_rows,
+  gn_accumulate<MODE, RIG, W>(d, s_rig, s_eval, j, chunk, pt, in_set, s_rows,
                            const_cast<double*>(gn_part(g, j & 1, p)) + (int64_t)chunk * kAcc);
 }
 
@@ -799,9 +872,8 @@ __attribute__((amdgpu_waves_per_eu((!RIG && !W) ? 4 : 1, (!RIG && !W) ? 4 : 8)))
   const int64_t n = d.m;
   const int C = chunks_for(n);
   if (chunk >= C) return;
-  const int64_t base = (int64_t)chunk * kGNChunk + threadIdx.x;
   GNPoints pt;
-  gn_load_points<0>(d.S, n, base, nullptr, false, g.part, pt);
+  gn_load_points(d.S, n, chunk, g.part, pt);
   __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
   if (RIG && d.ncam > 0)
     for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
@@ -816,7 +888,7 @@ __attribute__((amdgpu_waves_per_eu((!RIG && !W) ? 4 : 1, (!RIG && !W) ? 4 : 8)))
     // barrier) before s_eval is rewritten
     if (threadIdx.x < 12) s_eval[threadIdx.x] = st ? st->eval[threadIdx.x] : start[threadIdx.x];
     __syncthreads();
-    gn_accumulate<0, RIG, W>(d, s_rig, s_eval, j, base, pt, nullptr, s_rows,
+    gn_accumulate<0, RIG, W>(d, s_rig, s_eval, j, chunk, pt, nullptr, s_rows,
                           const_cast<double*>(gn_part(g, j & 1, p)) + (int64_t)chunk * kAcc);
   }
 }

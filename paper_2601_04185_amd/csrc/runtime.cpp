@@ -316,7 +316,7 @@ void plan_engine(Engine& e, int nq, const QPlan* pl, const imloc_ransac_params* 
     if (pl[q].ncam > 0) e.any_rig = true;
     else e.any_single = true;
     e.in_set_off[q] = in_bytes;
-    in_bytes += (pl[q].n + 255) & ~int64_t(255);
+    in_bytes += (gn_inset_bytes(pl[q].n) + 255) & ~int64_t(255);
     e.subset_off[q] = sub;
     if (pl[q].subset) sub += 6 * pl[q].m;
     e.kmax = std::max(e.kmax, pl[q].k);
@@ -1549,7 +1549,11 @@ struct Finished {
 };
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
-int64_t query_bytes(const QPlan& pl) { return align256(pl.n) + (pl.subset ? align256(24 * pl.m) : 0); }
+// a query's share of a server's byte pool: its compacted in-set, then its
+// gathered scoring subset
+int64_t query_bytes(const QPlan& pl) {
+  return align256(gn_inset_bytes(pl.n)) + (pl.subset ? align256(24 * pl.m) : 0);
+}
 
 }  // namespace
 
@@ -1846,7 +1850,7 @@ int imloc_server_step(imloc_server* srv, int64_t* done_tickets, int32_t capacity
       // the in-set bytes live in the byte pool, addressed relative to the in-set base
       d.in_set_off = (int64_t)((srv->byte_pool + sl.byte_off) - reinterpret_cast<char*>(e.in_set));
       if (sl.pl.subset) {
-        const float* b = reinterpret_cast<const float*>(srv->byte_pool + sl.byte_off + align256(sl.pl.n));
+        const float* b = reinterpret_cast<const float*>(srv->byte_pool + sl.byte_off + align256(gn_inset_bytes(sl.pl.n)));
         const int64_t m = sl.pl.m;
         d.S = CorrF32{b, b + m, b + 2 * m, b + 3 * m, b + 4 * m, b + 5 * m};
       }
