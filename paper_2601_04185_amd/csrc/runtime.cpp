@@ -976,7 +976,7 @@ int imloc_get_score_tuning(const imloc_ctx* c, int32_t* candidates_per_item, int
 
 int imloc_set_score_points(imloc_ctx* c, int32_t points_per_item) {
   if (!c) return IMLOC_EINVAL;
-  if (points_per_item != 512 && points_per_item != 1024 && points_per_item != 2048 && points_per_item != 4096)
+  if (points_per_item != 512 && points_per_item != 1024 && points_per_item != 2048 && points_per_item != kScoreMaxPoints)
     return set_err(c, IMLOC_EINVAL, "points_per_item must be 512, 1024, 2048 or 4096");
   c->tune.pts = points_per_item;
   return IMLOC_OK;

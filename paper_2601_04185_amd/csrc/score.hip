@@ -29,7 +29,10 @@
 // 64 * PPL correspondences) is converted once to fixed point (2^-32) and all
 // partials are added with integer atomics, as are the counts.  Integer sums
 // do not depend on the order, so a candidate's score is the same for any
-// tiling, grid size or mix of queries.
+// tiling, grid size or mix of queries.  The per-(candidate, wave) table in
+// LDS starts at zero and only a wave block with inliers writes its entry (its
+// count and float partial); the conversion to fixed point happens in the
+// item's final reduction, off the candidate loop.
 #include "imloc_device.h"
 #include "imloc_kernels.h"
 #include "query_device.h"
@@ -38,22 +41,24 @@ namespace imloc {
 
 constexpr int kScoreBlock = 256;
 constexpr int kScoreWaves = kScoreBlock / kWave;
+constexpr int kScoreMaxRounds = kScoreMaxPoints / (kScoreWaves * kScoreWaveBlock);  // wave blocks per wave and item
+static_assert(kScoreMaxRounds == 2, "a work item of 4,096 correspondences gives each wave two blocks");
 
 // Sum over the 64 lanes of a full wave with DPP lane moves (pairs, quads,
-// rows of 16 by shifts, then the row broadcasts 15 and 31), total read from
-// lane 63 (wave-uniform).  Every lane must be active.
+// rows of 16 by shifts, then the row broadcasts 15 and 31); lane 63 ends with
+// the total.  Every lane must be active.
 template <int CTRL>
 __device__ inline float dpp_move(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
-__device__ inline float wave_total_dpp(float x) {
+__device__ inline float wave_scan_dpp(float x) {
   x += dpp_move<0xb1>(x);   // quad_perm [1, 0, 3, 2]
   x += dpp_move<0x4e>(x);   // quad_perm [2, 3, 0, 1]
   x += dpp_move<0x114>(x);  // row_shr:4
   x += dpp_move<0x118>(x);  // row_shr:8
   x += dpp_move<0x142>(x);  // row_bcast:15
   x += dpp_move<0x143>(x);  // row_bcast:31
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+  return x;  // lane 63 holds the total
 }
 
 // Correspondences per work item: `pts` in float32 scoring (a multiple of the
@@ -143,7 +148,7 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
                                                uint32_t* __restrict__ ccnt, unsigned long long* __restrict__ cgain,
                                                BestState* st, int64_t tile, int64_t chunk, int ncand, int pts,
                                                uint32_t (*s_cnt)[kScoreWaves],
-                                               unsigned long long (*s_gain)[kScoreWaves], uint32_t* s_item,
+                                               float (*s_part)[kScoreMaxRounds * kScoreWaves], uint32_t* s_item,
                                                float4 (*s_rows)[3]) {
   constexpr int PPL = kScorePPL32;
   // the wave index in a scalar register: the candidate range and the block
@@ -213,7 +218,6 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
         bal[k] = __ballot(dd[k] < 0.f);
         cnt += (uint32_t)__popcll(bal[k]);
       }
-      unsigned long long gfx = 0;
       if (cnt) {  // G += w_i (w|w| - e') / (w|w|) over the inliers, point slots with no inlier skipped
         // (the empty volatile statements keep these wave-uniform branches as
         // branches: most candidates have no inlier in most slots)
@@ -227,14 +231,13 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
             if (dd[k] < 0.f) gain = fmaf(-pw[k] * dd[k], __builtin_amdgcn_rcpf(t), gain);
           }
         }
-        gain = wave_total_dpp(gain);
-        gfx = (unsigned long long)((double)gain * kGainScale);
+        gain = wave_scan_dpp(gain);  // the block's total in lane 63
+        if (lane == kWave - 1) {
+          s_cnt[c][wave] = MULTI ? s_cnt[c][wave] + cnt : cnt;
+          s_part[c][wave * kScoreMaxRounds + r] = gain;
+        }
       }
       item_cnt += cnt;
-      if (lane == 0) {
-        s_cnt[c][wave] = r == 0 ? cnt : s_cnt[c][wave] + cnt;
-        s_gain[c][wave] = r == 0 ? gfx : s_gain[c][wave] + gfx;
-      }
     }
   }
   if (lane == 0) s_item[wave] = item_cnt;
@@ -243,7 +246,15 @@ __device__ __forceinline__ void score_item_f32(const QueryDesc& d, const float* 
     const int c = threadIdx.x, w0 = (c / gsz) * wpg;
     uint32_t cnt = 0;
     unsigned long long g = 0;
-    for (int w = w0; w < w0 + wpg; ++w) { cnt += s_cnt[c][w]; g += s_gain[c][w]; }
+    for (int w = w0; w < w0 + wpg; ++w) {
+      cnt += s_cnt[c][w];
+      s_cnt[c][w] = 0;  // the table is empty again for the next item
+      for (int r = 0; r < rounds; ++r) {  // each wave block's float partial to fixed point once
+        const float p = s_part[c][w * kScoreMaxRounds + r];
+        if (p != 0.f) g += (unsigned long long)((double)p * kGainScale);
+        s_part[c][w * kScoreMaxRounds + r] = 0.f;
+      }
+    }
     const int64_t slot = d.cand_off + c0 + c;
     if (cnt) atomicAdd(&ccnt[slot], cnt);
     if (g) atomicAdd(&cgain[slot], g);
@@ -354,10 +365,21 @@ __global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __r
                                                             unsigned long long* __restrict__ cgain,
                                                             BestState* __restrict__ st, int nq, int pts,
                                                             const int64_t* __restrict__ item_off) {
-  __shared__ uint32_t s_cnt[CT][kScoreWaves];
+  __shared__ uint32_t s_cnt[CT][kScoreWaves];    // float32 items
+  __shared__ float s_part[CT][kScoreMaxRounds * kScoreWaves];
+  __shared__ uint32_t s_cnt64[CT][kScoreWaves];  // float64 items
   __shared__ unsigned long long s_gain[CT][kScoreWaves];
   __shared__ uint32_t s_item[kScoreWaves];
   __shared__ float4 s_rows[CT][3];
+  // the float32 (candidate, wave) table starts empty, and every item's final
+  // reduction empties what it read: a wave block writes its entry only when it
+  // holds inliers
+  for (int e = threadIdx.x; e < CT * kScoreWaves; e += kScoreBlock) {
+    (&s_cnt[0][0])[e] = 0;
+#pragma unroll
+    for (int r = 0; r < kScoreMaxRounds; ++r) (&s_part[0][0])[e * kScoreMaxRounds + r] = 0.f;
+  }
+  __syncthreads();
   const int64_t total = item_off[nq];
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     int lo = 0, hi = nq - 1;  // the query owning item w: last q with item_off[q] <= w
@@ -371,10 +393,10 @@ __global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __r
     const int64_t tile = local / chunks, chunk = local - tile * chunks;
     const int nc = ncand[lo];
     if (d.precision == 0)
-      score_item_f32<CT, MULTI>(d, proj, ccnt, cgain, st + lo, tile, chunk, nc, pts, s_cnt, s_gain, s_item,
+      score_item_f32<CT, MULTI>(d, proj, ccnt, cgain, st + lo, tile, chunk, nc, pts, s_cnt, s_part, s_item,
                                 s_rows);
     else
-      score_item_f64<CT>(d, pose, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt, s_gain, s_item);
+      score_item_f64<CT>(d, pose, ccnt, cgain, st + lo, tile, chunk, nc, s_cnt64, s_gain, s_item);
   }
 }
 
