@@ -187,10 +187,13 @@ int imloc_graph_counters(const imloc_ctx *ctx, int64_t *captures, int64_t *launc
 
 /* Launch shape of the scoring kernel: candidates per work item (32, 64 or
  * 128, or 0, the default: picked per round, the largest tile that still
- * gives about four work items per compute unit) and persistent workgroups.
- * Neither changes any result (per-candidate sums are integer-accumulated),
- * only the speed; the autotuner in the Python package picks them by timing.
- * imloc_get_score_tuning reports 0 while the tile is picked per round. */
+ * gives about four work items per compute unit) and workgroups (1 to 2^20;
+ * each walks the round's work list with a grid stride; or 0, the default:
+ * per round, about 1.5 per estimated work item, between 8 per compute unit
+ * and 2^18).  Neither changes any result (per-candidate sums are
+ * integer-accumulated), only the speed; the autotuner in the Python package
+ * picks them by timing.  imloc_get_score_tuning reports 0 for a value picked
+ * per round.  Returns IMLOC_EINVAL for other values. */
 int imloc_set_score_tuning(imloc_ctx *ctx, int32_t candidates_per_item, int32_t workgroups);
 int imloc_get_score_tuning(const imloc_ctx *ctx, int32_t *candidates_per_item, int32_t *workgroups);
 

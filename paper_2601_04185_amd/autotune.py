@@ -1,8 +1,9 @@
 """Autotuner of the scoring kernel's launch shape.
 
-The persistent scoring kernel takes three free parameters: candidates per
-work item (32, 64 or 128), correspondences per work item (512 to 4,096, the
-correspondence tile) and the number of persistent workgroups.  None changes a
+The scoring kernel takes three free parameters: candidates per work item
+(32, 64 or 128), correspondences per work item (512 to 4,096, the
+correspondence tile) and the number of workgroups (from a few per compute
+unit, each striding over many work items, to about one per item).  None changes a
 result (per-candidate scores are integer-accumulated over fixed 512-point
 wave blocks), so the tuner simply times each shape on the caller's own
 workload with HIP events (the library's per-stage timing) and keeps the
@@ -18,7 +19,7 @@ from . import Context, lib
 def candidate_shapes(cus: int):
     for ct in (32, 64, 128):
         for pts in (512, 1024, 2048, 4096):
-            for per_cu in (4, 8, 16, 32):
+            for per_cu in (4, 8, 16, 32, 64, 128, 256):
                 yield ct, pts, per_cu * cus
 
 

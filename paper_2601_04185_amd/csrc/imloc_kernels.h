@@ -24,6 +24,7 @@ constexpr int kMaxCams = 8;        // cameras of a rig query, at most
 constexpr int kScorePPL32 = 8;     // correspondences per lane, float32 scoring (fixes the summation order)
 constexpr int kScoreWaveBlock = 64 * kScorePPL32;  // a wave's 512 consecutive correspondences, float32 scoring
 constexpr int kScoreMaxPoints = 4096;  // the largest float32 work item (correspondences)
+constexpr int kScoreMaxBlocks = 1 << 18;  // the largest grid picked per round (workgroups)
 constexpr int kScorePPL64 = 2;     // correspondences per lane, float64 scoring
 constexpr double kGainScale = 4294967296.0;  // fixed-point scale of the accumulated truncated-cost gain
 

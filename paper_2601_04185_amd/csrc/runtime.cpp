@@ -122,7 +122,7 @@ struct imloc_ctx {
   // timing events, created when timing is switched on (imloc_set_timing)
   std::vector<hipEvent_t> events;
   size_t next_event = 0;
-  ScoreTune tune{0, 2048, 2048};  // ct == 0: the candidate tile is picked per round (round_tune)
+  ScoreTune tune{0, 0, 2048};  // ct == 0, blocks == 0: the tile and the grid are picked per round (round_tune)
   int cus = 256;
   int gn_mode = 0;  // Gauss-Newton launch form: 0 by size, 1 fused, 2 split
   // hipGraph replay of the fixed-sample pipeline
@@ -214,14 +214,33 @@ struct QPlan {
 // integer-accumulated over fixed wave blocks).
 using EstList = SmallVec<std::pair<int64_t, int64_t>, 4>;
 ScoreTune round_tune(const imloc_ctx* c, const std::pair<int64_t, int64_t>* est, size_t n_est) {
-  if (c->tune.ct > 0) return c->tune;
-  const int64_t pts = c->tune.pts;
-  for (int ct : {128, 64}) {
+  ScoreTune t = c->tune;
+  if (t.ct > 0 && t.blocks > 0) return t;
+  const int64_t pts = t.pts;
+  auto items_for = [&](int ct) {
     int64_t items = 0;
     for (size_t q = 0; q < n_est; ++q) items += (est[q].first + ct - 1) / ct * ((est[q].second + pts - 1) / pts);
-    if (items >= 4 * (int64_t)c->cus) return ScoreTune{ct, c->tune.blocks, c->tune.pts};
+    return items;
+  };
+  if (t.ct == 0) {
+    t.ct = 32;
+    for (int ct : {128, 64})
+      if (items_for(ct) >= 4 * (int64_t)c->cus) {
+        t.ct = ct;
+        break;
+      }
   }
-  return ScoreTune{32, c->tune.blocks, c->tune.pts};
+  if (t.blocks == 0) {
+    // About one work item per workgroup: the hardware dispatcher then hands
+    // the next item to whichever workgroup slot frees first, so ragged items
+    // (a query's last tile and chunk) leave a tail of about one item, where a
+    // grid of a few resident workgroups striding over many items each leaves
+    // a tail of a whole workgroup's share (3.7 % of the 256-query batch's
+    // scoring).  A P3P sample gives 1.4 candidates on average, up to 4.
+    const int64_t items = items_for(t.ct);
+    t.blocks = (int)std::min<int64_t>(kScoreMaxBlocks, std::max<int64_t>(8 * (int64_t)c->cus, items + items / 2));
+  }
+  return t;
 }
 
 // Scoring points of a query for the estimate above (a rig cuts its segments
@@ -863,8 +882,8 @@ int imloc_create(imloc_ctx** out, int device, void* hip_stream) {
   int cus = 256;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   c->cus = cus > 0 ? cus : 256;
-  c->tune.ct = 0;
-  c->tune.blocks = 16 * c->cus;
+  c->tune.ct = 0;      // the candidate tile and
+  c->tune.blocks = 0;  // the grid of the scoring launch: picked per round
   *out = c;
   return IMLOC_OK;
 }
@@ -954,7 +973,7 @@ int imloc_set_score_tuning(imloc_ctx* c, int32_t candidates_per_item, int32_t wo
   if (!c) return IMLOC_EINVAL;
   if (candidates_per_item != 0 && candidates_per_item != 32 && candidates_per_item != 64 && candidates_per_item != 128)
     return set_err(c, IMLOC_EINVAL, "candidates_per_item must be 0 (per round), 32, 64 or 128");
-  if (workgroups < 1 || workgroups > (1 << 20)) return set_err(c, IMLOC_EINVAL, "workgroups out of range");
+  if (workgroups < 0 || workgroups > (1 << 20)) return set_err(c, IMLOC_EINVAL, "workgroups out of range");
   c->tune.ct = candidates_per_item;
   c->tune.blocks = workgroups;
   return IMLOC_OK;

@@ -90,7 +90,7 @@ def test_tuning_does_not_change_results(pk):
     prm = pk.make_params(threshold_px=4.0, fixed_samples=3000, batch=3000)
     ref = None
     for ct, wg, pts in [(32, 64, 2048), (64, 2048, 512), (128, 517, 4096), (64, 1, 1024), (0, 4096, 2048),
-                        (0, 4096, 512)]:
+                        (0, 4096, 512), (0, 0, 2048), (128, 0, 1024), (64, 100000, 4096)]:
         ctx = pk.Context(0)
         ctx.set_score_tuning(ct, wg)
         ctx.set_score_points(pts)

@@ -157,7 +157,7 @@ def test_score_tiles_give_identical_scores(pk, orc, n):
     lo, hi, _ = orc.score_band(poses, q.corr(), q.K, 4.0, band_abs=1e-5, with_f32=True)
     ref = None
     for ct, wg, pts in [(128, 2048, 2048), (32, 300, 512), (64, 1024, 1024), (128, 4096, 4096), (32, 7, 4096),
-                        (64, 513, 512)]:
+                        (64, 513, 512), (0, 0, 2048), (32, 0, 512)]:
         c = pk.Context(0)
         c.set_score_tuning(ct, wg)
         c.set_score_points(pts)
@@ -177,6 +177,17 @@ def test_score_points_rejects_other_values(pk):
         with pytest.raises(pk.ImlocError):
             c.set_score_points(bad)
     assert c.score_points() == 2048
+
+
+def test_score_tuning_rejects_other_values(pk):
+    c = pk.Context(0)
+    assert c.score_tuning() == (0, 0)  # both picked per round
+    for ct, wg in ((16, 0), (256, 0), (128, -1), (64, (1 << 20) + 1)):
+        with pytest.raises(pk.ImlocError):
+            c.set_score_tuning(ct, wg)
+    assert c.score_tuning() == (0, 0)
+    c.set_score_tuning(64, 1 << 20)
+    assert c.score_tuning() == (64, 1 << 20)
 
 
 def test_score_ragged_candidate_counts(pk, ctx, orc):
