@@ -184,7 +184,7 @@ hipError_t launch_set_candidates(const QueryDesc* qd, const double* poses, int64
 // --- scoring -----------------------------------------------------------------
 struct ScoreTune {
   int ct;       // candidates per work item (32, 64 or 128)
-  int blocks;   // persistent workgroups
+  int blocks;   // workgroups of the launch (each strides over the work list)
   int pts;      // correspondences per float32 work item (512, 1024, 2048 or 4096)
 };
 hipError_t launch_worklist(const QueryDesc* qd, CandBuf cb, int nq, ScoreTune tune, int64_t* item_off,
