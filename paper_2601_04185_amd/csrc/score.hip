@@ -4,9 +4,8 @@
 // per-query top-k selection of the candidates to refine.
 //
 // Work decomposition: a work item is (query, tile of CT candidates, chunk of
-// P correspondences); the workgroups walk a device-side work list with a grid
-// stride (by default about one item each), so one launch covers any mix of
-// queries.
+// 256 * PPL correspondences); persistent workgroups walk a device-side work
+// list, so one launch covers any mix of queries.
 //
 // Layout: one lane per correspondence (PPL correspondences per lane kept in
 // registers, coalesced structure-of-arrays loads).  A work item first stages
@@ -355,8 +354,8 @@ __device__ __forceinline__ void score_item_f64(const QueryDesc& d, const double*
   __syncthreads();
 }
 
-// Workgroups over the work list with a grid stride; every workgroup exits
-// once the item index passes the device-side total.
+// Persistent workgroups over the work list; every workgroup exits once the
+// item index passes the device-side total.
 template <int CT, bool MULTI>
 __global__ __launch_bounds__(kScoreBlock) void score_kernel(const QueryDesc* __restrict__ qd,
                                                             const float* __restrict__ proj,
