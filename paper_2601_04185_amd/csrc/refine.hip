@@ -446,19 +446,6 @@ __device__ __forceinline__ bool gn_decide_wave(int j, int iters, const double* t
   return false;
 }
 
-__device__ __forceinline__ void gn_load_state(GNShared& s, const GNState* st, const double* start) {
-  if (threadIdx.x < 12) {
-    s.cur[threadIdx.x] = st ? st->cur[threadIdx.x] : start[threadIdx.x];
-    s.eval[threadIdx.x] = st ? st->eval[threadIdx.x] : start[threadIdx.x];
-  }
-  if (threadIdx.x == 0) {
-    s.cost = st ? st->cur_cost : __builtin_inf();
-    s.count = st ? st->cur_count : 0.0;
-    s.done = st ? st->done : 0;
-    s.accepted = st ? st->accepted : 0;
-  }
-}
-
 // A recorded state read into registers at kernel entry (threads 0..11 hold
 // one element of cur and eval, every thread the scalars), so that its latency
 // overlaps the other loads; gn_state_to_lds then publishes it.
@@ -883,6 +870,14 @@ __attribute__((amdgpu_waves_per_eu((!RIG && !W) ? 4 : 1, (!RIG && !W) ? 4 : 8)))
   const int64_t n = d.m;
   const int C = chunks_for(n);
   if (chunk >= C) return;
+  // the query's live problems, their flags read together (lane s: slot s);
+  // once every run has ended the workgroup exits before loading any point
+  // (most runs end within a few iterations)
+  const GNState* st0 = j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + q * g.kmax : nullptr;
+  const int lane = threadIdx.x & (kWave - 1);
+  uint64_t live = ns >= kWave ? ~0ull : (1ull << ns) - 1ull;
+  if (st0) live = __ballot(lane < ns && !st0[lane].done);
+  if (!live) return;
   GNPoints pt;
   gn_load_points(d.S, n, chunk, g.part, pt);
   __shared__ double s_rig[RIG ? kMaxCams * 16 : 1];
@@ -890,10 +885,10 @@ __attribute__((amdgpu_waves_per_eu((!RIG && !W) ? 4 : 1, (!RIG && !W) ? 4 : 8)))
     for (int e = threadIdx.x; e < 16 * d.ncam; e += kGNThreads) s_rig[e] = d.rig[e];
   __shared__ double s_eval[12];
   __shared__ double s_rows[kGNWaves][kAcc];
-  for (int slot = 0; slot < ns; ++slot) {
+  for (; live; live &= live - 1) {
+    const int slot = __builtin_ctzll(live);
     const int p = q * g.kmax + slot;
-    const GNState* st = j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr;
-    if (st && st->done) continue;
+    const GNState* st = st0 ? st0 + slot : nullptr;
     const double* start = st ? nullptr : gn_start<0>(g, p, q);
     // every thread has left the previous problem's accumulation (its last
     // barrier) before s_eval is rewritten
@@ -909,10 +904,18 @@ __attribute__((amdgpu_waves_per_eu((!RIG && !W) ? 4 : 1, (!RIG && !W) ? 4 : 8)))
 template <int MODE>
 __global__ __launch_bounds__(kGNThreads) void gn_decide_kernel(GNArgs g, int j) {
   const int p = blockIdx.x;
+  GNStateRegs sr;
+  gn_state_issue(j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr, sr);
   GNPart pr;
   gn_part_issue(gn_part(g, j & 1, p), g.cmax, pr);
   const int q = gn_query<MODE>(g, p);
   if (!gn_live<MODE>(g, p, q)) return;
+  // a run that has ended: its state carried to the slot the next launch
+  // reads, without waiting for the partial sums
+  if (j > 0 && sr.done) {
+    gn_store_state_regs(sr, g.gst + (int64_t)(j & 1) * g.nprob + p);
+    return;
+  }
   const QueryDesc& d = g.qd[q];
   const int64_t n = MODE == 0 ? d.m : d.n;
   const int iters = MODE == 0 ? d.lo_iters : d.final_iters;
@@ -922,8 +925,7 @@ __global__ __launch_bounds__(kGNThreads) void gn_decide_kernel(GNArgs g, int j) 
   __shared__ GNShared s;
   __shared__ int s_end;
   gn_part_sum(gn_part(g, j & 1, p), C, pr, s_grp, s_tot);
-  gn_load_state(s, j > 0 ? g.gst + (int64_t)((j - 1) & 1) * g.nprob + p : nullptr,
-                j > 0 ? nullptr : gn_start<MODE>(g, p, q));
+  gn_state_to_lds(s, sr, j > 0, j > 0 ? nullptr : gn_start<MODE>(g, p, q));
   __syncthreads();
   if (threadIdx.x < kWave) {
     const bool end = gn_decide_wave(j, iters, s_tot, s);
