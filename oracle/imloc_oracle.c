@@ -636,6 +636,16 @@ double orc_normal_equations(const orc_pose *P, const orc_corr *c, const orc_came
 
 void orc_pose_update(const orc_pose *P, const double d[6], orc_pose *o) { pose_update(P, d, o); }
 
+/* Converged: a Gauss-Newton step (dw in rad, dt in scene units) shorter
+ * than 1e-10 is not taken and ends the run (the refinement the paper follows
+ * also stops on a short step). */
+#define ORC_STEP_TOL2 1e-20
+int orc_step_converged(const double d[6]) {
+  double s = 0.0;
+  for (int k = 0; k < 6; ++k) s += d[k] * d[k];
+  return s < ORC_STEP_TOL2;
+}
+
 int orc_lo(const orc_pose *start, const orc_corr *c, const orc_camera *K, double tau, int32_t iters,
            orc_pose *out, double *cost, int64_t *count) {
   double tau2 = tau * tau, H[36], g[6];
@@ -647,6 +657,7 @@ int orc_lo(const orc_pose *start, const orc_corr *c, const orc_camera *K, double
     double rhs[6], d[6];
     for (int k = 0; k < 6; ++k) rhs[k] = -g[k];
     if (!chol6_solve(H, rhs, d)) break;
+    if (orc_step_converged(d)) break;
     orc_pose cand;
     pose_update(&cur, d, &cand);
     double H2[36], g2[6];
@@ -713,6 +724,7 @@ int orc_refine(const orc_pose *start, const orc_corr *c, const orc_camera *K, do
     double rhs[6], d[6];
     for (int k = 0; k < 6; ++k) rhs[k] = -g[k];
     if (!chol6_solve(H, rhs, d)) break;
+    if (orc_step_converged(d)) break;
     orc_pose cand;
     pose_update(&cur, d, &cand);
     double H2[36], g2[6];

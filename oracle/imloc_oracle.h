@@ -120,15 +120,21 @@ double orc_normal_equations(const orc_pose *P, const orc_corr *c, const orc_came
 /* Left update on SO(3) x R^3: R' = Exp(dw) R, t' = Exp(dw) t + dt. */
 void orc_pose_update(const orc_pose *P, const double d[6], orc_pose *o);
 
+/* 1 if the Gauss-Newton step d = (dw, dt) is shorter than 1e-10: such a
+ * step is not taken and ends the run (local optimisation, refinement). */
+int orc_step_converged(const double d[6]);
+
 /* Local optimisation: Gauss-Newton on sum_i w_i min(r_i^2, tau^2) over the
  * given point set, inlier set re-evaluated at every iterate, left update on
- * SO(3), a step that raises the cost is rejected and ends the run.
+ * SO(3), a step that raises the cost is rejected and ends the run, and so
+ * does a step shorter than 1e-10 (Euclidean norm of (dw, dt)), not taken.
  * Returns the number of accepted steps; *cost / *count at the output pose. */
 int orc_lo(const orc_pose *start, const orc_corr *c, const orc_camera *K, double tau,
            int32_t iters, orc_pose *out, double *cost, int64_t *count);
 
 /* Final refinement: IRLS Gauss-Newton on sum_{i in I} w_i s^2 ln(1 + r_i^2/s^2)
- * over the fixed set I = inliers of the full set at the start pose (tau).
+ * over the fixed set I = inliers of the full set at the start pose (tau),
+ * with the same two ends of a run as orc_lo.
  * Returns accepted steps; *cost at the output pose; *n_inl = |I|. */
 int orc_refine(const orc_pose *start, const orc_corr *c, const orc_camera *K, double tau,
                double s, int32_t iters, orc_pose *out, double *cost, int64_t *n_inl);

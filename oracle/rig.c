@@ -401,6 +401,7 @@ int orc_rig_lo(const orc_pose *start, const orc_rig_corr *c, const orc_rig_camer
     double rhs[6], d[6];
     for (int k = 0; k < 6; ++k) rhs[k] = -g[k];
     if (!rig_chol6(H, rhs, d)) break;
+    if (orc_step_converged(d)) break;
     orc_pose cand;
     orc_pose_update(&cur, d, &cand);
     double H2[36], g2[6];
@@ -469,6 +470,7 @@ int orc_rig_refine(const orc_pose *start, const orc_rig_corr *c, const orc_rig_c
     double rhs[6], d[6];
     for (int k = 0; k < 6; ++k) rhs[k] = -g[k];
     if (!rig_chol6(H, rhs, d)) break;
+    if (orc_step_converged(d)) break;
     orc_pose cand;
     orc_pose_update(&cur, d, &cand);
     double H2[36], g2[6];

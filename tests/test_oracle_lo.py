@@ -6,7 +6,9 @@ section).
 Pins: the gradient and Gauss-Newton matrix against central finite differences
 of the cost under the same left update; convergence to the ground truth on
 noise-free data; the fixed point against scipy.optimize.least_squares (plain
-and Cauchy loss) on the same point set; monotone cost."""
+and Cauchy loss) on the same point set; monotone cost; the run's ends (a
+cost-raising or shorter-than-1e-10 step, the cap) retold from the oracle's
+pieces."""
 import numpy as np
 import pytest
 from scipy.optimize import least_squares, minimize
@@ -111,6 +113,38 @@ def test_lo_cost_non_increasing(orc):
         _, _, cost, _, _ = orc.lo((R0, t0), q.corr(), q.K, 4.0, iters=it)
         assert cost <= prev + 1e-9 * abs(prev)
         prev = cost
+
+
+def test_lo_run_ends_as_read(orc):
+    """The run's control flow, retold from the oracle's own pieces (normal
+    equations, left update) with a numpy solve: a step is taken only if it
+    is at least 1e-10 long and does not raise the cost; the run ends at the
+    first step that fails either test, or at the cap (never reached here: 50)."""
+    ends = []
+    for seed, n, eps, sigma in ((15, 2500, 0.4, 1.0), (16, 1200, 0.6, 0.0), (17, 4000, 0.2, 1.5)):
+        q = synth.make_query(seed, n, eps, sigma)
+        rng = np.random.default_rng(seed)
+        R0, t0 = _perturb(q.R, q.t, rng, 0.01, 0.03)
+        R, t, cost, cnt, acc = orc.lo((R0, t0), q.corr(), q.K, 4.0, iters=50)
+        cur = (R0, t0)
+        c_cur, H, g, _ = orc.normal_equations(cur, q.corr(), q.K, 4.0)
+        taken, end = 0, "cap"
+        for _ in range(50):
+            d = np.linalg.solve(H, -g)
+            if d @ d < 1e-20:
+                end = "short step"
+                break
+            cand = orc.pose_update(cur, d)
+            c_new, H2, g2, _ = orc.normal_equations(cand, q.corr(), q.K, 4.0)
+            if not c_new <= c_cur:
+                end = "cost rise"
+                break
+            cur, c_cur, H, g = cand, c_new, H2, g2
+            taken += 1
+        assert acc == taken < 50, (seed, acc, taken)
+        assert rot_angle(R, cur[0]) < 1e-12 and np.linalg.norm(t - cur[1]) < 1e-11
+        ends.append(end)
+    assert "short step" in ends and "cap" not in ends, ends
 
 
 def test_refine_cauchy_matches_scipy(orc):
