@@ -23,6 +23,7 @@
 namespace imloc {
 
 constexpr int kAcc = 29;  // 21 (H upper) + 6 (g) + cost + count
+constexpr double kStepTol2 = 1e-20;  // squared length of a step that ends a run
 constexpr int kGNThreads = 256;
 constexpr int kGNWaves = kGNThreads / kWave;
 constexpr int kGNPPT = 2;                       // points per thread per chunk
@@ -423,6 +424,15 @@ __device__ __forceinline__ bool gn_decide_wave(int j, int iters, const double* t
   }
   double d[6];
   if (!solve6_schur(tot, d)) {
+    if (lane == 0) s.done = 1;
+    return true;
+  }
+  // converged: a step shorter than 1e-10 (norm of (dw, dt)) is not taken and
+  // ends the run (every lane holds d; the sum in element order)
+  double d2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) d2 += d[e] * d[e];
+  if (d2 < kStepTol2) {
     if (lane == 0) s.done = 1;
     return true;
   }
