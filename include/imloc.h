@@ -86,9 +86,10 @@ typedef struct {
   int64_t max_iters;         /* adaptive mode: cap (the paper: 100,000) */
   double confidence;         /* adaptive mode: stop when P(missing the best model) < 1 - confidence */
   int32_t lo_top_k;          /* candidates of a batch refined when they beat the running best (clamped to [1, 32]) */
-  int32_t lo_iters;          /* Gauss-Newton iterations of the local optimisation */
+  int32_t lo_iters;          /* Gauss-Newton iterations of the local optimisation, at most (a run also
+                                ends at a cost-raising step or one shorter than 1e-10) */
   int64_t max_score_points;  /* 0: score every correspondence; else stride-subsample to this many */
-  int32_t final_iters;       /* Cauchy refinement iterations (0: skip) */
+  int32_t final_iters;       /* Cauchy refinement iterations, at most, with the same two ends (0: skip) */
   double cauchy_scale_px;    /* s of rho(r^2) = s^2 ln(1 + r^2 / s^2) */
   int32_t exhaustive;        /* 1: sample h is the h-th 3-combination instead of a Philox draw */
   int32_t precision;         /* IMLOC_FP32_SCORE or IMLOC_FP64_ALL */
@@ -344,12 +345,14 @@ int imloc_triangulate_depth(imloc_ctx *ctx, int32_t H, int32_t W, const imloc_ca
  * up to four candidates per sample; each is scored against every scored
  * correspondence by sum_i w_i min(r_i^2, tau^2) (points behind the camera
  * count tau^2).  Per batch the lo_top_k lowest-scoring candidates that beat
- * the running best are refined by lo_iters Gauss-Newton iterations on that
- * truncated cost, and the lowest refined cost becomes the best model.  The
+ * the running best are refined by at most lo_iters Gauss-Newton iterations
+ * on that truncated cost (a step that raises the cost, or is shorter than
+ * 1e-10 in (rad, scene units), is not taken and ends the run), and the
+ * lowest refined cost becomes the best model.  The
  * adaptive rule stops once samples >= min(max_iters, max(min_iters,
  * ceil(ln(1 - confidence) / ln(1 - eps^3)))), eps = best inlier ratio.  The
- * best pose is then refined by final_iters Cauchy IRLS iterations over the
- * inliers of the full set.
+ * best pose is then refined by at most final_iters Cauchy IRLS iterations
+ * (the same two ends) over the inliers of the full set.
  *   pts: device arrays of n entries.  pose_out, stats: host (stats may be
  *   NULL).  inlier_mask: device uint8 [n] (may be NULL): 1 where the point
  *   is an inlier of the final pose.  Returns IMLOC_OK, IMLOC_NO_POSE (n < 3 or
@@ -421,16 +424,19 @@ int imloc_select_top_k(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const i
                        int32_t *n_sel);
 
 /* Local optimisation of np start poses (device double [np][12]) on n
- * correspondences; out_poses (device double [np][12]), cost (device double
- * [np]), count (device int64 [np]). */
+ * correspondences: at most iters Gauss-Newton steps each, a run ending at a
+ * step that raises the truncated cost or is shorter than 1e-10; out_poses
+ * (device double [np][12]), cost (device double [np]), count (device int64
+ * [np]). */
 int imloc_local_optimize(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K,
                          const double *start, int32_t np, double threshold_px, int32_t iters, double *out_poses,
                          double *cost, int64_t *count);
 
 /* Final Cauchy refinement of one start pose (device double [12]) over the
- * inliers of the n correspondences at that pose; out_pose (device double
- * [12]), cost (device double), mask (device uint8 [n], may be NULL) at the
- * refined pose. */
+ * inliers of the n correspondences at that pose, at most iters IRLS steps (a
+ * step that raises the cost or is shorter than 1e-10 ends the run); out_pose
+ * (device double [12]), cost (device double), mask (device uint8 [n], may be
+ * NULL) at the refined pose. */
 int imloc_refine(imloc_ctx *ctx, const imloc_corr *pts, int64_t n, const imloc_camera *K, const double *start,
                  double threshold_px, double cauchy_scale_px, int32_t iters, double *out_pose, double *cost,
                  uint8_t *mask);
